@@ -1,0 +1,544 @@
+/*
+ * FP64 CPU oracle of one chi^2 made-to-measure (M2M) step with moving-prior
+ * regularization (MPR), after Morganti & Gerhard (2012).
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the package smoke check and the
+ * benchmark's CPU-baseline leg load this library. It shares no source with
+ * the HIP library and is not a fallback for it.
+ *
+ * Everything is scalar double precision, written as the definitions read:
+ *   - weights: the paper's w_i with sum w = M initially (Sec. 3.2), carried
+ *     as u_i = N w_i / M so that u_i = 1 at the start (flat priors,
+ *     Sec. 2.2); w_i = u_i M / N.
+ *   - model observables y_j = sum_i w_i K_j(z_i)          (Sec. 2.1, eq. obs)
+ *   - time smoothing: the exponential kernel of eq. myts applied to a
+ *     y that is constant over each step, i.e.
+ *       ytilde <- ytilde + q (y - ytilde),  q = 1 - exp(-alpha dt),
+ *     with ytilde = y at t = 0.
+ *   - residuals Delta_j = (ytilde_j - Y_j) / sigma_j, chi^2 = sum Delta_j^2
+ *                                                  (eqs. delta and chi)
+ *   - force of change (eq. modFOC) for the weights u_i, with the chi^2
+ *     gradient of y_j with respect to u_i, (M/N) K_j:
+ *       G_i = mu dS/du_i - (M/N) sum_j K_j(z_i) Delta_j / sigma_j
+ *       dS/du_i = -ln(u_i / uhat_i)       (mass-neutral entropy, eq. S+)
+ *       dS/du_i = -ln(u_i / uhat_i) - 1   (weight entropy, eq. entropy)
+ *     integrated over one step as u_i <- u_i exp(eps dt G_i), with K and
+ *     Delta taken at the start of the step.
+ *   - leapfrog (Sec. 4.1) in drift-kick-drift form in the fixed potential.
+ *   - priors (Sec. 2.3.1): cells of a rectangular (E, x = L/L_c(E)) grid,
+ *     uhat = mean u of the cell, assigned to every particle in the cell.
+ *   - order within a step: force of change at z^k with Delta^k, push to
+ *     z^{k+1}, deposit at z^{k+1}, smoothing and residuals, then (MPR, every
+ *     prior_every correction steps) new priors from z^{k+1}.
+ *
+ * The Hernquist potential is eq. her (Sec. 3.1); the optional NFW halo is
+ *   Phi = -G M200 / f(c) ln(1 + r/r_s) / r,  f(c) = ln(1+c) - c/(1+c).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double G, M_star, a, upsilon; /* Hernquist mass is M_star * upsilon */
+    double M200, c, r_s;          /* NFW; M200 = 0 means none */
+} orc_potential;
+
+/* kin: 0 none, 1 v_z^2 moment, 2 Gauss-Hermite b_1..b_gh_nmax, 3 LOSVD */
+typedef struct {
+    int32_t n_r;
+    double r_min, r_max;
+    int32_t n_R;
+    double R_min, R_max;
+    int32_t kin;
+    int32_t gh_nmax;
+    int32_t n_v;
+    double v_min, v_max;
+} orc_layout;
+
+/* entropy: 0 = mass-neutral S+ with moving priors, 1 = weight entropy */
+typedef struct {
+    double dt, eps, mu, alpha, mass;
+    int32_t entropy, n_E, n_x, prior_every;
+    double E_lo, E_hi;
+} orc_params;
+
+typedef struct {
+    int64_t n;
+    double *x, *y, *z, *vx, *vy, *vz, *u, *uhat;
+    orc_potential pot;
+    orc_layout lay;
+    orc_params par;
+    int32_t J;
+    const double *Y, *sigma, *Vp, *sp;
+    double *ytilde, *yraw, *delta;
+    double chi2;
+    int64_t kstep;
+    uint8_t *flag;   /* optional: particle came within `band` of an edge */
+    double band;
+    int32_t nthreads;
+} orc_model;
+
+#define ORC_MAXK 80  /* at most 1 radial + 64 kinematic entries per particle */
+
+/* ------------------------------------------------------------- potential */
+static double nfw_fc(const orc_potential *p) {
+    return log(1.0 + p->c) - p->c / (1.0 + p->c);
+}
+
+double orc_phi(const orc_potential *p, double r) {
+    double phi = -p->G * p->M_star * p->upsilon / (r + p->a);
+    if (p->M200 > 0.0) {
+        double k = p->G * p->M200 / nfw_fc(p);
+        phi += (r > 0.0) ? -k * log1p(r / p->r_s) / r : -k / p->r_s;
+    }
+    return phi;
+}
+
+double orc_mass(const orc_potential *p, double r) {
+    double m = p->M_star * p->upsilon * r * r / ((r + p->a) * (r + p->a));
+    if (p->M200 > 0.0) {
+        double x = r / p->r_s;
+        m += p->M200 / nfw_fc(p) * (log1p(x) - x / (1.0 + x));
+    }
+    return m;
+}
+
+/* g = -grad Phi = -G M(<r) r_vec / r^3 ; zero at the centre by symmetry */
+void orc_accel(const orc_potential *p, double x, double y, double z, double *g) {
+    double r = sqrt(x * x + y * y + z * z);
+    if (r == 0.0) {
+        g[0] = g[1] = g[2] = 0.0;
+        return;
+    }
+    double s = -p->G * orc_mass(p, r) / (r * r * r);
+    g[0] = s * x;
+    g[1] = s * y;
+    g[2] = s * z;
+}
+
+/* energy of the circular orbit of radius r: Phi(r) + v_c^2/2, v_c^2 = G M / r */
+static double circ_energy(const orc_potential *p, double r) {
+    if (r == 0.0) return orc_phi(p, 0.0);
+    return orc_phi(p, r) + 0.5 * p->G * orc_mass(p, r) / r;
+}
+
+/* L_c(E): angular momentum of the circular orbit of energy E, by bisection
+ * of circ_energy(r) = E. 0 for E <= Phi(0), +inf for E >= 0. */
+double orc_lc(const orc_potential *p, double E) {
+    if (E <= orc_phi(p, 0.0)) return 0.0;
+    if (E >= 0.0) return INFINITY;
+    double lo = 0.0, hi = 1.0;
+    while (circ_energy(p, hi) < E && hi < 1e300) hi *= 2.0;
+    /* halve until the bracket is a few ulps wide (or stops shrinking) */
+    for (int it = 0; it < 2000 && hi - lo > 4e-16 * hi; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (circ_energy(p, mid) < E) lo = mid; else hi = mid;
+    }
+    double rc = 0.5 * (lo + hi);
+    return sqrt(p->G * orc_mass(p, rc) * rc);
+}
+
+/* -------------------------------------------------------- observables */
+int32_t orc_J(const orc_layout *L) {
+    int32_t per = 0;
+    if (L->kin == 1) per = 1;
+    else if (L->kin == 2) per = L->gh_nmax;
+    else if (L->kin == 3) per = L->n_v;
+    return L->n_r + L->n_R * per;
+}
+
+/* log edges e_k = lo (hi/lo)^(k/n), e_0 = lo, e_n = hi */
+static double log_edge(double lo, double hi, int n, int k) {
+    if (k == 0) return lo;
+    if (k == n) return hi;
+    return lo * pow(hi / lo, (double)k / (double)n);
+}
+
+static double lin_edge(double lo, double hi, int n, int k) {
+    if (k == 0) return lo;
+    if (k == n) return hi;
+    return lo + (hi - lo) * (double)k / (double)n;
+}
+
+/* index k with e_k <= v < e_{k+1}, or -1 outside [e_0, e_n) */
+static int find_bin(const double *e, int n, double v) {
+    if (!(v >= e[0]) || !(v < e[n])) return -1;
+    for (int k = 0; k < n; ++k)
+        if (v >= e[k] && v < e[k + 1]) return k;
+    return -1;
+}
+
+/* physicists' Hermite polynomial, explicit sum:
+ * H_n(x) = n! sum_{m=0}^{n/2} (-1)^m (2x)^(n-2m) / (m! (n-2m)!) */
+double orc_hermite(int n, double x) {
+    double s = 0.0;
+    double nf = tgamma(n + 1.0);
+    for (int m = 0; 2 * m <= n; ++m) {
+        double term = pow(2.0 * x, n - 2 * m) / (tgamma(m + 1.0) * tgamma(n - 2 * m + 1.0));
+        s += (m % 2 ? -term : term);
+    }
+    return nf * s;
+}
+
+/* Gauss-Hermite function u_n(nu) = (2^(n+1) pi n!)^(-1/2) H_n(nu) exp(-nu^2/2) */
+double orc_gh_u(int n, double nu) {
+    double norm = 1.0 / sqrt(pow(2.0, n + 1) * M_PI * tgamma(n + 1.0));
+    return norm * orc_hermite(n, nu) * exp(-0.5 * nu * nu);
+}
+
+typedef struct {
+    int32_t nr, nR, nv;
+    double *re, *Re, *ve;
+} edges_t;
+
+static void edges_make(const orc_layout *L, edges_t *E) {
+    E->nr = L->n_r;
+    E->nR = L->n_R;
+    E->nv = (L->kin == 3) ? L->n_v : 0;
+    E->re = (double *)malloc(sizeof(double) * (E->nr + 1));
+    E->Re = (double *)malloc(sizeof(double) * (E->nR + 1));
+    E->ve = (double *)malloc(sizeof(double) * (E->nv + 1));
+    for (int k = 0; k <= E->nr; ++k) E->re[k] = log_edge(L->r_min, L->r_max, E->nr, k);
+    for (int k = 0; k <= E->nR; ++k) E->Re[k] = log_edge(L->R_min, L->R_max, E->nR, k);
+    for (int k = 0; k <= E->nv; ++k) E->ve[k] = lin_edge(L->v_min, L->v_max, E->nv, k);
+}
+
+static void edges_free(edges_t *E) {
+    free(E->re);
+    free(E->Re);
+    free(E->ve);
+}
+
+static int near_edge(const double *e, int n, double v, double band, int absolute) {
+    for (int k = 0; k <= n; ++k) {
+        double tol = absolute ? band * fmax(1.0, fabs(e[k])) : band * e[k];
+        if (fabs(v - e[k]) <= tol) return 1;
+    }
+    return 0;
+}
+
+/* The kernels K_j(z) that are non-zero for one phase-space point: writes
+ * (index, value) pairs and returns their count. Observable order: n_r radial
+ * mass bins (K = 1 for r in the bin), then per annulus p (R = sqrt(x^2+y^2),
+ * line of sight z) its kinematic entries: v_z^2 (kin 1), 2 sqrt(pi) u_n(nu),
+ * nu = (v_z - V_p)/sigma_p, n = 1..gh_nmax (kin 2, eq. lumghn), or K = 1 for
+ * the LOSVD bin holding v_z (kin 3). A particle outside every range has no
+ * kernel (selection function, Sec. 2.1). */
+static int kernels(const orc_layout *L, const edges_t *E, const double *Vp, const double *sp,
+                   double x, double y, double z, double vz, int *idx, double *val) {
+    int cnt = 0;
+    double r = sqrt(x * x + y * y + z * z);
+    int k = find_bin(E->re, E->nr, r);
+    if (k >= 0) {
+        idx[cnt] = k;
+        val[cnt++] = 1.0;
+    }
+    if (L->kin == 0 || L->n_R == 0) return cnt;
+    double R = sqrt(x * x + y * y);
+    int p = find_bin(E->Re, E->nR, R);
+    if (p < 0) return cnt;
+    if (L->kin == 1) {
+        idx[cnt] = L->n_r + p;
+        val[cnt++] = vz * vz;
+    } else if (L->kin == 2) {
+        double nu = (vz - Vp[p]) / sp[p];
+        for (int n = 1; n <= L->gh_nmax; ++n) {
+            idx[cnt] = L->n_r + p * L->gh_nmax + (n - 1);
+            val[cnt++] = 2.0 * sqrt(M_PI) * orc_gh_u(n, nu);
+        }
+    } else if (L->kin == 3) {
+        int b = find_bin(E->ve, E->nv, vz);
+        if (b >= 0) {
+            idx[cnt] = L->n_r + p * L->n_v + b;
+            val[cnt++] = 1.0;
+        }
+    }
+    return cnt;
+}
+
+/* exported single-point evaluation (tests) */
+int orc_kernels(const orc_layout *L, const double *Vp, const double *sp, double x, double y,
+                double z, double vz, int32_t *idx, double *val) {
+    edges_t E;
+    edges_make(L, &E);
+    int ii[ORC_MAXK];
+    int n = kernels(L, &E, Vp, sp, x, y, z, vz, ii, val);
+    for (int k = 0; k < n; ++k) idx[k] = ii[k];
+    edges_free(&E);
+    return n;
+}
+
+static int particle_ambiguous(const orc_layout *L, const edges_t *E, double x, double y,
+                              double z, double vz, double band) {
+    double r = sqrt(x * x + y * y + z * z);
+    if (near_edge(E->re, E->nr, r, band, 0)) return 1;
+    if (L->kin == 0 || L->n_R == 0) return 0;
+    double R = sqrt(x * x + y * y);
+    if (near_edge(E->Re, E->nR, R, band, 0)) return 1;
+    if (L->kin == 3 && near_edge(E->ve, E->nv, vz, band, 1)) return 1;
+    return 0;
+}
+
+static int nthreads_of(int32_t want) {
+#ifdef _OPENMP
+    return want > 0 ? want : 1;
+#else
+    (void)want;
+    return 1;
+#endif
+}
+
+/* y_j = (M/N) sum_i u_i K_j(z_i). Optional: yabs_j = (M/N) sum |u_i K_ij|,
+ * yamb_j = the same sum over particles within `band` of an edge. With
+ * several threads each thread sums its contiguous block of particles and the
+ * blocks are added in thread order. */
+void orc_deposit(int64_t n, const double *x, const double *y, const double *z, const double *vx,
+                 const double *vy, const double *vz, const double *u, int64_t n_norm, double mass,
+                 const orc_layout *L, const double *Vp, const double *sp, double *yout,
+                 double *yabs, double *yamb, double band, int32_t nthreads) {
+    (void)vx;
+    (void)vy;
+    int J = orc_J(L);
+    edges_t E;
+    edges_make(L, &E);
+    int T = nthreads_of(nthreads);
+    double *acc = (double *)calloc((size_t)T * J * 3, sizeof(double));
+    double w0 = mass / (double)n_norm;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(T)
+#endif
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        int64_t lo = n * t / T, hi = n * (t + 1) / T;
+        double *a = acc + (size_t)t * J * 3;
+        int idx[ORC_MAXK];
+        double val[ORC_MAXK];
+        for (int64_t i = lo; i < hi; ++i) {
+            int m = kernels(L, &E, Vp, sp, x[i], y[i], z[i], vz[i], idx, val);
+            int amb = (yamb && m > 0) ? particle_ambiguous(L, &E, x[i], y[i], z[i], vz[i], band) : 0;
+            for (int k = 0; k < m; ++k) {
+                double wk = w0 * u[i] * val[k];
+                a[idx[k]] += wk;
+                a[J + idx[k]] += fabs(wk);
+                if (amb) a[2 * J + idx[k]] += fabs(wk);
+            }
+        }
+    }
+    for (int j = 0; j < J; ++j) {
+        double s = 0.0, sa = 0.0, sb = 0.0;
+        for (int t = 0; t < T; ++t) {
+            s += acc[(size_t)t * J * 3 + j];
+            sa += acc[(size_t)t * J * 3 + J + j];
+            sb += acc[(size_t)t * J * 3 + 2 * J + j];
+        }
+        yout[j] = s;
+        if (yabs) yabs[j] = sa;
+        if (yamb) yamb[j] = sb;
+    }
+    free(acc);
+    edges_free(&E);
+}
+
+/* ------------------------------------------------------------ MPR cells */
+/* E = v^2/2 + Phi(r), L = |r x v|, x = L / L_c(E). Cell (k, l) of the
+ * rectangular grid: k from E on [E_lo, E_hi) in n_E equal bins, l from x on
+ * [0, 1) in n_x equal bins; out-of-range values go to the end cells. For
+ * E >= 0 there is no circular orbit and x is taken as 0; for E <= Phi(0)
+ * L_c = 0 and x is taken as 1. Returns k * n_x + l. */
+int32_t orc_cell(const orc_potential *p, const orc_params *P, double x, double y, double z,
+                 double vx, double vy, double vz, double *Eout, double *xout) {
+    double r = sqrt(x * x + y * y + z * z);
+    double E = 0.5 * (vx * vx + vy * vy + vz * vz) + orc_phi(p, r);
+    double lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
+    double L = sqrt(lx * lx + ly * ly + lz * lz);
+    double xc;
+    if (E >= 0.0) xc = 0.0;
+    else {
+        double Lc = orc_lc(p, E);
+        xc = (Lc > 0.0) ? L / Lc : 1.0;
+    }
+    int k = (int)floor((E - P->E_lo) / (P->E_hi - P->E_lo) * P->n_E);
+    if (!(E - P->E_lo >= 0.0)) k = 0;
+    if (k < 0) k = 0;
+    if (k > P->n_E - 1) k = P->n_E - 1;
+    int l = (int)floor(xc * P->n_x);
+    if (l < 0) l = 0;
+    if (l > P->n_x - 1) l = P->n_x - 1;
+    if (Eout) *Eout = E;
+    if (xout) *xout = xc;
+    return k * P->n_x + l;
+}
+
+static int cell_ambiguous(const orc_params *P, double E, double xc, double band) {
+    double dE = (P->E_hi - P->E_lo) / P->n_E;
+    double t = (E - P->E_lo) / dE;
+    double fe = t - floor(t);
+    if ((fe * dE <= band * fabs(P->E_lo) || (1.0 - fe) * dE <= band * fabs(P->E_lo)) &&
+        t > 0.5 && t < P->n_E - 0.5)
+        return 1;
+    double tx = xc * P->n_x;
+    double fx = tx - floor(tx);
+    if ((fx <= band * P->n_x || 1.0 - fx <= band * P->n_x) && tx > 0.5 && tx < P->n_x - 0.5)
+        return 1;
+    return 0;
+}
+
+/* per-particle cells (tests and diagnostics) */
+void orc_cells(const orc_potential *p, const orc_params *P, int64_t n, const double *x,
+               const double *y, const double *z, const double *vx, const double *vy,
+               const double *vz, int32_t *cell, double *E, double *xc) {
+    for (int64_t i = 0; i < n; ++i)
+        cell[i] = orc_cell(p, P, x[i], y[i], z[i], vx[i], vy[i], vz[i], E ? E + i : NULL,
+                           xc ? xc + i : NULL);
+}
+
+/* ----------------------------------------------------------------- model */
+static void residuals(orc_model *m) {
+    double c2 = 0.0;
+    for (int j = 0; j < m->J; ++j) {
+        m->delta[j] = (m->ytilde[j] - m->Y[j]) / m->sigma[j];
+        c2 += m->delta[j] * m->delta[j];
+    }
+    m->chi2 = c2;
+}
+
+static void deposit_model(orc_model *m, double *out) {
+    orc_deposit(m->n, m->x, m->y, m->z, m->vx, m->vy, m->vz, m->u, m->n, m->par.mass, &m->lay,
+                m->Vp, m->sp, out, NULL, NULL, 0.0, m->nthreads);
+}
+
+/* t = 0: ytilde = y^0 = deposit of the initial state, then Delta, chi^2 */
+int orc_init(orc_model *m) {
+    if (m->J != orc_J(&m->lay)) return 1;
+    deposit_model(m, m->yraw);
+    for (int j = 0; j < m->J; ++j) m->ytilde[j] = m->yraw[j];
+    residuals(m);
+    return 0;
+}
+
+/* new priors: uhat_i = mean of u over the (E, x) cell of particle i */
+int orc_refresh_priors(orc_model *m) {
+    int C = m->par.n_E * m->par.n_x;
+    double *sum = (double *)calloc(C, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc(C, sizeof(int64_t));
+    int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * m->n);
+    int T = nthreads_of(m->nthreads);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static)
+#endif
+    for (int64_t i = 0; i < m->n; ++i) {
+        double E, xc;
+        cell[i] = orc_cell(&m->pot, &m->par, m->x[i], m->y[i], m->z[i], m->vx[i], m->vy[i],
+                           m->vz[i], &E, &xc);
+        if (m->flag && cell_ambiguous(&m->par, E, xc, m->band)) m->flag[i] = 1;
+    }
+    /* cell sums in particle order */
+    for (int64_t i = 0; i < m->n; ++i) {
+        sum[cell[i]] += m->u[i];
+        cnt[cell[i]] += 1;
+    }
+    for (int64_t i = 0; i < m->n; ++i) m->uhat[i] = sum[cell[i]] / (double)cnt[cell[i]];
+    free(sum);
+    free(cnt);
+    free(cell);
+    return 0;
+}
+
+/* n steps; correct = 0 advances and smooths without weight correction
+ * (relaxation). chi2_hist (optional) receives chi^2 after each step. */
+int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) {
+    const orc_params *P = &m->par;
+    double dt = P->dt;
+    double q = -expm1(-P->alpha * dt);
+    double cS = (P->entropy == 1) ? 1.0 : 0.0;
+    double w0 = P->mass / (double)m->n;
+    edges_t E;
+    edges_make(&m->lay, &E);
+    double *rj = (double *)malloc(sizeof(double) * m->J);
+    int T = nthreads_of(m->nthreads);
+    for (int s = 0; s < nsteps; ++s) {
+        for (int j = 0; j < m->J; ++j) rj[j] = m->delta[j] / m->sigma[j];
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static)
+#endif
+        for (int64_t i = 0; i < m->n; ++i) {
+            int idx[ORC_MAXK];
+            double val[ORC_MAXK];
+            if (correct) {
+                /* force of change at z^k with Delta^k */
+                int cnt = kernels(&m->lay, &E, m->Vp, m->sp, m->x[i], m->y[i], m->z[i], m->vz[i],
+                                  idx, val);
+                double chi = 0.0;
+                for (int k = 0; k < cnt; ++k) chi += val[k] * rj[idx[k]];
+                double G = P->mu * (-log(m->u[i] / m->uhat[i]) - cS) - w0 * chi;
+                m->u[i] *= exp(P->eps * dt * G);
+            }
+            /* drift - kick - drift */
+            double g[3];
+            m->x[i] += 0.5 * dt * m->vx[i];
+            m->y[i] += 0.5 * dt * m->vy[i];
+            m->z[i] += 0.5 * dt * m->vz[i];
+            orc_accel(&m->pot, m->x[i], m->y[i], m->z[i], g);
+            m->vx[i] += dt * g[0];
+            m->vy[i] += dt * g[1];
+            m->vz[i] += dt * g[2];
+            m->x[i] += 0.5 * dt * m->vx[i];
+            m->y[i] += 0.5 * dt * m->vy[i];
+            m->z[i] += 0.5 * dt * m->vz[i];
+            if (m->flag &&
+                particle_ambiguous(&m->lay, &E, m->x[i], m->y[i], m->z[i], m->vz[i], m->band))
+                m->flag[i] = 1;
+        }
+        deposit_model(m, m->yraw);
+        for (int j = 0; j < m->J; ++j) m->ytilde[j] += q * (m->yraw[j] - m->ytilde[j]);
+        residuals(m);
+        if (correct) {
+            m->kstep += 1;
+            if (P->entropy == 0 && P->prior_every > 0 && m->kstep % P->prior_every == 0)
+                orc_refresh_priors(m);
+        }
+        if (chi2_hist) chi2_hist[s] = m->chi2;
+    }
+    free(rj);
+    edges_free(&E);
+    return 0;
+}
+
+/* sum of w = u M / N per (E, x) cell (the grid diagnostic of Sec. 4.1) */
+void orc_cell_mass(const orc_potential *p, const orc_params *P, int64_t n, const double *x,
+                   const double *y, const double *z, const double *vx, const double *vy,
+                   const double *vz, const double *u, double mass, double *out) {
+    int C = P->n_E * P->n_x;
+    for (int c = 0; c < C; ++c) out[c] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = orc_cell(p, P, x[i], y[i], z[i], vx[i], vy[i], vz[i], NULL, NULL);
+        out[c] += u[i] * mass / (double)n;
+    }
+}
+
+/* one DKD step of a single particle (tests of the integrator) */
+void orc_push(const orc_potential *p, double dt, int64_t n, double *x, double *y, double *z,
+              double *vx, double *vy, double *vz, int32_t nsteps) {
+    for (int s = 0; s < nsteps; ++s)
+        for (int64_t i = 0; i < n; ++i) {
+            double g[3];
+            x[i] += 0.5 * dt * vx[i];
+            y[i] += 0.5 * dt * vy[i];
+            z[i] += 0.5 * dt * vz[i];
+            orc_accel(p, x[i], y[i], z[i], g);
+            vx[i] += dt * g[0];
+            vy[i] += dt * g[1];
+            vz[i] += dt * g[2];
+            x[i] += 0.5 * dt * vx[i];
+            y[i] += 0.5 * dt * vy[i];
+            z[i] += 0.5 * dt * vz[i];
+        }
+}

@@ -1,0 +1,277 @@
+"""ctypes binding of the FP64 CPU oracle (``m2m_oracle.c``).
+
+TEST INFRASTRUCTURE: imported only by the test-suite, the package smoke check
+and the CPU-baseline leg of the benchmark. The product path never loads it.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "m2m_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+KIN = {"none": 0, "v2": 1, "gh": 2, "losvd": 3}
+ENTROPY = {"mpr": 0, "gwr": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, IEEE double, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", LIB, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB
+
+
+class Potential(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
+                ("n_R", C.c_int32), ("R_min", C.c_double), ("R_max", C.c_double),
+                ("kin", C.c_int32), ("gh_nmax", C.c_int32), ("n_v", C.c_int32),
+                ("v_min", C.c_double), ("v_max", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("eps", C.c_double), ("mu", C.c_double),
+                ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
+                ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
+                ("E_lo", C.c_double), ("E_hi", C.c_double)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+class Model(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, _dp) for k in
+                                     ("x", "y", "z", "vx", "vy", "vz", "u", "uhat")] + [
+        ("pot", Potential), ("lay", Layout), ("par", Params), ("J", C.c_int32),
+        ("Y", _dp), ("sigma", _dp), ("Vp", _dp), ("sp", _dp),
+        ("ytilde", _dp), ("yraw", _dp), ("delta", _dp), ("chi2", C.c_double),
+        ("kstep", C.c_int64), ("flag", C.POINTER(C.c_uint8)), ("band", C.c_double),
+        ("nthreads", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.orc_phi.restype = C.c_double
+        L.orc_phi.argtypes = [C.POINTER(Potential), C.c_double]
+        L.orc_mass.restype = C.c_double
+        L.orc_mass.argtypes = [C.POINTER(Potential), C.c_double]
+        L.orc_lc.restype = C.c_double
+        L.orc_lc.argtypes = [C.POINTER(Potential), C.c_double]
+        L.orc_accel.argtypes = [C.POINTER(Potential), C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_J.restype = C.c_int32
+        L.orc_J.argtypes = [C.POINTER(Layout)]
+        L.orc_hermite.restype = C.c_double
+        L.orc_hermite.argtypes = [C.c_int, C.c_double]
+        L.orc_gh_u.restype = C.c_double
+        L.orc_gh_u.argtypes = [C.c_int, C.c_double]
+        L.orc_kernels.restype = C.c_int
+        L.orc_kernels.argtypes = [C.POINTER(Layout), _dp, _dp] + [C.c_double] * 4 + [
+            C.POINTER(C.c_int32), _dp]
+        L.orc_deposit.argtypes = [C.c_int64] + [_dp] * 7 + [C.c_int64, C.c_double,
+                                                             C.POINTER(Layout), _dp, _dp, _dp,
+                                                             _dp, _dp, C.c_double, C.c_int32]
+        L.orc_cell.restype = C.c_int32
+        L.orc_cell.argtypes = [C.POINTER(Potential), C.POINTER(Params)] + [C.c_double] * 6 + [
+            _dp, _dp]
+        L.orc_cells.argtypes = [C.POINTER(Potential), C.POINTER(Params), C.c_int64] + [_dp] * 6 + [
+            C.POINTER(C.c_int32), _dp, _dp]
+        L.orc_init.argtypes = [C.POINTER(Model)]
+        L.orc_refresh_priors.argtypes = [C.POINTER(Model)]
+        L.orc_steps.argtypes = [C.POINTER(Model), C.c_int32, C.c_int32, _dp]
+        L.orc_cell_mass.argtypes = [C.POINTER(Potential), C.POINTER(Params), C.c_int64] + [
+            _dp] * 7 + [C.c_double, _dp]
+        L.orc_push.argtypes = [C.POINTER(Potential), C.c_double, C.c_int64] + [_dp] * 6 + [
+            C.c_int32]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def potential(d) -> Potential:
+    d = d.as_dict() if hasattr(d, "as_dict") else d
+    return Potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")})
+
+
+def layout(d: dict) -> Layout:
+    return Layout(n_r=d["n_r"], r_min=d["r_min"], r_max=d["r_max"], n_R=d["n_R"],
+                  R_min=d["R_min"], R_max=d["R_max"], kin=KIN[d["kin"]], gh_nmax=d["gh_nmax"],
+                  n_v=d["n_v"], v_min=d["v_min"], v_max=d["v_max"])
+
+
+def params(d: dict) -> Params:
+    return Params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
+                  entropy=ENTROPY[d["entropy"]], n_E=d["n_E"], n_x=d["n_x"],
+                  prior_every=d["prior_every"], E_lo=d["E_lo"], E_hi=d["E_hi"])
+
+
+def J_of(lay: dict) -> int:
+    return int(lib().orc_J(C.byref(layout(lay))))
+
+
+def phi(pot, r: float) -> float:
+    return lib().orc_phi(C.byref(potential(pot)), float(r))
+
+
+def lc(pot, E: float) -> float:
+    return lib().orc_lc(C.byref(potential(pot)), float(E))
+
+
+def accel(pot, x, y, z):
+    g = np.zeros(3)
+    lib().orc_accel(C.byref(potential(pot)), float(x), float(y), float(z), _p(g))
+    return g
+
+
+def hermite(n: int, x: float) -> float:
+    return lib().orc_hermite(int(n), float(x))
+
+
+def gh_u(n: int, nu: float) -> float:
+    return lib().orc_gh_u(int(n), float(nu))
+
+
+def kernels(lay: dict, x, y, z, vz, V_p=None, sigma_p=None):
+    """Non-zero kernels of one point: dict {j: K_j}."""
+    nR = max(lay["n_R"], 1)
+    V = _f64(np.zeros(nR) if V_p is None else V_p)
+    S = _f64(np.ones(nR) if sigma_p is None else sigma_p)
+    idx = np.zeros(128, dtype=np.int32)
+    val = np.zeros(128)
+    n = lib().orc_kernels(C.byref(layout(lay)), _p(V), _p(S), float(x), float(y), float(z),
+                          float(vz), idx.ctypes.data_as(C.POINTER(C.c_int32)), _p(val))
+    return {int(idx[k]): float(val[k]) for k in range(n)}
+
+
+def deposit(parts: dict, u, lay: dict, mass=1.0, n_norm=None, V_p=None, sigma_p=None,
+            band=0.0, nthreads=1, with_abs=False):
+    """y_j = (mass / n_norm) sum_i u_i K_j(z_i). With ``with_abs`` also returns
+    the absolute sums and the sums over particles within ``band`` of an edge."""
+    x, y, z, vx, vy, vz = (_f64(parts[k]) for k in ("x", "y", "z", "vx", "vy", "vz"))
+    u = _f64(u)
+    n = x.size
+    J = J_of(lay)
+    nR = max(lay["n_R"], 1)
+    V = _f64(np.zeros(nR) if V_p is None else V_p)
+    S = _f64(np.ones(nR) if sigma_p is None else sigma_p)
+    out = np.zeros(J)
+    ya = np.zeros(J)
+    yb = np.zeros(J)
+    lib().orc_deposit(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(u),
+                      n if n_norm is None else int(n_norm), float(mass), C.byref(layout(lay)),
+                      _p(V), _p(S), _p(out), _p(ya) if with_abs else None,
+                      _p(yb) if with_abs else None, float(band), int(nthreads))
+    return (out, ya, yb) if with_abs else out
+
+
+def cells(pot, par: dict, parts: dict):
+    x, y, z, vx, vy, vz = (_f64(parts[k]) for k in ("x", "y", "z", "vx", "vy", "vz"))
+    n = x.size
+    c = np.zeros(n, dtype=np.int32)
+    E = np.zeros(n)
+    xc = np.zeros(n)
+    lib().orc_cells(C.byref(potential(pot)), C.byref(params(par)), n, _p(x), _p(y), _p(z),
+                    _p(vx), _p(vy), _p(vz), c.ctypes.data_as(C.POINTER(C.c_int32)), _p(E), _p(xc))
+    return c, E, xc
+
+
+def cell_mass(pot, par: dict, parts: dict, u, mass=1.0):
+    x, y, z, vx, vy, vz = (_f64(parts[k]) for k in ("x", "y", "z", "vx", "vy", "vz"))
+    out = np.zeros(par["n_E"] * par["n_x"])
+    lib().orc_cell_mass(C.byref(potential(pot)), C.byref(params(par)), x.size, _p(x), _p(y),
+                        _p(z), _p(vx), _p(vy), _p(vz), _p(_f64(u)), float(mass), _p(out))
+    return out
+
+
+def push(pot, dt, parts: dict, nsteps: int):
+    """Advance copies of the particles nsteps DKD steps; returns the new dict."""
+    arr = {k: _f64(parts[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    lib().orc_push(C.byref(potential(pot)), float(dt), arr["x"].size,
+                   *[_p(arr[k]) for k in ("x", "y", "z", "vx", "vy", "vz")], int(nsteps))
+    return arr
+
+
+class OracleFit:
+    """One M2M fit on the CPU in FP64 (owns copies of all arrays)."""
+
+    def __init__(self, pot, lay: dict, par: dict, parts: dict, Y, sigma, V_p=None,
+                 sigma_p=None, u=None, uhat=None, track_flags=False, band=3e-5, nthreads=1):
+        self.arr = {k: _f64(parts[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+        n = self.arr["x"].size
+        self.n = n
+        self.arr["u"] = _f64(np.ones(n) if u is None else u).copy()
+        self.arr["uhat"] = _f64(np.ones(n) if uhat is None else uhat).copy()
+        self.J = J_of(lay)
+        nR = max(lay["n_R"], 1)
+        self.Y = _f64(Y).copy()
+        self.sigma = _f64(sigma).copy()
+        self.Vp = _f64(np.zeros(nR) if V_p is None else V_p).copy()
+        self.sp = _f64(np.ones(nR) if sigma_p is None else sigma_p).copy()
+        self.ytilde = np.zeros(self.J)
+        self.yraw = np.zeros(self.J)
+        self.delta = np.zeros(self.J)
+        self.flag = np.zeros(n, dtype=np.uint8) if track_flags else None
+        m = Model()
+        m.n = n
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "uhat"):
+            setattr(m, k, _p(self.arr[k]))
+        m.pot = potential(pot)
+        m.lay = layout(lay)
+        m.par = params(par)
+        m.J = self.J
+        m.Y, m.sigma, m.Vp, m.sp = _p(self.Y), _p(self.sigma), _p(self.Vp), _p(self.sp)
+        m.ytilde, m.yraw, m.delta = _p(self.ytilde), _p(self.yraw), _p(self.delta)
+        m.kstep = 0
+        m.flag = self.flag.ctypes.data_as(C.POINTER(C.c_uint8)) if track_flags else None
+        m.band = band
+        m.nthreads = nthreads
+        self.m = m
+        if self.Y.size != self.J or self.sigma.size != self.J:
+            raise ValueError("target length does not match the layout")
+        if lib().orc_init(C.byref(m)) != 0:
+            raise RuntimeError("orc_init failed")
+
+    @property
+    def chi2(self) -> float:
+        return float(self.m.chi2)
+
+    @property
+    def kstep(self) -> int:
+        return int(self.m.kstep)
+
+    def step(self, n: int, correct: bool = True):
+        hist = np.zeros(max(n, 1))
+        lib().orc_steps(C.byref(self.m), int(n), int(bool(correct)), _p(hist))
+        return hist[:n]
+
+    def refresh_priors(self):
+        lib().orc_refresh_priors(C.byref(self.m))
+
+    def weights(self, mass=1.0):
+        return self.arr["u"] * mass / self.n
+
+    def state(self) -> dict:
+        return {k: v.copy() for k, v in self.arr.items()}
