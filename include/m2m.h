@@ -1,0 +1,245 @@
+/*
+ * m2m.h -- C ABI of the made-to-measure (chi^2 M2M) step with moving-prior
+ * regularization on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Morganti & Gerhard (2012), "Regularizing
+ * made-to-measure particle models of galaxies":
+ *   - particles z_i = (r_i, v_i) with weights w_i orbit in a fixed potential
+ *     (Sec. 2.1); they advance by a drift-kick-drift leapfrog (Sec. 4.1);
+ *   - model observables y_j = sum_i w_i K_j(z_i) (Sec. 2.1, eq. obs) with a
+ *     selection function, time-smoothed by the exponential kernel of eq. myts;
+ *   - residuals Delta_j = (ytilde_j - Y_j) / sigma(Y_j) and
+ *     chi^2 = sum_j Delta_j^2 (eqs. delta, chi);
+ *   - force of change (eq. modFOC) with the mass-neutral entropy S+ (eq. S+)
+ *     or the weight entropy (eq. entropy);
+ *   - moving priors (Sec. 2.3.1): mean weight in cells of an (E, x = L/L_c)
+ *     grid assigned as the prior of every particle in the cell.
+ *
+ * Conventions fixed by this interface
+ *   Weights. The library carries u_i = N w_i / M ("u", 1 for equal weights;
+ *     M = params.mass) and the priors uhat_i in the same units. The model
+ *     observable is y_j = (M/N) sum_i u_i K_j(z_i). The force of change per
+ *     step of length dt, with K and Delta taken at the start of the step, is
+ *       u_i <- u_i exp(eps dt G_i),
+ *       G_i = mu dS/du_i - (M/N) sum_j K_j(z_i) Delta_j / sigma_j,
+ *       dS/du_i = -ln(u_i/uhat_i)        (M2M_S_MPR, eq. S+)
+ *       dS/du_i = -ln(u_i/uhat_i) - 1    (M2M_S_GWR, eq. entropy).
+ *   Smoothing. ytilde <- ytilde + q (y - ytilde), q = 1 - exp(-alpha dt)
+ *     (eq. myts for y constant over a step); ytilde = y at t = 0.
+ *   Step order. Force of change at z^k with Delta^k, leapfrog push to
+ *     z^{k+1}, deposit at z^{k+1}, smoothing, residuals; with M2M_S_MPR and
+ *     prior_every > 0, every prior_every-th correction step then recomputes
+ *     the cell priors from z^{k+1}; they act from the next step on.
+ *   Potential. Hernquist (eq. her) of mass M_star*upsilon and scale a, plus
+ *     optionally NFW: Phi = -G M200/f(c) ln(1 + r/r_s)/r,
+ *     f(c) = ln(1+c) - c/(1+c). M200 = 0 means no halo.
+ *   Observables, in this order (J = m2m_num_observables):
+ *     n_r radial mass bins, K = 1 for r in [e_k, e_{k+1}),
+ *       e_k = r_min (r_max/r_min)^(k/n_r) (e_0 = r_min, e_{n_r} = r_max);
+ *     then per projected annulus p (R = sqrt(x^2 + y^2), the same log edges
+ *     on [R_min, R_max); the line of sight is z), contiguous:
+ *       M2M_KIN_V2:    one entry, K = v_z^2;
+ *       M2M_KIN_GH:    gh_nmax entries n = 1..gh_nmax, K = 2 sqrt(pi) u_n(nu),
+ *                      u_n = (2^(n+1) pi n!)^(-1/2) H_n(nu) exp(-nu^2/2),
+ *                      nu = (v_z - V_p)/sigma_p (eq. lumghn);
+ *       M2M_KIN_LOSVD: n_v entries, K = 1 for v_z in the k-th of n_v equal
+ *                      bins of [v_min, v_max).
+ *     A particle outside a range has no kernel there (selection function).
+ *   Prior cells. k = floor((E - E_lo)/(E_hi - E_lo) n_E), l = floor(x n_x),
+ *     both clamped into the grid; E = v^2/2 + Phi(r), x = |r x v| / L_c(E);
+ *     x = 0 for E >= 0 and x = 1 for E <= Phi(0). Empty cells keep their
+ *     previous prior (no particle reads them).
+ *
+ * Memory and ownership
+ *   Particle arrays (x, y, z, vx, vy, vz, u, u_prior) are device pointers in
+ *   structure-of-arrays layout, float (M2M_F32) or double (M2M_F64), each
+ *   16-byte aligned, owned by the caller and required to outlive the
+ *   context. The library owns (or borrows, if a workspace is passed) one
+ *   device workspace per context holding targets, observables, tables and
+ *   reduction buffers. All device work is enqueued on the stream given at
+ *   creation (a hipStream_t passed as void*; NULL is the null stream).
+ *
+ * Errors
+ *   Every call returns a status and never aborts. Invalid arguments give
+ *   M2M_EINVAL, allocation failure M2M_ENOMEM, a failing HIP call
+ *   M2M_EDEVICE, a call out of order M2M_ESTATE. Asynchronous calls report
+ *   device-side problems (a non-finite chi^2) at the next synchronizing call
+ *   (m2m_get_*, m2m_observe, m2m_batch_poll) as M2M_ENONFINITE.
+ *   m2m_last_error gives a message for the last failure on a context.
+ *   A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef M2M_H
+#define M2M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct m2m_ctx m2m_ctx;
+typedef struct m2m_batch m2m_batch;
+
+typedef enum {
+    M2M_OK = 0,
+    M2M_EINVAL = 1,
+    M2M_ENOMEM = 2,
+    M2M_EDEVICE = 3,
+    M2M_ESTATE = 4,
+    M2M_ENONFINITE = 5,
+    M2M_EUNSUPPORTED = 6
+} m2m_status;
+
+typedef enum { M2M_F32 = 0, M2M_F64 = 1 } m2m_dtype;
+typedef enum { M2M_S_MPR = 0, M2M_S_GWR = 1 } m2m_entropy;
+typedef enum { M2M_KIN_NONE = 0, M2M_KIN_V2 = 1, M2M_KIN_GH = 2, M2M_KIN_LOSVD = 3 } m2m_kin;
+
+/* Fixed spherical potential (Sec. 3.1, eq. her; NFW halo optional). */
+typedef struct {
+    double G, M_star, a, upsilon; /* Hernquist mass M_star*upsilon, scale a > 0 */
+    double M200, c, r_s;          /* NFW: M200 = 0 for none; else c > 0, r_s > 0 */
+} m2m_potential;
+
+/* Observable kernels K_j (Sec. 2.1; eq. lumghn). Radii are in length units,
+ * velocities in velocity units. n_r >= 1; kin is an m2m_kin. */
+typedef struct {
+    int32_t n_r;
+    double r_min, r_max;  /* 0 < r_min < r_max */
+    int32_t n_R;          /* annuli; 0 allowed only with kin = M2M_KIN_NONE */
+    double R_min, R_max;  /* 0 < R_min < R_max */
+    int32_t kin;
+    int32_t gh_nmax;      /* M2M_KIN_GH: 1..8 */
+    int32_t n_v;          /* M2M_KIN_LOSVD: 1..256 */
+    double v_min, v_max;  /* M2M_KIN_LOSVD: v_min < v_max */
+} m2m_obs_layout;
+
+/* Step parameters (eqs. modFOC, myts, S+, entropy; Sec. 2.3.1, 4.1). */
+typedef struct {
+    double dt;           /* leapfrog step, > 0 */
+    double eps;          /* force-of-change rate, >= 0 */
+    double mu;           /* entropy weight, >= 0 */
+    double alpha;        /* smoothing rate (1/time), >= 0 */
+    double mass;         /* total mass M: w_i = u_i M / N, > 0 */
+    int32_t entropy;     /* m2m_entropy */
+    int32_t n_E, n_x;    /* prior grid, n_E, n_x >= 1, n_E * n_x <= 4096 */
+    int32_t prior_every; /* correction steps between prior refreshes; 0 = never */
+    double E_lo, E_hi;   /* energy range of the grid, E_lo < E_hi */
+} m2m_params;
+
+/* Number of observables J of a layout (0 if the layout is invalid). */
+int32_t m2m_num_observables(const m2m_obs_layout* layout);
+
+/* Bytes of device workspace a context needs for n particles. */
+size_t m2m_workspace_bytes(const m2m_obs_layout* layout, const m2m_params* params, int64_t n,
+                           int32_t dtype);
+
+/* Create a context over caller-owned device particle arrays (Sec. 2.1).
+ * n >= 1 particles; dtype is an m2m_dtype; u and u_prior hold u_i and uhat_i
+ * (see "Weights"). workspace: NULL to let the library allocate it, else a
+ * device buffer of at least m2m_workspace_bytes(...) bytes owned by the
+ * caller. hip_stream: the stream all work of this context is ordered on.
+ * On success *out receives the context; on failure *out is NULL. */
+m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
+                      const m2m_params* params, int64_t n, int32_t dtype, void* x, void* y,
+                      void* z, void* vx, void* vy, void* vz, void* u, void* u_prior,
+                      void* workspace, size_t workspace_bytes, void* hip_stream, m2m_ctx** out);
+
+/* Targets Y_j and errors sigma(Y_j) (eq. delta), host arrays of J doubles,
+ * copied. V_p, sigma_p: host arrays of n_R doubles, the Gauss-Hermite centres
+ * (required for M2M_KIN_GH, ignored otherwise, may be NULL). The first call
+ * also measures the current state: ytilde = y (t = 0). Later calls replace
+ * the data and recompute Delta from the current ytilde. EINVAL for J not
+ * matching the layout, non-finite values or sigma <= 0, sigma_p <= 0. */
+m2m_status m2m_set_targets(m2m_ctx* ctx, int32_t J, const double* Y, const double* sigma,
+                           const double* V_p, const double* sigma_p);
+
+/* Enqueue n_steps M2M steps (asynchronous). correct = 0 runs them without
+ * weight correction (relaxation, Sec. 4.1): push, deposit and smoothing. */
+m2m_status m2m_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct);
+
+/* Recompute the cell priors from the current state now (Sec. 2.3.1) and
+ * assign them; asynchronous. EINVAL unless entropy is M2M_S_MPR. */
+m2m_status m2m_update_priors(m2m_ctx* ctx);
+
+/* Weights w_i = u_i M / N into dst (n values of the context's dtype), on the
+ * device (dst_is_device = 1) or the host. Synchronizes the stream. */
+m2m_status m2m_get_weights(m2m_ctx* ctx, void* dst, int32_t dst_is_device);
+
+/* Host copies (J doubles each; any pointer may be NULL) of the last raw
+ * deposit y, the smoothed ytilde, the residuals Delta, and chi^2.
+ * Synchronizes. */
+m2m_status m2m_get_observables(m2m_ctx* ctx, double* y, double* y_tilde, double* delta,
+                               double* chi2);
+
+/* chi^2 after each of the last steps, oldest first: up to max values into
+ * out (host), their number in *n_out. Synchronizes. */
+m2m_status m2m_get_chi2_history(m2m_ctx* ctx, double* out, int32_t max, int32_t* n_out);
+
+/* Measure the current particle state without changing it: y_j (host, J
+ * doubles) with the given Gauss-Hermite centres (host, n_R doubles each;
+ * NULL uses the ones set by m2m_set_targets, or V = 0, sigma = 1).
+ * Synchronizes. Used to build targets from a realization (Sec. 3.1). */
+m2m_status m2m_observe(m2m_ctx* ctx, const double* V_p, const double* sigma_p, double* y);
+
+/* Checkpoint of everything the context holds besides the particle arrays
+ * (ytilde, cell priors, counters, targets). With host_blob = NULL, *bytes
+ * receives the size. Synchronizes. m2m_set_state restores it into a context
+ * created with the same layout and parameters. */
+m2m_status m2m_get_state(m2m_ctx* ctx, void* host_blob, size_t* bytes);
+m2m_status m2m_set_state(m2m_ctx* ctx, const void* host_blob, size_t bytes);
+
+/* Run n_steps steps like m2m_step, launching the two kernels of each step
+ * directly (no graph) with HIP events around each launch on the context's
+ * stream, and return the mean duration in milliseconds of the fused step
+ * kernel (ms_step) and of the finalize kernel (ms_finalize). Synchronizes.
+ * Used to report achieved bandwidth against the roofline. */
+m2m_status m2m_profile_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct, double* ms_step,
+                            double* ms_finalize);
+
+/* Release the context and its library-owned workspace (synchronizes). */
+m2m_status m2m_destroy(m2m_ctx* ctx);
+
+/* Text of the last failure on ctx (never NULL). */
+const char* m2m_last_error(const m2m_ctx* ctx);
+
+/* Launch shape of the fused step kernel for contexts created afterwards and
+ * for batches: threads per block (256, 512 or 1024), particles per lane
+ * (1, 2 or 4) and tiles (blocks) per compute unit (1..16). EINVAL otherwise.
+ * Chosen by the package's autotuner. */
+m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu);
+m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu);
+
+/* ---------------------------------------------------------- batching --
+ * Many fits of uneven size stepping together: every step runs one fused
+ * kernel over the tiles of all active fits (tiles never straddle fits) and
+ * one finalize kernel, replayed from a captured HIP graph. Each fit's
+ * result equals the fit run alone up to the rounding of its in-tile sums.
+ * Fits keep their own streams for set-up; the batch runs on its own stream. */
+
+/* hbm_budget: bytes of particle state plus workspace the batch may hold
+ * (0 = no limit). max_fits >= 1. */
+m2m_status m2m_batch_create(int32_t max_fits, size_t hbm_budget, void* hip_stream,
+                            m2m_batch** out);
+/* Add a fit (targets set) to run n_steps correction steps. ENOMEM when its
+ * footprint would exceed the budget or the batch is full; the fit is then
+ * not admitted and can be retried later. ESTATE if already in a batch. */
+m2m_status m2m_batch_admit(m2m_batch* b, m2m_ctx* fit, int32_t n_steps);
+/* Enqueue steps_per_launch steps of every admitted fit with steps left. */
+m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
+/* Synchronize, then hand back (and remove from the batch) up to max_done
+ * fits that have run all their steps. *n_done receives their number;
+ * *n_active (may be NULL) the number still running. */
+m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
+                          int32_t* n_active);
+/* Bytes of budget in use. */
+size_t m2m_batch_footprint(const m2m_batch* b);
+/* Remove a fit before it finished (cancellation); synchronizes. */
+m2m_status m2m_batch_cancel(m2m_batch* b, m2m_ctx* fit);
+m2m_status m2m_batch_destroy(m2m_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* M2M_H */

@@ -323,12 +323,34 @@ void orc_deposit(int64_t n, const double *x, const double *y, const double *z, c
         double val[ORC_MAXK];
         for (int64_t i = lo; i < hi; ++i) {
             int m = kernels(L, &E, Vp, sp, x[i], y[i], z[i], vz[i], idx, val);
-            int amb = (yamb && m > 0) ? particle_ambiguous(L, &E, x[i], y[i], z[i], vz[i], band) : 0;
             for (int k = 0; k < m; ++k) {
                 double wk = w0 * u[i] * val[k];
                 a[idx[k]] += wk;
                 a[J + idx[k]] += fabs(wk);
-                if (amb) a[2 * J + idx[k]] += fabs(wk);
+            }
+            if (yamb && particle_ambiguous(L, &E, x[i], y[i], z[i], vz[i], band)) {
+                /* a point this close to an edge may fall on either side of it:
+                 * its |w K| counts as ambiguous for every bin it reaches when r,
+                 * R or v_z moves by twice the band either way */
+                const double f[7][4] = {{1, 1, 1, 0},         {1 + 2 * band, 1 + 2 * band, 1 + 2 * band, 0},
+                                        {1 - 2 * band, 1 - 2 * band, 1 - 2 * band, 0},
+                                        {1 + 2 * band, 1 + 2 * band, 1, 0},
+                                        {1 - 2 * band, 1 - 2 * band, 1, 0},
+                                        {1, 1, 1, 2 * band},  {1, 1, 1, -2 * band}};
+                double seen[ORC_MAXK * 7];
+                int nseen = 0;
+                for (int v = 0; v < 7; ++v) {
+                    double dv = f[v][3] * fmax(1.0, fabs(vz[i]));
+                    int mm = kernels(L, &E, Vp, sp, x[i] * f[v][0], y[i] * f[v][1], z[i] * f[v][2],
+                                     vz[i] + dv, idx, val);
+                    for (int k = 0; k < mm; ++k) {
+                        int dup = 0;
+                        for (int q = 0; q < nseen; ++q) dup |= (seen[q] == (double)idx[k]);
+                        if (dup) continue;
+                        seen[nseen++] = (double)idx[k];
+                        a[2 * J + idx[k]] += fabs(w0 * u[i] * val[k]);
+                    }
+                }
             }
         }
     }

@@ -1,0 +1,1135 @@
+// Host side of the C ABI declared in include/m2m.h: validation, workspace
+// layout, tables (bin edges, L_c(E)), graph capture of the step loop, and
+// the batch of fits that step together.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "m2m.h"
+#include "m2m_internal.h"
+
+using namespace m2m;
+
+namespace {
+
+constexpr int kGraphSteps = 8;      // M2M steps per captured graph
+constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
+
+// launch shape for contexts and batches created from now on
+int g_block = 256, g_ppl = 4, g_tiles_per_cu = 4;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int n_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
+}
+
+size_t max_lds() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || n <= 0)
+        return 65536;
+    return (size_t)n;
+}
+
+int kin_per_annulus(const m2m_obs_layout& L) {
+    switch (L.kin) {
+        case M2M_KIN_NONE: return 0;
+        case M2M_KIN_V2: return 1;
+        case M2M_KIN_GH: return L.gh_nmax;
+        case M2M_KIN_LOSVD: return L.n_v;
+        default: return -1;
+    }
+}
+
+// "" if the layout is valid, else the reason
+std::string check_layout(const m2m_obs_layout* L) {
+    if (!L) return "layout is NULL";
+    if (L->n_r < 1 || L->n_r > 4096) return "n_r must be in 1..4096";
+    if (!(is_fin(L->r_min) && is_fin(L->r_max) && L->r_min > 0 && L->r_max > L->r_min))
+        return "need 0 < r_min < r_max";
+    if (L->kin < M2M_KIN_NONE || L->kin > M2M_KIN_LOSVD) return "unknown kin";
+    if (L->kin != M2M_KIN_NONE) {
+        if (L->n_R < 1 || L->n_R > 4096) return "n_R must be in 1..4096";
+        if (!(is_fin(L->R_min) && is_fin(L->R_max) && L->R_min > 0 && L->R_max > L->R_min))
+            return "need 0 < R_min < R_max";
+    } else if (L->n_R < 0 || L->n_R > 4096) {
+        return "n_R must be in 0..4096";
+    }
+    if (L->gh_nmax < 0 || L->n_v < 0) return "gh_nmax and n_v must be >= 0";
+    if (L->kin == M2M_KIN_GH && (L->gh_nmax < 1 || L->gh_nmax > kMaxGH)) return "gh_nmax must be in 1..8";
+    if (L->kin == M2M_KIN_LOSVD) {
+        if (L->n_v < 1 || L->n_v > kMaxLOSVD) return "n_v must be in 1..256";
+        if (!(is_fin(L->v_min) && is_fin(L->v_max) && L->v_max > L->v_min)) return "need v_min < v_max";
+    }
+    const int64_t J = (int64_t)L->n_r + (int64_t)(L->kin == M2M_KIN_NONE ? 0 : L->n_R) * kin_per_annulus(*L);
+    if (J > 16384) return "too many observables";
+    return "";
+}
+
+int32_t num_obs(const m2m_obs_layout& L) {
+    if (L.kin == M2M_KIN_NONE) return L.n_r;
+    return L.n_r + L.n_R * kin_per_annulus(L);
+}
+
+std::string check_params(const m2m_params* P) {
+    if (!P) return "params is NULL";
+    if (!(is_fin(P->dt) && P->dt > 0)) return "dt must be > 0";
+    if (!(is_fin(P->eps) && P->eps >= 0)) return "eps must be >= 0";
+    if (!(is_fin(P->mu) && P->mu >= 0)) return "mu must be >= 0";
+    if (!(is_fin(P->alpha) && P->alpha >= 0)) return "alpha must be >= 0";
+    if (!(is_fin(P->mass) && P->mass > 0)) return "mass must be > 0";
+    if (P->entropy != M2M_S_MPR && P->entropy != M2M_S_GWR) return "unknown entropy";
+    if (P->n_E < 1 || P->n_x < 1 || (int64_t)P->n_E * P->n_x > kMaxCells) return "need n_E, n_x >= 1 and n_E*n_x <= 4096";
+    if (P->prior_every < 0) return "prior_every must be >= 0";
+    if (!(is_fin(P->E_lo) && is_fin(P->E_hi) && P->E_hi > P->E_lo)) return "need E_lo < E_hi";
+    return "";
+}
+
+std::string check_potential(const m2m_potential* p) {
+    if (!p) return "potential is NULL";
+    if (!(is_fin(p->G) && p->G > 0)) return "G must be > 0";
+    if (!(is_fin(p->M_star) && is_fin(p->upsilon) && p->M_star * p->upsilon >= 0)) return "bad Hernquist mass";
+    if (!(is_fin(p->a) && p->a > 0)) return "a must be > 0";
+    if (!(is_fin(p->M200) && p->M200 >= 0)) return "M200 must be >= 0";
+    if (p->M200 > 0 && !(is_fin(p->c) && p->c > 0 && is_fin(p->r_s) && p->r_s > 0))
+        return "NFW needs c > 0 and r_s > 0";
+    return "";
+}
+
+// ---------------------------------------------------------------- physics --
+// (independent host evaluation, FP64: bin edges and the L_c(E) table)
+struct HostPot {
+    double GMh, a, GM200, c, rs, fc;
+    explicit HostPot(const m2m_potential& p) {
+        GMh = p.G * p.M_star * p.upsilon;
+        a = p.a;
+        GM200 = p.M200 > 0 ? p.G * p.M200 : 0.0;
+        c = p.c;
+        rs = p.r_s;
+        fc = p.M200 > 0 ? std::log1p(c) - c / (1.0 + c) : 1.0;
+    }
+    double phi(double r) const {
+        double v = -GMh / (r + a);
+        if (GM200 > 0) v += (r > 0) ? -GM200 / fc * std::log1p(r / rs) / r : -GM200 / (fc * rs);
+        return v;
+    }
+    double GM(double r) const {  // G M(<r)
+        double m = GMh * r * r / ((r + a) * (r + a));
+        if (GM200 > 0) {
+            const double q = r / rs;
+            m += GM200 / fc * (std::log1p(q) - q / (1.0 + q));
+        }
+        return m;
+    }
+    double ecirc(double r) const { return r > 0 ? phi(r) + 0.5 * GM(r) / r : phi(0.0); }
+    // ln of the radius of the circular orbit with energy E (phi(0) < E < 0),
+    // by bisection in ln r
+    double ln_rc(double E) const {
+        double lo = -60.0, hi = 60.0;  // ln r bracket
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (ecirc(std::exp(mid)) < E) lo = mid; else hi = mid;
+            if (hi - lo < 1e-15) break;
+        }
+        return 0.5 * (lo + hi);
+    }
+};
+
+double log_edge(double lo, double hi, int n, int k) {
+    if (k == 0) return lo;
+    if (k == n) return hi;
+    return lo * std::pow(hi / lo, (double)k / (double)n);
+}
+
+double lin_edge(double lo, double hi, int n, int k) {
+    if (k == 0) return lo;
+    if (k == n) return hi;
+    return lo + (hi - lo) * (double)k / (double)n;
+}
+
+// ln zeta range of the L_c table: zeta = (E - Phi0) / (-E)
+constexpr double kLz0 = -16.1180956509583;  // ln 1e-7
+constexpr double kLz1 = 20.7232658369464;   // ln 1e9
+
+// ---------------------------------------------------------------- layout ---
+struct WsLayout {
+    size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab;
+    size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
+    int seg_cap, row_len, nbj, ncj, J, C;
+};
+
+int seg_cap_of(int64_t n, int row_len) {
+    // at least ~1024 particles per tile, and partial rows of at most
+    // 16 bytes per particle (half the FP32 particle state)
+    const int64_t by_n = (n + 1023) / 1024;
+    const int64_t by_mem = (16 * n) / ((int64_t)row_len * 8);
+    int64_t cap = std::min(by_n, std::max<int64_t>(by_mem, 1));
+    cap = std::max<int64_t>(1, std::min<int64_t>(cap, 4096));
+    cap = std::min<int64_t>(cap, std::max<int64_t>(1, n / kSegAlign));
+    return (int)cap;
+}
+
+WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64) {
+    WsLayout w{};
+    const size_t sz = f64 ? 8 : 4;
+    w.J = num_obs(L);
+    w.C = P.n_E * P.n_x;
+    w.row_len = w.J + 2 * w.C;
+    w.nbj = (w.J + kFinCols - 1) / kFinCols;
+    w.ncj = (w.C + kFinCols - 1) / kFinCols;
+    w.seg_cap = seg_cap_of(n, w.row_len);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    w.st = take(sizeof(FitState));
+    w.fd = take(sizeof(FitDev));
+    w.tiles = take(sizeof(Tile) * (size_t)w.seg_cap);
+    w.jobs = take(sizeof(FinJob) * (size_t)(w.nbj + w.ncj));
+    const int nR = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
+    const int nv = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
+    w.redge2 = take(sz * (size_t)(L.n_r + 1));
+    w.Redge2 = take(sz * (size_t)(nR + 1));
+    w.vedge = take(sz * (size_t)(nv + 1));
+    w.Vp = take(sz * (size_t)std::max(nR, 1));
+    w.isp = take(sz * (size_t)std::max(nR, 1));
+    w.rp = take(sz * (size_t)w.J);
+    w.ucell = take(sz * (size_t)w.C);
+    w.lctab = take(sz * (size_t)kLcTable);
+    w.Y = take(8 * (size_t)w.J);
+    w.sigma = take(8 * (size_t)w.J);
+    w.yv = take(8 * (size_t)w.J);
+    w.ytil = take(8 * (size_t)w.J);
+    w.delta = take(8 * (size_t)w.J);
+    w.obs = take(8 * (size_t)w.J);
+    w.hist = take(8 * (size_t)kHistCap);
+    w.chi2p = take(8 * (size_t)w.nbj);
+    w.partials = take(8 * (size_t)w.seg_cap * (size_t)w.row_len);
+    w.total = o;
+    return w;
+}
+
+}  // namespace
+
+// ================================================================ context ==
+struct m2m_ctx {
+    m2m_potential pot{};
+    m2m_obs_layout lay{};
+    m2m_params par{};
+    int64_t n = 0;
+    bool f64 = false;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    WsLayout w{};
+    FitDev fd{};
+    FitDev* fd_dev = nullptr;
+    FitState* st = nullptr;
+    Tile* tiles = nullptr;
+    FinJob* jobs = nullptr;
+    int n_tiles = 0;
+    int n_jobs = 0;
+    size_t lds = 0;
+    int block = 256, ppl = 4;
+    bool targets = false;
+    bool ytil_init = false;
+    std::vector<double> Vp, sp;  // current Gauss-Hermite centres (host)
+    hipGraphExec_t graph = nullptr;
+    m2m_batch* batch = nullptr;
+    std::string err;
+};
+
+namespace {
+
+m2m_status fail(m2m_ctx* c, m2m_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+m2m_status hip_fail(m2m_ctx* c, hipError_t e, const char* what) {
+    return fail(c, M2M_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define M2M_HIP(c, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+    } while (0)
+
+template <typename T>
+std::vector<unsigned char> as_bytes(const std::vector<double>& v) {
+    std::vector<unsigned char> out(v.size() * sizeof(T));
+    for (size_t i = 0; i < v.size(); ++i) {
+        const T t = (T)v[i];
+        std::memcpy(out.data() + i * sizeof(T), &t, sizeof(T));
+    }
+    return out;
+}
+
+m2m_status upload(m2m_ctx* c, size_t off, const std::vector<double>& v) {
+    std::vector<unsigned char> b = c->f64 ? as_bytes<double>(v) : as_bytes<float>(v);
+    if (b.empty()) return M2M_OK;
+    M2M_HIP(c, hipMemcpy(c->ws + off, b.data(), b.size(), hipMemcpyHostToDevice));
+    return M2M_OK;
+}
+
+m2m_status upload_gh(m2m_ctx* c, const std::vector<double>& V, const std::vector<double>& S) {
+    std::vector<double> isp(S.size());
+    for (size_t i = 0; i < S.size(); ++i) isp[i] = 1.0 / S[i];
+    m2m_status s = upload(c, c->w.Vp, V);
+    if (s != M2M_OK) return s;
+    return upload(c, c->w.isp, isp);
+}
+
+// Split [0, n) into `count` tiles of near-equal size with aligned boundaries.
+void split_tiles(int64_t n, int count, int fit, int row0, std::vector<Tile>& out) {
+    for (int t = 0; t < count; ++t) {
+        int64_t b = n * t / count, e = n * (t + 1) / count;
+        b = b / kSegAlign * kSegAlign;
+        e = (t == count - 1) ? n : e / kSegAlign * kSegAlign;
+        out.push_back(Tile{fit, row0 + t, b, e});
+    }
+}
+
+void fin_jobs(const WsLayout& w, int fit, int n_rows, std::vector<FinJob>& out) {
+    for (int b = 0; b < w.nbj; ++b) out.push_back(FinJob{fit, 0, b * kFinCols, n_rows});
+    for (int b = 0; b < w.ncj; ++b) out.push_back(FinJob{fit, 1, b * kFinCols, n_rows});
+}
+
+m2m_status sync(m2m_ctx* c) {
+    M2M_HIP(c, hipStreamSynchronize(c->stream));
+    return M2M_OK;
+}
+
+m2m_status read_state(m2m_ctx* c, FitState& s) {
+    M2M_HIP(c, hipStreamSynchronize(c->stream));
+    M2M_HIP(c, hipMemcpy(&s, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
+    return M2M_OK;
+}
+
+// Assign cell priors computed by the last refresh, if still pending.
+m2m_status flush_assign(m2m_ctx* c) {
+    FitState s{};
+    m2m_status r = read_state(c, s);
+    if (r != M2M_OK) return r;
+    if (s.assign_pending) {
+        M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
+        return sync(c);
+    }
+    return M2M_OK;
+}
+
+m2m_status check_error(m2m_ctx* c) {
+    FitState s{};
+    m2m_status r = read_state(c, s);
+    if (r != M2M_OK) return r;
+    if (s.error & 1) return fail(c, M2M_ENONFINITE, "chi^2 became non-finite");
+    return M2M_OK;
+}
+
+m2m_status run_direct(m2m_ctx* c, int steps) {
+    for (int k = 0; k < steps; ++k) {
+        M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                               kModeStep, c->stream));
+        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream));
+    }
+    return M2M_OK;
+}
+
+m2m_status ensure_graph(m2m_ctx* c) {
+    if (c->graph) return M2M_OK;
+    if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    M2M_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
+        e = launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                        kModeStep, c->cap);
+        if (e == hipSuccess)
+            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->cap);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    return M2M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t m2m_num_observables(const m2m_obs_layout* layout) {
+    if (!check_layout(layout).empty()) return 0;
+    return num_obs(*layout);
+}
+
+size_t m2m_workspace_bytes(const m2m_obs_layout* layout, const m2m_params* params, int64_t n,
+                           int32_t dtype) {
+    if (!check_layout(layout).empty() || !check_params(params).empty() || n < 1) return 0;
+    if (dtype != M2M_F32 && dtype != M2M_F64) return 0;
+    return plan(*layout, *params, n, dtype == M2M_F64).total;
+}
+
+m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu) {
+    if (block != 256 && block != 512 && block != 1024) return M2M_EINVAL;
+    if (ppl != 1 && ppl != 2 && ppl != 4) return M2M_EINVAL;
+    if (tiles_per_cu < 1 || tiles_per_cu > 16) return M2M_EINVAL;
+    g_block = block;
+    g_ppl = ppl;
+    g_tiles_per_cu = tiles_per_cu;
+    return M2M_OK;
+}
+
+m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu) {
+    if (block) *block = g_block;
+    if (ppl) *ppl = g_ppl;
+    if (tiles_per_cu) *tiles_per_cu = g_tiles_per_cu;
+    return M2M_OK;
+}
+
+const char* m2m_last_error(const m2m_ctx* ctx) {
+    if (!ctx) return "context is NULL";
+    return ctx->err.c_str();
+}
+
+m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
+                      const m2m_params* params, int64_t n, int32_t dtype, void* x, void* y,
+                      void* z, void* vx, void* vy, void* vz, void* u, void* u_prior,
+                      void* workspace, size_t workspace_bytes, void* hip_stream, m2m_ctx** out) {
+    if (!out) return M2M_EINVAL;
+    *out = nullptr;
+    std::string why = check_potential(pot);
+    if (why.empty()) why = check_layout(layout);
+    if (why.empty()) why = check_params(params);
+    if (!why.empty()) return M2M_EINVAL;
+    if (n < 1 || (dtype != M2M_F32 && dtype != M2M_F64)) return M2M_EINVAL;
+    void* ptrs[8] = {x, y, z, vx, vy, vz, u, u_prior};
+    for (void* p : ptrs)
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 15u)) return M2M_EINVAL;
+
+    m2m_ctx* c = new (std::nothrow) m2m_ctx();
+    if (!c) return M2M_ENOMEM;
+    c->pot = *pot;
+    c->lay = *layout;
+    c->par = *params;
+    c->n = n;
+    c->f64 = dtype == M2M_F64;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->block = c->f64 ? 256 : g_block;
+    c->ppl = c->f64 ? std::min(g_ppl, 2) : g_ppl;
+    c->w = plan(c->lay, c->par, n, c->f64);
+    const WsLayout& w = c->w;
+    c->lds = step_lds_bytes(c->f64, w.J, c->lay.n_r,
+                            c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
+                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0);
+    if (c->lds > max_lds()) {
+        delete c;
+        return M2M_EUNSUPPORTED;
+    }
+    if (workspace) {
+        if (workspace_bytes < w.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+            delete c;
+            return M2M_EINVAL;
+        }
+        c->ws = static_cast<unsigned char*>(workspace);
+        c->ws_bytes = workspace_bytes;
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, w.total) != hipSuccess) {
+            delete c;
+            return M2M_ENOMEM;
+        }
+        c->ws = static_cast<unsigned char*>(p);
+        c->ws_bytes = w.total;
+        c->own_ws = true;
+    }
+    auto bail = [&](m2m_status s) {
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return s;
+    };
+    if (hipMemsetAsync(c->ws, 0, w.total, c->stream) != hipSuccess) return bail(M2M_EDEVICE);
+
+    // ---- static description
+    FitDev& f = c->fd;
+    f.x = x; f.y = y; f.z = z; f.vx = vx; f.vy = vy; f.vz = vz; f.u = u; f.uh = u_prior;
+    f.n = n;
+    const HostPot hp(c->pot);
+    f.GMh = hp.GMh;
+    f.a = hp.a;
+    f.GMn = hp.GM200 > 0 ? hp.GM200 / hp.fc : 0.0;
+    f.rs = hp.GM200 > 0 ? hp.rs : 1.0;
+    f.phi0 = hp.phi(0.0);
+    const m2m_obs_layout& L = c->lay;
+    f.n_r = L.n_r;
+    f.n_R = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
+    f.kin = L.kin;
+    f.nk = kin_per_annulus(L);
+    f.J = w.J;
+    f.n_v = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
+    f.gh_nmax = L.kin == M2M_KIN_GH ? L.gh_nmax : 0;
+    f.C = w.C;
+    f.lr0 = std::log2(L.r_min * L.r_min);
+    f.lrs = L.n_r / std::log2((L.r_max * L.r_max) / (L.r_min * L.r_min));
+    if (f.n_R > 0) {
+        f.lR0 = std::log2(L.R_min * L.R_min);
+        f.lRs = L.n_R / std::log2((L.R_max * L.R_max) / (L.R_min * L.R_min));
+    }
+    if (f.n_v > 0) {
+        f.vmin = L.v_min;
+        f.vidv = L.n_v / (L.v_max - L.v_min);
+    }
+    unsigned char* b = c->ws;
+    f.redge2 = b + w.redge2;
+    f.Redge2 = b + w.Redge2;
+    f.vedge = b + w.vedge;
+    f.Vp = b + w.Vp;
+    f.isp = b + w.isp;
+    f.rp = b + w.rp;
+    f.Y = reinterpret_cast<double*>(b + w.Y);
+    f.sigma = reinterpret_cast<double*>(b + w.sigma);
+    f.yv = reinterpret_cast<double*>(b + w.yv);
+    f.ytil = reinterpret_cast<double*>(b + w.ytil);
+    f.delta = reinterpret_cast<double*>(b + w.delta);
+    f.obs_out = reinterpret_cast<double*>(b + w.obs);
+    f.partials = reinterpret_cast<double*>(b + w.partials);
+    f.row_len = w.row_len;
+    f.n_bin_jobs = w.nbj;
+    f.n_cell_jobs = w.ncj;
+    f.entropy = c->par.entropy;
+    f.n_E = c->par.n_E;
+    f.n_x = c->par.n_x;
+    f.prior_every = c->par.prior_every;
+    f.E_lo = c->par.E_lo;
+    f.E_hi = c->par.E_hi;
+    f.E_scale = c->par.n_E / (c->par.E_hi - c->par.E_lo);
+    f.ucell = b + w.ucell;
+    f.lctab = b + w.lctab;
+    f.lz0 = kLz0;
+    f.ilz = (kLcTable - 1) / (kLz1 - kLz0);
+    const double dt = c->par.dt;
+    f.dt = dt;
+    f.w0 = c->par.mass / (double)n;
+    f.foc_mu = c->par.eps * dt * c->par.mu;
+    f.foc_cs = c->par.entropy == M2M_S_GWR ? 1.0 : 0.0;
+    f.foc_chi = c->par.eps * dt * f.w0;
+    f.q = -std::expm1(-c->par.alpha * dt);
+    f.chi2_hist = reinterpret_cast<double*>(b + w.hist);
+    f.chi2_part = reinterpret_cast<double*>(b + w.chi2p);
+    f.st = reinterpret_cast<FitState*>(b + w.st);
+    c->fd_dev = reinterpret_cast<FitDev*>(b + w.fd);
+    c->st = f.st;
+    c->tiles = reinterpret_cast<Tile*>(b + w.tiles);
+    c->jobs = reinterpret_cast<FinJob*>(b + w.jobs);
+
+    // ---- tables
+    std::vector<double> re2(L.n_r + 1), Re2(f.n_R + 1), ve(f.n_v + 1, 0.0);
+    for (int k = 0; k <= L.n_r; ++k) {
+        const double e = log_edge(L.r_min, L.r_max, L.n_r, k);
+        re2[k] = e * e;
+    }
+    for (int k = 0; k <= f.n_R; ++k) {
+        const double e = log_edge(L.R_min, L.R_max, L.n_R, k);
+        Re2[k] = e * e;
+    }
+    for (int k = 0; k <= f.n_v; ++k) ve[k] = lin_edge(L.v_min, L.v_max, L.n_v, k);
+    std::vector<double> lct(kLcTable);
+    const double phi0 = hp.phi(0.0);
+    for (int k = 0; k < kLcTable; ++k) {
+        const double lz = kLz0 + (kLz1 - kLz0) * k / (kLcTable - 1);
+        const double E = phi0 / (1.0 + std::exp(lz));
+        lct[k] = hp.ln_rc(E);
+    }
+    std::vector<double> ones(w.C, 1.0);
+    c->Vp.assign(std::max(f.n_R, 1), 0.0);
+    c->sp.assign(std::max(f.n_R, 1), 1.0);
+    m2m_status s = M2M_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(M2M_EDEVICE);
+    if ((s = upload(c, w.redge2, re2)) != M2M_OK) return bail(s);
+    if ((s = upload(c, w.Redge2, Re2)) != M2M_OK) return bail(s);
+    if ((s = upload(c, w.vedge, ve)) != M2M_OK) return bail(s);
+    if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);
+    if ((s = upload(c, w.ucell, ones)) != M2M_OK) return bail(s);
+    if ((s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return bail(s);
+
+    // ---- tiles of this fit alone
+    const int target = std::max(1, g_tiles_per_cu * n_cus());
+    const int count = std::max(1, std::min(w.seg_cap, target));
+    std::vector<Tile> tl;
+    split_tiles(n, count, 0, 0, tl);
+    std::vector<FinJob> jb;
+    fin_jobs(w, 0, count, jb);
+    c->n_tiles = (int)tl.size();
+    c->n_jobs = (int)jb.size();
+    if (hipMemcpy(c->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->jobs, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->fd_dev, &f, sizeof(FitDev), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(M2M_EDEVICE);
+    *out = c;
+    return M2M_OK;
+}
+
+m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double* sigma,
+                           const double* V_p, const double* sigma_p) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (J != c->w.J) return fail(c, M2M_EINVAL, "J does not match the layout");
+    if (!Y || !sigma) return fail(c, M2M_EINVAL, "Y and sigma are required");
+    for (int j = 0; j < J; ++j)
+        if (!is_fin(Y[j]) || !is_fin(sigma[j]) || !(sigma[j] > 0))
+            return fail(c, M2M_EINVAL, "targets must be finite with sigma > 0");
+    std::vector<double> V = c->Vp, S = c->sp;
+    if (c->lay.kin == M2M_KIN_GH) {
+        if (!V_p || !sigma_p) return fail(c, M2M_EINVAL, "Gauss-Hermite layout needs V_p and sigma_p");
+        for (int p = 0; p < c->fd.n_R; ++p) {
+            if (!is_fin(V_p[p]) || !is_fin(sigma_p[p]) || !(sigma_p[p] > 0))
+                return fail(c, M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
+            V[p] = V_p[p];
+            S[p] = sigma_p[p];
+        }
+    }
+    m2m_status s = sync(c);
+    if (s != M2M_OK) return s;
+    M2M_HIP(c, hipMemcpy(c->fd.Y, Y, sizeof(double) * J, hipMemcpyHostToDevice));
+    M2M_HIP(c, hipMemcpy(c->fd.sigma, sigma, sizeof(double) * J, hipMemcpyHostToDevice));
+    c->Vp = V;
+    c->sp = S;
+    if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
+    if (!c->ytil_init) {
+        M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                               kModeInit, c->stream));
+        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeInit, c->stream));
+        c->ytil_init = true;
+    } else {
+        M2M_HIP(c, launch_residuals(c->f64, c->fd_dev, c->stream));
+    }
+    c->targets = true;
+    return check_error(c);
+}
+
+m2m_status m2m_step(m2m_ctx* c, int32_t n_steps, int32_t correct) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
+    if (n_steps < 0) return fail(c, M2M_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return M2M_OK;
+    M2M_HIP(c, launch_poke(c->st, n_steps, correct ? 1 : 0, c->stream));
+    const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
+    if (full > 0) {
+        m2m_status s = ensure_graph(c);
+        if (s != M2M_OK) return s;
+        for (int k = 0; k < full; ++k) M2M_HIP(c, hipGraphLaunch(c->graph, c->stream));
+    }
+    return run_direct(c, rem);
+}
+
+m2m_status m2m_update_priors(m2m_ctx* c) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
+    M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                           kModeCells, c->stream));
+    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeCells, c->stream));
+    M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
+    return M2M_OK;
+}
+
+m2m_status m2m_get_weights(m2m_ctx* c, void* dst, int32_t dst_is_device) {
+    if (!c || !dst) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    m2m_status s = flush_assign(c);
+    if (s != M2M_OK) return s;
+    const double scale = c->par.mass / (double)c->n;
+    if (dst_is_device) {
+        M2M_HIP(c, launch_weights(c->f64, c->fd.u, dst, c->n, scale, c->stream));
+        s = sync(c);
+    } else {
+        const size_t sz = c->f64 ? 8 : 4;
+        M2M_HIP(c, hipMemcpy(dst, c->fd.u, sz * (size_t)c->n, hipMemcpyDeviceToHost));
+        if (c->f64) {
+            double* d = static_cast<double*>(dst);
+            for (int64_t i = 0; i < c->n; ++i) d[i] *= scale;
+        } else {
+            float* d = static_cast<float*>(dst);
+            for (int64_t i = 0; i < c->n; ++i) d[i] = (float)((double)d[i] * scale);
+        }
+    }
+    if (s != M2M_OK) return s;
+    return check_error(c);
+}
+
+m2m_status m2m_get_observables(m2m_ctx* c, double* y, double* y_tilde, double* delta,
+                               double* chi2) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    FitState st{};
+    m2m_status s = read_state(c, st);
+    if (s != M2M_OK) return s;
+    const size_t J = (size_t)c->w.J;
+    if (y) M2M_HIP(c, hipMemcpy(y, c->fd.yv, 8 * J, hipMemcpyDeviceToHost));
+    if (y_tilde) M2M_HIP(c, hipMemcpy(y_tilde, c->fd.ytil, 8 * J, hipMemcpyDeviceToHost));
+    if (delta) M2M_HIP(c, hipMemcpy(delta, c->fd.delta, 8 * J, hipMemcpyDeviceToHost));
+    if (chi2) *chi2 = st.chi2;
+    if (st.error & 1) return fail(c, M2M_ENONFINITE, "chi^2 became non-finite");
+    return M2M_OK;
+}
+
+m2m_status m2m_get_chi2_history(m2m_ctx* c, double* out, int32_t max, int32_t* n_out) {
+    if (!c || !n_out || max < 0 || (max > 0 && !out)) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    FitState st{};
+    m2m_status s = read_state(c, st);
+    if (s != M2M_OK) return s;
+    std::vector<double> ring(kHistCap);
+    M2M_HIP(c, hipMemcpy(ring.data(), c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
+    const int64_t have = std::min<int64_t>(st.tstep, kHistCap);
+    const int64_t take = std::min<int64_t>(have, max);
+    for (int64_t k = 0; k < take; ++k) {
+        const int64_t t = st.tstep - take + k;
+        out[k] = ring[(size_t)(t % kHistCap)];
+    }
+    *n_out = (int32_t)take;
+    return M2M_OK;
+}
+
+m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, double* y) {
+    if (!c || !y) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    const bool tmp = c->lay.kin == M2M_KIN_GH && V_p && sigma_p;
+    m2m_status s = sync(c);
+    if (s != M2M_OK) return s;
+    if (tmp) {
+        std::vector<double> V(V_p, V_p + c->fd.n_R), S(sigma_p, sigma_p + c->fd.n_R);
+        for (int p = 0; p < c->fd.n_R; ++p)
+            if (!is_fin(V[p]) || !is_fin(S[p]) || !(S[p] > 0))
+                return fail(c, M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
+        if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
+    }
+    M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                           kModeObserve, c->stream));
+    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream));
+    if ((s = sync(c)) != M2M_OK) return s;
+    M2M_HIP(c, hipMemcpy(y, c->fd.obs_out, 8 * (size_t)c->w.J, hipMemcpyDeviceToHost));
+    if (tmp && (s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return s;
+    return M2M_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint32_t magic, version;
+    int64_t n;
+    int32_t J, C, dtype, n_R;
+    int32_t targets, ytil_init, pad0, pad1;
+};
+}  // namespace
+
+m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
+    if (!c || !bytes) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    const size_t J = (size_t)c->w.J, C = (size_t)c->w.C, nR = c->Vp.size();
+    const size_t sz = c->f64 ? 8 : 4;
+    const size_t need = sizeof(StateHeader) + sizeof(FitState) + 8 * (5 * J + 2 * nR) +
+                        sz * (C + J) + 8 * (size_t)kHistCap;
+    if (!host_blob) {
+        *bytes = need;
+        return M2M_OK;
+    }
+    if (*bytes < need) return fail(c, M2M_EINVAL, "state buffer too small");
+    m2m_status s = sync(c);
+    if (s != M2M_OK) return s;
+    unsigned char* p = static_cast<unsigned char*>(host_blob);
+    StateHeader h{kStateMagic, 1u, c->n, (int32_t)J, (int32_t)C, c->f64 ? 1 : 0, (int32_t)nR,
+                  c->targets ? 1 : 0, c->ytil_init ? 1 : 0, 0, 0};
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    M2M_HIP(c, hipMemcpy(p, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
+    p += sizeof(FitState);
+    double* const dev[5] = {c->fd.ytil, c->fd.yv, c->fd.delta, c->fd.Y, c->fd.sigma};
+    for (double* d : dev) {
+        M2M_HIP(c, hipMemcpy(p, d, 8 * J, hipMemcpyDeviceToHost));
+        p += 8 * J;
+    }
+    std::memcpy(p, c->Vp.data(), 8 * nR);
+    p += 8 * nR;
+    std::memcpy(p, c->sp.data(), 8 * nR);
+    p += 8 * nR;
+    M2M_HIP(c, hipMemcpy(p, c->fd.ucell, sz * C, hipMemcpyDeviceToHost));
+    p += sz * C;
+    M2M_HIP(c, hipMemcpy(p, c->fd.rp, sz * J, hipMemcpyDeviceToHost));
+    p += sz * J;
+    M2M_HIP(c, hipMemcpy(p, c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return M2M_OK;
+}
+
+m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
+    if (!c || !host_blob) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    size_t need = 0;
+    m2m_get_state(c, nullptr, &need);
+    if (bytes < need) return fail(c, M2M_EINVAL, "state blob too small");
+    const unsigned char* p = static_cast<const unsigned char*>(host_blob);
+    StateHeader h{};
+    std::memcpy(&h, p, sizeof h);
+    const size_t J = (size_t)c->w.J, C = (size_t)c->w.C, nR = c->Vp.size();
+    if (h.magic != kStateMagic || h.version != 1u || h.n != c->n || h.J != (int32_t)J ||
+        h.C != (int32_t)C || h.dtype != (c->f64 ? 1 : 0) || h.n_R != (int32_t)nR)
+        return fail(c, M2M_EINVAL, "state blob does not match this context");
+    p += sizeof h;
+    m2m_status s = sync(c);
+    if (s != M2M_OK) return s;
+    FitState st{};
+    std::memcpy(&st, p, sizeof st);
+    st.ticket = 0;
+    st.steps_left = 0;
+    M2M_HIP(c, hipMemcpy(c->st, &st, sizeof st, hipMemcpyHostToDevice));
+    p += sizeof(FitState);
+    double* const dev[5] = {c->fd.ytil, c->fd.yv, c->fd.delta, c->fd.Y, c->fd.sigma};
+    for (double* d : dev) {
+        M2M_HIP(c, hipMemcpy(d, p, 8 * J, hipMemcpyHostToDevice));
+        p += 8 * J;
+    }
+    std::vector<double> V(nR), S(nR);
+    std::memcpy(V.data(), p, 8 * nR);
+    p += 8 * nR;
+    std::memcpy(S.data(), p, 8 * nR);
+    p += 8 * nR;
+    c->Vp = V;
+    c->sp = S;
+    if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
+    M2M_HIP(c, hipMemcpy(c->fd.ucell, p, (c->f64 ? 8 : 4) * C, hipMemcpyHostToDevice));
+    p += (c->f64 ? 8 : 4) * C;
+    M2M_HIP(c, hipMemcpy(c->fd.rp, p, (c->f64 ? 8 : 4) * J, hipMemcpyHostToDevice));
+    p += (c->f64 ? 8 : 4) * J;
+    M2M_HIP(c, hipMemcpy(c->fd.chi2_hist, p, 8 * (size_t)kHistCap, hipMemcpyHostToDevice));
+    c->targets = h.targets != 0;
+    c->ytil_init = h.ytil_init != 0;
+    return M2M_OK;
+}
+
+m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double* ms_step,
+                            double* ms_finalize) {
+    if (!c || n_steps < 1) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
+    std::vector<hipEvent_t> ev(3 * (size_t)n_steps, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(c, M2M_EDEVICE, "hipEventCreate");
+        }
+    m2m_status s = M2M_OK;
+    hipError_t e = launch_poke(c->st, n_steps, correct ? 1 : 0, c->stream);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        e = hipEventRecord(ev[3 * k], c->stream);
+        if (e == hipSuccess)
+            e = launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+                            kModeStep, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], c->stream);
+        if (e == hipSuccess)
+            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double t1 = 0.0, t2 = 0.0;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+        t1 += a;
+        t2 += b;
+    }
+    if (e != hipSuccess) s = hip_fail(c, e, "profile");
+    for (auto& f : ev) (void)hipEventDestroy(f);
+    if (ms_step) *ms_step = t1 / n_steps;
+    if (ms_finalize) *ms_finalize = t2 / n_steps;
+    return s;
+}
+
+m2m_status m2m_destroy(m2m_ctx* c) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->own_ws) (void)hipFree(c->ws);
+    delete c;
+    return M2M_OK;
+}
+
+}  // extern "C"
+
+// ================================================================= batch ===
+struct m2m_batch {
+    int max_fits = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<m2m_ctx*> fits;
+    bool dirty = true;
+    int f64 = -1;
+    FitDev* fits_dev = nullptr;
+    Tile* tiles_dev = nullptr;
+    FinJob* jobs_dev = nullptr;
+    int32_t* gather_dev = nullptr;
+    int32_t* gather_host = nullptr;
+    size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
+    int n_tiles = 0, n_jobs = 0;
+    size_t lds = 0;
+    int block = 256, ppl = 4;
+    hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+size_t footprint(const m2m_ctx* c) {
+    return (size_t)c->n * 8 * (c->f64 ? 8 : 4) + c->w.total;
+}
+
+hipError_t grow(void** p, size_t* cap, size_t need) {
+    if (need <= *cap) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    size_t n = std::max(need, *cap * 2);
+    hipError_t e = hipMalloc(p, n);
+    *cap = e == hipSuccess ? n : 0;
+    return e;
+}
+
+m2m_status rebuild(m2m_batch* b) {
+    // launches in flight may still read the old tables and graph
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->n_tiles = b->n_jobs = 0;
+    if (b->fits.empty()) {
+        b->dirty = false;
+        return M2M_OK;
+    }
+    const bool f64 = b->f64 == 1;
+    b->block = f64 ? 256 : g_block;
+    b->ppl = f64 ? std::min(g_ppl, 2) : g_ppl;
+    std::vector<FitDev> fd;
+    std::vector<Tile> tl;
+    std::vector<FinJob> jb;
+    double ntot = 0;
+    for (m2m_ctx* c : b->fits) ntot += (double)c->n;
+    const int target = std::max(1, g_tiles_per_cu * n_cus());
+    size_t lds = 0;
+    for (size_t f = 0; f < b->fits.size(); ++f) {
+        m2m_ctx* c = b->fits[f];
+        fd.push_back(c->fd);
+        int cnt = (int)std::lround(target * (double)c->n / ntot);
+        cnt = std::max(1, std::min(cnt, c->w.seg_cap));
+        split_tiles(c->n, cnt, (int)f, 0, tl);
+        fin_jobs(c->w, (int)f, cnt, jb);
+        lds = std::max(lds, c->lds);
+    }
+    if (grow(reinterpret_cast<void**>(&b->fits_dev), &b->cap_fits, sizeof(FitDev) * fd.size()) != hipSuccess ||
+        grow(reinterpret_cast<void**>(&b->tiles_dev), &b->cap_tiles, sizeof(Tile) * tl.size()) != hipSuccess ||
+        grow(reinterpret_cast<void**>(&b->jobs_dev), &b->cap_jobs, sizeof(FinJob) * jb.size()) != hipSuccess)
+        return M2M_ENOMEM;
+    if (hipMemcpyAsync(b->fits_dev, fd.data(), sizeof(FitDev) * fd.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->tiles_dev, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->jobs_dev, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return M2M_EDEVICE;
+    b->n_tiles = (int)tl.size();
+    b->n_jobs = (int)jb.size();
+    b->lds = lds;
+    // graph of kGraphSteps steps over this composition
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return M2M_EDEVICE;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
+        e = launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+                        kModeStep, b->cap);
+        if (e == hipSuccess)
+            e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->cap);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return M2M_EDEVICE;
+    }
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return M2M_EDEVICE;
+    }
+    b->dirty = false;
+    return M2M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+m2m_status m2m_batch_create(int32_t max_fits, size_t hbm_budget, void* hip_stream,
+                            m2m_batch** out) {
+    if (!out) return M2M_EINVAL;
+    *out = nullptr;
+    if (max_fits < 1 || max_fits > 65536) return M2M_EINVAL;
+    m2m_batch* b = new (std::nothrow) m2m_batch();
+    if (!b) return M2M_ENOMEM;
+    b->max_fits = max_fits;
+    b->budget = hbm_budget;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b->gather_dev), sizeof(int32_t) * 2 * (size_t)max_fits) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->gather_host), sizeof(int32_t) * 2 * (size_t)max_fits, 0) != hipSuccess) {
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        if (b->gather_dev) (void)hipFree(b->gather_dev);
+        delete b;
+        return M2M_EDEVICE;
+    }
+    *out = b;
+    return M2M_OK;
+}
+
+size_t m2m_batch_footprint(const m2m_batch* b) {
+    if (!b) return 0;
+    size_t s = 0;
+    for (const m2m_ctx* c : b->fits) s += footprint(c);
+    return s;
+}
+
+m2m_status m2m_batch_admit(m2m_batch* b, m2m_ctx* c, int32_t n_steps) {
+    if (!b || !c || n_steps < 0) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is already in a batch");
+    if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
+    if (b->f64 != -1 && b->f64 != (c->f64 ? 1 : 0))
+        return fail(c, M2M_EINVAL, "a batch holds fits of one particle dtype");
+    if ((int)b->fits.size() >= b->max_fits) return fail(c, M2M_ENOMEM, "batch is full");
+    if (b->budget && m2m_batch_footprint(b) + footprint(c) > b->budget)
+        return fail(c, M2M_ENOMEM, "fit does not fit the HBM budget");
+    m2m_status s = flush_assign(c);  // also waits for the fit's own stream
+    if (s != M2M_OK) return s;
+    M2M_HIP(c, launch_poke(c->st, n_steps, 1, b->stream));
+    b->f64 = c->f64 ? 1 : 0;
+    b->fits.push_back(c);
+    c->batch = b;
+    b->dirty = true;
+    return M2M_OK;
+}
+
+m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
+    if (!b || steps_per_launch < 0) return M2M_EINVAL;
+    if (b->dirty) {
+        m2m_status s = rebuild(b);
+        if (s != M2M_OK) return s;
+    }
+    if (b->fits.empty() || steps_per_launch == 0) return M2M_OK;
+    const bool f64 = b->f64 == 1;
+    const int full = steps_per_launch / kGraphSteps, rem = steps_per_launch % kGraphSteps;
+    for (int k = 0; k < full; ++k)
+        if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
+    for (int k = 0; k < rem; ++k) {
+        if (launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+                        kModeStep, b->stream) != hipSuccess ||
+            launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
+            return M2M_EDEVICE;
+    }
+    return M2M_OK;
+}
+
+m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
+                          int32_t* n_active) {
+    if (!b || !n_done || max_done < 0 || (max_done > 0 && !done)) return M2M_EINVAL;
+    *n_done = 0;
+    if (b->dirty) {
+        m2m_status s = rebuild(b);
+        if (s != M2M_OK) return s;
+    }
+    const int nf = (int)b->fits.size();
+    if (nf > 0) {
+        if (launch_gather(b->fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
+            hipMemcpyAsync(b->gather_host, b->gather_dev, sizeof(int32_t) * 2 * nf,
+                           hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+            return M2M_EDEVICE;
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+    std::vector<m2m_ctx*> keep;
+    bool bad = false;
+    for (int f = 0; f < nf; ++f) {
+        m2m_ctx* c = b->fits[f];
+        const bool finished = b->gather_host[2 * f] <= 0;
+        if (finished && *n_done < max_done) {
+            done[(*n_done)++] = c;
+            c->batch = nullptr;
+            if (b->gather_host[2 * f + 1] & 1) {
+                c->err = "chi^2 became non-finite";
+                bad = true;
+            }
+        } else {
+            keep.push_back(c);
+        }
+    }
+    if (keep.size() != b->fits.size()) {
+        b->fits.swap(keep);
+        b->dirty = true;
+        if (b->fits.empty()) b->f64 = -1;
+    }
+    if (n_active) *n_active = (int32_t)b->fits.size();
+    return bad ? M2M_ENONFINITE : M2M_OK;
+}
+
+m2m_status m2m_batch_cancel(m2m_batch* b, m2m_ctx* c) {
+    if (!b || !c || c->batch != b) return M2M_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+    if (launch_poke(c->st, 0, -1, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return M2M_EDEVICE;
+    b->fits.erase(std::find(b->fits.begin(), b->fits.end(), c));
+    c->batch = nullptr;
+    b->dirty = true;
+    if (b->fits.empty()) b->f64 = -1;
+    return M2M_OK;
+}
+
+m2m_status m2m_batch_destroy(m2m_batch* b) {
+    if (!b) return M2M_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (m2m_ctx* c : b->fits) c->batch = nullptr;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->fits_dev) (void)hipFree(b->fits_dev);
+    if (b->tiles_dev) (void)hipFree(b->tiles_dev);
+    if (b->jobs_dev) (void)hipFree(b->jobs_dev);
+    if (b->gather_dev) (void)hipFree(b->gather_dev);
+    if (b->gather_host) (void)hipHostFree(b->gather_host);
+    delete b;
+    return M2M_OK;
+}
+
+}  // extern "C"

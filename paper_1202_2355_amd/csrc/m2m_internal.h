@@ -1,0 +1,103 @@
+// Internal device-side structures shared by the HIP kernels (m2m_kernels.hip)
+// and the host side of the C ABI (m2m_api.cpp). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace m2m {
+
+constexpr int kMaxGH = 8;          // largest Gauss-Hermite order
+constexpr int kMaxLOSVD = 256;     // largest LOSVD bin count
+constexpr int kMaxCells = 4096;    // largest n_E * n_x
+constexpr int kLcTable = 8192;     // entries of the ln r_c(ln zeta) table
+constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
+constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
+constexpr int kHistCap = 8192;     // chi^2 history ring per fit
+constexpr int kSegAlign = 4;       // tile boundaries are multiples of 4 particles
+
+// kernel launch modes (bit set)
+enum : int32_t {
+    kModeStep = 1,       // a full M2M step: (assign) FOC, push, deposit, (cells)
+    kModeInit = 2,       // deposit the current state; finalize sets ytilde = y
+    kModeObserve = 4,    // deposit the current state into obs_out only
+    kModeCells = 8,      // accumulate the prior cells of the current state only
+};
+
+// Dynamic per-fit state, device resident, written only by the kernels (and by
+// the host between launches, on the fit's stream).
+struct FitState {
+    int64_t kstep;           // correction steps done (prior schedule)
+    int64_t tstep;           // all steps done (chi^2 history index)
+    int32_t steps_left;      // steps still to run; kernels skip the fit at 0
+    int32_t correct;         // force of change on (1) or relaxation (0)
+    int32_t assign_pending;  // fresh cell priors wait to be assigned
+    int32_t error;           // bit 0: non-finite chi^2 seen
+    uint32_t ticket;         // finalize: blocks done this launch
+    int32_t pad0;
+    double chi2;             // chi^2 after the last step
+};
+
+// Static per-fit description (device copy). Pointers are device addresses.
+struct FitDev {
+    // particle state (float or double, SoA)
+    void *x, *y, *z, *vx, *vy, *vz, *u, *uh;
+    int64_t n;
+    // potential: Hernquist G M upsilon, a; NFW G M200 / f(c), r_s; Phi(0)
+    double GMh, a, GMn, rs, phi0;
+    // observables
+    int32_t n_r, n_R, kin, nk, J, n_v, gh_nmax, C;
+    double lr0, lrs;         // radial bin guess: (log2(r^2) - lr0) * lrs
+    double lR0, lRs;         // annulus bin guess
+    double vmin, vidv;       // LOSVD bin guess: (v - vmin) * vidv
+    void *redge2, *Redge2, *vedge, *Vp, *isp, *rp;  // tables in the state dtype
+    double *Y, *sigma, *yv, *ytil, *delta, *obs_out;
+    double *partials;        // tile rows of row_len doubles
+    int32_t row_len;         // J + 2 C
+    int32_t n_bin_jobs;      // ceil(J / kFinCols)
+    int32_t n_cell_jobs;     // ceil(C / kFinCols)
+    int32_t entropy;
+    // priors
+    int32_t n_E, n_x, prior_every, pad1;
+    double E_lo, E_hi, E_scale;  // E_scale = n_E / (E_hi - E_lo)
+    void *ucell, *lctab;         // C values; kLcTable values of ln r_c(ln zeta)
+    double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
+    // step constants
+    double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
+    double *chi2_hist;
+    double *chi2_part;           // one per bin job
+    FitState *st;
+};
+
+// One tile: a contiguous particle range of one fit, owned by one block.
+struct Tile {
+    int32_t fit;   // index into the launch's fit table
+    int32_t row;   // tile row in the fit's partials
+    int64_t begin, end;
+};
+
+// One finalize block: kFinCols columns of one fit.
+struct FinJob {
+    int32_t fit;
+    int32_t kind;  // 0: observable columns, 1: cell columns
+    int32_t col0;
+    int32_t n_tiles;  // rows of the fit to reduce
+};
+
+// ---- launchers (m2m_kernels.hip) ------------------------------------------
+hipError_t launch_step(bool f64, int block, int ppl, const FitDev* fits, const Tile* tiles,
+                       int n_tiles, size_t lds_bytes, int32_t mode, hipStream_t s);
+hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
+                           int32_t mode, hipStream_t s);
+hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
+                         hipStream_t s);
+hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double scale,
+                          hipStream_t s);
+hipError_t launch_poke(FitState* st, int32_t steps_left, int32_t correct, hipStream_t s);
+hipError_t launch_gather(const FitDev* fits, int n, int32_t* out, hipStream_t s);
+hipError_t launch_residuals(bool f64, const FitDev* fit, hipStream_t s);
+size_t step_lds_bytes(bool f64, int J, int n_r, int n_R, int n_v);
+
+}  // namespace m2m

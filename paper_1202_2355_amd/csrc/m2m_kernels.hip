@@ -1,0 +1,687 @@
+// HIP kernels (gfx950) of the chi^2 M2M step with moving priors.
+//
+// One M2M step is two kernels:
+//   k_step      one streaming pass over the particles of every active fit,
+//               one block per tile: (assign the new cell priors) -> force of
+//               change at z^k (eq. modFOC with eq. S+ or eq. entropy) ->
+//               drift-kick-drift push -> deposit of w K_j(z^{k+1}) (eq. obs)
+//               into LDS bins -> (prior-cell sums, Sec. 2.3.1). Each tile
+//               writes one row of FP64 partial sums.
+//   k_finalize  FP64 reduction of the tile rows of every fit in a fixed
+//               order -> y, smoothed ytilde (eq. myts), Delta and chi^2
+//               (eqs. delta, chi), the FP32 force table for the next step,
+//               and the cell means that become the new priors.
+// Particle state is structure-of-arrays, read and written once per step
+// (coalesced, PPL consecutive particles per lane). In FP32 the in-tile bin
+// sums are compensated: every LDS atomic add returns the old value, the
+// rounding error of that add is recovered exactly (TwoSum) and accumulated
+// in a second LDS array.
+#include <hip/hip_runtime.h>
+
+#include "m2m_internal.h"
+
+namespace m2m {
+namespace {
+
+// ------------------------------------------------------------- math --------
+template <typename T>
+struct Mth;
+
+template <>
+struct Mth<float> {
+    __device__ static float exp_(float x) { return __expf(x); }
+    __device__ static float log_(float x) { return __logf(x); }
+    __device__ static float log2_(float x) { return __log2f(x); }
+    __device__ static float sqrt_(float x) { return __builtin_sqrtf(x); }
+    __device__ static float log1p_(float x) { return log1pf(x); }
+    __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+    static constexpr float nfw_series_max = 0.1f;
+};
+
+template <>
+struct Mth<double> {
+    __device__ static double exp_(double x) { return exp(x); }
+    __device__ static double log_(double x) { return log(x); }
+    __device__ static double log2_(double x) { return log2(x); }
+    __device__ static double sqrt_(double x) { return sqrt(x); }
+    __device__ static double log1p_(double x) { return log1p(x); }
+    __device__ static double rcp_(double x) { return 1.0 / x; }
+    static constexpr double nfw_series_max = 1e-3;
+};
+
+// normalized Hermite recurrence coefficients: H_{n+1} = a_n nu H_n - b_n H_{n-1}
+// with a_n = sqrt(2/(n+1)), b_n = sqrt(n/(n+1)), n = 1..7
+__constant__ double kGhA[kMaxGH] = {0.0,
+                                   1.0,                   // sqrt(2/2)
+                                   0.81649658092772603,   // sqrt(2/3)
+                                   0.70710678118654752,   // sqrt(2/4)
+                                   0.63245553203367587,   // sqrt(2/5)
+                                   0.57735026918962576,   // sqrt(2/6)
+                                   0.53452248382484880,   // sqrt(2/7)
+                                   0.5};                  // sqrt(2/8)
+__constant__ double kGhB[kMaxGH] = {0.0,
+                                   0.70710678118654752,   // sqrt(1/2)
+                                   0.81649658092772603,   // sqrt(2/3)
+                                   0.86602540378443865,   // sqrt(3/4)
+                                   0.89442719099991588,   // sqrt(4/5)
+                                   0.91287092917527690,   // sqrt(5/6)
+                                   0.92582009977255146,   // sqrt(6/7)
+                                   0.93541434669348535};  // sqrt(7/8)
+
+// ------------------------------------------------------------- LDS ---------
+template <typename T>
+struct Tabs {
+    T *rp, *sum, *comp, *re2, *Re2, *ve, *Vp, *isp;
+};
+
+template <typename T>
+__device__ __forceinline__ Tabs<T> carve(unsigned char* raw, const FitDev& fd) {
+    constexpr bool kComp = sizeof(T) == 4;
+    T* p = reinterpret_cast<T*>(raw);
+    Tabs<T> t;
+    t.rp = p;
+    p += fd.J;
+    t.sum = p;
+    p += fd.J;
+    t.comp = p;
+    if (kComp) p += fd.J;
+    t.re2 = p;
+    p += fd.n_r + 1;
+    t.Re2 = p;
+    p += fd.n_R + 1;
+    t.ve = p;
+    p += fd.n_v + 1;
+    t.Vp = p;
+    p += fd.n_R;
+    t.isp = p;
+    return t;
+}
+
+// ------------------------------------------------------------- binning -----
+// k with e[k] <= v < e[k+1] for ascending e[0..n], or -1 outside [e[0], e[n]).
+// The arithmetic guess g is refined against the stored edges, so the bin is
+// decided by the same edge values everywhere.
+template <typename T>
+__device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
+    if (!(v >= e[0]) || !(v < e[n])) return -1;
+    g = fmin(fmax(g, T(0)), T(n - 1));
+    int k = (int)g;
+    if (v < e[k]) {
+        --k;
+        if (k > 0 && v < e[k]) --k;
+    } else if (v >= e[k + 1]) {
+        ++k;
+        if (k < n - 1 && v >= e[k + 1]) ++k;
+    }
+    if (!(v >= e[k] && v < e[k + 1])) {  // the guess was off by more than 2
+        int lo = 0, hi = n;               // invariant e[lo] <= v < e[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (v >= e[mid]) lo = mid; else hi = mid;
+        }
+        k = lo;
+    }
+    return k;
+}
+
+// Visit the non-zero kernels K_j of one phase-space point: f(j, K_j).
+template <typename T, typename F>
+__device__ __forceinline__ void visit(const FitDev& fd, const Tabs<T>& tb, T x, T y, T z, T vz,
+                                      F&& f) {
+    const T R2 = x * x + y * y;
+    const T r2 = R2 + z * z;
+    const int kr = refine_bin<T>(r2, tb.re2, fd.n_r, (Mth<T>::log2_(r2) - T(fd.lr0)) * T(fd.lrs));
+    if (kr >= 0) f(kr, T(1));
+    if (fd.kin == 0) return;
+    const int p = refine_bin<T>(R2, tb.Re2, fd.n_R, (Mth<T>::log2_(R2) - T(fd.lR0)) * T(fd.lRs));
+    if (p < 0) return;
+    const int base = fd.n_r + p * fd.nk;
+    if (fd.kin == 1) {
+        f(base, vz * vz);
+    } else if (fd.kin == 2) {
+        const T nu = (vz - tb.Vp[p]) * tb.isp[p];
+        const T g = T(1.41421356237309505) * Mth<T>::exp_(T(-0.5) * nu * nu);
+        T hm = T(1);
+        T h = T(1.41421356237309505) * nu;
+        f(base, g * h);
+        for (int n = 1; n < fd.gh_nmax; ++n) {
+            const T hn = T(kGhA[n]) * nu * h - T(kGhB[n]) * hm;
+            hm = h;
+            h = hn;
+            f(base + n, g * h);
+        }
+    } else {
+        const int b = refine_bin<T>(vz, tb.ve, fd.n_v, (vz - T(fd.vmin)) * T(fd.vidv));
+        if (b >= 0) f(base + b, T(1));
+    }
+}
+
+// ------------------------------------------------------------- potential ---
+template <typename T>
+__device__ __forceinline__ T phi_of(const FitDev& fd, T r) {
+    T p = -T(fd.GMh) / (r + T(fd.a));
+    if (fd.GMn > 0.0) {
+        const T q = r / T(fd.rs);
+        const T l = (q > T(1e-4)) ? Mth<T>::log1p_(q) / q : T(1) - q * (T(0.5) - q * T(1.0 / 3.0));
+        p -= T(fd.GMn) / T(fd.rs) * l;
+    }
+    return p;
+}
+
+// s(r) with g = -s(r) * (x, y, z): G M(<r) / r^3
+template <typename T>
+__device__ __forceinline__ T accel_of(const FitDev& fd, T r) {
+    if (!(r > T(0))) return T(0);
+    const T ra = r + T(fd.a);
+    T s = T(fd.GMh) / (r * ra * ra);
+    if (fd.GMn > 0.0) {
+        const T q = r / T(fd.rs);
+        T m;
+        if (q < T(Mth<T>::nfw_series_max)) {
+            // ln(1+q) - q/(1+q) = sum_{k>=2} (-1)^k (k-1) q^k / k
+            m = q * q *
+                (T(0.5) -
+                 q * (T(2.0 / 3.0) -
+                      q * (T(0.75) - q * (T(0.8) - q * (T(5.0 / 6.0) - q * (T(6.0 / 7.0) - q * T(0.875)))))));
+        } else {
+            m = Mth<T>::log1p_(q) - q / (T(1) + q);
+        }
+        s += T(fd.GMn) * m / (r * r * r);
+    }
+    return s;
+}
+
+// Prior cell (k, l) -> k n_x + l of one phase-space point.
+template <typename T>
+__device__ __forceinline__ int cell_of(const FitDev& fd, T x, T y, T z, T vx, T vy, T vz) {
+    const T r = Mth<T>::sqrt_(x * x + y * y + z * z);
+    const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi_of<T>(fd, r);
+    const T lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
+    const T L = Mth<T>::sqrt_(lx * lx + ly * ly + lz * lz);
+    const T phi0 = T(fd.phi0);
+    T xc;
+    if (!(E < T(0))) {
+        xc = T(0);
+    } else if (!(E > phi0)) {
+        xc = T(1);
+    } else {
+        // radius of the circular orbit of energy E from the table of
+        // ln r_c(ln zeta), zeta = (E - Phi(0)) / (-E); in FP64 refined by
+        // Newton steps on E_c(r) = Phi(r) + r Phi'(r) / 2 = E
+        const T zeta = (E - phi0) / (-E);
+        const T t = (Mth<T>::log_(zeta) - T(fd.lz0)) * T(fd.ilz);
+        const T tc = fmin(fmax(t, T(0)), T(kLcTable - 2));
+        const int i = (int)tc;
+        const T f = t - T(i);  // extrapolates linearly beyond the table
+        const T* tab = static_cast<const T*>(fd.lctab);
+        T rc = Mth<T>::exp_(tab[i] + f * (tab[i + 1] - tab[i]));
+        if (sizeof(T) == 8) {
+            for (int it = 0; it < 2; ++it) {
+                const T s = accel_of<T>(fd, rc);
+                const T Ec = phi_of<T>(fd, rc) + T(0.5) * s * rc * rc;
+                const T ra = rc + T(fd.a);
+                T dEc = T(0.5) * s * rc + T(fd.GMh) * T(fd.a) / (ra * ra * ra);
+                if (fd.GMn > 0.0) {
+                    const T q1 = T(1) + rc / T(fd.rs);
+                    dEc += T(0.5) * T(fd.GMn) / (T(fd.rs) * T(fd.rs) * q1 * q1);
+                }
+                const T rn = rc - (Ec - E) / dEc;
+                rc = (rn > T(0)) ? rn : T(0.5) * rc;
+            }
+        }
+        const T Lc = rc * rc * Mth<T>::sqrt_(accel_of<T>(fd, rc));  // sqrt(G M(<r) r)
+        xc = (Lc > T(0)) ? L / Lc : T(1);
+    }
+    const T te = fmin((E - T(fd.E_lo)) * T(fd.E_scale), T(fd.n_E));
+    int k = (te >= T(0)) ? (int)te : 0;
+    k = min(k, fd.n_E - 1);
+    const T tx = fmin(xc * T(fd.n_x), T(fd.n_x));
+    int l = (tx >= T(0)) ? (int)tx : 0;
+    l = min(l, fd.n_x - 1);
+    return k * fd.n_x + l;
+}
+
+// ------------------------------------------------------------- accumulate --
+__device__ __forceinline__ void bin_add(float* s, float* c, int j, float v) {
+    const float old = atomicAdd(&s[j], v);
+    const float t = old + v;  // the value the add stored
+    const float bp = t - old;
+    const float e = (old - (t - bp)) + (v - bp);  // exact rounding error (TwoSum)
+    atomicAdd(&c[j], e);
+}
+
+__device__ __forceinline__ void bin_add(double* s, double*, int j, double v) {
+    atomicAdd(&s[j], v);
+}
+
+// ------------------------------------------------------------- vector I/O --
+template <typename T, int PPL>
+struct alignas(sizeof(T) * PPL) Pack {
+    T v[PPL];
+};
+
+template <typename T, int PPL>
+__device__ __forceinline__ void load(const T* __restrict__ p, int64_t i, int cnt, T (&o)[PPL]) {
+    if (cnt == PPL) {
+        const Pack<T, PPL> t = *reinterpret_cast<const Pack<T, PPL>*>(p + i);
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) o[k] = t.v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) o[k] = (k < cnt) ? p[i + k] : T(0);
+    }
+}
+
+template <typename T, int PPL>
+__device__ __forceinline__ void store(T* __restrict__ p, int64_t i, int cnt, const T (&o)[PPL]) {
+    if (cnt == PPL) {
+        Pack<T, PPL> t;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) t.v[k] = o[k];
+        *reinterpret_cast<Pack<T, PPL>*>(p + i) = t;
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k)
+            if (k < cnt) p[i + k] = o[k];
+    }
+}
+
+// ------------------------------------------------------------- step --------
+template <typename T, int BLOCK, int PPL>
+__global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
+                                                const Tile* __restrict__ tiles, int32_t mode) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Tile tl = tiles[blockIdx.x];
+    const FitDev& fd = fits[tl.fit];
+    const FitState* st = fd.st;
+    const bool step = (mode & kModeStep) != 0;
+    if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
+    const bool cells_only = (mode & kModeCells) != 0;
+    const bool correct = step && st->correct != 0;
+    const bool refresh = cells_only || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
+                                        ((st->kstep + 1) % fd.prior_every) == 0);
+    const bool assign = step && st->assign_pending != 0;
+    const bool deposit = !cells_only;
+    const int J = fd.J, C = fd.C;
+
+    Tabs<T> tb = carve<T>(lds_raw, fd);
+    {
+        const T* rp = static_cast<const T*>(fd.rp);
+        for (int j = threadIdx.x; j < J; j += BLOCK) {
+            tb.rp[j] = rp[j];
+            tb.sum[j] = T(0);
+            if (sizeof(T) == 4) tb.comp[j] = T(0);
+        }
+        const T* re2 = static_cast<const T*>(fd.redge2);
+        for (int j = threadIdx.x; j <= fd.n_r; j += BLOCK) tb.re2[j] = re2[j];
+        const T* Re2 = static_cast<const T*>(fd.Redge2);
+        for (int j = threadIdx.x; j <= fd.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
+        const T* ve = static_cast<const T*>(fd.vedge);
+        for (int j = threadIdx.x; j <= fd.n_v; j += BLOCK) tb.ve[j] = ve[j];
+        const T* Vp = static_cast<const T*>(fd.Vp);
+        const T* isp = static_cast<const T*>(fd.isp);
+        for (int j = threadIdx.x; j < fd.n_R; j += BLOCK) {
+            tb.Vp[j] = Vp[j];
+            tb.isp[j] = isp[j];
+        }
+    }
+    // the cell columns of a tile row are zero here: the finalize clears them
+    // after reading them (and the workspace starts cleared)
+    double* row = fd.partials + (size_t)tl.row * (size_t)fd.row_len;
+    __syncthreads();
+
+    T* __restrict__ X = static_cast<T*>(fd.x);
+    T* __restrict__ Y = static_cast<T*>(fd.y);
+    T* __restrict__ Z = static_cast<T*>(fd.z);
+    T* __restrict__ VX = static_cast<T*>(fd.vx);
+    T* __restrict__ VY = static_cast<T*>(fd.vy);
+    T* __restrict__ VZ = static_cast<T*>(fd.vz);
+    T* __restrict__ U = static_cast<T*>(fd.u);
+    T* __restrict__ UH = static_cast<T*>(fd.uh);
+    const T* __restrict__ ucell = static_cast<const T*>(fd.ucell);
+    const T dt = T(fd.dt), hdt = T(0.5 * fd.dt), w0 = T(fd.w0);
+    const T foc_mu = T(fd.foc_mu), foc_cs = T(fd.foc_cs);
+    const bool push = step;
+
+    for (int64_t i0 = tl.begin + (int64_t)threadIdx.x * PPL; i0 < tl.end;
+         i0 += (int64_t)BLOCK * PPL) {
+        const int cnt = (int)min<int64_t>(PPL, tl.end - i0);
+        T px[PPL], py[PPL], pz[PPL], qx[PPL], qy[PPL], qz[PPL], pu[PPL], ph[PPL];
+        load<T, PPL>(X, i0, cnt, px);
+        load<T, PPL>(Y, i0, cnt, py);
+        load<T, PPL>(Z, i0, cnt, pz);
+        load<T, PPL>(VX, i0, cnt, qx);
+        load<T, PPL>(VY, i0, cnt, qy);
+        load<T, PPL>(VZ, i0, cnt, qz);
+        load<T, PPL>(U, i0, cnt, pu);
+        if (correct || assign) load<T, PPL>(UH, i0, cnt, ph);
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            if (k >= cnt) continue;
+            T x = px[k], y = py[k], z = pz[k], vx = qx[k], vy = qy[k], vz = qz[k], u = pu[k];
+            if (assign) ph[k] = ucell[cell_of<T>(fd, x, y, z, vx, vy, vz)];
+            if (correct) {
+                // force of change at z^k with the residuals of step k
+                T chi = T(0);
+                visit<T>(fd, tb, x, y, z, vz, [&](int j, T K) { chi += K * tb.rp[j]; });
+                const T lr = Mth<T>::log_(u * Mth<T>::rcp_(ph[k]));
+                u = u * Mth<T>::exp_(-foc_mu * (lr + foc_cs) - chi);
+            }
+            if (push) {
+                x += hdt * vx;
+                y += hdt * vy;
+                z += hdt * vz;
+                const T s = accel_of<T>(fd, Mth<T>::sqrt_(x * x + y * y + z * z)) * dt;
+                vx -= s * x;
+                vy -= s * y;
+                vz -= s * z;
+                x += hdt * vx;
+                y += hdt * vy;
+                z += hdt * vz;
+            }
+            if (deposit) {
+                const T w = u * w0;
+                visit<T>(fd, tb, x, y, z, vz, [&](int j, T K) { bin_add(tb.sum, tb.comp, j, w * K); });
+            }
+            if (refresh) {
+                const int c = cell_of<T>(fd, x, y, z, vx, vy, vz);
+                unsafeAtomicAdd(&row[J + c], (double)u);
+                unsafeAtomicAdd(&row[J + C + c], 1.0);
+            }
+            px[k] = x;
+            py[k] = y;
+            pz[k] = z;
+            qx[k] = vx;
+            qy[k] = vy;
+            qz[k] = vz;
+            pu[k] = u;
+        }
+        if (push) {
+            store<T, PPL>(X, i0, cnt, px);
+            store<T, PPL>(Y, i0, cnt, py);
+            store<T, PPL>(Z, i0, cnt, pz);
+            store<T, PPL>(VX, i0, cnt, qx);
+            store<T, PPL>(VY, i0, cnt, qy);
+            store<T, PPL>(VZ, i0, cnt, qz);
+            if (correct) store<T, PPL>(U, i0, cnt, pu);
+            if (assign) store<T, PPL>(UH, i0, cnt, ph);
+        }
+    }
+    __syncthreads();
+    if (deposit)
+        for (int j = threadIdx.x; j < J; j += BLOCK)
+            row[j] = (sizeof(T) == 4) ? (double)tb.sum[j] + (double)tb.comp[j] : (double)tb.sum[j];
+}
+
+// ------------------------------------------------------------- finalize ----
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
+                                                         const FinJob* __restrict__ jobs,
+                                                         int32_t mode) {
+    constexpr int kWaves = kFinThreads / 64;
+    __shared__ double part[kWaves][kFinCols];
+    __shared__ double part2[kWaves][kFinCols];
+    __shared__ int last;
+    const FinJob jb = jobs[blockIdx.x];
+    const FitDev& fd = fits[jb.fit];
+    FitState* st = fd.st;
+    const bool step = (mode & kModeStep) != 0;
+    const bool cells_mode = (mode & kModeCells) != 0;
+    const bool observe = (mode & kModeObserve) != 0;
+    const bool init = (mode & kModeInit) != 0;
+    if (step && st->steps_left <= 0) return;
+    const bool correct = step && st->correct != 0;
+    const bool refresh = cells_mode || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
+                                        ((st->kstep + 1) % fd.prior_every) == 0);
+    const bool bins = jb.kind == 0;
+    if (bins && cells_mode) return;
+    if (!bins && !refresh) return;
+    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
+                            (refresh ? (uint32_t)fd.n_cell_jobs : 0u);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = jb.col0 + lane;
+    const int J = fd.J, C = fd.C;
+    const int ncols = bins ? J : C;
+    double acc = 0.0, acc2 = 0.0;
+    if (col < ncols) {
+        double* base = fd.partials + (bins ? col : J + col);
+        const size_t stride = (size_t)fd.row_len;
+        for (int t = wave; t < jb.n_tiles; t += kWaves) {
+            acc += base[(size_t)t * stride];
+            if (!bins) {
+                acc2 += base[(size_t)t * stride + C];
+                // leave the cell columns cleared for the next accumulation
+                base[(size_t)t * stride] = 0.0;
+                base[(size_t)t * stride + C] = 0.0;
+            }
+        }
+    }
+    part[wave][lane] = acc;
+    part2[wave][lane] = acc2;
+    __syncthreads();
+    if (wave == 0) {
+        double tot = 0.0, tot2 = 0.0;
+        for (int w = 0; w < kWaves; ++w) {
+            tot += part[w][lane];
+            tot2 += part2[w][lane];
+        }
+        double d2 = 0.0;
+        if (col < ncols) {
+            if (bins) {
+                if (observe) {
+                    fd.obs_out[col] = tot;
+                } else {
+                    fd.yv[col] = tot;
+                    const double yt = init ? tot : fd.ytil[col] + fd.q * (tot - fd.ytil[col]);
+                    fd.ytil[col] = yt;
+                    const double s = fd.sigma[col];
+                    const double d = (yt - fd.Y[col]) / s;
+                    fd.delta[col] = d;
+                    static_cast<T*>(fd.rp)[col] = (T)(fd.foc_chi * d / s);
+                    d2 = d * d;
+                }
+            } else if (tot2 > 0.0) {
+                static_cast<T*>(fd.ucell)[col] = (T)(tot / tot2);
+            }
+        }
+        if (bins && !observe) {
+            // chi^2 of these columns: fixed-order butterfly over the wave
+            for (int off = 32; off >= 1; off >>= 1) d2 += __shfl_xor(d2, off, 64);
+            if (lane == 0) fd.chi2_part[jb.col0 / kFinCols] = d2;
+        }
+    }
+    if (observe) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&st->ticket, 1u);
+        last = (prev == n_part - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    st->ticket = 0u;
+    if (!cells_mode) {
+        double chi2 = 0.0;
+        for (int b = 0; b < fd.n_bin_jobs; ++b) chi2 += fd.chi2_part[b];
+        st->chi2 = chi2;
+        if (!isfinite(chi2)) st->error |= 1;
+        if (step) fd.chi2_hist[st->tstep % kHistCap] = chi2;
+    }
+    if (step) {
+        st->tstep += 1;
+        st->steps_left -= 1;
+        if (correct) st->kstep += 1;
+        st->assign_pending = refresh ? 1 : 0;
+    }
+    if (cells_mode) st->assign_pending = 1;
+}
+
+// ------------------------------------------------------------- assign ------
+template <typename T>
+__global__ __launch_bounds__(256) void k_assign(const FitDev* __restrict__ fits,
+                                                const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const FitDev& fd = fits[tl.fit];
+    const T* X = static_cast<const T*>(fd.x);
+    const T* Y = static_cast<const T*>(fd.y);
+    const T* Z = static_cast<const T*>(fd.z);
+    const T* VX = static_cast<const T*>(fd.vx);
+    const T* VY = static_cast<const T*>(fd.vy);
+    const T* VZ = static_cast<const T*>(fd.vz);
+    T* UH = static_cast<T*>(fd.uh);
+    const T* ucell = static_cast<const T*>(fd.ucell);
+    for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += 256)
+        UH[i] = ucell[cell_of<T>(fd, X[i], Y[i], Z[i], VX[i], VY[i], VZ[i])];
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // every tile of this launch belongs to one fit; the flag is consumed
+        // by this launch as a whole and only read by later launches
+        fd.st->assign_pending = 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_weights(const T* __restrict__ u, T* __restrict__ w,
+                                                 int64_t n, double scale) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) w[i] = (T)((double)u[i] * scale);
+}
+
+__global__ void k_poke(FitState* st, int32_t steps_left, int32_t correct) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (steps_left >= 0) st->steps_left = steps_left;
+        if (correct >= 0) st->correct = correct;
+    }
+}
+
+__global__ void k_gather(const FitDev* __restrict__ fits, int n, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const FitState* st = fits[i].st;
+        out[2 * i] = st->steps_left;
+        out[2 * i + 1] = st->error;
+    }
+}
+
+// Residuals, force table and chi^2 from the current ytilde (new targets).
+template <typename T>
+__global__ __launch_bounds__(256) void k_residuals(const FitDev* __restrict__ fits) {
+    __shared__ double red[256];
+    const FitDev& fd = fits[0];
+    double d2 = 0.0;
+    for (int j = threadIdx.x; j < fd.J; j += 256) {
+        const double s = fd.sigma[j];
+        const double d = (fd.ytil[j] - fd.Y[j]) / s;
+        fd.delta[j] = d;
+        static_cast<T*>(fd.rp)[j] = (T)(fd.foc_chi * d / s);
+        d2 += d * d;
+    }
+    red[threadIdx.x] = d2;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        fd.st->chi2 = red[0];
+        if (!isfinite(red[0])) fd.st->error |= 1;
+    }
+}
+
+template <typename T, int BLOCK, int PPL>
+hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, int n_tiles, size_t lds,
+                         int32_t mode, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<T, BLOCK, PPL>), dim3(n_tiles), dim3(BLOCK), lds, s, fits, tiles,
+                       mode);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t step_lds_bytes(bool f64, int J, int n_r, int n_R, int n_v) {
+    const size_t sz = f64 ? 8 : 4;
+    const size_t n = (size_t)J * (f64 ? 2 : 3) + (size_t)(n_r + 1) + (size_t)(n_R + 1) +
+                     (size_t)(n_v + 1) + 2 * (size_t)n_R;
+    return ((n * sz + 15) / 16) * 16;
+}
+
+hipError_t launch_step(bool f64, int block, int ppl, const FitDev* fits, const Tile* tiles,
+                       int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (f64) {
+        if (ppl >= 2) return launch_step_t<double, 256, 2>(fits, tiles, n_tiles, lds, mode, s);
+        return launch_step_t<double, 256, 1>(fits, tiles, n_tiles, lds, mode, s);
+    }
+#define M2M_STEP_CASE(B, P) \
+    if (block == B && ppl == P) return launch_step_t<float, B, P>(fits, tiles, n_tiles, lds, mode, s);
+    M2M_STEP_CASE(256, 1)
+    M2M_STEP_CASE(256, 2)
+    M2M_STEP_CASE(256, 4)
+    M2M_STEP_CASE(512, 1)
+    M2M_STEP_CASE(512, 2)
+    M2M_STEP_CASE(512, 4)
+    M2M_STEP_CASE(1024, 1)
+    M2M_STEP_CASE(1024, 2)
+    M2M_STEP_CASE(1024, 4)
+#undef M2M_STEP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
+                           int32_t mode, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_finalize<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
+                           mode);
+    else
+        hipLaunchKernelGGL(k_finalize<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
+                           mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
+                         hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_assign<double>, dim3(n_tiles), dim3(256), 0, s, fits, tiles);
+    else
+        hipLaunchKernelGGL(k_assign<float>, dim3(n_tiles), dim3(256), 0, s, fits, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double scale,
+                          hipStream_t s) {
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_weights<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const double*>(u), static_cast<double*>(w), n, scale);
+    else
+        hipLaunchKernelGGL(k_weights<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const float*>(u), static_cast<float*>(w), n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_poke(FitState* st, int32_t steps_left, int32_t correct, hipStream_t s) {
+    hipLaunchKernelGGL(k_poke, dim3(1), dim3(64), 0, s, st, steps_left, correct);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const FitDev* fits, int n, int32_t* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, fits, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residuals(bool f64, const FitDev* fit, hipStream_t s) {
+    if (f64)
+        hipLaunchKernelGGL(k_residuals<double>, dim3(1), dim3(256), 0, s, fit);
+    else
+        hipLaunchKernelGGL(k_residuals<float>, dim3(1), dim3(256), 0, s, fit);
+    return hipGetLastError();
+}
+
+}  // namespace m2m

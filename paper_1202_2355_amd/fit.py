@@ -1,0 +1,152 @@
+"""One M2M fit on the GPU: device-resident particles behind an ``m2m_ctx``.
+
+PyTorch provides the device memory (the particle arrays are torch tensors the
+fit keeps alive) and the stream; every computation runs in ``libm2m.so``.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+FIELDS = ("x", "y", "z", "vx", "vy", "vz")
+
+
+def _torch_dtype(dtype: str):
+    return {"f32": torch.float32, "f64": torch.float64}[dtype]
+
+
+def _dp(a: np.ndarray | None):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Fit:
+    """Particles (dict of arrays x, y, z, vx, vy, vz), a potential, an
+    observable layout and step parameters (dicts as built by ``workloads``).
+
+    ``u`` and ``u_prior`` default to 1 (equal weights, flat priors)."""
+
+    def __init__(self, potential, layout: dict, params: dict, particles: dict, dtype: str = "f32",
+                 u=None, u_prior=None, device: str = "cuda", stream=None):
+        A.lib()
+        self.dtype = dtype
+        self.layout = dict(layout)
+        self.params = dict(params)
+        tdt = _torch_dtype(dtype)
+        self.n = int(np.asarray(particles["x"]).shape[0])
+        self.t = {}
+        for k in FIELDS:
+            v = particles[k]
+            self.t[k] = (v.to(device=device, dtype=tdt).contiguous().clone() if torch.is_tensor(v)
+                         else torch.as_tensor(np.asarray(v), dtype=tdt, device=device).contiguous())
+        ones = torch.ones(self.n, dtype=tdt, device=device)
+        self.t["u"] = ones.clone() if u is None else torch.as_tensor(np.asarray(u), dtype=tdt, device=device).contiguous().clone()
+        self.t["uh"] = ones.clone() if u_prior is None else torch.as_tensor(np.asarray(u_prior), dtype=tdt, device=device).contiguous().clone()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.J = A.m2m_num_observables(self.layout)
+        self.n_R = self.layout["n_R"] if self.layout["kin"] != "none" else 0
+        ctx = C.c_void_p()
+        ptrs = [C.c_void_p(self.t[k].data_ptr()) for k in (*FIELDS, "u", "uh")]
+        st = A.lib().m2m_create(C.byref(A.potential(potential)), C.byref(A.obs_layout(self.layout)),
+                                C.byref(A.params(self.params)), self.n, A.DTYPE[dtype], *ptrs,
+                                None, 0, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        A.check(st, "m2m_create")
+        self.ctx = ctx
+
+    # ------------------------------------------------------------- calls --
+    def _chk(self, st, where):
+        A.check(st, where, self.ctx)
+
+    def set_targets(self, Y, sigma, V_p=None, sigma_p=None):
+        Y, sigma, V_p, sigma_p = _f64(Y), _f64(sigma), _f64(V_p), _f64(sigma_p)
+        self._chk(A.lib().m2m_set_targets(self.ctx, int(Y.size), _dp(Y), _dp(sigma), _dp(V_p),
+                                          _dp(sigma_p)), "m2m_set_targets")
+
+    def step(self, n_steps: int, correct: bool = True):
+        self._chk(A.lib().m2m_step(self.ctx, int(n_steps), int(bool(correct))), "m2m_step")
+
+    def update_priors(self):
+        self._chk(A.lib().m2m_update_priors(self.ctx), "m2m_update_priors")
+
+    def weights(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float64 if self.dtype == "f64" else np.float32)
+        self._chk(A.lib().m2m_get_weights(self.ctx, out.ctypes.data_as(C.c_void_p), 0),
+                  "m2m_get_weights")
+        return out
+
+    def weights_device(self) -> torch.Tensor:
+        out = torch.empty_like(self.t["u"])
+        self._chk(A.lib().m2m_get_weights(self.ctx, C.c_void_p(out.data_ptr()), 1),
+                  "m2m_get_weights")
+        return out
+
+    def observables(self) -> dict:
+        y, yt, d = np.zeros(self.J), np.zeros(self.J), np.zeros(self.J)
+        c2 = C.c_double()
+        self._chk(A.lib().m2m_get_observables(self.ctx, _dp(y), _dp(yt), _dp(d), C.byref(c2)),
+                  "m2m_get_observables")
+        return dict(y=y, ytilde=yt, delta=d, chi2=c2.value)
+
+    def chi2_history(self, max_n: int = 8192) -> np.ndarray:
+        out = np.zeros(max_n)
+        n = C.c_int32()
+        self._chk(A.lib().m2m_get_chi2_history(self.ctx, _dp(out), int(max_n), C.byref(n)),
+                  "m2m_get_chi2_history")
+        return out[: n.value]
+
+    def observe(self, V_p=None, sigma_p=None) -> np.ndarray:
+        y = np.zeros(self.J)
+        self._chk(A.lib().m2m_observe(self.ctx, _dp(_f64(V_p)), _dp(_f64(sigma_p)), _dp(y)),
+                  "m2m_observe")
+        return y
+
+    def profile_step(self, n_steps: int, correct: bool = True):
+        """Mean per-kernel durations (ms) of n_steps directly launched steps."""
+        a, b = C.c_double(), C.c_double()
+        self._chk(A.lib().m2m_profile_step(self.ctx, int(n_steps), int(bool(correct)), C.byref(a),
+                                           C.byref(b)), "m2m_profile_step")
+        return a.value, b.value
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        self._chk(A.lib().m2m_get_state(self.ctx, None, C.byref(n)), "m2m_get_state")
+        buf = C.create_string_buffer(n.value)
+        self._chk(A.lib().m2m_get_state(self.ctx, buf, C.byref(n)), "m2m_get_state")
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._chk(A.lib().m2m_set_state(self.ctx, buf, len(blob)), "m2m_set_state")
+
+    def particles(self) -> dict:
+        """Host copies (float64) of the particle state, u and u_prior.
+        Pending prior assignments are applied first."""
+        self.weights()  # synchronizes and flushes pending priors
+        return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in self.t.items()}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            A.check(A.lib().m2m_destroy(self.ctx), "m2m_destroy")
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

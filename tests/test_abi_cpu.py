@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every function the header declares;
+host-only entry points answer without a GPU."""
+
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "m2m.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(m2m_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("m2m_create", "m2m_set_targets", "m2m_step", "m2m_update_priors",
+              "m2m_get_weights", "m2m_destroy", "m2m_batch_run"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_1202_2355_amd import _abi
+    lib = _abi.lib()
+    for n in _declared():
+        assert hasattr(lib, n), n
+        assert isinstance(getattr(lib, n), ctypes._CFuncPtr)
+    assert set(_abi.SIGNATURES) == set(_declared())
+
+
+def test_host_only_entry_points():
+    from paper_1202_2355_amd import _abi
+    from workloads import workload
+    wl = workload(3)
+    assert _abi.m2m_num_observables(wl.layout) == 50 + 40 * 64
+    bad = dict(wl.layout, n_r=0)
+    assert _abi.m2m_num_observables(bad) == 0
+    assert _abi.m2m_workspace_bytes(wl.layout, wl.params, wl.N) > 0
+    assert _abi.m2m_workspace_bytes(wl.layout, wl.params, 0) == 0
+    b0 = _abi.m2m_get_launch()
+    with pytest.raises(_abi.M2MError):
+        _abi.m2m_set_launch(300, 4, 4)
+    _abi.m2m_set_launch(512, 2, 2)
+    assert _abi.m2m_get_launch() == (512, 2, 2)
+    _abi.m2m_set_launch(*b0)
+
+
+def test_create_rejects_bad_arguments_without_touching_memory():
+    import ctypes as C
+    from paper_1202_2355_amd import _abi
+    from workloads import workload
+    wl = workload(1)
+    ctx = C.c_void_p()
+    ptrs = [C.c_void_p(0)] * 8   # NULL arrays are rejected before any device call
+    st = _abi.lib().m2m_create(C.byref(_abi.potential(wl.potential)),
+                               C.byref(_abi.obs_layout(wl.layout)), C.byref(_abi.params(wl.params)),
+                               100, 0, *ptrs, None, 0, None, C.byref(ctx))
+    assert st == _abi.M2M_EINVAL and not ctx.value
+    bad = dict(wl.params, dt=-1.0)
+    st = _abi.lib().m2m_create(C.byref(_abi.potential(wl.potential)),
+                               C.byref(_abi.obs_layout(wl.layout)), C.byref(_abi.params(bad)),
+                               100, 0, *([C.c_void_p(4096)] * 8), None, 0, None, C.byref(ctx))
+    assert st == _abi.M2M_EINVAL

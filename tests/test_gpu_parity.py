@@ -1,0 +1,319 @@
+"""GPU parity of the HIP path against the FP64 oracle (run on an MI355X).
+
+Criteria
+* observables of one state: |y_gpu - y_ora| <= rel * sum_i |w_i K_ij|
+  + sum over particles within 4 float32 ulps of an edge of |w_i K_ij|,
+  rel = 1e-5 for FP32 particle state, 1e-12 for FP64;
+* weights after independent runs from the same initial state:
+  ||u_gpu - u_ora|| / ||u_ora|| <= 1e-4 and max_i |u_gpu/u_ora - 1| <= 1e-4 for
+  every particle the oracle never saw within 1e-5 r of an observable or cell
+  edge (FP32); 1e-10 for FP64 state, whose only differences are summation
+  order and last-bit differences of the elementary functions.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from m2m_testlib import (BAND_F32, BAND_F64, assert_observables, cast, oracle_targets,
+                         random_weights, weight_errors)
+from workloads import workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_2355_amd import _abi
+    _abi.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def Fit(gpu):
+    from paper_1202_2355_amd.fit import Fit
+    return Fit
+
+
+def _gh_centres(n_R, seed=3):
+    g = np.random.default_rng(seed)
+    return g.uniform(-0.05, 0.05, n_R), g.uniform(0.25, 0.6, n_R)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("wlid", [1, 2, 3])
+def test_observe_one_state(oracle, Fit, wlid, dtype):
+    wl = workload(wlid)
+    n = 50_003
+    _say("observe", wl.name, dtype, n)
+    parts = cast(wl.initial_particles(n=n, seed=100 + wlid), dtype)
+    u = cast({"u": random_weights(n, 7)}, dtype)["u"]
+    V, S = _gh_centres(wl.layout["n_R"])
+    V, S = cast({"V": V, "S": S}, dtype).values()
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype, u=u)
+    y = f.observe(V, S)
+    band = BAND_F32 if dtype == "f32" else BAND_F64
+    yo, ya, yb = oracle.deposit(parts, u, wl.layout, mass=wl.params["mass"], V_p=V, sigma_p=S,
+                                band=band, nthreads=8, with_abs=True)
+    worst = assert_observables(y, yo, ya, yb, 1e-5 if dtype == "f32" else 1e-12, wl.name)
+    _say("observe", wl.name, dtype, "max |dy|/sum|wK| =", worst)
+    f.close()
+
+
+def _run_pair(oracle, Fit, wl, n, steps, dtype, band, seed=11):
+    T = oracle_targets(oracle, wl)
+    parts = cast(wl.initial_particles(n=n, seed=seed), dtype)
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype)
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, T["Y"], T["sigma"], T["V_p"],
+                         T["sigma_p"], track_flags=True, band=band, nthreads=8)
+    return T, parts, f, o
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_initial_residuals_and_one_step(oracle, Fit, dtype):
+    wl = workload(2)
+    n = 30_001
+    _say("one step", wl.name, dtype, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 1, dtype, 1e-5)
+    ob0 = f.observables()
+    rel = 1e-5 if dtype == "f32" else 1e-12
+    np.testing.assert_allclose(ob0["ytilde"], o.ytilde, rtol=0, atol=1e-4 * np.abs(o.ytilde).max())
+    assert ob0["chi2"] == pytest.approx(o.chi2, rel=1e-3 if dtype == "f32" else 1e-10)
+    f.step(1)
+    o.step(1)
+    st = f.particles()
+    ob1 = f.observables()
+    # per-step observables: the oracle deposits the GPU's own state of step 1
+    band = BAND_F32 if dtype == "f32" else BAND_F64
+    yo, ya, yb = oracle.deposit(st, st["u"], wl.layout, mass=1.0, V_p=T["V_p"],
+                                sigma_p=T["sigma_p"], band=band, nthreads=8, with_abs=True)
+    assert_observables(ob1["y"], yo, ya, yb, rel, "step-1 deposit")
+    r2, rmax, _, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("one step", dtype, "weights rel2", r2, "max", rmax, "flagged", frac)
+    assert r2 <= (1e-6 if dtype == "f32" else 1e-13)
+    assert rmax <= (1e-6 if dtype == "f32" else 1e-12)
+    f.close()
+
+
+def test_run_fp32_matches_oracle_200_steps(oracle, Fit):
+    """Workload 1 with FP32 particle state: weights after 200 steps."""
+    wl = workload(1)
+    n = 20_003
+    _say("run fp32", wl.name, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 200, "f32", 1e-5)
+    f.step(200)
+    hist_o = o.step(200)
+    hist_g = f.chi2_history(200)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("run fp32 200 steps: rel2", r2, "max(unflagged)", rmax, "max(all)", rall, "flagged", frac)
+    assert r2 <= 1e-4
+    assert rmax <= 1e-4
+    np.testing.assert_allclose(hist_g, hist_o, rtol=1e-4)
+    f.close()
+
+
+def test_run_fp64_matches_oracle_200_steps(oracle, Fit):
+    """Workload 1 as specified (FP64 particle state): weights after 200 steps."""
+    wl = workload(1)
+    n = 20_003
+    _say("run fp64", wl.name, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 200, "f64", 1e-12)
+    f.step(200)
+    o.step(200)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("run fp64 200 steps: rel2", r2, "max(unflagged)", rmax, "max(all)", rall, "flagged", frac)
+    assert r2 <= 1e-10
+    assert rmax <= 1e-10
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(st[k], o.arr[k], rtol=0, atol=1e-9)
+    ob = f.observables()
+    np.testing.assert_allclose(ob["ytilde"], o.ytilde, rtol=1e-10, atol=1e-15)
+    assert ob["chi2"] == pytest.approx(o.chi2, rel=1e-9)
+    f.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_prior_refresh_matches_oracle(oracle, Fit, dtype):
+    wl = workload(3)
+    n = 40_001
+    _say("priors", wl.name, dtype, n)
+    parts = cast(wl.initial_particles(n=n, seed=5), dtype)
+    u = cast({"u": random_weights(n, 9, spread=0.5)}, dtype)["u"]
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype, u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    cell, E, xc = oracle.cells(wl.potential, wl.params, parts)
+    P = wl.params
+    band_e = 1e-5 * abs(P["E_lo"]) if dtype == "f32" else 1e-12
+    band_x = 1e-5 if dtype == "f32" else 1e-12
+    dE = (P["E_hi"] - P["E_lo"]) / P["n_E"]
+    te = (E - P["E_lo"]) / dE
+    tx = xc * P["n_x"]
+    amb = (np.abs(te - np.round(te)) * dE <= band_e) | (np.abs(tx - np.round(tx)) <= band_x * P["n_x"])
+    C = P["n_E"] * P["n_x"]
+    sums = np.bincount(cell, weights=u, minlength=C)
+    cnts = np.bincount(cell, minlength=C)
+    uh_o = sums[cell] / cnts[cell]
+    dirty = np.zeros(C, bool)
+    dirty[cell[amb]] = True
+    ok = ~dirty[cell]
+    _say("priors", dtype, "clean fraction", ok.mean())
+    # a cell with one member near an edge is excluded whole; most are clean
+    assert ok.mean() > 0.75
+    np.testing.assert_allclose(uh[ok], uh_o[ok], rtol=1e-6 if dtype == "f32" else 1e-13)
+    f.close()
+
+
+def test_batch_equals_alone(oracle, Fit):
+    from paper_1202_2355_amd.batch import Batch
+    wl = workload(2)
+    T = oracle_targets(oracle, wl)
+    sizes = [9_001, 33_333, 70_007]
+    steps = [40, 25, 40]
+    _say("batch vs alone", sizes, steps)
+    alone = []
+    parts = [cast(wl.initial_particles(n=n, seed=20 + k), "f32") for k, n in enumerate(sizes)]
+    for k, n in enumerate(sizes):
+        f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f32")
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        f.step(steps[k])
+        alone.append((f.particles()["u"], f.observables()))
+        f.close()
+    fits = []
+    b = Batch(max_fits=8)
+    for k, n in enumerate(sizes):
+        f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f32")
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        b.admit(f, steps[k])
+        fits.append(f)
+    done = b.run_to_completion(steps_per_launch=16)
+    assert len(done) == 3
+    for k, f in enumerate(fits):
+        u = f.particles()["u"]
+        ob = f.observables()
+        # same tiles of FP64-reduced, compensated sums: the runs differ only by
+        # the order of atomic adds, i.e. by last-bit roundings of FP32 state
+        np.testing.assert_allclose(u, alone[k][0], rtol=1e-5)
+        yt = alone[k][1]["ytilde"]
+        assert np.abs(ob["ytilde"] - yt).max() <= 1e-6 * np.abs(yt).max()
+        f.close()
+    b.close()
+
+
+def test_checkpoint_resume(oracle, Fit):
+    wl = workload(2)
+    T = oracle_targets(oracle, wl)
+    n = 25_003
+    _say("checkpoint", n)
+    parts = cast(wl.initial_particles(n=n, seed=31), "f32")
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    f.step(30)
+    blob = f.get_state()
+    mid = f.particles()
+    f.step(30)
+    end = f.particles()
+    g = Fit(wl.potential, wl.layout, wl.params, {k: mid[k] for k in ("x", "y", "z", "vx", "vy", "vz")},
+            dtype="f32", u=mid["u"], u_prior=mid["uh"])
+    g.set_state(blob)
+    g.step(30)
+    end2 = g.particles()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(end2[k], end[k], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(end2["u"], end["u"], rtol=1e-5)
+    yt, yt2 = f.observables()["ytilde"], g.observables()["ytilde"]
+    assert np.abs(yt2 - yt).max() <= 1e-6 * np.abs(yt).max()
+    assert g.chi2_history(60).size == 60   # history carried over: 30 + 30 steps
+    f.close()
+    g.close()
+
+
+@pytest.mark.parametrize("n", [4_000_003, 200_001])
+def test_compensated_deposit_is_exact_to_fp64_rounding(oracle, Fit, n):
+    """All particles in one radial bin: the in-tile FP32 sums carry their
+    exact rounding errors (TwoSum on the LDS atomics), so the deposit equals
+    the FP64 sum of the FP32 contributions far below FP32 accuracy."""
+    from workloads import make_layout, make_params, make_potential
+    pot = make_potential()
+    g = np.random.default_rng(4)
+    r = g.uniform(1.0, 2.0, n)
+    parts = {"x": r, "y": np.zeros(n), "z": np.zeros(n), "vx": np.zeros(n), "vy": np.zeros(n),
+             "vz": np.zeros(n)}
+    parts = cast(parts, "f32")
+    u = cast({"u": g.uniform(0.5, 1.5, n)}, "f32")["u"]
+    lay = make_layout(1, 0.5, 4.0)
+    par = make_params(pot)
+    _say("compensated deposit", n)
+    f = Fit(pot, lay, par, parts, dtype="f32", u=u)
+    y = f.observe()[0]
+    # the GPU forms each contribution in FP32 as float(u * float(1/N))
+    w0 = np.float32(1.0 / n)
+    contrib = (u.astype(np.float32) * w0).astype(np.float64)
+    exact = np.sum(np.sort(contrib))
+    plain = np.float32(0)
+    rel = abs(y / exact - 1)
+    _say("compensated deposit rel err", rel, "(one FP32 ulp", 2.0 ** -24, ")")
+    assert rel < 1e-12
+    f.close()
+
+
+def test_invalid_arguments(Fit):
+    from paper_1202_2355_amd._abi import M2M_EINVAL, M2M_ESTATE, M2MError
+    wl = workload(1)
+    parts = wl.initial_particles(n=1000)
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    with pytest.raises(M2MError) as e:
+        f.step(1)
+    assert e.value.status == M2M_ESTATE
+    J = f.J
+    for Y, S in [(np.ones(J), np.zeros(J)), (np.full(J, np.nan), np.ones(J)),
+                 (np.ones(J - 1), np.ones(J - 1))]:
+        with pytest.raises(M2MError) as e:
+            f.set_targets(Y, S)
+        assert e.value.status == M2M_EINVAL
+    f.set_targets(np.ones(J), np.ones(J))
+    f.step(2)
+    assert np.isfinite(f.observables()["chi2"])
+    f.close()
+
+
+@pytest.mark.parametrize("wlid,steps", [(2, 10), (3, 3)])
+def test_full_size_workloads(oracle, Fit, wlid, steps):
+    """Workloads 2 and 3 at their full particle counts, in the launch shape
+    the benchmark uses: observables of the initial state and weights after a
+    few steps against the oracle."""
+    from bench import LAUNCH
+    from paper_1202_2355_amd import _abi
+    wl = workload(wlid)
+    _abi.m2m_set_launch(*LAUNCH[wlid])
+    _say("full size", wl.name, wl.N, "launch", LAUNCH[wlid])
+    T = oracle_targets(oracle, wl)
+    parts = cast(wl.initial_particles(), "f32")
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    y0 = f.observe(T["V_p"], T["sigma_p"])
+    yo, ya, yb = oracle.deposit(parts, np.ones(wl.N), wl.layout, V_p=T["V_p"], sigma_p=T["sigma_p"],
+                                band=BAND_F32, nthreads=16, with_abs=True)
+    assert_observables(y0, yo, ya, yb, 1e-5, wl.name + " initial")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, T["Y"], T["sigma"], T["V_p"],
+                         T["sigma_p"], track_flags=True, band=1e-5, nthreads=16)
+    f.step(steps)
+    o.step(steps)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("full size", wl.name, "rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    assert r2 <= 1e-4 and rmax <= 1e-4
+    f.close()
+    _abi.m2m_set_launch(256, 4, 4)

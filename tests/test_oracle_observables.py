@@ -231,3 +231,18 @@ def test_gh_first_order_relations_h1h2(oracle):
     assert h1 == pytest.approx(-d / (math.sqrt(2) * S), rel=1e-3)
     h2 = _gh_moment(oracle, lay, 2, 0.3, S + d, 0.3, S)
     assert h2 == pytest.approx(-d / (math.sqrt(2) * S), rel=1e-3)
+
+
+def test_ambiguity_covers_both_sides_of_an_edge(oracle):
+    """A point just outside the outer edge has no kernel, but it is within the
+    band of that edge: its weight counts as ambiguous for the last bin. A point
+    on an inner edge is ambiguous for the bins on both sides."""
+    lay = make_layout(4, 1.0, 16.0)          # edges 1, 2, 4, 8, 16
+    for r, inside in ((16.0 * (1 + 1e-9), False), (16.0 * (1 - 1e-9), True), (8.0, True)):
+        p = dict(x=np.array([r]), y=np.zeros(1), z=np.zeros(1), vx=np.zeros(1), vy=np.zeros(1),
+                 vz=np.zeros(1))
+        y, ya, yb = oracle.deposit(p, np.ones(1), lay, band=1e-7, with_abs=True)
+        assert y[3] == (1.0 if inside else 0.0)
+        assert yb[3] == 1.0
+        assert yb[2] == (1.0 if r == 8.0 else 0.0)
+        assert yb[0] == yb[1] == 0.0
