@@ -100,12 +100,108 @@ def cpu_baseline(wl, seconds: float):
                       f"(FP64, OpenMP, targets from a 2^20-particle target realization)"}
 
 
+def run_batch(args, Fit, torch):
+    """Workload 4: 64 fits of uneven size stepping as one batch, against the
+    same fits stepped one launch per fit."""
+    from paper_1202_2355_amd.batch import Batch
+    from workloads import make_targets
+    from workloads.configs import batch_fits
+    from workloads.device import om_model_device
+    fits_wl = batch_fits(args.fits)
+    fits = []
+    t0 = time.perf_counter()
+    for wl in fits_wl:
+        ic = om_model_device(wl.N, wl.potential, float("inf"), seed=wl.seed * 10 + 1)
+        tp = om_model_device(wl.n_target, wl.potential, wl.target_ra, seed=wl.seed * 10 + 2)
+        tf = Fit(wl.potential, wl.layout, wl.params, tp, dtype="f32")
+        T = make_targets(lambda V, S: tf.observe(V, S), wl)
+        tf.close()
+        f = Fit(wl.potential, wl.layout, wl.params, ic, dtype="f32")
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        fits.append(f)
+        del ic, tp
+    ntot = sum(f.n for f in fits)
+    print(f"[bench] batch of {len(fits)} fits, {ntot} particles, inputs in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    b = Batch(max_fits=len(fits))
+    for f in fits:
+        assert b.admit(f, args.warmup + args.steps + 40)
+    b.run(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    b.run(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    assert b.particles() == ntot
+    ms_step, ms_fin = b.profile(20)
+    for f in list(fits):
+        b.cancel(f)
+    # comparator: the same fits, each stepped by its own launches
+    k_alone = max(4, args.steps // 10)
+    ev0.record()
+    for _ in range(k_alone):
+        for f in fits:
+            f.step(1)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_alone = ev0.elapsed_time(ev1) / k_alone
+    b.close()
+    for f in fits:
+        f.close()
+    return {"name": "batch64_gh", "N": ntot, "J": fits_wl[0].J, "ms": ms, "ms_step": ms_step,
+            "ms_fin": ms_fin, "dtype": "f32", "layout": fits_wl[0].layout, "params": fits_wl[0].params,
+            "extra": {"fits": len(fits), "one_launch_per_fit_particle_steps_per_s":
+                      ntot / (ms_alone * 1e-3), "one_launch_per_fit_ms_per_step": ms_alone}}
+
+
+def run_serve(args, torch):
+    """Workload 5: a Poisson trace of fit requests through the continuous-
+    batching server; throughput and p50/p99 latency."""
+    from paper_1202_2355_amd.fit import Fit
+    from paper_1202_2355_amd.serve import Request, Server
+    from workloads import add_noise, workload
+    from workloads.configs import serve_trace
+    from workloads.device import om_model_device, plummer_jeans_device
+    base = workload(3)
+    tp = om_model_device(1 << 22, base.potential, base.target_ra, seed=base.seed * 10 + 2)
+    tf = Fit(base.potential, base.layout, base.params, tp, dtype=args.state)
+    Y_true = tf.observe()
+    tf.close()
+    del tp
+    levels = (0.01, 0.02, 0.05)
+    datasets = []
+    for k, s in enumerate(levels):
+        Y, sig = add_noise(Y_true, base.layout, s, np.random.Generator(np.random.Philox(key=50 + k)))
+        datasets.append({"Y": Y, "sigma": sig})
+    arrival, wls = serve_trace(n_requests=args.requests, state=args.state)
+    reqs = [Request(rid=k, arrival=float(arrival[k]), potential=w.potential, params=w.params,
+                    layout=w.layout, n=w.N, steps=w.steps, dataset=levels.index(w.noise),
+                    seed=w.seed) for k, w in enumerate(wls)]
+    tdt = torch.float32 if args.state == "f32" else torch.float64
+    model = lambda r: plummer_jeans_device(r.n, r.potential, r.seed, dtype=tdt)
+    srv = Server(datasets, hbm_budget=int(args.hbm_gb * 2 ** 30), max_fits=64,
+                 steps_per_launch=args.steps_per_launch, dtype=args.state, initial_model=model)
+    # warm-up request (first graph capture, first allocations), not counted
+    srv.run([Request(rid=-1, arrival=0.0, potential=base.potential, params=base.params,
+                     layout=base.layout, n=100_000, steps=64, dataset=0, seed=1)])
+    m = srv.run(reqs, realtime=True, log=sys.stderr)
+    srv.close()
+    return m
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--fits", type=int, default=64, help="workload 4: number of fits")
+    ap.add_argument("--requests", type=int, default=500, help="workload 5: trace length")
+    ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
+    ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
+    ap.add_argument("--steps-per-launch", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
@@ -119,9 +215,43 @@ def main(argv=None):
     from paper_1202_2355_amd.fit import Fit
     from workloads import workload
 
+    _abi.m2m_set_launch(*LAUNCH[args.workload])
+    if args.workload == 5:
+        m = run_serve(args, torch)
+        out = {"metric": "particle-steps/sec (push+deposit+weight update) at 1 GPU; "
+                         "p50/p99 fit latency",
+               "value": m["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
+               "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": args.state, "data": "synthetic",
+               "config": {"workload": "serve_losvd", "requests": m["requests"],
+                          "arrival_rate_per_s": 20.0, "hbm_budget_gb": args.hbm_gb,
+                          "steps_per_launch": args.steps_per_launch,
+                          "launch": list(LAUNCH[5])},
+               "latency": {"p50_s": m["p50_latency_s"], "p99_s": m["p99_latency_s"],
+                           "mean_s": m["mean_latency_s"]},
+               "roofline": None, "cpu_baseline": None}
+        print(json.dumps(out), flush=True)
+        return 0
+    if args.workload == 4:
+        r = run_batch(args, Fit, torch)
+        bpp = BYTES_PER_PSTEP["f32"]
+        achieved = bpp * r["N"] / (r["ms_step"] * 1e-3) / 1e9
+        out = {"metric": "particle-steps/sec (push+deposit+weight update) at 1 GPU",
+               "value": r["N"] * args.steps / (r["ms"] * 1e-3), "unit": "particle-steps/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": r["ms"] / args.steps, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": r["name"], "particles": r["N"], "observables": r["J"],
+                          "launch": list(LAUNCH[4]), **r["extra"]},
+               "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": None, "kernel_ms": r["ms_step"],
+                            "finalize_ms": r["ms_fin"], "bytes_per_particle_step": bpp},
+               "cpu_baseline": None}
+        print(json.dumps(out), flush=True)
+        return 0
     wl = workload(args.workload)
     dtype = wl.state
-    _abi.m2m_set_launch(*LAUNCH[args.workload])
     print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={LAUNCH[args.workload]}",
           file=sys.stderr, flush=True)
     fit = make_fit_and_targets(wl, Fit, dtype)

@@ -232,6 +232,12 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
  * *n_active (may be NULL) the number still running. */
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
                           int32_t* n_active);
+/* Like m2m_profile_step for the batch: steps_per_launch steps with the two
+ * kernels of each step launched directly and timed by HIP events on the
+ * batch stream; mean durations in milliseconds. Synchronizes. */
+m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize);
+/* Particles of the admitted fits that still have steps left. Synchronizes. */
+int64_t m2m_batch_particles(m2m_batch* b);
 /* Bytes of budget in use. */
 size_t m2m_batch_footprint(const m2m_batch* b);
 /* Remove a fit before it finished (cancellation); synchronizes. */

@@ -1,0 +1,103 @@
+"""Launch-shape search for the fused step kernel.
+
+The shape is (threads per block, particles per lane, tiles per compute
+unit): the tile count sets how many blocks stream the particles (and how
+many partial rows the finalize reduces), the block size and particles per
+lane set the waves per CU and the memory-level parallelism of each wave. The
+search times whole M2M steps (step + finalize kernels, graph replays) on
+fresh copies of the same particles and keeps the fastest shape.
+"""
+
+from __future__ import annotations
+
+import itertools
+import json
+import sys
+import time
+
+import torch
+
+from . import _abi as A
+from .fit import Fit
+
+BLOCKS = (256, 512, 1024)
+PPLS = (1, 2, 4)
+TILES_PER_CU = (1, 2, 4, 8)
+
+
+def time_shape(make_fit, shape, steps=40, warmup=16):
+    A.m2m_set_launch(*shape)
+    fit = make_fit()
+    fit.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fit.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fit.close()
+    return ms
+
+
+def search(make_fit, blocks=BLOCKS, ppls=PPLS, tiles=TILES_PER_CU, steps=40, log=sys.stderr,
+           dtype="f32"):
+    """Time every shape; returns (best shape, {shape: ms per step})."""
+    before = A.m2m_get_launch()
+    res = {}
+    try:
+        for b, p, t in itertools.product(blocks, ppls, tiles):
+            if dtype == "f64" and (b != 256 or p > 2):
+                continue
+            ms = time_shape(make_fit, (b, p, t), steps=steps)
+            res[(b, p, t)] = ms
+            if log:
+                print(f"[autotune] block={b} ppl={p} tiles/cu={t}: {1e3 * ms:.2f} us/step",
+                      file=log, flush=True)
+    finally:
+        A.m2m_set_launch(*before)
+    best = min(res, key=res.get)
+    return best, res
+
+
+def main(argv=None):
+    import argparse
+    import os
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    from workloads import make_targets, workload
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    wl = workload(args.workload)
+    t0 = time.time()
+    tp = wl.target_particles(n=1 << 20)
+    tf = Fit(wl.potential, wl.layout, wl.params, tp, dtype=wl.state)
+    T = make_targets(lambda V, S: tf.observe(V, S), wl)
+    tf.close()
+    ic = wl.initial_particles()
+    dev = {k: torch.as_tensor(v, dtype=torch.float32 if wl.state == "f32" else torch.float64,
+                              device="cuda") for k, v in ic.items()}
+    print(f"[autotune] {wl.name}: inputs ready in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+
+    def make_fit():
+        f = Fit(wl.potential, wl.layout, wl.params, dev, dtype=wl.state)
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        return f
+
+    best, res = search(make_fit, steps=args.steps, dtype=wl.state)
+    out = {"workload": wl.name, "best": list(best), "us_per_step": 1e3 * res[best],
+           "all": {f"{b},{p},{t}": 1e3 * ms for (b, p, t), ms in res.items()}}
+    print(json.dumps(out))
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,6 +51,17 @@ class Batch:
         A.check(A.lib().m2m_batch_cancel(self.h, fit.ctx), "m2m_batch_cancel")
         self.by_ctx.pop(fit.ctx.value, None)
 
+    def profile(self, n_steps: int):
+        """Mean per-kernel durations (ms) of n_steps directly launched steps."""
+        a, b = C.c_double(), C.c_double()
+        A.check(A.lib().m2m_batch_profile(self.h, int(n_steps), C.byref(a), C.byref(b)),
+                "m2m_batch_profile")
+        return a.value, b.value
+
+    def particles(self) -> int:
+        """Particles of the fits that still have steps left."""
+        return int(A.lib().m2m_batch_particles(self.h))
+
     @property
     def footprint(self) -> int:
         return int(A.lib().m2m_batch_footprint(self.h))

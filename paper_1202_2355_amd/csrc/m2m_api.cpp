@@ -1104,6 +1104,61 @@ m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_
     return bad ? M2M_ENONFINITE : M2M_OK;
 }
 
+m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize) {
+    if (!b || n_steps < 1) return M2M_EINVAL;
+    if (b->dirty) {
+        m2m_status s = rebuild(b);
+        if (s != M2M_OK) return s;
+    }
+    if (b->fits.empty()) return M2M_ESTATE;
+    const bool f64 = b->f64 == 1;
+    std::vector<hipEvent_t> ev(3 * (size_t)n_steps, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        e = hipEventRecord(ev[3 * k], b->stream);
+        if (e == hipSuccess)
+            e = launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+                            kModeStep, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], b->stream);
+        if (e == hipSuccess)
+            e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    double t1 = 0.0, t2 = 0.0;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        float a = 0.f, c = 0.f;
+        e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[3 * k + 1], ev[3 * k + 2]);
+        t1 += a;
+        t2 += c;
+    }
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return M2M_EDEVICE;
+    if (ms_step) *ms_step = t1 / n_steps;
+    if (ms_finalize) *ms_finalize = t2 / n_steps;
+    return M2M_OK;
+}
+
+int64_t m2m_batch_particles(m2m_batch* b) {
+    if (!b) return 0;
+    const int nf = (int)b->fits.size();
+    if (nf == 0) return 0;
+    if (b->dirty && rebuild(b) != M2M_OK) return -1;
+    if (launch_gather(b->fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->gather_host, b->gather_dev, sizeof(int32_t) * 2 * nf,
+                       hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return -1;
+    int64_t n = 0;
+    for (int f = 0; f < nf; ++f)
+        if (b->gather_host[2 * f] > 0) n += b->fits[f]->n;
+    return n;
+}
+
 m2m_status m2m_batch_cancel(m2m_batch* b, m2m_ctx* c) {
     if (!b || !c || c->batch != b) return M2M_EINVAL;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;

@@ -43,7 +43,7 @@ class Fit:
         self.layout = dict(layout)
         self.params = dict(params)
         tdt = _torch_dtype(dtype)
-        self.n = int(np.asarray(particles["x"]).shape[0])
+        self.n = int(particles["x"].shape[0]) if hasattr(particles["x"], "shape") else len(particles["x"])
         self.t = {}
         for k in FIELDS:
             v = particles[k]

@@ -1,0 +1,141 @@
+"""Continuous-batching server of M2M fit requests.
+
+A request is a target data set plus a potential (the mass-to-light and halo
+scans of the paper's applications, Sec. 6): the server draws the request's
+initial particle model on the device, keeps its particles and weights
+resident, and admits it into the running batch as soon as a slot and the
+HBM budget allow (footprint: particle state plus the library workspace).
+Every loop iteration enqueues a few batched steps, then retires the fits
+that finished and copies their weights to the host. Latency is measured from
+a request's arrival to its weights being on the host.
+"""
+
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .batch import Batch
+from .fit import Fit
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the trace
+    potential: object       # workloads.Potential
+    params: dict
+    layout: dict
+    n: int
+    steps: int
+    dataset: int            # index into the server's target data sets
+    seed: int
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    weights: np.ndarray | None = field(default=None, repr=False)
+
+
+def footprint_bytes(req: Request, dtype: str) -> int:
+    sz = 8 if dtype == "f64" else 4
+    return req.n * 8 * sz + A.m2m_workspace_bytes(req.layout, req.params, req.n, dtype)
+
+
+class Server:
+    def __init__(self, datasets, hbm_budget: int, max_fits: int = 64, steps_per_launch: int = 32,
+                 dtype: str = "f32", keep_weights: bool = False, initial_model=None):
+        """datasets: list of dicts with Y and sigma (and V_p, sigma_p for
+        Gauss-Hermite layouts). initial_model(req) -> dict of device tensors."""
+        self.datasets = datasets
+        self.budget = int(hbm_budget)
+        self.max_fits = max_fits
+        self.spl = steps_per_launch
+        self.dtype = dtype
+        self.keep = keep_weights
+        self.initial_model = initial_model
+        self.stream = torch.cuda.current_stream()
+        self.batch = Batch(max_fits=max_fits, hbm_budget=self.budget, stream=self.stream)
+        self.live = {}
+
+    def _admit(self, req: Request, now: float) -> bool:
+        if self.batch.active >= self.max_fits:
+            return False
+        if self.batch.footprint + footprint_bytes(req, self.dtype) > self.budget:
+            return False
+        parts = self.initial_model(req)
+        fit = Fit(req.potential, req.layout, req.params, parts, dtype=self.dtype, stream=self.stream)
+        del parts
+        d = self.datasets[req.dataset]
+        fit.set_targets(d["Y"], d["sigma"], d.get("V_p"), d.get("sigma_p"))
+        if not self.batch.admit(fit, req.steps):
+            fit.close()
+            return False
+        req.t_admit = now
+        self.live[id(fit)] = (fit, req)
+        return True
+
+    def run(self, requests, realtime: bool = True, log=None):
+        """Serve ``requests`` (sorted by arrival). Returns the metrics dict."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = deque()
+        done = []
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        sim_now = 0.0
+        while pending or waiting or self.batch.active:
+            now = clock() if realtime else sim_now
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            while waiting and self._admit(waiting[0], now):
+                waiting.popleft()
+            if self.batch.active:
+                self.batch.run(self.spl)
+                fin, _ = self.batch.poll()
+                t = clock() if realtime else now
+                for fit in fin:
+                    _, req = self.live.pop(id(fit))
+                    w = fit.weights()
+                    req.t_done = clock() if realtime else t
+                    if self.keep:
+                        req.weights = w
+                    fit.close()
+                    done.append(req)
+                if log and fin:
+                    print(f"[serve] t={now:.3f}s done={len(done)} active={self.batch.active} "
+                          f"waiting={len(waiting)}", file=log, flush=True)
+            elif pending:
+                if realtime:
+                    time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
+                else:
+                    sim_now = pending[0].arrival
+            if not realtime:
+                sim_now = max(sim_now, now)
+        makespan = (clock() if realtime else sim_now)
+        lat = np.array([r.t_done - r.arrival for r in done])
+        work = float(sum(r.n * r.steps for r in done))
+        first = min(r.arrival for r in done) if done else 0.0
+        last = max(r.t_done for r in done) if done else 0.0
+        return {
+            "requests": len(done),
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_latency_s": float(lat.mean()) if len(lat) else None,
+            "particle_steps": work,
+            "particle_steps_per_s": work / max(last - first, 1e-9),
+            "makespan_s": makespan,
+            "done": done,
+        }
+
+    def close(self):
+        for fit, _ in list(self.live.values()):
+            try:
+                self.batch.cancel(fit)
+            except Exception:
+                pass
+            fit.close()
+        self.live.clear()
+        self.batch.close()
