@@ -202,6 +202,8 @@ def main(argv=None):
     ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
     ap.add_argument("--steps-per-launch", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB float32 device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
@@ -269,6 +271,13 @@ def main(argv=None):
     print(f"[bench] timed {args.steps} steps: {ms:.3f} ms (wall {1e3 * t_wall:.3f} ms), "
           f"chi2/J {ob['chi2'] / wl.J:.4f}", file=sys.stderr, flush=True)
     ms_step, ms_fin = fit.profile_step(50)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     bpp = BYTES_PER_PSTEP[dtype]
     achieved = bpp * wl.N / (ms_step * 1e-3) / 1e9
     tb = measured_traffic(wl.name, wl.N)

@@ -210,6 +210,17 @@ const char* m2m_last_error(const m2m_ctx* ctx);
 m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu);
 m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu);
 
+/* In-tile accumulation of the deposits (eq. obs) for FP32 particle state,
+ * for contexts and batches created afterwards: M2M_DEPOSIT_F64 (default)
+ * adds each w_i K_j(z_i), formed in FP32, into FP64 bins in LDS;
+ * M2M_DEPOSIT_F32_COMPENSATED adds it into FP32 bins and carries the exact
+ * rounding error of every add (TwoSum) in a second FP32 array. Tile sums are
+ * reduced across tiles in FP64 in a fixed order either way. FP64 particle
+ * state always uses FP64 bins. EINVAL for an unknown mode. */
+typedef enum { M2M_DEPOSIT_F64 = 0, M2M_DEPOSIT_F32_COMPENSATED = 1 } m2m_deposit_mode;
+m2m_status m2m_set_deposit_mode(int32_t mode);
+int32_t m2m_get_deposit_mode(void);
+
 /* ---------------------------------------------------------- batching --
  * Many fits of uneven size stepping together: every step runs one fused
  * kernel over the tiles of all active fits (tiles never straddle fits) and

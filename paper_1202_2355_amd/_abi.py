@@ -75,6 +75,8 @@ SIGNATURES = {
     "m2m_last_error": (C.c_char_p, [_vp]),
     "m2m_set_launch": (_st, [_i32, _i32, _i32]),
     "m2m_get_launch": (_st, [C.POINTER(_i32)] * 3),
+    "m2m_set_deposit_mode": (_st, [_i32]),
+    "m2m_get_deposit_mode": (_i32, []),
     "m2m_batch_create": (_st, [_i32, C.c_size_t, _vp, C.POINTER(_vp)]),
     "m2m_batch_admit": (_st, [_vp, _vp, _i32]),
     "m2m_batch_run": (_st, [_vp, _i32]),
@@ -148,6 +150,19 @@ def m2m_workspace_bytes(layout: dict, par: dict, n: int, dtype: str = "f32") -> 
 
 def m2m_set_launch(block: int, ppl: int, tiles_per_cu: int):
     check(lib().m2m_set_launch(int(block), int(ppl), int(tiles_per_cu)), "m2m_set_launch")
+
+
+M2M_DEPOSIT_F64, M2M_DEPOSIT_F32_COMPENSATED = 0, 1
+DEPOSIT = {"f64": M2M_DEPOSIT_F64, "f32c": M2M_DEPOSIT_F32_COMPENSATED}
+
+
+def m2m_set_deposit_mode(mode):
+    mode = DEPOSIT[mode] if isinstance(mode, str) else int(mode)
+    check(lib().m2m_set_deposit_mode(mode), "m2m_set_deposit_mode")
+
+
+def m2m_get_deposit_mode() -> int:
+    return int(lib().m2m_get_deposit_mode())
 
 
 def m2m_get_launch():

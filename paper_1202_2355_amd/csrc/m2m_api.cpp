@@ -23,6 +23,7 @@ constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
 
 // launch shape for contexts and batches created from now on
 int g_block = 256, g_ppl = 4, g_tiles_per_cu = 4;
+int g_deposit = M2M_DEPOSIT_F64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -248,6 +249,7 @@ struct m2m_ctx {
     int n_jobs = 0;
     size_t lds = 0;
     int block = 256, ppl = 4;
+    bool acc64 = true;
     bool targets = false;
     bool ytil_init = false;
     std::vector<double> Vp, sp;  // current Gauss-Hermite centres (host)
@@ -346,7 +348,7 @@ m2m_status check_error(m2m_ctx* c) {
 
 m2m_status run_direct(m2m_ctx* c, int steps) {
     for (int k = 0; k < steps; ++k) {
-        M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                                kModeStep, c->stream));
         M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream));
     }
@@ -359,7 +361,7 @@ m2m_status ensure_graph(m2m_ctx* c) {
     M2M_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        e = launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                         kModeStep, c->cap);
         if (e == hipSuccess)
             e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->cap);
@@ -406,6 +408,14 @@ m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu) {
     return M2M_OK;
 }
 
+m2m_status m2m_set_deposit_mode(int32_t mode) {
+    if (mode != M2M_DEPOSIT_F64 && mode != M2M_DEPOSIT_F32_COMPENSATED) return M2M_EINVAL;
+    g_deposit = mode;
+    return M2M_OK;
+}
+
+int32_t m2m_get_deposit_mode(void) { return g_deposit; }
+
 m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu) {
     if (block) *block = g_block;
     if (ppl) *ppl = g_ppl;
@@ -445,9 +455,11 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->ppl = c->f64 ? std::min(g_ppl, 2) : g_ppl;
     c->w = plan(c->lay, c->par, n, c->f64);
     const WsLayout& w = c->w;
-    c->lds = step_lds_bytes(c->f64, w.J, c->lay.n_r,
+    const int kpriv = private_copies(c->f64, w.J);
+    c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
+    c->lds = step_lds_bytes(c->f64, c->acc64, w.J, c->lay.n_r,
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
-                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0);
+                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv);
     if (c->lds > max_lds()) {
         delete c;
         return M2M_EUNSUPPORTED;
@@ -520,6 +532,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.obs_out = reinterpret_cast<double*>(b + w.obs);
     f.partials = reinterpret_cast<double*>(b + w.partials);
     f.row_len = w.row_len;
+    f.kpriv = kpriv;
     f.n_bin_jobs = w.nbj;
     f.n_cell_jobs = w.ncj;
     f.entropy = c->par.entropy;
@@ -622,7 +635,7 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     if (!c->ytil_init) {
-        M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                                kModeInit, c->stream));
         M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeInit, c->stream));
         c->ytil_init = true;
@@ -653,7 +666,7 @@ m2m_status m2m_update_priors(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
-    M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeCells, c->stream));
     M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeCells, c->stream));
     M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
@@ -731,7 +744,7 @@ m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, dou
                 return fail(c, M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
         if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     }
-    M2M_HIP(c, launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeObserve, c->stream));
     M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream));
     if ((s = sync(c)) != M2M_OK) return s;
@@ -850,7 +863,7 @@ m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double
     for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
         e = hipEventRecord(ev[3 * k], c->stream);
         if (e == hipSuccess)
-            e = launch_step(c->f64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+            e = launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                             kModeStep, c->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], c->stream);
         if (e == hipSuccess)
@@ -904,6 +917,7 @@ struct m2m_batch {
     int n_tiles = 0, n_jobs = 0;
     size_t lds = 0;
     int block = 256, ppl = 4;
+    bool acc64 = true;
     hipGraphExec_t graph = nullptr;
 };
 
@@ -938,6 +952,7 @@ m2m_status rebuild(m2m_batch* b) {
     const bool f64 = b->f64 == 1;
     b->block = f64 ? 256 : g_block;
     b->ppl = f64 ? std::min(g_ppl, 2) : g_ppl;
+    b->acc64 = f64 || g_deposit == M2M_DEPOSIT_F64;
     std::vector<FitDev> fd;
     std::vector<Tile> tl;
     std::vector<FinJob> jb;
@@ -970,7 +985,7 @@ m2m_status rebuild(m2m_batch* b) {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return M2M_EDEVICE;
     for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+        e = launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
                         kModeStep, b->cap);
         if (e == hipSuccess)
             e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->cap);
@@ -1055,7 +1070,7 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
     for (int k = 0; k < full; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
     for (int k = 0; k < rem; ++k) {
-        if (launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+        if (launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
                         kModeStep, b->stream) != hipSuccess ||
             launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
             return M2M_EDEVICE;
@@ -1119,7 +1134,7 @@ m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, dou
     for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
         e = hipEventRecord(ev[3 * k], b->stream);
         if (e == hipSuccess)
-            e = launch_step(f64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
+            e = launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
                             kModeStep, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], b->stream);
         if (e == hipSuccess)

@@ -56,6 +56,8 @@ struct FitDev {
     double *Y, *sigma, *yv, *ytil, *delta, *obs_out;
     double *partials;        // tile rows of row_len doubles
     int32_t row_len;         // J + 2 C
+    int32_t kpriv;           // private copies of the in-tile bins (power of 2)
+    int32_t pad2;
     int32_t n_bin_jobs;      // ceil(J / kFinCols)
     int32_t n_cell_jobs;     // ceil(C / kFinCols)
     int32_t entropy;
@@ -87,8 +89,9 @@ struct FinJob {
 };
 
 // ---- launchers (m2m_kernels.hip) ------------------------------------------
-hipError_t launch_step(bool f64, int block, int ppl, const FitDev* fits, const Tile* tiles,
-                       int n_tiles, size_t lds_bytes, int32_t mode, hipStream_t s);
+hipError_t launch_step(bool f64, bool acc64, int block, int ppl, const FitDev* fits,
+                       const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
+                       hipStream_t s);
 hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
                            int32_t mode, hipStream_t s);
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
@@ -98,6 +101,7 @@ hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double sc
 hipError_t launch_poke(FitState* st, int32_t steps_left, int32_t correct, hipStream_t s);
 hipError_t launch_gather(const FitDev* fits, int n, int32_t* out, hipStream_t s);
 hipError_t launch_residuals(bool f64, const FitDev* fit, hipStream_t s);
-size_t step_lds_bytes(bool f64, int J, int n_r, int n_R, int n_v);
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv);
+int private_copies(bool f64, int J);
 
 }  // namespace m2m

@@ -69,41 +69,106 @@ __constant__ double kGhB[kMaxGH] = {0.0,
                                    0.93541434669348535};  // sqrt(7/8)
 
 // ------------------------------------------------------------- LDS ---------
-template <typename T>
+// In-tile bins: FP64 sums (A = double), or FP32 sums with an FP32 array of
+// their compensation (A = float). They are kept in kpriv private copies,
+// interleaved (copy g of bin j at j * kpriv + g); lane l adds into copy
+// l mod kpriv. The FP64 arrays come first so that they are 8-byte aligned.
+template <typename T, typename A>
 struct Tabs {
-    T *rp, *sum, *comp, *re2, *Re2, *ve, *Vp, *isp;
+    A *sum, *comp;
+    T *rp, *re2, *Re2, *ve, *Vp, *isp;
 };
 
-template <typename T>
-__device__ __forceinline__ Tabs<T> carve(unsigned char* raw, const FitDev& fd) {
-    constexpr bool kComp = sizeof(T) == 4;
-    T* p = reinterpret_cast<T*>(raw);
-    Tabs<T> t;
+template <typename T, typename A>
+__device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, int n_r, int n_R,
+                                            int n_v) {
+    Tabs<T, A> t;
+    A* q = reinterpret_cast<A*>(raw);
+    t.sum = q;
+    q += J * kp;
+    t.comp = q;
+    if (sizeof(A) == 4) q += J * kp;
+    T* p = reinterpret_cast<T*>(q);
     t.rp = p;
-    p += fd.J;
-    t.sum = p;
-    p += fd.J;
-    t.comp = p;
-    if (kComp) p += fd.J;
+    p += J;
     t.re2 = p;
-    p += fd.n_r + 1;
+    p += n_r + 1;
     t.Re2 = p;
-    p += fd.n_R + 1;
+    p += n_R + 1;
     t.ve = p;
-    p += fd.n_v + 1;
+    p += n_v + 1;
     t.Vp = p;
-    p += fd.n_R;
+    p += n_R;
     t.isp = p;
     return t;
 }
 
+// ------------------------------------------------------------- per tile ----
+// What the particle loop reads of its fit, loaded once per tile (uniform
+// values, held in scalar registers) instead of from the fit table in the loop.
+template <typename T>
+struct Hot {
+    int n_r, n_R, kin, nk, gh_nmax, n_v, J, C, kp, n_E, n_x;
+    T lr0, lrs, lR0, lRs, vmin, vidv;
+    T r2lo, r2hi, R2lo, R2hi, vlo, vhi;  // range ends: squared radii, velocities
+    T GMh, a, GMn, rs, phi0;
+    T dt, hdt, w0, foc_mu, foc_cs;
+    T E_lo, E_scale, lz0, ilz;
+    const T* lctab;
+};
+
+template <typename T>
+__device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
+    Hot<T> h;
+    h.n_r = fd.n_r;
+    h.n_R = fd.n_R;
+    h.kin = fd.kin;
+    h.nk = fd.nk;
+    h.gh_nmax = fd.gh_nmax;
+    h.n_v = fd.n_v;
+    h.J = fd.J;
+    h.C = fd.C;
+    h.kp = fd.kpriv;
+    h.n_E = fd.n_E;
+    h.n_x = fd.n_x;
+    h.lr0 = T(fd.lr0);
+    h.lrs = T(fd.lrs);
+    h.lR0 = T(fd.lR0);
+    h.lRs = T(fd.lRs);
+    h.vmin = T(fd.vmin);
+    h.vidv = T(fd.vidv);
+    const T* re2 = static_cast<const T*>(fd.redge2);
+    const T* Re2 = static_cast<const T*>(fd.Redge2);
+    const T* ve = static_cast<const T*>(fd.vedge);
+    h.r2lo = re2[0];
+    h.r2hi = re2[fd.n_r];
+    h.R2lo = Re2[0];
+    h.R2hi = Re2[fd.n_R];
+    h.vlo = ve[0];
+    h.vhi = ve[fd.n_v];
+    h.GMh = T(fd.GMh);
+    h.a = T(fd.a);
+    h.GMn = T(fd.GMn);
+    h.rs = T(fd.rs);
+    h.phi0 = T(fd.phi0);
+    h.dt = T(fd.dt);
+    h.hdt = T(0.5 * fd.dt);
+    h.w0 = T(fd.w0);
+    h.foc_mu = T(fd.foc_mu);
+    h.foc_cs = T(fd.foc_cs);
+    h.E_lo = T(fd.E_lo);
+    h.E_scale = T(fd.E_scale);
+    h.lz0 = T(fd.lz0);
+    h.ilz = T(fd.ilz);
+    h.lctab = static_cast<const T*>(fd.lctab);
+    return h;
+}
+
 // ------------------------------------------------------------- binning -----
-// k with e[k] <= v < e[k+1] for ascending e[0..n], or -1 outside [e[0], e[n]).
-// The arithmetic guess g is refined against the stored edges, so the bin is
-// decided by the same edge values everywhere.
+// k with e[k] <= v < e[k+1] for ascending e[0..n], or -1 outside [e[0], e[n]),
+// decided by comparison with the stored edges.
 template <typename T>
 __device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
-    if (!(v >= e[0]) || !(v < e[n])) return -1;
     g = fmin(fmax(g, T(0)), T(n - 1));
     int k = (int)g;
     if (v < e[k]) {
@@ -124,58 +189,94 @@ __device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
     return k;
 }
 
-// Visit the non-zero kernels K_j of one phase-space point: f(j, K_j).
-template <typename T, typename F>
-__device__ __forceinline__ void visit(const FitDev& fd, const Tabs<T>& tb, T x, T y, T z, T vz,
-                                      F&& f) {
+// The arithmetic position g of v in bin units is accurate to a few 1e-6, so a
+// point more than 1e-4 of a bin from both edges is in bin floor(g); only
+// points closer to an edge are compared with the stored edges.
+template <typename T>
+__device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
+    if (!(v >= lo) || !(v < hi)) return -1;
+    const T gc = fmin(fmax(g, T(0)), T(n));
+    const int k = min((int)gc, n - 1);
+    const T fr = g - T(k);
+    if (fr > T(1e-4) && fr < T(1) - T(1e-4)) return k;
+    return refine_bin<T>(v, e, n, g);
+}
+
+// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1)
+// and kn kinematic entries j = jk + m with values k[m].
+template <typename T>
+struct Kern {
+    int jr, jk, kn;
+    T k[kMaxGH];
+};
+
+template <typename T, typename A>
+__device__ __forceinline__ Kern<T> kernels(const Hot<T>& h, const Tabs<T, A>& tb, T x, T y, T z,
+                                           T vz) {
+    Kern<T> o;
     const T R2 = x * x + y * y;
     const T r2 = R2 + z * z;
-    const int kr = refine_bin<T>(r2, tb.re2, fd.n_r, (Mth<T>::log2_(r2) - T(fd.lr0)) * T(fd.lrs));
-    if (kr >= 0) f(kr, T(1));
-    if (fd.kin == 0) return;
-    const int p = refine_bin<T>(R2, tb.Re2, fd.n_R, (Mth<T>::log2_(R2) - T(fd.lR0)) * T(fd.lRs));
-    if (p < 0) return;
-    const int base = fd.n_r + p * fd.nk;
-    if (fd.kin == 1) {
-        f(base, vz * vz);
-    } else if (fd.kin == 2) {
+    o.jr = bin_of<T>(r2, tb.re2, h.n_r, (Mth<T>::log2_(r2) - h.lr0) * h.lrs, h.r2lo, h.r2hi);
+    o.jk = -1;
+    o.kn = 0;
+    if (h.kin == 0) return o;
+    const int p = bin_of<T>(R2, tb.Re2, h.n_R, (Mth<T>::log2_(R2) - h.lR0) * h.lRs, h.R2lo, h.R2hi);
+    if (p < 0) return o;
+    const int base = h.n_r + p * h.nk;
+    if (h.kin == 1) {
+        o.jk = base;
+        o.kn = 1;
+        o.k[0] = vz * vz;
+    } else if (h.kin == 2) {
+        // 2 sqrt(pi) u_n(nu) = sqrt2 e^{-nu^2/2} H_n(nu) / sqrt(2^n n!) by the
+        // normalized three-term recurrence
         const T nu = (vz - tb.Vp[p]) * tb.isp[p];
         const T g = T(1.41421356237309505) * Mth<T>::exp_(T(-0.5) * nu * nu);
         T hm = T(1);
-        T h = T(1.41421356237309505) * nu;
-        f(base, g * h);
-        for (int n = 1; n < fd.gh_nmax; ++n) {
-            const T hn = T(kGhA[n]) * nu * h - T(kGhB[n]) * hm;
-            hm = h;
-            h = hn;
-            f(base + n, g * h);
+        T hc = T(1.41421356237309505) * nu;
+        o.jk = base;
+        o.kn = h.gh_nmax;
+        o.k[0] = g * hc;
+#pragma unroll
+        for (int n = 1; n < kMaxGH; ++n) {
+            if (n < h.gh_nmax) {
+                const T hn = T(kGhA[n]) * nu * hc - T(kGhB[n]) * hm;
+                hm = hc;
+                hc = hn;
+                o.k[n] = g * hc;
+            }
         }
     } else {
-        const int b = refine_bin<T>(vz, tb.ve, fd.n_v, (vz - T(fd.vmin)) * T(fd.vidv));
-        if (b >= 0) f(base + b, T(1));
+        const int b = bin_of<T>(vz, tb.ve, h.n_v, (vz - h.vmin) * h.vidv, h.vlo, h.vhi);
+        if (b >= 0) {
+            o.jk = base + b;
+            o.kn = 1;
+            o.k[0] = T(1);
+        }
     }
+    return o;
 }
 
 // ------------------------------------------------------------- potential ---
 template <typename T>
-__device__ __forceinline__ T phi_of(const FitDev& fd, T r) {
-    T p = -T(fd.GMh) / (r + T(fd.a));
-    if (fd.GMn > 0.0) {
-        const T q = r / T(fd.rs);
+__device__ __forceinline__ T phi_of(const Hot<T>& h, T r) {
+    T p = -h.GMh / (r + h.a);
+    if (h.GMn > T(0)) {
+        const T q = r / h.rs;
         const T l = (q > T(1e-4)) ? Mth<T>::log1p_(q) / q : T(1) - q * (T(0.5) - q * T(1.0 / 3.0));
-        p -= T(fd.GMn) / T(fd.rs) * l;
+        p -= h.GMn / h.rs * l;
     }
     return p;
 }
 
 // s(r) with g = -s(r) * (x, y, z): G M(<r) / r^3
 template <typename T>
-__device__ __forceinline__ T accel_of(const FitDev& fd, T r) {
+__device__ __forceinline__ T accel_of(const Hot<T>& h, T r) {
     if (!(r > T(0))) return T(0);
-    const T ra = r + T(fd.a);
-    T s = T(fd.GMh) / (r * ra * ra);
-    if (fd.GMn > 0.0) {
-        const T q = r / T(fd.rs);
+    const T ra = r + h.a;
+    T s = h.GMh / (r * ra * ra);
+    if (h.GMn > T(0)) {
+        const T q = r / h.rs;
         T m;
         if (q < T(Mth<T>::nfw_series_max)) {
             // ln(1+q) - q/(1+q) = sum_{k>=2} (-1)^k (k-1) q^k / k
@@ -186,72 +287,98 @@ __device__ __forceinline__ T accel_of(const FitDev& fd, T r) {
         } else {
             m = Mth<T>::log1p_(q) - q / (T(1) + q);
         }
-        s += T(fd.GMn) * m / (r * r * r);
+        s += h.GMn * m / (r * r * r);
     }
     return s;
 }
 
 // Prior cell (k, l) -> k n_x + l of one phase-space point.
 template <typename T>
-__device__ __forceinline__ int cell_of(const FitDev& fd, T x, T y, T z, T vx, T vy, T vz) {
+__device__ __forceinline__ int cell_of(const Hot<T>& h, T x, T y, T z, T vx, T vy, T vz) {
     const T r = Mth<T>::sqrt_(x * x + y * y + z * z);
-    const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi_of<T>(fd, r);
+    const T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi_of<T>(h, r);
     const T lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
     const T L = Mth<T>::sqrt_(lx * lx + ly * ly + lz * lz);
-    const T phi0 = T(fd.phi0);
     T xc;
     if (!(E < T(0))) {
         xc = T(0);
-    } else if (!(E > phi0)) {
+    } else if (!(E > h.phi0)) {
         xc = T(1);
     } else {
         // radius of the circular orbit of energy E from the table of
         // ln r_c(ln zeta), zeta = (E - Phi(0)) / (-E); in FP64 refined by
         // Newton steps on E_c(r) = Phi(r) + r Phi'(r) / 2 = E
-        const T zeta = (E - phi0) / (-E);
-        const T t = (Mth<T>::log_(zeta) - T(fd.lz0)) * T(fd.ilz);
+        const T zeta = (E - h.phi0) / (-E);
+        const T t = (Mth<T>::log_(zeta) - h.lz0) * h.ilz;
         const T tc = fmin(fmax(t, T(0)), T(kLcTable - 2));
         const int i = (int)tc;
         const T f = t - T(i);  // extrapolates linearly beyond the table
-        const T* tab = static_cast<const T*>(fd.lctab);
-        T rc = Mth<T>::exp_(tab[i] + f * (tab[i + 1] - tab[i]));
+        T rc = Mth<T>::exp_(h.lctab[i] + f * (h.lctab[i + 1] - h.lctab[i]));
         if (sizeof(T) == 8) {
             for (int it = 0; it < 2; ++it) {
-                const T s = accel_of<T>(fd, rc);
-                const T Ec = phi_of<T>(fd, rc) + T(0.5) * s * rc * rc;
-                const T ra = rc + T(fd.a);
-                T dEc = T(0.5) * s * rc + T(fd.GMh) * T(fd.a) / (ra * ra * ra);
-                if (fd.GMn > 0.0) {
-                    const T q1 = T(1) + rc / T(fd.rs);
-                    dEc += T(0.5) * T(fd.GMn) / (T(fd.rs) * T(fd.rs) * q1 * q1);
+                const T s = accel_of<T>(h, rc);
+                const T Ec = phi_of<T>(h, rc) + T(0.5) * s * rc * rc;
+                const T ra = rc + h.a;
+                T dEc = T(0.5) * s * rc + h.GMh * h.a / (ra * ra * ra);
+                if (h.GMn > T(0)) {
+                    const T q1 = T(1) + rc / h.rs;
+                    dEc += T(0.5) * h.GMn / (h.rs * h.rs * q1 * q1);
                 }
                 const T rn = rc - (Ec - E) / dEc;
                 rc = (rn > T(0)) ? rn : T(0.5) * rc;
             }
         }
-        const T Lc = rc * rc * Mth<T>::sqrt_(accel_of<T>(fd, rc));  // sqrt(G M(<r) r)
+        const T Lc = rc * rc * Mth<T>::sqrt_(accel_of<T>(h, rc));  // sqrt(G M(<r) r)
         xc = (Lc > T(0)) ? L / Lc : T(1);
     }
-    const T te = fmin((E - T(fd.E_lo)) * T(fd.E_scale), T(fd.n_E));
+    const T te = fmin((E - h.E_lo) * h.E_scale, T(h.n_E));
     int k = (te >= T(0)) ? (int)te : 0;
-    k = min(k, fd.n_E - 1);
-    const T tx = fmin(xc * T(fd.n_x), T(fd.n_x));
+    k = min(k, h.n_E - 1);
+    const T tx = fmin(xc * T(h.n_x), T(h.n_x));
     int l = (tx >= T(0)) ? (int)tx : 0;
-    l = min(l, fd.n_x - 1);
-    return k * fd.n_x + l;
+    l = min(l, h.n_x - 1);
+    return k * h.n_x + l;
 }
 
 // ------------------------------------------------------------- accumulate --
-__device__ __forceinline__ void bin_add(float* s, float* c, int j, float v) {
-    const float old = atomicAdd(&s[j], v);
+// Add the kernels of one particle (weight w) into its private bin copies.
+// FP64 bins: one FP64 LDS atomic add per kernel (gfx950 runs these about six
+// times faster than FP32 LDS atomic adds). FP32 bins: every add returns the
+// value it replaced, and the exact rounding error of the add (TwoSum) goes
+// into the compensation array; all adds of the particle are issued before
+// their errors are formed.
+__device__ __forceinline__ float two_sum_err(float old, float v) {
     const float t = old + v;  // the value the add stored
     const float bp = t - old;
-    const float e = (old - (t - bp)) + (v - bp);  // exact rounding error (TwoSum)
-    atomicAdd(&c[j], e);
+    return (old - (t - bp)) + (v - bp);
 }
 
-__device__ __forceinline__ void bin_add(double* s, double*, int j, double v) {
-    atomicAdd(&s[j], v);
+template <typename T>
+__device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, float>& tb,
+                                        const Kern<T>& kk, T w, int priv) {
+    const int kp = h.kp;
+    float o_r = 0.f;
+    float o_k[kMaxGH];
+    const float wf = (float)w;
+    if (kk.jr >= 0) o_r = atomicAdd(&tb.sum[kk.jr * kp + priv], wf);
+#pragma unroll
+    for (int m = 0; m < kMaxGH; ++m)
+        if (m < kk.kn) o_k[m] = atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (float)(w * kk.k[m]));
+    if (kk.jr >= 0) atomicAdd(&tb.comp[kk.jr * kp + priv], two_sum_err(o_r, wf));
+#pragma unroll
+    for (int m = 0; m < kMaxGH; ++m)
+        if (m < kk.kn)
+            atomicAdd(&tb.comp[(kk.jk + m) * kp + priv], two_sum_err(o_k[m], (float)(w * kk.k[m])));
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& tb,
+                                        const Kern<T>& kk, T w, int priv) {
+    const int kp = h.kp;
+    if (kk.jr >= 0) atomicAdd(&tb.sum[kk.jr * kp + priv], (double)w);
+#pragma unroll
+    for (int m = 0; m < kMaxGH; ++m)
+        if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
 }
 
 // ------------------------------------------------------------- vector I/O --
@@ -287,7 +414,7 @@ __device__ __forceinline__ void store(T* __restrict__ p, int64_t i, int cnt, con
 }
 
 // ------------------------------------------------------------- step --------
-template <typename T, int BLOCK, int PPL>
+template <typename T, typename A, int BLOCK, int PPL>
 __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -301,26 +428,29 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     const bool refresh = cells_only || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
                                         ((st->kstep + 1) % fd.prior_every) == 0);
     const bool assign = step && st->assign_pending != 0;
-    const bool deposit = !cells_only;
-    const int J = fd.J, C = fd.C;
+    const bool deposit_on = !cells_only;
+    const bool push = step;
+    const Hot<T> h = hot_of<T>(fd);
+    const int J = h.J, C = h.C, kp = h.kp;
 
-    Tabs<T> tb = carve<T>(lds_raw, fd);
+    Tabs<T, A> tb = carve<T, A>(lds_raw, J, kp, h.n_r, h.n_R, h.n_v);
+    const int priv = threadIdx.x & (kp - 1);
     {
         const T* rp = static_cast<const T*>(fd.rp);
-        for (int j = threadIdx.x; j < J; j += BLOCK) {
-            tb.rp[j] = rp[j];
-            tb.sum[j] = T(0);
-            if (sizeof(T) == 4) tb.comp[j] = T(0);
+        for (int j = threadIdx.x; j < J; j += BLOCK) tb.rp[j] = rp[j];
+        for (int j = threadIdx.x; j < J * kp; j += BLOCK) {
+            tb.sum[j] = A(0);
+            if (sizeof(A) == 4) tb.comp[j] = A(0);
         }
         const T* re2 = static_cast<const T*>(fd.redge2);
-        for (int j = threadIdx.x; j <= fd.n_r; j += BLOCK) tb.re2[j] = re2[j];
+        for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.re2[j] = re2[j];
         const T* Re2 = static_cast<const T*>(fd.Redge2);
-        for (int j = threadIdx.x; j <= fd.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
+        for (int j = threadIdx.x; j <= h.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
         const T* ve = static_cast<const T*>(fd.vedge);
-        for (int j = threadIdx.x; j <= fd.n_v; j += BLOCK) tb.ve[j] = ve[j];
+        for (int j = threadIdx.x; j <= h.n_v; j += BLOCK) tb.ve[j] = ve[j];
         const T* Vp = static_cast<const T*>(fd.Vp);
         const T* isp = static_cast<const T*>(fd.isp);
-        for (int j = threadIdx.x; j < fd.n_R; j += BLOCK) {
+        for (int j = threadIdx.x; j < h.n_R; j += BLOCK) {
             tb.Vp[j] = Vp[j];
             tb.isp[j] = isp[j];
         }
@@ -339,13 +469,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     T* __restrict__ U = static_cast<T*>(fd.u);
     T* __restrict__ UH = static_cast<T*>(fd.uh);
     const T* __restrict__ ucell = static_cast<const T*>(fd.ucell);
-    const T dt = T(fd.dt), hdt = T(0.5 * fd.dt), w0 = T(fd.w0);
-    const T foc_mu = T(fd.foc_mu), foc_cs = T(fd.foc_cs);
-    const bool push = step;
+    const int64_t end = tl.end;
 
-    for (int64_t i0 = tl.begin + (int64_t)threadIdx.x * PPL; i0 < tl.end;
+    for (int64_t i0 = tl.begin + (int64_t)threadIdx.x * PPL; i0 < end;
          i0 += (int64_t)BLOCK * PPL) {
-        const int cnt = (int)min<int64_t>(PPL, tl.end - i0);
+        const int cnt = (int)min<int64_t>(PPL, end - i0);
         T px[PPL], py[PPL], pz[PPL], qx[PPL], qy[PPL], qz[PPL], pu[PPL], ph[PPL];
         load<T, PPL>(X, i0, cnt, px);
         load<T, PPL>(Y, i0, cnt, py);
@@ -359,32 +487,32 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
         for (int k = 0; k < PPL; ++k) {
             if (k >= cnt) continue;
             T x = px[k], y = py[k], z = pz[k], vx = qx[k], vy = qy[k], vz = qz[k], u = pu[k];
-            if (assign) ph[k] = ucell[cell_of<T>(fd, x, y, z, vx, vy, vz)];
+            if (assign) ph[k] = ucell[cell_of<T>(h, x, y, z, vx, vy, vz)];
             if (correct) {
                 // force of change at z^k with the residuals of step k
-                T chi = T(0);
-                visit<T>(fd, tb, x, y, z, vz, [&](int j, T K) { chi += K * tb.rp[j]; });
+                const Kern<T> kk = kernels<T, A>(h, tb, x, y, z, vz);
+                T chi = (kk.jr >= 0) ? tb.rp[kk.jr] : T(0);
+#pragma unroll
+                for (int m = 0; m < kMaxGH; ++m)
+                    if (m < kk.kn) chi += kk.k[m] * tb.rp[kk.jk + m];
                 const T lr = Mth<T>::log_(u * Mth<T>::rcp_(ph[k]));
-                u = u * Mth<T>::exp_(-foc_mu * (lr + foc_cs) - chi);
+                u = u * Mth<T>::exp_(-h.foc_mu * (lr + h.foc_cs) - chi);
             }
             if (push) {
-                x += hdt * vx;
-                y += hdt * vy;
-                z += hdt * vz;
-                const T s = accel_of<T>(fd, Mth<T>::sqrt_(x * x + y * y + z * z)) * dt;
+                x += h.hdt * vx;
+                y += h.hdt * vy;
+                z += h.hdt * vz;
+                const T s = accel_of<T>(h, Mth<T>::sqrt_(x * x + y * y + z * z)) * h.dt;
                 vx -= s * x;
                 vy -= s * y;
                 vz -= s * z;
-                x += hdt * vx;
-                y += hdt * vy;
-                z += hdt * vz;
+                x += h.hdt * vx;
+                y += h.hdt * vy;
+                z += h.hdt * vz;
             }
-            if (deposit) {
-                const T w = u * w0;
-                visit<T>(fd, tb, x, y, z, vz, [&](int j, T K) { bin_add(tb.sum, tb.comp, j, w * K); });
-            }
+            if (deposit_on) deposit<T>(h, tb, kernels<T, A>(h, tb, x, y, z, vz), u * h.w0, priv);
             if (refresh) {
-                const int c = cell_of<T>(fd, x, y, z, vx, vy, vz);
+                const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
                 unsafeAtomicAdd(&row[J + c], (double)u);
                 unsafeAtomicAdd(&row[J + C + c], 1.0);
             }
@@ -408,9 +536,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
         }
     }
     __syncthreads();
-    if (deposit)
-        for (int j = threadIdx.x; j < J; j += BLOCK)
-            row[j] = (sizeof(T) == 4) ? (double)tb.sum[j] + (double)tb.comp[j] : (double)tb.sum[j];
+    if (deposit_on)
+        for (int j = threadIdx.x; j < J; j += BLOCK) {
+            double t = 0.0;
+            for (int g = 0; g < kp; ++g) {
+                t += (double)tb.sum[j * kp + g];
+                if (sizeof(A) == 4) t += (double)tb.comp[j * kp + g];
+            }
+            row[j] = t;
+        }
 }
 
 // ------------------------------------------------------------- finalize ----
@@ -448,9 +582,21 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     if (col < ncols) {
         double* base = fd.partials + (bins ? col : J + col);
         const size_t stride = (size_t)fd.row_len;
-        for (int t = wave; t < jb.n_tiles; t += kWaves) {
-            acc += base[(size_t)t * stride];
-            if (!bins) {
+        int t = wave;
+        if (bins) {
+            // eight rows in flight, added in row order
+            constexpr int U = 8;
+            for (; t + (U - 1) * kWaves < jb.n_tiles; t += U * kWaves) {
+                double v[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) v[k] = base[(size_t)(t + k * kWaves) * stride];
+#pragma unroll
+                for (int k = 0; k < U; ++k) acc += v[k];
+            }
+            for (; t < jb.n_tiles; t += kWaves) acc += base[(size_t)t * stride];
+        } else {
+            for (; t < jb.n_tiles; t += kWaves) {
+                acc += base[(size_t)t * stride];
                 acc2 += base[(size_t)t * stride + C];
                 // leave the cell columns cleared for the next accumulation
                 base[(size_t)t * stride] = 0.0;
@@ -533,8 +679,9 @@ __global__ __launch_bounds__(256) void k_assign(const FitDev* __restrict__ fits,
     const T* VZ = static_cast<const T*>(fd.vz);
     T* UH = static_cast<T*>(fd.uh);
     const T* ucell = static_cast<const T*>(fd.ucell);
+    const Hot<T> h = hot_of<T>(fd);
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += 256)
-        UH[i] = ucell[cell_of<T>(fd, X[i], Y[i], Z[i], VX[i], VY[i], VZ[i])];
+        UH[i] = ucell[cell_of<T>(h, X[i], Y[i], Z[i], VX[i], VY[i], VZ[i])];
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // every tile of this launch belongs to one fit; the flag is consumed
@@ -591,32 +738,45 @@ __global__ __launch_bounds__(256) void k_residuals(const FitDev* __restrict__ fi
     }
 }
 
-template <typename T, int BLOCK, int PPL>
+template <typename T, typename A, int BLOCK, int PPL>
 hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, int n_tiles, size_t lds,
                          int32_t mode, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<T, BLOCK, PPL>), dim3(n_tiles), dim3(BLOCK), lds, s, fits, tiles,
+    hipLaunchKernelGGL((k_step<T, A, BLOCK, PPL>), dim3(n_tiles), dim3(BLOCK), lds, s, fits, tiles,
                        mode);
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t step_lds_bytes(bool f64, int J, int n_r, int n_R, int n_v) {
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv) {
+    (void)acc64;  // FP64 sums and FP32 sum + compensation both take 8 bytes per bin copy
     const size_t sz = f64 ? 8 : 4;
-    const size_t n = (size_t)J * (f64 ? 2 : 3) + (size_t)(n_r + 1) + (size_t)(n_R + 1) +
-                     (size_t)(n_v + 1) + 2 * (size_t)n_R;
-    return ((n * sz + 15) / 16) * 16;
+    const size_t bins = (size_t)J * (size_t)kpriv * 8;
+    const size_t tabs = ((size_t)J + (size_t)(n_r + 1) + (size_t)(n_R + 1) + (size_t)(n_v + 1) +
+                         2 * (size_t)n_R) * sz;
+    return ((bins + tabs + 15) / 16) * 16;
 }
 
-hipError_t launch_step(bool f64, int block, int ppl, const FitDev* fits, const Tile* tiles,
-                       int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
+// Private bin copies: as many as fit in 48 KiB of LDS, at most 8.
+int private_copies(bool f64, int J) {
+    (void)f64;
+    const size_t per = (size_t)J * 8;
+    int k = 8;
+    while (k > 1 && per * (size_t)k > 48 * 1024) k >>= 1;
+    return k;
+}
+
+hipError_t launch_step(bool f64, bool acc64, int block, int ppl, const FitDev* fits,
+                       const Tile* tiles, int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     if (f64) {
-        if (ppl >= 2) return launch_step_t<double, 256, 2>(fits, tiles, n_tiles, lds, mode, s);
-        return launch_step_t<double, 256, 1>(fits, tiles, n_tiles, lds, mode, s);
+        if (ppl >= 2) return launch_step_t<double, double, 256, 2>(fits, tiles, n_tiles, lds, mode, s);
+        return launch_step_t<double, double, 256, 1>(fits, tiles, n_tiles, lds, mode, s);
     }
-#define M2M_STEP_CASE(B, P) \
-    if (block == B && ppl == P) return launch_step_t<float, B, P>(fits, tiles, n_tiles, lds, mode, s);
+#define M2M_STEP_CASE(B, P)                                                                    \
+    if (block == B && ppl == P)                                                                \
+        return acc64 ? launch_step_t<float, double, B, P>(fits, tiles, n_tiles, lds, mode, s)  \
+                     : launch_step_t<float, float, B, P>(fits, tiles, n_tiles, lds, mode, s);
     M2M_STEP_CASE(256, 1)
     M2M_STEP_CASE(256, 2)
     M2M_STEP_CASE(256, 4)

@@ -105,12 +105,17 @@ def test_initial_residuals_and_one_step(oracle, Fit, dtype):
     f.close()
 
 
-def test_run_fp32_matches_oracle_200_steps(oracle, Fit):
-    """Workload 1 with FP32 particle state: weights after 200 steps."""
+@pytest.mark.parametrize("mode", ["f64", "f32c"])
+def test_run_fp32_matches_oracle_200_steps(oracle, Fit, mode):
+    """Workload 1 with FP32 particle state: weights after 200 steps, with
+    FP64 and with compensated FP32 in-tile deposit sums."""
+    from paper_1202_2355_amd import _abi
     wl = workload(1)
     n = 20_003
-    _say("run fp32", wl.name, n)
+    _say("run fp32", wl.name, n, "deposit", mode)
+    _abi.m2m_set_deposit_mode(mode)
     T, parts, f, o = _run_pair(oracle, Fit, wl, n, 200, "f32", 1e-5)
+    _abi.m2m_set_deposit_mode("f64")
     f.step(200)
     hist_o = o.step(200)
     hist_g = f.chi2_history(200)
@@ -240,12 +245,16 @@ def test_checkpoint_resume(oracle, Fit):
     g.close()
 
 
+@pytest.mark.parametrize("mode", ["f32c", "f64"])
 @pytest.mark.parametrize("n", [4_000_003, 200_001])
-def test_compensated_deposit_is_exact_to_fp64_rounding(oracle, Fit, n):
-    """All particles in one radial bin: the in-tile FP32 sums carry their
-    exact rounding errors (TwoSum on the LDS atomics), so the deposit equals
-    the FP64 sum of the FP32 contributions far below FP32 accuracy."""
+def test_compensated_deposit_is_exact_to_fp64_rounding(oracle, Fit, n, mode):
+    """All particles in one radial bin: FP32 in-tile sums that carry their
+    exact rounding errors (TwoSum on the LDS atomics), and FP64 in-tile sums,
+    both give the FP64 sum of the FP32 contributions far below FP32
+    accuracy."""
+    from paper_1202_2355_amd import _abi
     from workloads import make_layout, make_params, make_potential
+    _abi.m2m_set_deposit_mode(mode)
     pot = make_potential()
     g = np.random.default_rng(4)
     r = g.uniform(1.0, 2.0, n)
@@ -262,11 +271,11 @@ def test_compensated_deposit_is_exact_to_fp64_rounding(oracle, Fit, n):
     w0 = np.float32(1.0 / n)
     contrib = (u.astype(np.float32) * w0).astype(np.float64)
     exact = np.sum(np.sort(contrib))
-    plain = np.float32(0)
     rel = abs(y / exact - 1)
-    _say("compensated deposit rel err", rel, "(one FP32 ulp", 2.0 ** -24, ")")
-    assert rel < 1e-12
+    _say("deposit", mode, "rel err", rel, "(one FP32 ulp", 2.0 ** -24, ")")
     f.close()
+    _abi.m2m_set_deposit_mode("f64")
+    assert rel < 1e-12
 
 
 def test_invalid_arguments(Fit):
