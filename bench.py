@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 # launch shape (threads per block, particles per lane, tiles per CU) of the
 # fused step kernel per workload, as chosen by paper_1202_2355_amd.autotune
-LAUNCH = {1: (256, 1, 4), 2: (256, 4, 4), 3: (256, 4, 4), 4: (256, 4, 4), 5: (256, 4, 4)}
+LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (1024, 1), 5: (1024, 1)}
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_PSTEP = {"f32": 60, "f64": 120}   # read x, v, u, uhat; write x, v, u

@@ -189,11 +189,12 @@ m2m_status m2m_observe(m2m_ctx* ctx, const double* V_p, const double* sigma_p, d
 m2m_status m2m_get_state(m2m_ctx* ctx, void* host_blob, size_t* bytes);
 m2m_status m2m_set_state(m2m_ctx* ctx, const void* host_blob, size_t bytes);
 
-/* Run n_steps steps like m2m_step, launching the two kernels of each step
- * directly (no graph) with HIP events around each launch on the context's
- * stream, and return the mean duration in milliseconds of the fused step
- * kernel (ms_step) and of the finalize kernel (ms_finalize). Synchronizes.
- * Used to report achieved bandwidth against the roofline. */
+/* Timing by HIP events on the context's stream, back-to-back launches only:
+ * runs n_steps steps as m2m_step does (they advance the fit), then n_steps
+ * launches of the finalize reduction in a measuring mode that changes no
+ * state. ms_finalize is the mean finalize time and ms_step the mean step time
+ * minus it, i.e. the fused step kernel plus one launch gap (milliseconds).
+ * Synchronizes. Used to report achieved bandwidth against the roofline. */
 m2m_status m2m_profile_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct, double* ms_step,
                             double* ms_finalize);
 
@@ -204,11 +205,11 @@ m2m_status m2m_destroy(m2m_ctx* ctx);
 const char* m2m_last_error(const m2m_ctx* ctx);
 
 /* Launch shape of the fused step kernel for contexts created afterwards and
- * for batches: threads per block (256, 512 or 1024), particles per lane
- * (1, 2 or 4) and tiles (blocks) per compute unit (1..16). EINVAL otherwise.
- * Chosen by the package's autotuner. */
-m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu);
-m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu);
+ * for batches rebuilt afterwards: threads per block (256, 512 or 1024) and
+ * tiles (blocks) per compute unit (1..16); each thread handles one particle
+ * at a time. EINVAL otherwise. Chosen by the package's autotuner. */
+m2m_status m2m_set_launch(int32_t block, int32_t tiles_per_cu);
+m2m_status m2m_get_launch(int32_t* block, int32_t* tiles_per_cu);
 
 /* In-tile accumulation of the deposits (eq. obs) for FP32 particle state,
  * for contexts and batches created afterwards: M2M_DEPOSIT_F64 (default)
@@ -243,9 +244,8 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
  * *n_active (may be NULL) the number still running. */
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
                           int32_t* n_active);
-/* Like m2m_profile_step for the batch: steps_per_launch steps with the two
- * kernels of each step launched directly and timed by HIP events on the
- * batch stream; mean durations in milliseconds. Synchronizes. */
+/* Like m2m_profile_step for the batch (n_steps batched steps, then n_steps
+ * measuring finalize launches over all fits). Synchronizes. */
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize);
 /* Particles of the admitted fits that still have steps left. Synchronizes. */
 int64_t m2m_batch_particles(m2m_batch* b);

@@ -73,8 +73,8 @@ SIGNATURES = {
     "m2m_profile_step": (_st, [_vp, _i32, _i32, _dp, _dp]),
     "m2m_destroy": (_st, [_vp]),
     "m2m_last_error": (C.c_char_p, [_vp]),
-    "m2m_set_launch": (_st, [_i32, _i32, _i32]),
-    "m2m_get_launch": (_st, [C.POINTER(_i32)] * 3),
+    "m2m_set_launch": (_st, [_i32, _i32]),
+    "m2m_get_launch": (_st, [C.POINTER(_i32)] * 2),
     "m2m_set_deposit_mode": (_st, [_i32]),
     "m2m_get_deposit_mode": (_i32, []),
     "m2m_batch_create": (_st, [_i32, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -148,8 +148,8 @@ def m2m_workspace_bytes(layout: dict, par: dict, n: int, dtype: str = "f32") -> 
                                          int(n), DTYPE[dtype]))
 
 
-def m2m_set_launch(block: int, ppl: int, tiles_per_cu: int):
-    check(lib().m2m_set_launch(int(block), int(ppl), int(tiles_per_cu)), "m2m_set_launch")
+def m2m_set_launch(block: int, tiles_per_cu: int):
+    check(lib().m2m_set_launch(int(block), int(tiles_per_cu)), "m2m_set_launch")
 
 
 M2M_DEPOSIT_F64, M2M_DEPOSIT_F32_COMPENSATED = 0, 1
@@ -166,6 +166,6 @@ def m2m_get_deposit_mode() -> int:
 
 
 def m2m_get_launch():
-    b, p, t = _i32(), _i32(), _i32()
-    lib().m2m_get_launch(C.byref(b), C.byref(p), C.byref(t))
-    return b.value, p.value, t.value
+    b, t = _i32(), _i32()
+    lib().m2m_get_launch(C.byref(b), C.byref(t))
+    return b.value, t.value

@@ -1,9 +1,9 @@
 """Launch-shape search for the fused step kernel.
 
-The shape is (threads per block, particles per lane, tiles per compute
-unit): the tile count sets how many blocks stream the particles (and how
-many partial rows the finalize reduces), the block size and particles per
-lane set the waves per CU and the memory-level parallelism of each wave. The
+The shape is (threads per block, tiles per compute unit): the tile count
+sets how many blocks stream the particles (and how many partial rows the
+finalize reduces), the block size sets the waves per CU that share one set
+of LDS bins. The
 search times whole M2M steps (step + finalize kernels, graph replays) on
 fresh copies of the same particles and keeps the fastest shape.
 """
@@ -21,7 +21,6 @@ from . import _abi as A
 from .fit import Fit
 
 BLOCKS = (256, 512, 1024)
-PPLS = (1, 2, 4)
 TILES_PER_CU = (1, 2, 4, 8)
 
 
@@ -40,19 +39,18 @@ def time_shape(make_fit, shape, steps=40, warmup=16):
     return ms
 
 
-def search(make_fit, blocks=BLOCKS, ppls=PPLS, tiles=TILES_PER_CU, steps=40, log=sys.stderr,
-           dtype="f32"):
+def search(make_fit, blocks=BLOCKS, tiles=TILES_PER_CU, steps=40, log=sys.stderr, dtype="f32"):
     """Time every shape; returns (best shape, {shape: ms per step})."""
     before = A.m2m_get_launch()
     res = {}
     try:
-        for b, p, t in itertools.product(blocks, ppls, tiles):
-            if dtype == "f64" and (b != 256 or p > 2):
+        for b, t in itertools.product(blocks, tiles):
+            if dtype == "f64" and b != 256:
                 continue
-            ms = time_shape(make_fit, (b, p, t), steps=steps)
-            res[(b, p, t)] = ms
+            ms = time_shape(make_fit, (b, t), steps=steps)
+            res[(b, t)] = ms
             if log:
-                print(f"[autotune] block={b} ppl={p} tiles/cu={t}: {1e3 * ms:.2f} us/step",
+                print(f"[autotune] block={b} tiles/cu={t}: {1e3 * ms:.2f} us/step",
                       file=log, flush=True)
     finally:
         A.m2m_set_launch(*before)
@@ -92,7 +90,7 @@ def main(argv=None):
 
     best, res = search(make_fit, steps=args.steps, dtype=wl.state)
     out = {"workload": wl.name, "best": list(best), "us_per_step": 1e3 * res[best],
-           "all": {f"{b},{p},{t}": 1e3 * ms for (b, p, t), ms in res.items()}}
+           "all": {f"{b},{t}": 1e3 * ms for (b, t), ms in res.items()}}
     print(json.dumps(out))
     if args.out:
         with open(args.out, "w") as fh:

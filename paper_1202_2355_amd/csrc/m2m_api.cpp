@@ -22,7 +22,7 @@ constexpr int kGraphSteps = 8;      // M2M steps per captured graph
 constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
 
 // launch shape for contexts and batches created from now on
-int g_block = 256, g_ppl = 4, g_tiles_per_cu = 4;
+int g_block = 1024, g_tiles_per_cu = 1;
 int g_deposit = M2M_DEPOSIT_F64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -248,7 +248,7 @@ struct m2m_ctx {
     int n_tiles = 0;
     int n_jobs = 0;
     size_t lds = 0;
-    int block = 256, ppl = 4;
+    int block = 256, kin = 0;
     bool acc64 = true;
     bool targets = false;
     bool ytil_init = false;
@@ -306,7 +306,7 @@ void split_tiles(int64_t n, int count, int fit, int row0, std::vector<Tile>& out
         int64_t b = n * t / count, e = n * (t + 1) / count;
         b = b / kSegAlign * kSegAlign;
         e = (t == count - 1) ? n : e / kSegAlign * kSegAlign;
-        out.push_back(Tile{fit, row0 + t, b, e});
+        out.push_back(Tile{fit, row0 + t, b, e, count, 0});
     }
 }
 
@@ -346,10 +346,11 @@ m2m_status check_error(m2m_ctx* c) {
     return M2M_OK;
 }
 
+// One M2M step: the fused step kernel over all tiles, then the finalize.
 m2m_status run_direct(m2m_ctx* c, int steps) {
     for (int k = 0; k < steps; ++k) {
-        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
-                               kModeStep, c->stream));
+        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
+                               c->lds, kModeStep, c->stream));
         M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream));
     }
     return M2M_OK;
@@ -361,7 +362,7 @@ m2m_status ensure_graph(m2m_ctx* c) {
     M2M_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        e = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                         kModeStep, c->cap);
         if (e == hipSuccess)
             e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->cap);
@@ -398,12 +399,10 @@ size_t m2m_workspace_bytes(const m2m_obs_layout* layout, const m2m_params* param
     return plan(*layout, *params, n, dtype == M2M_F64).total;
 }
 
-m2m_status m2m_set_launch(int32_t block, int32_t ppl, int32_t tiles_per_cu) {
+m2m_status m2m_set_launch(int32_t block, int32_t tiles_per_cu) {
     if (block != 256 && block != 512 && block != 1024) return M2M_EINVAL;
-    if (ppl != 1 && ppl != 2 && ppl != 4) return M2M_EINVAL;
     if (tiles_per_cu < 1 || tiles_per_cu > 16) return M2M_EINVAL;
     g_block = block;
-    g_ppl = ppl;
     g_tiles_per_cu = tiles_per_cu;
     return M2M_OK;
 }
@@ -416,9 +415,8 @@ m2m_status m2m_set_deposit_mode(int32_t mode) {
 
 int32_t m2m_get_deposit_mode(void) { return g_deposit; }
 
-m2m_status m2m_get_launch(int32_t* block, int32_t* ppl, int32_t* tiles_per_cu) {
+m2m_status m2m_get_launch(int32_t* block, int32_t* tiles_per_cu) {
     if (block) *block = g_block;
-    if (ppl) *ppl = g_ppl;
     if (tiles_per_cu) *tiles_per_cu = g_tiles_per_cu;
     return M2M_OK;
 }
@@ -452,7 +450,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->f64 = dtype == M2M_F64;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->block = c->f64 ? 256 : g_block;
-    c->ppl = c->f64 ? std::min(g_ppl, 2) : g_ppl;
+    c->kin = kin_class(c->lay.kin, c->lay.gh_nmax);
     c->w = plan(c->lay, c->par, n, c->f64);
     const WsLayout& w = c->w;
     const int kpriv = private_copies(c->f64, w.J);
@@ -635,7 +633,7 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     if (!c->ytil_init) {
-        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                                kModeInit, c->stream));
         M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeInit, c->stream));
         c->ytil_init = true;
@@ -666,7 +664,7 @@ m2m_status m2m_update_priors(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
-    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeCells, c->stream));
     M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeCells, c->stream));
     M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
@@ -744,7 +742,7 @@ m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, dou
                 return fail(c, M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
         if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     }
-    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeObserve, c->stream));
     M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream));
     if ((s = sync(c)) != M2M_OK) return s;
@@ -851,39 +849,36 @@ m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double
     if (!c || n_steps < 1) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
-    std::vector<hipEvent_t> ev(3 * (size_t)n_steps, nullptr);
-    for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto& f : ev)
-                if (f) (void)hipEventDestroy(f);
-            return fail(c, M2M_EDEVICE, "hipEventCreate");
-        }
-    m2m_status s = M2M_OK;
-    hipError_t e = launch_poke(c->st, n_steps, correct ? 1 : 0, c->stream);
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-        e = hipEventRecord(ev[3 * k], c->stream);
-        if (e == hipSuccess)
-            e = launch_step(c->f64, c->acc64, c->block, c->ppl, c->fd_dev, c->tiles, c->n_tiles, c->lds,
-                            kModeStep, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], c->stream);
-        if (e == hipSuccess)
-            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], c->stream);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    // (1) n whole steps as m2m_step runs them (graph replays)
+    if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+    if (e == hipSuccess) {
+        m2m_status st = m2m_step(c, n_steps, correct);
+        if (st != M2M_OK) e = hipErrorUnknown;
     }
+    if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+    // (2) n back-to-back finalize launches of the same reduction (measuring
+    // mode: no state changes)
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        if (k == 0) e = hipEventRecord(ev[2], c->stream);
+        if (e == hipSuccess)
+            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    double t1 = 0.0, t2 = 0.0;
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-        float a = 0.f, b = 0.f;
-        e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
-        t1 += a;
-        t2 += b;
-    }
-    if (e != hipSuccess) s = hip_fail(c, e, "profile");
-    for (auto& f : ev) (void)hipEventDestroy(f);
-    if (ms_step) *ms_step = t1 / n_steps;
-    if (ms_finalize) *ms_finalize = t2 / n_steps;
-    return s;
+    float t_all = 0.f, t_fin = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_all, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_fin, ev[2], ev[3]);
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(c, e, "profile");
+    const double fin = (double)t_fin / n_steps;
+    if (ms_step) *ms_step = (double)t_all / n_steps - fin;
+    if (ms_finalize) *ms_finalize = fin;
+    return M2M_OK;
 }
 
 m2m_status m2m_destroy(m2m_ctx* c) {
@@ -916,7 +911,7 @@ struct m2m_batch {
     size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
     int n_tiles = 0, n_jobs = 0;
     size_t lds = 0;
-    int block = 256, ppl = 4;
+    int block = 256, kin = -1;
     bool acc64 = true;
     hipGraphExec_t graph = nullptr;
 };
@@ -951,7 +946,6 @@ m2m_status rebuild(m2m_batch* b) {
     }
     const bool f64 = b->f64 == 1;
     b->block = f64 ? 256 : g_block;
-    b->ppl = f64 ? std::min(g_ppl, 2) : g_ppl;
     b->acc64 = f64 || g_deposit == M2M_DEPOSIT_F64;
     std::vector<FitDev> fd;
     std::vector<Tile> tl;
@@ -985,8 +979,8 @@ m2m_status rebuild(m2m_batch* b) {
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return M2M_EDEVICE;
     for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
-                        kModeStep, b->cap);
+        e = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
+                        b->lds, kModeStep, b->cap);
         if (e == hipSuccess)
             e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->cap);
     }
@@ -1045,6 +1039,8 @@ m2m_status m2m_batch_admit(m2m_batch* b, m2m_ctx* c, int32_t n_steps) {
     if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
     if (b->f64 != -1 && b->f64 != (c->f64 ? 1 : 0))
         return fail(c, M2M_EINVAL, "a batch holds fits of one particle dtype");
+    if (!b->fits.empty() && b->kin != c->kin)
+        return fail(c, M2M_EINVAL, "a batch holds fits of one kind of kinematic observable");
     if ((int)b->fits.size() >= b->max_fits) return fail(c, M2M_ENOMEM, "batch is full");
     if (b->budget && m2m_batch_footprint(b) + footprint(c) > b->budget)
         return fail(c, M2M_ENOMEM, "fit does not fit the HBM budget");
@@ -1052,6 +1048,7 @@ m2m_status m2m_batch_admit(m2m_batch* b, m2m_ctx* c, int32_t n_steps) {
     if (s != M2M_OK) return s;
     M2M_HIP(c, launch_poke(c->st, n_steps, 1, b->stream));
     b->f64 = c->f64 ? 1 : 0;
+    b->kin = c->kin;
     b->fits.push_back(c);
     c->batch = b;
     b->dirty = true;
@@ -1069,12 +1066,11 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
     const int full = steps_per_launch / kGraphSteps, rem = steps_per_launch % kGraphSteps;
     for (int k = 0; k < full; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
-    for (int k = 0; k < rem; ++k) {
-        if (launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
-                        kModeStep, b->stream) != hipSuccess ||
+    for (int k = 0; k < rem; ++k)
+        if (launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
+                        b->lds, kModeStep, b->stream) != hipSuccess ||
             launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
             return M2M_EDEVICE;
-    }
     return M2M_OK;
 }
 
@@ -1127,34 +1123,27 @@ m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, dou
     }
     if (b->fits.empty()) return M2M_ESTATE;
     const bool f64 = b->f64 == 1;
-    std::vector<hipEvent_t> ev(3 * (size_t)n_steps, nullptr);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-        e = hipEventRecord(ev[3 * k], b->stream);
-        if (e == hipSuccess)
-            e = launch_step(f64, b->acc64, b->block, b->ppl, b->fits_dev, b->tiles_dev, b->n_tiles, b->lds,
-                            kModeStep, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], b->stream);
-        if (e == hipSuccess)
-            e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], b->stream);
-    }
+    if (e == hipSuccess) e = hipEventRecord(ev[0], b->stream);
+    if (e == hipSuccess && m2m_batch_run(b, n_steps) != M2M_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k)
+        e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeObserve, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    double t1 = 0.0, t2 = 0.0;
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-        float a = 0.f, c = 0.f;
-        e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[3 * k + 1], ev[3 * k + 2]);
-        t1 += a;
-        t2 += c;
-    }
+    float t_all = 0.f, t_fin = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_all, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t_fin, ev[2], ev[3]);
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return M2M_EDEVICE;
-    if (ms_step) *ms_step = t1 / n_steps;
-    if (ms_finalize) *ms_finalize = t2 / n_steps;
+    const double fin = (double)t_fin / n_steps;
+    if (ms_step) *ms_step = (double)t_all / n_steps - fin;
+    if (ms_finalize) *ms_finalize = fin;
     return M2M_OK;
 }
 

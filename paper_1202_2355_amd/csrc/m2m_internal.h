@@ -75,9 +75,11 @@ struct FitDev {
 
 // One tile: a contiguous particle range of one fit, owned by one block.
 struct Tile {
-    int32_t fit;   // index into the launch's fit table
-    int32_t row;   // tile row in the fit's partials
+    int32_t fit;     // index into the launch's fit table
+    int32_t row;     // tile row in the fit's partials
     int64_t begin, end;
+    int32_t n_rows;  // tiles of this fit in the launch
+    int32_t pad;
 };
 
 // One finalize block: kFinCols columns of one fit.
@@ -89,9 +91,11 @@ struct FinJob {
 };
 
 // ---- launchers (m2m_kernels.hip) ------------------------------------------
-hipError_t launch_step(bool f64, bool acc64, int block, int ppl, const FitDev* fits,
+// kin: kinematic kind of every fit in the launch, from kin_class()
+hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* fits,
                        const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
                        hipStream_t s);
+int kin_class(int kin, int gh_nmax);
 hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
                            int32_t mode, hipStream_t s);
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,

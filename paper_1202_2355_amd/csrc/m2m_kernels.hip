@@ -9,13 +9,11 @@
 //               writes one row of FP64 partial sums.
 //   k_finalize  FP64 reduction of the tile rows of every fit in a fixed
 //               order -> y, smoothed ytilde (eq. myts), Delta and chi^2
-//               (eqs. delta, chi), the FP32 force table for the next step,
-//               and the cell means that become the new priors.
+//               (eqs. delta, chi), the force table for the next step, and
+//               the cell means that become the new priors.
 // Particle state is structure-of-arrays, read and written once per step
-// (coalesced, PPL consecutive particles per lane). In FP32 the in-tile bin
-// sums are compensated: every LDS atomic add returns the old value, the
-// rounding error of that add is recovered exactly (TwoSum) and accumulated
-// in a second LDS array.
+// (coalesced, one particle per lane, the next batch prefetched). k_step is
+// specialized at compile time on the kind of kinematic observable.
 #include <hip/hip_runtime.h>
 
 #include "m2m_internal.h"
@@ -24,15 +22,17 @@ namespace m2m {
 namespace {
 
 // ------------------------------------------------------------- math --------
+// FP32: the hardware transcendental and reciprocal instructions (about 1 ulp;
+// arguments here are never denormal). FP64: the correctly rounded library.
 template <typename T>
 struct Mth;
 
 template <>
 struct Mth<float> {
-    __device__ static float exp_(float x) { return __expf(x); }
-    __device__ static float log_(float x) { return __logf(x); }
-    __device__ static float log2_(float x) { return __log2f(x); }
-    __device__ static float sqrt_(float x) { return __builtin_sqrtf(x); }
+    __device__ static float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    __device__ static float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+    __device__ static float log2_(float x) { return __builtin_amdgcn_logf(x); }
+    __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     __device__ static float log1p_(float x) { return log1pf(x); }
     __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static constexpr float nfw_series_max = 0.1f;
@@ -105,13 +105,13 @@ __device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, i
 
 // ------------------------------------------------------------- per tile ----
 // What the particle loop reads of its fit, loaded once per tile (uniform
-// values, held in scalar registers) instead of from the fit table in the loop.
+// values) instead of from the fit table inside the loop.
 template <typename T>
 struct Hot {
-    int n_r, n_R, kin, nk, gh_nmax, n_v, J, C, kp, n_E, n_x;
+    int n_r, n_R, nk, gh_nmax, n_v, J, C, kp, n_E, n_x;
     T lr0, lrs, lR0, lRs, vmin, vidv;
     T r2lo, r2hi, R2lo, R2hi, vlo, vhi;  // range ends: squared radii, velocities
-    T GMh, a, GMn, rs, phi0;
+    T GMh, a, GMn, rs, irs, phi0;
     T dt, hdt, w0, foc_mu, foc_cs;
     T E_lo, E_scale, lz0, ilz;
     const T* lctab;
@@ -122,7 +122,6 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
     Hot<T> h;
     h.n_r = fd.n_r;
     h.n_R = fd.n_R;
-    h.kin = fd.kin;
     h.nk = fd.nk;
     h.gh_nmax = fd.gh_nmax;
     h.n_v = fd.n_v;
@@ -150,6 +149,7 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
     h.a = T(fd.a);
     h.GMn = T(fd.GMn);
     h.rs = T(fd.rs);
+    h.irs = T(1.0 / fd.rs);
     h.phi0 = T(fd.phi0);
     h.dt = T(fd.dt);
     h.hdt = T(0.5 * fd.dt);
@@ -165,8 +165,8 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
 }
 
 // ------------------------------------------------------------- binning -----
-// k with e[k] <= v < e[k+1] for ascending e[0..n], or -1 outside [e[0], e[n]),
-// decided by comparison with the stored edges.
+// k with e[k] <= v < e[k+1] for ascending e[0..n], decided by comparison with
+// the stored edges (v is known to lie in [e[0], e[n])).
 template <typename T>
 __device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
     g = fmin(fmax(g, T(0)), T(n - 1));
@@ -189,9 +189,10 @@ __device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
     return k;
 }
 
-// The arithmetic position g of v in bin units is accurate to a few 1e-6, so a
-// point more than 1e-4 of a bin from both edges is in bin floor(g); only
-// points closer to an edge are compared with the stored edges.
+// Bin of v, or -1 outside [lo, hi). The arithmetic position g of v in bin
+// units is accurate to a few 1e-6, so a point more than 1e-4 of a bin from
+// both edges is in bin floor(g); only points closer to an edge are compared
+// with the stored edges.
 template <typename T>
 __device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
     if (!(v >= lo) || !(v < hi)) return -1;
@@ -202,44 +203,53 @@ __device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
     return refine_bin<T>(v, e, n, g);
 }
 
-// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1)
-// and kn kinematic entries j = jk + m with values k[m].
-template <typename T>
-struct Kern {
-    int jr, jk, kn;
-    T k[kMaxGH];
+// kinds of kinematic observables, fixed at compile time in k_step
+enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4 };
+
+template <int KIN>
+struct KinSlots {
+    static constexpr int n = (KIN == kKinGH4) ? 4 : (KIN == kKinGHN) ? kMaxGH : 1;
 };
 
-template <typename T, typename A>
-__device__ __forceinline__ Kern<T> kernels(const Hot<T>& h, const Tabs<T, A>& tb, T x, T y, T z,
-                                           T vz) {
-    Kern<T> o;
+// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1)
+// and kn kinematic entries j = jk + m with values k[m].
+template <typename T, int KIN>
+struct Kern {
+    int jr, jk, kn;
+    T k[KinSlots<KIN>::n];
+};
+
+template <typename T, typename A, int KIN>
+__device__ __forceinline__ Kern<T, KIN> kernels(const Hot<T>& h, const Tabs<T, A>& tb, T x, T y,
+                                                T z, T vz) {
+    Kern<T, KIN> o;
     const T R2 = x * x + y * y;
     const T r2 = R2 + z * z;
     o.jr = bin_of<T>(r2, tb.re2, h.n_r, (Mth<T>::log2_(r2) - h.lr0) * h.lrs, h.r2lo, h.r2hi);
     o.jk = -1;
     o.kn = 0;
-    if (h.kin == 0) return o;
+    if (KIN == kKinNone) return o;
     const int p = bin_of<T>(R2, tb.Re2, h.n_R, (Mth<T>::log2_(R2) - h.lR0) * h.lRs, h.R2lo, h.R2hi);
     if (p < 0) return o;
     const int base = h.n_r + p * h.nk;
-    if (h.kin == 1) {
+    if (KIN == kKinV2) {
         o.jk = base;
         o.kn = 1;
         o.k[0] = vz * vz;
-    } else if (h.kin == 2) {
+    } else if (KIN == kKinGH4 || KIN == kKinGHN) {
         // 2 sqrt(pi) u_n(nu) = sqrt2 e^{-nu^2/2} H_n(nu) / sqrt(2^n n!) by the
         // normalized three-term recurrence
+        constexpr int NS = KinSlots<KIN>::n;
         const T nu = (vz - tb.Vp[p]) * tb.isp[p];
         const T g = T(1.41421356237309505) * Mth<T>::exp_(T(-0.5) * nu * nu);
         T hm = T(1);
         T hc = T(1.41421356237309505) * nu;
         o.jk = base;
-        o.kn = h.gh_nmax;
+        o.kn = (KIN == kKinGH4) ? 4 : h.gh_nmax;
         o.k[0] = g * hc;
 #pragma unroll
-        for (int n = 1; n < kMaxGH; ++n) {
-            if (n < h.gh_nmax) {
+        for (int n = 1; n < NS; ++n) {
+            if (KIN == kKinGH4 || n < h.gh_nmax) {
                 const T hn = T(kGhA[n]) * nu * hc - T(kGhB[n]) * hm;
                 hm = hc;
                 hc = hn;
@@ -262,9 +272,9 @@ template <typename T>
 __device__ __forceinline__ T phi_of(const Hot<T>& h, T r) {
     T p = -h.GMh / (r + h.a);
     if (h.GMn > T(0)) {
-        const T q = r / h.rs;
+        const T q = r * h.irs;
         const T l = (q > T(1e-4)) ? Mth<T>::log1p_(q) / q : T(1) - q * (T(0.5) - q * T(1.0 / 3.0));
-        p -= h.GMn / h.rs * l;
+        p -= h.GMn * h.irs * l;
     }
     return p;
 }
@@ -274,9 +284,9 @@ template <typename T>
 __device__ __forceinline__ T accel_of(const Hot<T>& h, T r) {
     if (!(r > T(0))) return T(0);
     const T ra = r + h.a;
-    T s = h.GMh / (r * ra * ra);
+    T s = h.GMh * Mth<T>::rcp_(r * ra * ra);
     if (h.GMn > T(0)) {
-        const T q = r / h.rs;
+        const T q = r * h.irs;
         T m;
         if (q < T(Mth<T>::nfw_series_max)) {
             // ln(1+q) - q/(1+q) = sum_{k>=2} (-1)^k (k-1) q^k / k
@@ -285,9 +295,9 @@ __device__ __forceinline__ T accel_of(const Hot<T>& h, T r) {
                  q * (T(2.0 / 3.0) -
                       q * (T(0.75) - q * (T(0.8) - q * (T(5.0 / 6.0) - q * (T(6.0 / 7.0) - q * T(0.875)))))));
         } else {
-            m = Mth<T>::log1p_(q) - q / (T(1) + q);
+            m = Mth<T>::log1p_(q) - q * Mth<T>::rcp_(T(1) + q);
         }
-        s += h.GMn * m / (r * r * r);
+        s += h.GMn * m * Mth<T>::rcp_(r * r * r);
     }
     return s;
 }
@@ -321,8 +331,8 @@ __device__ __forceinline__ int cell_of(const Hot<T>& h, T x, T y, T z, T vx, T v
                 const T ra = rc + h.a;
                 T dEc = T(0.5) * s * rc + h.GMh * h.a / (ra * ra * ra);
                 if (h.GMn > T(0)) {
-                    const T q1 = T(1) + rc / h.rs;
-                    dEc += T(0.5) * h.GMn / (h.rs * h.rs * q1 * q1);
+                    const T q1 = T(1) + rc * h.irs;
+                    dEc += T(0.5) * h.GMn * h.irs * h.irs / (q1 * q1);
                 }
                 const T rn = rc - (Ec - E) / dEc;
                 rc = (rn > T(0)) ? rn : T(0.5) * rc;
@@ -346,75 +356,51 @@ __device__ __forceinline__ int cell_of(const Hot<T>& h, T x, T y, T z, T vx, T v
 // times faster than FP32 LDS atomic adds). FP32 bins: every add returns the
 // value it replaced, and the exact rounding error of the add (TwoSum) goes
 // into the compensation array; all adds of the particle are issued before
-// their errors are formed.
+// their errors are formed. The error terms are exact only if every value is
+// rounded where the source rounds it: FP contraction is off in this part (a
+// product fused into the error's add would differ from the value added).
 __device__ __forceinline__ float two_sum_err(float old, float v) {
+#pragma clang fp contract(off)
     const float t = old + v;  // the value the add stored
     const float bp = t - old;
     return (old - (t - bp)) + (v - bp);
 }
 
-template <typename T>
+template <typename T, int KIN>
 __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, float>& tb,
-                                        const Kern<T>& kk, T w, int priv) {
+                                        const Kern<T, KIN>& kk, T u, int priv) {
+#pragma clang fp contract(off)
+    constexpr int NS = KinSlots<KIN>::n;
     const int kp = h.kp;
+    const float wf = (float)(u * h.w0);
     float o_r = 0.f;
-    float o_k[kMaxGH];
-    const float wf = (float)w;
+    float v[NS], o_k[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) v[m] = (float)(wf * kk.k[m]);
     if (kk.jr >= 0) o_r = atomicAdd(&tb.sum[kk.jr * kp + priv], wf);
 #pragma unroll
-    for (int m = 0; m < kMaxGH; ++m)
-        if (m < kk.kn) o_k[m] = atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (float)(w * kk.k[m]));
+    for (int m = 0; m < NS; ++m)
+        if (m < kk.kn) o_k[m] = atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], v[m]);
     if (kk.jr >= 0) atomicAdd(&tb.comp[kk.jr * kp + priv], two_sum_err(o_r, wf));
 #pragma unroll
-    for (int m = 0; m < kMaxGH; ++m)
-        if (m < kk.kn)
-            atomicAdd(&tb.comp[(kk.jk + m) * kp + priv], two_sum_err(o_k[m], (float)(w * kk.k[m])));
+    for (int m = 0; m < NS; ++m)
+        if (m < kk.kn) atomicAdd(&tb.comp[(kk.jk + m) * kp + priv], two_sum_err(o_k[m], v[m]));
 }
 
-template <typename T>
+template <typename T, int KIN>
 __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& tb,
-                                        const Kern<T>& kk, T w, int priv) {
+                                        const Kern<T, KIN>& kk, T u, int priv) {
+    constexpr int NS = KinSlots<KIN>::n;
     const int kp = h.kp;
+    const T w = u * h.w0;
     if (kk.jr >= 0) atomicAdd(&tb.sum[kk.jr * kp + priv], (double)w);
 #pragma unroll
-    for (int m = 0; m < kMaxGH; ++m)
+    for (int m = 0; m < NS; ++m)
         if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
 }
 
-// ------------------------------------------------------------- vector I/O --
-template <typename T, int PPL>
-struct alignas(sizeof(T) * PPL) Pack {
-    T v[PPL];
-};
-
-template <typename T, int PPL>
-__device__ __forceinline__ void load(const T* __restrict__ p, int64_t i, int cnt, T (&o)[PPL]) {
-    if (cnt == PPL) {
-        const Pack<T, PPL> t = *reinterpret_cast<const Pack<T, PPL>*>(p + i);
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) o[k] = t.v[k];
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) o[k] = (k < cnt) ? p[i + k] : T(0);
-    }
-}
-
-template <typename T, int PPL>
-__device__ __forceinline__ void store(T* __restrict__ p, int64_t i, int cnt, const T (&o)[PPL]) {
-    if (cnt == PPL) {
-        Pack<T, PPL> t;
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) t.v[k] = o[k];
-        *reinterpret_cast<Pack<T, PPL>*>(p + i) = t;
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPL; ++k)
-            if (k < cnt) p[i + k] = o[k];
-    }
-}
-
 // ------------------------------------------------------------- step --------
-template <typename T, typename A, int BLOCK, int PPL>
+template <typename T, typename A, int BLOCK, int KIN>
 __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -460,79 +446,85 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     double* row = fd.partials + (size_t)tl.row * (size_t)fd.row_len;
     __syncthreads();
 
-    T* __restrict__ X = static_cast<T*>(fd.x);
-    T* __restrict__ Y = static_cast<T*>(fd.y);
-    T* __restrict__ Z = static_cast<T*>(fd.z);
-    T* __restrict__ VX = static_cast<T*>(fd.vx);
-    T* __restrict__ VY = static_cast<T*>(fd.vy);
-    T* __restrict__ VZ = static_cast<T*>(fd.vz);
-    T* __restrict__ U = static_cast<T*>(fd.u);
-    T* __restrict__ UH = static_cast<T*>(fd.uh);
+    // particle arrays from the tile start: 32-bit offsets within the tile
+    T* __restrict__ X = static_cast<T*>(fd.x) + tl.begin;
+    T* __restrict__ Y = static_cast<T*>(fd.y) + tl.begin;
+    T* __restrict__ Z = static_cast<T*>(fd.z) + tl.begin;
+    T* __restrict__ VX = static_cast<T*>(fd.vx) + tl.begin;
+    T* __restrict__ VY = static_cast<T*>(fd.vy) + tl.begin;
+    T* __restrict__ VZ = static_cast<T*>(fd.vz) + tl.begin;
+    T* __restrict__ U = static_cast<T*>(fd.u) + tl.begin;
+    T* __restrict__ UH = static_cast<T*>(fd.uh) + tl.begin;
     const T* __restrict__ ucell = static_cast<const T*>(fd.ucell);
-    const int64_t end = tl.end;
+    const int len = (int)(tl.end - tl.begin);
+    const bool need_uh = correct || assign;
 
-    for (int64_t i0 = tl.begin + (int64_t)threadIdx.x * PPL; i0 < end;
-         i0 += (int64_t)BLOCK * PPL) {
-        const int cnt = (int)min<int64_t>(PPL, end - i0);
-        T px[PPL], py[PPL], pz[PPL], qx[PPL], qy[PPL], qz[PPL], pu[PPL], ph[PPL];
-        load<T, PPL>(X, i0, cnt, px);
-        load<T, PPL>(Y, i0, cnt, py);
-        load<T, PPL>(Z, i0, cnt, pz);
-        load<T, PPL>(VX, i0, cnt, qx);
-        load<T, PPL>(VY, i0, cnt, qy);
-        load<T, PPL>(VZ, i0, cnt, qz);
-        load<T, PPL>(U, i0, cnt, pu);
-        if (correct || assign) load<T, PPL>(UH, i0, cnt, ph);
+    // software pipeline: the loads of the next particle are in flight while
+    // the current one is computed
+    int i = threadIdx.x;
+    T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
+    if (i < len) {
+        nx = X[i];
+        ny = Y[i];
+        nz = Z[i];
+        nvx = VX[i];
+        nvy = VY[i];
+        nvz = VZ[i];
+        nu = U[i];
+        if (need_uh) nh = UH[i];
+    }
+    for (; i < len; i += BLOCK) {
+        T x = nx, y = ny, z = nz, vx = nvx, vy = nvy, vz = nvz, u = nu, uh = nh;
+        const int inext = i + BLOCK;
+        if (inext < len) {
+            nx = X[inext];
+            ny = Y[inext];
+            nz = Z[inext];
+            nvx = VX[inext];
+            nvy = VY[inext];
+            nvz = VZ[inext];
+            nu = U[inext];
+            if (need_uh) nh = UH[inext];
+        }
+        if (assign) uh = ucell[cell_of<T>(h, x, y, z, vx, vy, vz)];
+        if (correct) {
+            // force of change at z^k with the residuals of step k
+            const Kern<T, KIN> kk = kernels<T, A, KIN>(h, tb, x, y, z, vz);
+            T chi = (kk.jr >= 0) ? tb.rp[kk.jr] : T(0);
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            if (k >= cnt) continue;
-            T x = px[k], y = py[k], z = pz[k], vx = qx[k], vy = qy[k], vz = qz[k], u = pu[k];
-            if (assign) ph[k] = ucell[cell_of<T>(h, x, y, z, vx, vy, vz)];
-            if (correct) {
-                // force of change at z^k with the residuals of step k
-                const Kern<T> kk = kernels<T, A>(h, tb, x, y, z, vz);
-                T chi = (kk.jr >= 0) ? tb.rp[kk.jr] : T(0);
-#pragma unroll
-                for (int m = 0; m < kMaxGH; ++m)
-                    if (m < kk.kn) chi += kk.k[m] * tb.rp[kk.jk + m];
-                const T lr = Mth<T>::log_(u * Mth<T>::rcp_(ph[k]));
-                u = u * Mth<T>::exp_(-h.foc_mu * (lr + h.foc_cs) - chi);
-            }
-            if (push) {
-                x += h.hdt * vx;
-                y += h.hdt * vy;
-                z += h.hdt * vz;
-                const T s = accel_of<T>(h, Mth<T>::sqrt_(x * x + y * y + z * z)) * h.dt;
-                vx -= s * x;
-                vy -= s * y;
-                vz -= s * z;
-                x += h.hdt * vx;
-                y += h.hdt * vy;
-                z += h.hdt * vz;
-            }
-            if (deposit_on) deposit<T>(h, tb, kernels<T, A>(h, tb, x, y, z, vz), u * h.w0, priv);
-            if (refresh) {
-                const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
-                unsafeAtomicAdd(&row[J + c], (double)u);
-                unsafeAtomicAdd(&row[J + C + c], 1.0);
-            }
-            px[k] = x;
-            py[k] = y;
-            pz[k] = z;
-            qx[k] = vx;
-            qy[k] = vy;
-            qz[k] = vz;
-            pu[k] = u;
+            for (int m = 0; m < KinSlots<KIN>::n; ++m)
+                if (m < kk.kn) chi += kk.k[m] * tb.rp[kk.jk + m];
+            const T lr = Mth<T>::log_(u * Mth<T>::rcp_(uh));
+            u = u * Mth<T>::exp_(-h.foc_mu * (lr + h.foc_cs) - chi);
         }
         if (push) {
-            store<T, PPL>(X, i0, cnt, px);
-            store<T, PPL>(Y, i0, cnt, py);
-            store<T, PPL>(Z, i0, cnt, pz);
-            store<T, PPL>(VX, i0, cnt, qx);
-            store<T, PPL>(VY, i0, cnt, qy);
-            store<T, PPL>(VZ, i0, cnt, qz);
-            if (correct) store<T, PPL>(U, i0, cnt, pu);
-            if (assign) store<T, PPL>(UH, i0, cnt, ph);
+            x += h.hdt * vx;
+            y += h.hdt * vy;
+            z += h.hdt * vz;
+            const T s = accel_of<T>(h, Mth<T>::sqrt_(x * x + y * y + z * z)) * h.dt;
+            vx -= s * x;
+            vy -= s * y;
+            vz -= s * z;
+            x += h.hdt * vx;
+            y += h.hdt * vy;
+            z += h.hdt * vz;
+        }
+        if (deposit_on)
+            deposit<T, KIN>(h, tb, kernels<T, A, KIN>(h, tb, x, y, z, vz), u, priv);
+        if (refresh) {
+            const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
+            unsafeAtomicAdd(&row[J + c], (double)u);
+            unsafeAtomicAdd(&row[J + C + c], 1.0);
+        }
+        if (push) {
+            X[i] = x;
+            Y[i] = y;
+            Z[i] = z;
+            VX[i] = vx;
+            VY[i] = vy;
+            VZ[i] = vz;
+            if (correct) U[i] = u;
+            if (assign) UH[i] = uh;
         }
     }
     __syncthreads();
@@ -738,12 +730,25 @@ __global__ __launch_bounds__(256) void k_residuals(const FitDev* __restrict__ fi
     }
 }
 
-template <typename T, typename A, int BLOCK, int PPL>
+template <typename T, typename A, int BLOCK, int KIN>
 hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, int n_tiles, size_t lds,
                          int32_t mode, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<T, A, BLOCK, PPL>), dim3(n_tiles), dim3(BLOCK), lds, s, fits, tiles,
-                       mode);
+    hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                       tiles, mode);
     return hipGetLastError();
+}
+
+template <typename T, typename A, int BLOCK>
+hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, int n_tiles,
+                           size_t lds, int32_t mode, hipStream_t s) {
+    switch (kin) {
+        case kKinNone: return launch_step_t<T, A, BLOCK, kKinNone>(fits, tiles, n_tiles, lds, mode, s);
+        case kKinV2: return launch_step_t<T, A, BLOCK, kKinV2>(fits, tiles, n_tiles, lds, mode, s);
+        case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, n_tiles, lds, mode, s);
+        case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, n_tiles, lds, mode, s);
+        case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, n_tiles, lds, mode, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -766,27 +771,29 @@ int private_copies(bool f64, int J) {
     return k;
 }
 
-hipError_t launch_step(bool f64, bool acc64, int block, int ppl, const FitDev* fits,
+int kin_class(int kin, int gh_nmax) {
+    switch (kin) {
+        case 0: return kKinNone;
+        case 1: return kKinV2;
+        case 2: return gh_nmax == 4 ? kKinGH4 : kKinGHN;
+        case 3: return kKinLOSVD;
+        default: return -1;
+    }
+}
+
+hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* fits,
                        const Tile* tiles, int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    if (f64) {
-        if (ppl >= 2) return launch_step_t<double, double, 256, 2>(fits, tiles, n_tiles, lds, mode, s);
-        return launch_step_t<double, double, 256, 1>(fits, tiles, n_tiles, lds, mode, s);
+    if (f64) return launch_step_kin<double, double, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
+    if (acc64) {
+        if (block == 256) return launch_step_kin<float, double, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
+        if (block == 512) return launch_step_kin<float, double, 512>(kin, fits, tiles, n_tiles, lds, mode, s);
+        if (block == 1024) return launch_step_kin<float, double, 1024>(kin, fits, tiles, n_tiles, lds, mode, s);
+    } else {
+        if (block == 256) return launch_step_kin<float, float, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
+        if (block == 512) return launch_step_kin<float, float, 512>(kin, fits, tiles, n_tiles, lds, mode, s);
+        if (block == 1024) return launch_step_kin<float, float, 1024>(kin, fits, tiles, n_tiles, lds, mode, s);
     }
-#define M2M_STEP_CASE(B, P)                                                                    \
-    if (block == B && ppl == P)                                                                \
-        return acc64 ? launch_step_t<float, double, B, P>(fits, tiles, n_tiles, lds, mode, s)  \
-                     : launch_step_t<float, float, B, P>(fits, tiles, n_tiles, lds, mode, s);
-    M2M_STEP_CASE(256, 1)
-    M2M_STEP_CASE(256, 2)
-    M2M_STEP_CASE(256, 4)
-    M2M_STEP_CASE(512, 1)
-    M2M_STEP_CASE(512, 2)
-    M2M_STEP_CASE(512, 4)
-    M2M_STEP_CASE(1024, 1)
-    M2M_STEP_CASE(1024, 2)
-    M2M_STEP_CASE(1024, 4)
-#undef M2M_STEP_CASE
     return hipErrorInvalidValue;
 }
 

@@ -44,9 +44,9 @@ def test_host_only_entry_points():
     assert _abi.m2m_workspace_bytes(wl.layout, wl.params, 0) == 0
     b0 = _abi.m2m_get_launch()
     with pytest.raises(_abi.M2MError):
-        _abi.m2m_set_launch(300, 4, 4)
-    _abi.m2m_set_launch(512, 2, 2)
-    assert _abi.m2m_get_launch() == (512, 2, 2)
+        _abi.m2m_set_launch(300, 4)
+    _abi.m2m_set_launch(512, 2)
+    assert _abi.m2m_get_launch() == (512, 2)
     _abi.m2m_set_launch(*b0)
 
 

@@ -306,6 +306,7 @@ def test_full_size_workloads(oracle, Fit, wlid, steps):
     from bench import LAUNCH
     from paper_1202_2355_amd import _abi
     wl = workload(wlid)
+    before = _abi.m2m_get_launch()
     _abi.m2m_set_launch(*LAUNCH[wlid])
     _say("full size", wl.name, wl.N, "launch", LAUNCH[wlid])
     T = oracle_targets(oracle, wl)
@@ -325,4 +326,4 @@ def test_full_size_workloads(oracle, Fit, wlid, steps):
     _say("full size", wl.name, "rel2", r2, "max(unflagged)", rmax, "flagged", frac)
     assert r2 <= 1e-4 and rmax <= 1e-4
     f.close()
-    _abi.m2m_set_launch(256, 4, 4)
+    _abi.m2m_set_launch(*before)
