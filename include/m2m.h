@@ -55,8 +55,11 @@
  *   structure-of-arrays layout, float (M2M_F32) or double (M2M_F64), each
  *   16-byte aligned, owned by the caller and required to outlive the
  *   context. The library owns (or borrows, if a workspace is passed) one
- *   device workspace per context holding targets, observables, tables and
- *   reduction buffers. All device work is enqueued on the stream given at
+ *   device workspace per context holding targets, observables, tables,
+ *   reduction buffers and the prior cell of every particle at the last
+ *   refresh (2 bytes per particle). New priors reach u_prior at the start of
+ *   the step after a refresh, or at m2m_get_weights / m2m_get_state /
+ *   m2m_update_priors, whichever comes first. All device work is enqueued on the stream given at
  *   creation (a hipStream_t passed as void*; NULL is the null stream).
  *
  * Errors

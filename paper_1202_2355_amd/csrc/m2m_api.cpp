@@ -167,7 +167,7 @@ constexpr double kLz1 = 20.7232658369464;   // ln 1e9
 
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
-    size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab;
+    size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
     int seg_cap, row_len, nbj, ncj, J, C;
 };
@@ -221,6 +221,7 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.hist = take(8 * (size_t)kHistCap);
     w.chi2p = take(8 * (size_t)w.nbj);
     w.partials = take(8 * (size_t)w.seg_cap * (size_t)w.row_len);
+    w.cidx = take(2 * (size_t)n);
     w.total = o;
     return w;
 }
@@ -249,6 +250,7 @@ struct m2m_ctx {
     int n_jobs = 0;
     size_t lds = 0;
     int block = 256, kin = 0;
+    hipGraphExec_t graph_fin = nullptr;
     bool acc64 = true;
     bool targets = false;
     bool ytil_init = false;
@@ -351,35 +353,57 @@ m2m_status run_direct(m2m_ctx* c, int steps) {
     for (int k = 0; k < steps; ++k) {
         M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
                                c->lds, kModeStep, c->stream));
-        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->stream));
+        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, c->stream));
     }
     return M2M_OK;
+}
+
+// Capture kGraphSteps repetitions of body(stream) on the capture stream and
+// instantiate them as one graph.
+template <typename F>
+hipError_t capture_steps(hipStream_t cap, F body, hipGraphExec_t* out) {
+    *out = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = body(cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) *out = nullptr;
+    return e;
 }
 
 m2m_status ensure_graph(m2m_ctx* c) {
     if (c->graph) return M2M_OK;
     if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-    M2M_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
-                        kModeStep, c->cap);
-        if (e == hipSuccess)
-            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeStep, c->cap);
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
-    if (e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return hip_fail(c, e, "capture");
-    }
-    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        c->graph = nullptr;
-        return hip_fail(c, e, "hipGraphInstantiate");
-    }
+    const hipError_t e = capture_steps(
+        c->cap,
+        [c](hipStream_t s) {
+            hipError_t r = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles,
+                                       c->n_tiles, c->lds, kModeStep, s);
+            if (r == hipSuccess)
+                r = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, s);
+            return r;
+        },
+        &c->graph);
+    if (e != hipSuccess) return hip_fail(c, e, "step graph");
+    return M2M_OK;
+}
+
+// The reduction part of a step in a measuring mode that changes no state
+// (observe-mode finalize), as a graph like the steps.
+m2m_status ensure_measure_graph(m2m_ctx* c) {
+    if (c->graph_fin) return M2M_OK;
+    if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    const hipError_t e = capture_steps(
+        c->cap,
+        [c](hipStream_t s) {
+            return launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, s);
+        },
+        &c->graph_fin);
+    if (e != hipSuccess) return hip_fail(c, e, "measure graph");
     return M2M_OK;
 }
 
@@ -457,7 +481,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
     c->lds = step_lds_bytes(c->f64, c->acc64, w.J, c->lay.n_r,
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
-                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv);
+                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C);
     if (c->lds > max_lds()) {
         delete c;
         return M2M_EUNSUPPORTED;
@@ -542,6 +566,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.E_scale = c->par.n_E / (c->par.E_hi - c->par.E_lo);
     f.ucell = b + w.ucell;
     f.lctab = b + w.lctab;
+    f.cidx = reinterpret_cast<uint16_t*>(b + w.cidx);
     f.lz0 = kLz0;
     f.ilz = (kLcTable - 1) / (kLz1 - kLz0);
     const double dt = c->par.dt;
@@ -635,7 +660,7 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     if (!c->ytil_init) {
         M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                                kModeInit, c->stream));
-        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeInit, c->stream));
+        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeInit, c->stream));
         c->ytil_init = true;
     } else {
         M2M_HIP(c, launch_residuals(c->f64, c->fd_dev, c->stream));
@@ -666,7 +691,7 @@ m2m_status m2m_update_priors(m2m_ctx* c) {
     if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
     M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeCells, c->stream));
-    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeCells, c->stream));
+    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeCells, c->stream));
     M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
     return M2M_OK;
 }
@@ -744,7 +769,7 @@ m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, dou
     }
     M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
                            kModeObserve, c->stream));
-    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream));
+    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, c->stream));
     if ((s = sync(c)) != M2M_OK) return s;
     M2M_HIP(c, hipMemcpy(y, c->fd.obs_out, 8 * (size_t)c->w.J, hipMemcpyDeviceToHost));
     if (tmp && (s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return s;
@@ -772,7 +797,9 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
         return M2M_OK;
     }
     if (*bytes < need) return fail(c, M2M_EINVAL, "state buffer too small");
-    m2m_status s = sync(c);
+    // a saved state never has an assignment pending: the cell of each
+    // particle is kept in the workspace, not in the state
+    m2m_status s = flush_assign(c);
     if (s != M2M_OK) return s;
     unsigned char* p = static_cast<unsigned char*>(host_blob);
     StateHeader h{kStateMagic, 1u, c->n, (int32_t)J, (int32_t)C, c->f64 ? 1 : 0, (int32_t)nR,
@@ -818,7 +845,9 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     FitState st{};
     std::memcpy(&st, p, sizeof st);
     st.ticket = 0;
+    st.mticket = 0;
     st.steps_left = 0;
+    st.assign_pending = 0;
     M2M_HIP(c, hipMemcpy(c->st, &st, sizeof st, hipMemcpyHostToDevice));
     p += sizeof(FitState);
     double* const dev[5] = {c->fd.ytil, c->fd.yv, c->fd.delta, c->fd.Y, c->fd.sigma};
@@ -860,12 +889,14 @@ m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double
         if (st != M2M_OK) e = hipErrorUnknown;
     }
     if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-    // (2) n back-to-back finalize launches of the same reduction (measuring
-    // mode: no state changes)
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-        if (k == 0) e = hipEventRecord(ev[2], c->stream);
-        if (e == hipSuccess)
-            e = launch_finalize(c->f64, c->fd_dev, c->jobs, c->n_jobs, kModeObserve, c->stream);
+    // (2) the same n reductions in measuring mode (no state changes),
+    // launched the same way
+    if (e == hipSuccess && ensure_measure_graph(c) != M2M_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+    for (int k = 0; k + kGraphSteps <= n_steps && e == hipSuccess; k += kGraphSteps)
+        e = hipGraphLaunch(c->graph_fin, c->stream);
+    for (int k = 0; k < n_steps % kGraphSteps && e == hipSuccess; ++k) {
+        e = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, c->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -886,6 +917,7 @@ m2m_status m2m_destroy(m2m_ctx* c) {
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_fin) (void)hipGraphExecDestroy(c->graph_fin);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own_ws) (void)hipFree(c->ws);
     delete c;
@@ -909,11 +941,12 @@ struct m2m_batch {
     int32_t* gather_dev = nullptr;
     int32_t* gather_host = nullptr;
     size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
-    int n_tiles = 0, n_jobs = 0;
+    int n_tiles = 0, n_jobs = 0, n_fits = 0;
     size_t lds = 0;
     int block = 256, kin = -1;
     bool acc64 = true;
     hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph_fin = nullptr;
 };
 
 namespace {
@@ -939,7 +972,11 @@ m2m_status rebuild(m2m_batch* b) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
-    b->n_tiles = b->n_jobs = 0;
+    if (b->graph_fin) {
+        (void)hipGraphExecDestroy(b->graph_fin);
+        b->graph_fin = nullptr;
+    }
+    b->n_tiles = b->n_jobs = b->n_fits = 0;
     if (b->fits.empty()) {
         b->dirty = false;
         return M2M_OK;
@@ -974,28 +1011,29 @@ m2m_status rebuild(m2m_batch* b) {
         return M2M_EDEVICE;
     b->n_tiles = (int)tl.size();
     b->n_jobs = (int)jb.size();
+    b->n_fits = (int)fd.size();
     b->lds = lds;
-    // graph of kGraphSteps steps over this composition
-    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    // graphs of kGraphSteps steps over this composition, and of the same
+    // reductions in measuring mode (m2m_batch_profile)
+    hipError_t e = capture_steps(
+        b->cap,
+        [b, f64](hipStream_t s) {
+            hipError_t r = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev,
+                                       b->n_tiles, b->lds, kModeStep, s);
+            if (r == hipSuccess)
+                r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s);
+            return r;
+        },
+        &b->graph);
+    if (e == hipSuccess)
+        e = capture_steps(
+            b->cap,
+            [b, f64](hipStream_t s) {
+                return launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
+                                       kModeObserve, s);
+            },
+            &b->graph_fin);
     if (e != hipSuccess) return M2M_EDEVICE;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
-                        b->lds, kModeStep, b->cap);
-        if (e == hipSuccess)
-            e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->cap);
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return M2M_EDEVICE;
-    }
-    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        b->graph = nullptr;
-        return M2M_EDEVICE;
-    }
     b->dirty = false;
     return M2M_OK;
 }
@@ -1069,7 +1107,7 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
     for (int k = 0; k < rem; ++k)
         if (launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
                         b->lds, kModeStep, b->stream) != hipSuccess ||
-            launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
+            launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
             return M2M_EDEVICE;
     return M2M_OK;
 }
@@ -1131,8 +1169,12 @@ m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, dou
     if (e == hipSuccess && m2m_batch_run(b, n_steps) != M2M_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k)
-        e = launch_finalize(f64, b->fits_dev, b->jobs_dev, b->n_jobs, kModeObserve, b->stream);
+    for (int k = 0; k + kGraphSteps <= n_steps && e == hipSuccess; k += kGraphSteps)
+        e = hipGraphLaunch(b->graph_fin, b->stream);
+    for (int k = 0; k < n_steps % kGraphSteps && e == hipSuccess; ++k) {
+        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeObserve,
+                            b->stream);
+    }
     if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     float t_all = 0.f, t_fin = 0.f;
@@ -1181,6 +1223,7 @@ m2m_status m2m_batch_destroy(m2m_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     for (m2m_ctx* c : b->fits) c->batch = nullptr;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_fin) (void)hipGraphExecDestroy(b->graph_fin);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->fits_dev) (void)hipFree(b->fits_dev);
     if (b->tiles_dev) (void)hipFree(b->tiles_dev);

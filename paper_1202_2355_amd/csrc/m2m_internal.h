@@ -16,7 +16,7 @@ constexpr int kLcTable = 8192;     // entries of the ln r_c(ln zeta) table
 constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
 constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
-constexpr int kSegAlign = 4;       // tile boundaries are multiples of 4 particles
+constexpr int kSegAlign = 64;      // tile boundaries are multiples of 64 particles
 
 // kernel launch modes (bit set)
 enum : int32_t {
@@ -36,7 +36,7 @@ struct FitState {
     int32_t assign_pending;  // fresh cell priors wait to be assigned
     int32_t error;           // bit 0: non-finite chi^2 seen
     uint32_t ticket;         // finalize: blocks done this launch
-    int32_t pad0;
+    uint32_t mticket;        // the same in observe mode
     double chi2;             // chi^2 after the last step
 };
 
@@ -65,6 +65,7 @@ struct FitDev {
     int32_t n_E, n_x, prior_every, pad1;
     double E_lo, E_hi, E_scale;  // E_scale = n_E / (E_hi - E_lo)
     void *ucell, *lctab;         // C values; kLcTable values of ln r_c(ln zeta)
+    uint16_t *cidx;              // n values: cell of each particle at the last refresh
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
     // step constants
     double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
@@ -96,8 +97,9 @@ hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* f
                        const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
                        hipStream_t s);
 int kin_class(int kin, int gh_nmax);
-hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
-                           int32_t mode, hipStream_t s);
+// the column jobs of the fits of the table (n_fits of them)
+hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
+                           int n_jobs, int32_t mode, hipStream_t s);
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
                          hipStream_t s);
 hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double scale,
@@ -105,7 +107,7 @@ hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double sc
 hipError_t launch_poke(FitState* st, int32_t steps_left, int32_t correct, hipStream_t s);
 hipError_t launch_gather(const FitDev* fits, int n, int32_t* out, hipStream_t s);
 hipError_t launch_residuals(bool f64, const FitDev* fit, hipStream_t s);
-size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv);
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C);
 int private_copies(bool f64, int J);
 
 }  // namespace m2m

@@ -72,23 +72,29 @@ __constant__ double kGhB[kMaxGH] = {0.0,
 // In-tile bins: FP64 sums (A = double), or FP32 sums with an FP32 array of
 // their compensation (A = float). They are kept in kpriv private copies,
 // interleaved (copy g of bin j at j * kpriv + g); lane l adds into copy
-// l mod kpriv. The FP64 arrays come first so that they are 8-byte aligned.
+// l mod kpriv. Then the prior-cell sums of the tile (FP64 weight sums and
+// integer counts), then the tables. The 8-byte arrays come first so that
+// they are aligned.
 template <typename T, typename A>
 struct Tabs {
     A *sum, *comp;
+    double* csum;
+    uint32_t* ccnt;
     T *rp, *re2, *Re2, *ve, *Vp, *isp;
 };
 
 template <typename T, typename A>
 __device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, int n_r, int n_R,
-                                            int n_v) {
+                                            int n_v, int C) {
     Tabs<T, A> t;
     A* q = reinterpret_cast<A*>(raw);
     t.sum = q;
     q += J * kp;
     t.comp = q;
     if (sizeof(A) == 4) q += J * kp;
-    T* p = reinterpret_cast<T*>(q);
+    t.csum = reinterpret_cast<double*>(q);
+    t.ccnt = reinterpret_cast<uint32_t*>(t.csum + C);
+    T* p = reinterpret_cast<T*>(t.ccnt + ((C + 1) & ~1));  // 8-byte aligned
     t.rp = p;
     p += J;
     t.re2 = p;
@@ -406,8 +412,35 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const Tile tl = tiles[blockIdx.x];
     const FitDev& fd = fits[tl.fit];
-    const FitState* st = fd.st;
     const bool step = (mode & kModeStep) != 0;
+
+    // particle arrays from the tile start (32-bit offsets within the tile);
+    // the first particle of every lane is requested before anything else so
+    // that its latency overlaps the set-up below
+    T* __restrict__ X = static_cast<T*>(fd.x) + tl.begin;
+    T* __restrict__ Y = static_cast<T*>(fd.y) + tl.begin;
+    T* __restrict__ Z = static_cast<T*>(fd.z) + tl.begin;
+    T* __restrict__ VX = static_cast<T*>(fd.vx) + tl.begin;
+    T* __restrict__ VY = static_cast<T*>(fd.vy) + tl.begin;
+    T* __restrict__ VZ = static_cast<T*>(fd.vz) + tl.begin;
+    T* __restrict__ U = static_cast<T*>(fd.u) + tl.begin;
+    T* __restrict__ UH = static_cast<T*>(fd.uh) + tl.begin;
+    uint16_t* __restrict__ CI = fd.cidx + tl.begin;
+    const int len = (int)(tl.end - tl.begin);
+    int i = threadIdx.x;
+    T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
+    if (i < len) {
+        nx = X[i];
+        ny = Y[i];
+        nz = Z[i];
+        nvx = VX[i];
+        nvy = VY[i];
+        nvz = VZ[i];
+        nu = U[i];
+        if (step) nh = UH[i];
+    }
+
+    const FitState* st = fd.st;
     if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
     const bool cells_only = (mode & kModeCells) != 0;
     const bool correct = step && st->correct != 0;
@@ -419,7 +452,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     const Hot<T> h = hot_of<T>(fd);
     const int J = h.J, C = h.C, kp = h.kp;
 
-    Tabs<T, A> tb = carve<T, A>(lds_raw, J, kp, h.n_r, h.n_R, h.n_v);
+    Tabs<T, A> tb = carve<T, A>(lds_raw, J, kp, h.n_r, h.n_R, h.n_v, C);
     const int priv = threadIdx.x & (kp - 1);
     {
         const T* rp = static_cast<const T*>(fd.rp);
@@ -428,6 +461,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             tb.sum[j] = A(0);
             if (sizeof(A) == 4) tb.comp[j] = A(0);
         }
+        if (refresh)
+            for (int j = threadIdx.x; j < C; j += BLOCK) {
+                tb.csum[j] = 0.0;
+                tb.ccnt[j] = 0u;
+            }
         const T* re2 = static_cast<const T*>(fd.redge2);
         for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.re2[j] = re2[j];
         const T* Re2 = static_cast<const T*>(fd.Redge2);
@@ -441,38 +479,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             tb.isp[j] = isp[j];
         }
     }
-    // the cell columns of a tile row are zero here: the finalize clears them
-    // after reading them (and the workspace starts cleared)
     double* row = fd.partials + (size_t)tl.row * (size_t)fd.row_len;
-    __syncthreads();
-
-    // particle arrays from the tile start: 32-bit offsets within the tile
-    T* __restrict__ X = static_cast<T*>(fd.x) + tl.begin;
-    T* __restrict__ Y = static_cast<T*>(fd.y) + tl.begin;
-    T* __restrict__ Z = static_cast<T*>(fd.z) + tl.begin;
-    T* __restrict__ VX = static_cast<T*>(fd.vx) + tl.begin;
-    T* __restrict__ VY = static_cast<T*>(fd.vy) + tl.begin;
-    T* __restrict__ VZ = static_cast<T*>(fd.vz) + tl.begin;
-    T* __restrict__ U = static_cast<T*>(fd.u) + tl.begin;
-    T* __restrict__ UH = static_cast<T*>(fd.uh) + tl.begin;
     const T* __restrict__ ucell = static_cast<const T*>(fd.ucell);
-    const int len = (int)(tl.end - tl.begin);
     const bool need_uh = correct || assign;
+    __syncthreads();
 
     // software pipeline: the loads of the next particle are in flight while
     // the current one is computed
-    int i = threadIdx.x;
-    T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
-    if (i < len) {
-        nx = X[i];
-        ny = Y[i];
-        nz = Z[i];
-        nvx = VX[i];
-        nvy = VY[i];
-        nvz = VZ[i];
-        nu = U[i];
-        if (need_uh) nh = UH[i];
-    }
     for (; i < len; i += BLOCK) {
         T x = nx, y = ny, z = nz, vx = nvx, vy = nvy, vz = nvz, u = nu, uh = nh;
         const int inext = i + BLOCK;
@@ -486,7 +499,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             nu = U[inext];
             if (need_uh) nh = UH[inext];
         }
-        if (assign) uh = ucell[cell_of<T>(h, x, y, z, vx, vy, vz)];
+        // the prior of the particle's cell at the last refresh (same
+        // phase-space point: no push in between)
+        if (assign) uh = ucell[min((int)CI[i], C - 1)];
         if (correct) {
             // force of change at z^k with the residuals of step k
             const Kern<T, KIN> kk = kernels<T, A, KIN>(h, tb, x, y, z, vz);
@@ -509,12 +524,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             y += h.hdt * vy;
             z += h.hdt * vz;
         }
-        if (deposit_on)
-            deposit<T, KIN>(h, tb, kernels<T, A, KIN>(h, tb, x, y, z, vz), u, priv);
+        if (deposit_on) deposit<T, KIN>(h, tb, kernels<T, A, KIN>(h, tb, x, y, z, vz), u, priv);
         if (refresh) {
             const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
-            unsafeAtomicAdd(&row[J + c], (double)u);
-            unsafeAtomicAdd(&row[J + C + c], 1.0);
+            atomicAdd(&tb.csum[c], (double)u);
+            atomicAdd(&tb.ccnt[c], 1u);
+            CI[i] = (uint16_t)c;
         }
         if (push) {
             X[i] = x;
@@ -537,14 +552,27 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             }
             row[j] = t;
         }
+    if (refresh)
+        for (int j = threadIdx.x; j < C; j += BLOCK) {
+            row[J + j] = tb.csum[j];
+            row[J + C + j] = (double)tb.ccnt[j];
+        }
 }
 
 // ------------------------------------------------------------- finalize ----
+// One block per job of kFinCols columns of one fit: the column sums over the
+// fit's tile rows in a fixed order (wave w takes rows w, w + 16, ...; the
+// waves are then added in order), then for observable columns the smoothing
+// (eq. myts), Delta and chi^2 (eqs. delta, chi) and the force table, and for
+// cell columns the cell means that become the priors (Sec. 2.3.1). The last
+// block of a fit to finish (ticket) ends the step: chi^2 from the parts of
+// the bin jobs and the step counters, prior schedule and assignment flag.
 template <typename T>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
                                                          const FinJob* __restrict__ jobs,
                                                          int32_t mode) {
     constexpr int kWaves = kFinThreads / 64;
+    constexpr int U = 16;  // rows in flight per lane
     __shared__ double part[kWaves][kFinCols];
     __shared__ double part2[kWaves][kFinCols];
     __shared__ int last;
@@ -555,44 +583,58 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     const bool cells_mode = (mode & kModeCells) != 0;
     const bool observe = (mode & kModeObserve) != 0;
     const bool init = (mode & kModeInit) != 0;
-    if (step && st->steps_left <= 0) return;
-    const bool correct = step && st->correct != 0;
-    const bool refresh = cells_mode || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
-                                        ((st->kstep + 1) % fd.prior_every) == 0);
     const bool bins = jb.kind == 0;
-    if (bins && cells_mode) return;
-    if (!bins && !refresh) return;
-    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
-                            (refresh ? (uint32_t)fd.n_cell_jobs : 0u);
-
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = jb.col0 + lane;
     const int J = fd.J, C = fd.C;
-    const int ncols = bins ? J : C;
+    const size_t stride = (size_t)fd.row_len;
+
+    // observable columns: the rows and the smoothing inputs are requested
+    // before the fit's state is known (their latency overlaps its load)
     double acc = 0.0, acc2 = 0.0;
-    if (col < ncols) {
-        double* base = fd.partials + (bins ? col : J + col);
-        const size_t stride = (size_t)fd.row_len;
-        int t = wave;
-        if (bins) {
-            // eight rows in flight, added in row order
-            constexpr int U = 8;
-            for (; t + (U - 1) * kWaves < jb.n_tiles; t += U * kWaves) {
+    double yt0 = 0.0, sg = 1.0, Yj = 0.0;
+    if (bins && !cells_mode) {
+        if (col < J) {
+            const double* base = fd.partials + col;
+            for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
                 double v[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) v[k] = base[(size_t)(t + k * kWaves) * stride];
+                for (int k = 0; k < U; ++k) {
+                    const int t = t0 + k * kWaves;
+                    v[k] = (t < jb.n_tiles) ? base[(size_t)t * stride] : 0.0;
+                }
 #pragma unroll
                 for (int k = 0; k < U; ++k) acc += v[k];
             }
-            for (; t < jb.n_tiles; t += kWaves) acc += base[(size_t)t * stride];
-        } else {
-            for (; t < jb.n_tiles; t += kWaves) {
-                acc += base[(size_t)t * stride];
-                acc2 += base[(size_t)t * stride + C];
-                // leave the cell columns cleared for the next accumulation
-                base[(size_t)t * stride] = 0.0;
-                base[(size_t)t * stride + C] = 0.0;
+            if (wave == 0 && !observe) {
+                yt0 = fd.ytil[col];
+                sg = fd.sigma[col];
+                Yj = fd.Y[col];
+            }
+        }
+    }
+    if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
+    const bool correct = step && st->correct != 0;
+    const bool refresh = cells_mode || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
+                                        ((st->kstep + 1) % fd.prior_every) == 0);
+    if (bins && cells_mode) return;
+    if (!bins && !refresh) return;
+    if (!bins && col < C) {
+        // cell columns, read only on refresh steps
+        const double* base = fd.partials + J + col;
+        for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
+            double v[U], w[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int t = t0 + k * kWaves;
+                v[k] = (t < jb.n_tiles) ? base[(size_t)t * stride] : 0.0;
+                w[k] = (t < jb.n_tiles) ? base[(size_t)t * stride + C] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                acc += v[k];
+                acc2 += w[k];
             }
         }
     }
@@ -606,23 +648,20 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
             tot2 += part2[w][lane];
         }
         double d2 = 0.0;
-        if (col < ncols) {
-            if (bins) {
-                if (observe) {
-                    fd.obs_out[col] = tot;
-                } else {
-                    fd.yv[col] = tot;
-                    const double yt = init ? tot : fd.ytil[col] + fd.q * (tot - fd.ytil[col]);
-                    fd.ytil[col] = yt;
-                    const double s = fd.sigma[col];
-                    const double d = (yt - fd.Y[col]) / s;
-                    fd.delta[col] = d;
-                    static_cast<T*>(fd.rp)[col] = (T)(fd.foc_chi * d / s);
-                    d2 = d * d;
-                }
-            } else if (tot2 > 0.0) {
-                static_cast<T*>(fd.ucell)[col] = (T)(tot / tot2);
+        if (bins && col < J) {
+            if (observe) {
+                fd.obs_out[col] = tot;
+            } else {
+                fd.yv[col] = tot;
+                const double yt = init ? tot : yt0 + fd.q * (tot - yt0);
+                fd.ytil[col] = yt;
+                const double d = (yt - Yj) / sg;
+                fd.delta[col] = d;
+                static_cast<T*>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
+                d2 = d * d;
             }
+        } else if (!bins && col < C && tot2 > 0.0) {
+            static_cast<T*>(fd.ucell)[col] = (T)(tot / tot2);
         }
         if (bins && !observe) {
             // chi^2 of these columns: fixed-order butterfly over the wave
@@ -630,20 +669,31 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
             if (lane == 0) fd.chi2_part[jb.col0 / kFinCols] = d2;
         }
     }
-    if (observe) return;
+    // the last job of this fit ends the step; in observe mode the same
+    // hand-over runs on a separate counter and changes no state
+    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
+                            (refresh ? (uint32_t)fd.n_cell_jobs : 0u);
+    uint32_t* ticket = observe ? &st->mticket : &st->ticket;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        const uint32_t prev = atomicAdd(&st->ticket, 1u);
+        const uint32_t prev = atomicAdd(ticket, 1u);
         last = (prev == n_part - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
+    if (!last || wave != 0) return;
     __threadfence();
-    st->ticket = 0u;
+    double chi2 = 0.0;
     if (!cells_mode) {
-        double chi2 = 0.0;
-        for (int b = 0; b < fd.n_bin_jobs; ++b) chi2 += fd.chi2_part[b];
+        // lane l adds parts l, l + 64, ... in order, then a fixed-order
+        // butterfly over the wave
+        for (int b = lane; b < fd.n_bin_jobs; b += 64) chi2 += fd.chi2_part[b];
+        for (int off = 32; off >= 1; off >>= 1) chi2 += __shfl_xor(chi2, off, 64);
+    }
+    if (lane != 0) return;
+    *ticket = 0u;
+    if (observe) return;
+    if (!cells_mode) {
         st->chi2 = chi2;
         if (!isfinite(chi2)) st->error |= 1;
         if (step) fd.chi2_hist[st->tstep % kHistCap] = chi2;
@@ -663,17 +713,12 @@ __global__ __launch_bounds__(256) void k_assign(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
     const FitDev& fd = fits[tl.fit];
-    const T* X = static_cast<const T*>(fd.x);
-    const T* Y = static_cast<const T*>(fd.y);
-    const T* Z = static_cast<const T*>(fd.z);
-    const T* VX = static_cast<const T*>(fd.vx);
-    const T* VY = static_cast<const T*>(fd.vy);
-    const T* VZ = static_cast<const T*>(fd.vz);
     T* UH = static_cast<T*>(fd.uh);
+    const uint16_t* CI = fd.cidx;
     const T* ucell = static_cast<const T*>(fd.ucell);
-    const Hot<T> h = hot_of<T>(fd);
+    const int C = fd.C;
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += 256)
-        UH[i] = ucell[cell_of<T>(h, X[i], Y[i], Z[i], VX[i], VY[i], VZ[i])];
+        UH[i] = ucell[min((int)CI[i], C - 1)];
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // every tile of this launch belongs to one fit; the flag is consumed
@@ -753,10 +798,10 @@ hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, int n
 
 }  // namespace
 
-size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv) {
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C) {
     (void)acc64;  // FP64 sums and FP32 sum + compensation both take 8 bytes per bin copy
     const size_t sz = f64 ? 8 : 4;
-    const size_t bins = (size_t)J * (size_t)kpriv * 8;
+    const size_t bins = (size_t)J * (size_t)kpriv * 8 + (size_t)C * 8 + (size_t)((C + 1) & ~1) * 4;
     const size_t tabs = ((size_t)J + (size_t)(n_r + 1) + (size_t)(n_R + 1) + (size_t)(n_v + 1) +
                          2 * (size_t)n_R) * sz;
     return ((bins + tabs + 15) / 16) * 16;
@@ -797,8 +842,8 @@ hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* f
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int n_jobs,
-                           int32_t mode, hipStream_t s) {
+hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
+                           int n_jobs, int32_t mode, hipStream_t s) {
     if (n_jobs <= 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(k_finalize<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
@@ -806,6 +851,7 @@ hipError_t launch_finalize(bool f64, const FitDev* fits, const FinJob* jobs, int
     else
         hipLaunchKernelGGL(k_finalize<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
                            mode);
+    (void)n_fits;
     return hipGetLastError();
 }
 
