@@ -987,15 +987,19 @@ m2m_status rebuild(m2m_batch* b) {
     std::vector<FitDev> fd;
     std::vector<Tile> tl;
     std::vector<FinJob> jb;
-    double ntot = 0;
-    for (m2m_ctx* c : b->fits) ntot += (double)c->n;
+    int64_t ntot = 0;
+    for (m2m_ctx* c : b->fits) ntot += c->n;
+    // one tile size for the whole batch, so that every block streams about
+    // the same number of particles: about target tiles in all
     const int target = std::max(1, g_tiles_per_cu * n_cus());
+    int64_t tile = (ntot + target - 1) / target;
+    tile = (tile + kSegAlign - 1) / kSegAlign * kSegAlign;
     size_t lds = 0;
     for (size_t f = 0; f < b->fits.size(); ++f) {
         m2m_ctx* c = b->fits[f];
         fd.push_back(c->fd);
-        int cnt = (int)std::lround(target * (double)c->n / ntot);
-        cnt = std::max(1, std::min(cnt, c->w.seg_cap));
+        int cnt = (int)std::min<int64_t>((c->n + tile - 1) / tile, c->w.seg_cap);
+        cnt = std::max(1, cnt);
         split_tiles(c->n, cnt, (int)f, 0, tl);
         fin_jobs(c->w, (int)f, cnt, jb);
         lds = std::max(lds, c->lds);

@@ -37,6 +37,8 @@ class Request:
     seed: int
     t_admit: float = float("nan")
     t_done: float = float("nan")
+    it_admit: int = -1      # server loop iteration of admission / completion
+    it_done: int = -1
     weights: np.ndarray | None = field(default=None, repr=False)
 
 
@@ -61,7 +63,7 @@ class Server:
         self.batch = Batch(max_fits=max_fits, hbm_budget=self.budget, stream=self.stream)
         self.live = {}
 
-    def _admit(self, req: Request, now: float) -> bool:
+    def _admit(self, req: Request, now: float, it: int = -1) -> bool:
         if self.batch.active >= self.max_fits:
             return False
         if self.batch.footprint + footprint_bytes(req, self.dtype) > self.budget:
@@ -75,6 +77,7 @@ class Server:
             fit.close()
             return False
         req.t_admit = now
+        req.it_admit = it
         self.live[id(fit)] = (fit, req)
         return True
 
@@ -86,11 +89,13 @@ class Server:
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         sim_now = 0.0
+        it = 0
         while pending or waiting or self.batch.active:
+            it += 1
             now = clock() if realtime else sim_now
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            while waiting and self._admit(waiting[0], now):
+            while waiting and self._admit(waiting[0], now, it):
                 waiting.popleft()
             if self.batch.active:
                 self.batch.run(self.spl)
@@ -100,6 +105,7 @@ class Server:
                     _, req = self.live.pop(id(fit))
                     w = fit.weights()
                     req.t_done = clock() if realtime else t
+                    req.it_done = it
                     if self.keep:
                         req.weights = w
                     fit.close()

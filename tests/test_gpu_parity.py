@@ -327,3 +327,42 @@ def test_full_size_workloads(oracle, Fit, wlid, steps):
     assert r2 <= 1e-4 and rmax <= 1e-4
     f.close()
     _abi.m2m_set_launch(*before)
+
+
+def test_fp32_vs_fp64_state_per_observable(oracle, Fit):
+    """FP32 against FP64 particle state, both on the GPU from the same initial
+    state (the FP32 run starts from its rounding): the error of every raw
+    observable y_j relative to sum_i |w_i K_ij| after 1, 10, 100 and 200
+    steps. Reported per observable group (median and maximum); a particle
+    that the rounding moves across a bin edge shows up in the maximum."""
+    wl = workload(2)
+    T = oracle_targets(oracle, wl)
+    n = 100_003
+    p64 = wl.initial_particles(n=n, seed=41)
+    fd = Fit(wl.potential, wl.layout, wl.params, p64, dtype="f64")
+    fs = Fit(wl.potential, wl.layout, wl.params, cast(p64, "f32"), dtype="f32")
+    for f in (fd, fs):
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    nr = wl.layout["n_r"]
+    done = 0
+    rows = []
+    for k in (1, 10, 100, 200):
+        fd.step(k - done)
+        fs.step(k - done)
+        done = k
+        y64 = fd.observables()["y"]
+        y32 = fs.observables()["y"]
+        st = fd.particles()
+        _, ya, _ = oracle.deposit(st, st["u"], wl.layout, V_p=T["V_p"], sigma_p=T["sigma_p"],
+                                  nthreads=8, with_abs=True)
+        ok = ya > 0
+        e = np.zeros_like(ya)
+        e[ok] = np.abs(y32[ok] - y64[ok]) / ya[ok]
+        er, ek = e[:nr], e[nr:]
+        rows.append((k, np.median(er), er.max(), np.median(ek), ek.max()))
+        _say(f"fp32 vs fp64 step {k}: radial median {rows[-1][1]:.2e} max {rows[-1][2]:.2e}; "
+             f"GH median {rows[-1][3]:.2e} max {rows[-1][4]:.2e}")
+    fd.close()
+    fs.close()
+    assert rows[0][1] <= 1e-5 and rows[0][3] <= 1e-5
+    assert rows[-1][1] <= 1e-3 and rows[-1][3] <= 1e-3

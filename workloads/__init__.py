@@ -35,4 +35,4 @@ from .configs import (  # noqa: F401
     J_of,
     rng,
 )
-from .targets import fit_gauss_hermite_centres, add_noise, make_targets  # noqa: F401
+from .targets import fit_gauss_hermite_centres, add_noise, floor_model_noise, make_targets  # noqa: F401

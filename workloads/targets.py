@@ -87,6 +87,17 @@ def add_noise(Y_true: np.ndarray, layout: dict, s: float, g: np.random.Generator
     return Y, sig
 
 
+def floor_model_noise(Y_true: np.ndarray, sigma: np.ndarray, n_model: int, mass=1.0):
+    """Errors no smaller than the particle noise of an n_model-particle model:
+    sigma^2 + 4 (|Y_true| + m1) m1 with m1 = mass / n_model (twice the Poisson
+    error of a model observable carrying |Y_true| in particles of mass m1, and
+    at least two particle masses where the target is empty). Data sets served
+    to fits of at least n_model particles use it, so that no bin asks for
+    more accuracy than the model's own sampling can give."""
+    m1 = mass / float(n_model)
+    return np.sqrt(sigma * sigma + 4.0 * (np.abs(Y_true) + m1) * m1)
+
+
 def make_targets(observe, wl, lum=None):
     """Targets of workload ``wl`` measured by ``observe(V_p, sigma_p)`` on its
     target realization. Returns dict(Y, sigma, V_p, sigma_p, Y_true)."""
