@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 # launch shape (threads per block, tiles per CU) of the fused step kernel per
 # workload, as chosen by paper_1202_2355_amd.autotune
-LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (1024, 1), 5: (1024, 1)}
+LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (512, 6), 5: (512, 6)}
 
 SERVE_N_MIN = 100_000   # smallest fit of the serving trace (errors floored at its noise)
 METRIC = "particle-steps/sec (push+deposit+weight update) at 1 GPU; p50/p99 fit latency"
@@ -102,7 +102,7 @@ def cpu_baseline(wl, seconds: float):
                       f"(FP64, OpenMP, targets from a 2^20-particle target realization)"}
 
 
-def run_batch(args, Fit, torch):
+def run_batch(args, Fit, torch, _abi):
     """Workload 4: 64 fits of uneven size stepping as one batch, against the
     same fits stepped one launch per fit."""
     from paper_1202_2355_amd.batch import Batch
@@ -112,6 +112,9 @@ def run_batch(args, Fit, torch):
     fits_wl = batch_fits(args.fits)
     fits = []
     t0 = time.perf_counter()
+    # contexts take the single-fit launch shape at creation (the comparator
+    # steps them one launch per fit); the batch takes its own at admission
+    _abi.m2m_set_launch(*LAUNCH[2])
     for wl in fits_wl:
         ic = om_model_device(wl.N, wl.potential, float("inf"), seed=wl.seed * 10 + 1)
         tp = om_model_device(wl.n_target, wl.potential, wl.target_ra, seed=wl.seed * 10 + 2)
@@ -125,6 +128,7 @@ def run_batch(args, Fit, torch):
     ntot = sum(f.n for f in fits)
     print(f"[bench] batch of {len(fits)} fits, {ntot} particles, inputs in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    _abi.m2m_set_launch(*LAUNCH[4])
     b = Batch(max_fits=len(fits))
     for f in fits:
         assert b.admit(f, args.warmup + args.steps + 40)
@@ -236,7 +240,7 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return 0
     if args.workload == 4:
-        r = run_batch(args, Fit, torch)
+        r = run_batch(args, Fit, torch, _abi)
         bpp = BYTES_PER_PSTEP["f32"]
         achieved = bpp * r["N"] / (r["ms_step"] * 1e-3) / 1e9
         out = {"metric": METRIC,

@@ -990,9 +990,11 @@ m2m_status rebuild(m2m_batch* b) {
     int64_t ntot = 0;
     for (m2m_ctx* c : b->fits) ntot += c->n;
     // one tile size for the whole batch, so that every block streams about
-    // the same number of particles: about target tiles in all
+    // the same number of particles; each fit's last tile may be short, so
+    // the size leaves one spare tile per fit: at most target tiles in all
     const int target = std::max(1, g_tiles_per_cu * n_cus());
-    int64_t tile = (ntot + target - 1) / target;
+    const int64_t room = std::max<int64_t>(1, target - (int64_t)b->fits.size());
+    int64_t tile = (ntot + room - 1) / room;
     tile = (tile + kSegAlign - 1) / kSegAlign * kSegAlign;
     size_t lds = 0;
     for (size_t f = 0; f < b->fits.size(); ++f) {

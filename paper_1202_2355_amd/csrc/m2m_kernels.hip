@@ -21,6 +21,24 @@
 namespace m2m {
 namespace {
 
+// ------------------------------------------------------------- memory ------
+// Device arrays reached through pointers stored in the fit table are seen
+// through the global address space: accesses compile to global (not flat)
+// loads and stores, which do not also wait on the LDS counter, so loads in
+// flight overlap the LDS work of the particle loop.
+template <typename T>
+using G = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ G<T> gmem(T* p) {
+    return (G<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ G<T> gmem(void* p) {
+    return (G<T>)static_cast<T*>(p);
+}
+
 // ------------------------------------------------------------- math --------
 // FP32: the hardware transcendental and reciprocal instructions (about 1 ulp;
 // arguments here are never denormal). FP64: the correctly rounded library.
@@ -120,7 +138,7 @@ struct Hot {
     T GMh, a, GMn, rs, irs, phi0;
     T dt, hdt, w0, foc_mu, foc_cs;
     T E_lo, E_scale, lz0, ilz;
-    const T* lctab;
+    G<const T> lctab;
 };
 
 template <typename T>
@@ -142,9 +160,9 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
     h.lRs = T(fd.lRs);
     h.vmin = T(fd.vmin);
     h.vidv = T(fd.vidv);
-    const T* re2 = static_cast<const T*>(fd.redge2);
-    const T* Re2 = static_cast<const T*>(fd.Redge2);
-    const T* ve = static_cast<const T*>(fd.vedge);
+    const G<const T> re2 = gmem<const T>(fd.redge2);
+    const G<const T> Re2 = gmem<const T>(fd.Redge2);
+    const G<const T> ve = gmem<const T>(fd.vedge);
     h.r2lo = re2[0];
     h.r2hi = re2[fd.n_r];
     h.R2lo = Re2[0];
@@ -166,7 +184,7 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
     h.E_scale = T(fd.E_scale);
     h.lz0 = T(fd.lz0);
     h.ilz = T(fd.ilz);
-    h.lctab = static_cast<const T*>(fd.lctab);
+    h.lctab = gmem<const T>(fd.lctab);
     return h;
 }
 
@@ -417,15 +435,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     // particle arrays from the tile start (32-bit offsets within the tile);
     // the first particle of every lane is requested before anything else so
     // that its latency overlaps the set-up below
-    T* __restrict__ X = static_cast<T*>(fd.x) + tl.begin;
-    T* __restrict__ Y = static_cast<T*>(fd.y) + tl.begin;
-    T* __restrict__ Z = static_cast<T*>(fd.z) + tl.begin;
-    T* __restrict__ VX = static_cast<T*>(fd.vx) + tl.begin;
-    T* __restrict__ VY = static_cast<T*>(fd.vy) + tl.begin;
-    T* __restrict__ VZ = static_cast<T*>(fd.vz) + tl.begin;
-    T* __restrict__ U = static_cast<T*>(fd.u) + tl.begin;
-    T* __restrict__ UH = static_cast<T*>(fd.uh) + tl.begin;
-    uint16_t* __restrict__ CI = fd.cidx + tl.begin;
+    const G<T> __restrict__ X = gmem<T>(fd.x) + tl.begin;
+    const G<T> __restrict__ Y = gmem<T>(fd.y) + tl.begin;
+    const G<T> __restrict__ Z = gmem<T>(fd.z) + tl.begin;
+    const G<T> __restrict__ VX = gmem<T>(fd.vx) + tl.begin;
+    const G<T> __restrict__ VY = gmem<T>(fd.vy) + tl.begin;
+    const G<T> __restrict__ VZ = gmem<T>(fd.vz) + tl.begin;
+    const G<T> __restrict__ U = gmem<T>(fd.u) + tl.begin;
+    const G<T> __restrict__ UH = gmem<T>(fd.uh) + tl.begin;
+    const G<uint16_t> __restrict__ CI = gmem(fd.cidx) + tl.begin;
     const int len = (int)(tl.end - tl.begin);
     int i = threadIdx.x;
     T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
@@ -440,7 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
         if (step) nh = UH[i];
     }
 
-    const FitState* st = fd.st;
+    const G<const FitState> st = gmem<const FitState>(fd.st);
     if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
     const bool cells_only = (mode & kModeCells) != 0;
     const bool correct = step && st->correct != 0;
@@ -455,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     Tabs<T, A> tb = carve<T, A>(lds_raw, J, kp, h.n_r, h.n_R, h.n_v, C);
     const int priv = threadIdx.x & (kp - 1);
     {
-        const T* rp = static_cast<const T*>(fd.rp);
+        const G<const T> rp = gmem<const T>(fd.rp);
         for (int j = threadIdx.x; j < J; j += BLOCK) tb.rp[j] = rp[j];
         for (int j = threadIdx.x; j < J * kp; j += BLOCK) {
             tb.sum[j] = A(0);
@@ -466,21 +484,21 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
                 tb.csum[j] = 0.0;
                 tb.ccnt[j] = 0u;
             }
-        const T* re2 = static_cast<const T*>(fd.redge2);
+        const G<const T> re2 = gmem<const T>(fd.redge2);
         for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.re2[j] = re2[j];
-        const T* Re2 = static_cast<const T*>(fd.Redge2);
+        const G<const T> Re2 = gmem<const T>(fd.Redge2);
         for (int j = threadIdx.x; j <= h.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
-        const T* ve = static_cast<const T*>(fd.vedge);
+        const G<const T> ve = gmem<const T>(fd.vedge);
         for (int j = threadIdx.x; j <= h.n_v; j += BLOCK) tb.ve[j] = ve[j];
-        const T* Vp = static_cast<const T*>(fd.Vp);
-        const T* isp = static_cast<const T*>(fd.isp);
+        const G<const T> Vp = gmem<const T>(fd.Vp);
+        const G<const T> isp = gmem<const T>(fd.isp);
         for (int j = threadIdx.x; j < h.n_R; j += BLOCK) {
             tb.Vp[j] = Vp[j];
             tb.isp[j] = isp[j];
         }
     }
-    double* row = fd.partials + (size_t)tl.row * (size_t)fd.row_len;
-    const T* __restrict__ ucell = static_cast<const T*>(fd.ucell);
+    const G<double> row = gmem(fd.partials) + (size_t)tl.row * (size_t)fd.row_len;
+    const G<const T> __restrict__ ucell = gmem<const T>(fd.ucell);
     const bool need_uh = correct || assign;
     __syncthreads();
 
@@ -579,6 +597,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     const FinJob jb = jobs[blockIdx.x];
     const FitDev& fd = fits[jb.fit];
     FitState* st = fd.st;
+    const G<FitState> gst = gmem(fd.st);
     const bool step = (mode & kModeStep) != 0;
     const bool cells_mode = (mode & kModeCells) != 0;
     const bool observe = (mode & kModeObserve) != 0;
@@ -596,7 +615,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     double yt0 = 0.0, sg = 1.0, Yj = 0.0;
     if (bins && !cells_mode) {
         if (col < J) {
-            const double* base = fd.partials + col;
+            const G<const double> base = gmem<const double>(fd.partials) + col;
             for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
                 double v[U];
 #pragma unroll
@@ -608,21 +627,21 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
                 for (int k = 0; k < U; ++k) acc += v[k];
             }
             if (wave == 0 && !observe) {
-                yt0 = fd.ytil[col];
-                sg = fd.sigma[col];
-                Yj = fd.Y[col];
+                yt0 = gmem(fd.ytil)[col];
+                sg = gmem(fd.sigma)[col];
+                Yj = gmem(fd.Y)[col];
             }
         }
     }
-    if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
-    const bool correct = step && st->correct != 0;
+    if (step && gst->steps_left <= 0) return;  // uniform: the fit is idle
+    const bool correct = step && gst->correct != 0;
     const bool refresh = cells_mode || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
-                                        ((st->kstep + 1) % fd.prior_every) == 0);
+                                        ((gst->kstep + 1) % fd.prior_every) == 0);
     if (bins && cells_mode) return;
     if (!bins && !refresh) return;
     if (!bins && col < C) {
         // cell columns, read only on refresh steps
-        const double* base = fd.partials + J + col;
+        const G<const double> base = gmem<const double>(fd.partials) + J + col;
         for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
             double v[U], w[U];
 #pragma unroll
@@ -650,23 +669,23 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
         double d2 = 0.0;
         if (bins && col < J) {
             if (observe) {
-                fd.obs_out[col] = tot;
+                gmem(fd.obs_out)[col] = tot;
             } else {
-                fd.yv[col] = tot;
+                gmem(fd.yv)[col] = tot;
                 const double yt = init ? tot : yt0 + fd.q * (tot - yt0);
-                fd.ytil[col] = yt;
+                gmem(fd.ytil)[col] = yt;
                 const double d = (yt - Yj) / sg;
-                fd.delta[col] = d;
-                static_cast<T*>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
+                gmem(fd.delta)[col] = d;
+                gmem<T>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
                 d2 = d * d;
             }
         } else if (!bins && col < C && tot2 > 0.0) {
-            static_cast<T*>(fd.ucell)[col] = (T)(tot / tot2);
+            gmem<T>(fd.ucell)[col] = (T)(tot / tot2);
         }
         if (bins && !observe) {
             // chi^2 of these columns: fixed-order butterfly over the wave
             for (int off = 32; off >= 1; off >>= 1) d2 += __shfl_xor(d2, off, 64);
-            if (lane == 0) fd.chi2_part[jb.col0 / kFinCols] = d2;
+            if (lane == 0) gmem(fd.chi2_part)[jb.col0 / kFinCols] = d2;
         }
     }
     // the last job of this fit ends the step; in observe mode the same
@@ -687,24 +706,24 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     if (!cells_mode) {
         // lane l adds parts l, l + 64, ... in order, then a fixed-order
         // butterfly over the wave
-        for (int b = lane; b < fd.n_bin_jobs; b += 64) chi2 += fd.chi2_part[b];
+        for (int b = lane; b < fd.n_bin_jobs; b += 64) chi2 += gmem(fd.chi2_part)[b];
         for (int off = 32; off >= 1; off >>= 1) chi2 += __shfl_xor(chi2, off, 64);
     }
     if (lane != 0) return;
     *ticket = 0u;
     if (observe) return;
     if (!cells_mode) {
-        st->chi2 = chi2;
-        if (!isfinite(chi2)) st->error |= 1;
-        if (step) fd.chi2_hist[st->tstep % kHistCap] = chi2;
+        gst->chi2 = chi2;
+        if (!isfinite(chi2)) gst->error |= 1;
+        if (step) gmem(fd.chi2_hist)[gst->tstep % kHistCap] = chi2;
     }
     if (step) {
-        st->tstep += 1;
-        st->steps_left -= 1;
-        if (correct) st->kstep += 1;
-        st->assign_pending = refresh ? 1 : 0;
+        gst->tstep += 1;
+        gst->steps_left -= 1;
+        if (correct) gst->kstep += 1;
+        gst->assign_pending = refresh ? 1 : 0;
     }
-    if (cells_mode) st->assign_pending = 1;
+    if (cells_mode) gst->assign_pending = 1;
 }
 
 // ------------------------------------------------------------- assign ------
@@ -713,9 +732,9 @@ __global__ __launch_bounds__(256) void k_assign(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
     const FitDev& fd = fits[tl.fit];
-    T* UH = static_cast<T*>(fd.uh);
-    const uint16_t* CI = fd.cidx;
-    const T* ucell = static_cast<const T*>(fd.ucell);
+    const G<T> UH = gmem<T>(fd.uh);
+    const G<const uint16_t> CI = gmem<const uint16_t>(fd.cidx);
+    const G<const T> ucell = gmem<const T>(fd.ucell);
     const int C = fd.C;
     for (int64_t i = tl.begin + threadIdx.x; i < tl.end; i += 256)
         UH[i] = ucell[min((int)CI[i], C - 1)];
