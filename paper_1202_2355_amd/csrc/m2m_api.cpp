@@ -348,13 +348,16 @@ m2m_status check_error(m2m_ctx* c) {
     return M2M_OK;
 }
 
-// One M2M step: the fused step kernel over all tiles, then the finalize.
+// One M2M step: the step kernel over all tiles, then the finalize.
+hipError_t launch_one_step(m2m_ctx* c, hipStream_t s) {
+    hipError_t e = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
+                               c->lds, kModeStep, s);
+    if (e == hipSuccess) e = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, s);
+    return e;
+}
+
 m2m_status run_direct(m2m_ctx* c, int steps) {
-    for (int k = 0; k < steps; ++k) {
-        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
-                               c->lds, kModeStep, c->stream));
-        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, c->stream));
-    }
+    for (int k = 0; k < steps; ++k) M2M_HIP(c, launch_one_step(c, c->stream));
     return M2M_OK;
 }
 
@@ -380,14 +383,7 @@ m2m_status ensure_graph(m2m_ctx* c) {
     if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     const hipError_t e = capture_steps(
         c->cap,
-        [c](hipStream_t s) {
-            hipError_t r = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles,
-                                       c->n_tiles, c->lds, kModeStep, s);
-            if (r == hipSuccess)
-                r = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, s);
-            return r;
-        },
-        &c->graph);
+        [c](hipStream_t s) { return launch_one_step(c, s); }, &c->graph);
     if (e != hipSuccess) return hip_fail(c, e, "step graph");
     return M2M_OK;
 }
@@ -965,6 +961,16 @@ hipError_t grow(void** p, size_t* cap, size_t need) {
     return e;
 }
 
+// One batched step: the step kernel over the tiles of all fits, then the
+// finalize jobs of all fits.
+hipError_t batch_step(m2m_batch* b, bool f64, hipStream_t s) {
+    hipError_t e = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
+                               b->lds, kModeStep, s);
+    if (e == hipSuccess)
+        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s);
+    return e;
+}
+
 m2m_status rebuild(m2m_batch* b) {
     // launches in flight may still read the old tables and graph
     if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
@@ -1023,14 +1029,7 @@ m2m_status rebuild(m2m_batch* b) {
     // reductions in measuring mode (m2m_batch_profile)
     hipError_t e = capture_steps(
         b->cap,
-        [b, f64](hipStream_t s) {
-            hipError_t r = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev,
-                                       b->n_tiles, b->lds, kModeStep, s);
-            if (r == hipSuccess)
-                r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s);
-            return r;
-        },
-        &b->graph);
+        [b, f64](hipStream_t s) { return batch_step(b, f64, s); }, &b->graph);
     if (e == hipSuccess)
         e = capture_steps(
             b->cap,
@@ -1111,10 +1110,7 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
     for (int k = 0; k < full; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
     for (int k = 0; k < rem; ++k)
-        if (launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
-                        b->lds, kModeStep, b->stream) != hipSuccess ||
-            launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, b->stream) != hipSuccess)
-            return M2M_EDEVICE;
+        if (batch_step(b, f64, b->stream) != hipSuccess) return M2M_EDEVICE;
     return M2M_OK;
 }
 

@@ -15,6 +15,7 @@ constexpr int kMaxCells = 4096;    // largest n_E * n_x
 constexpr int kLcTable = 8192;     // entries of the ln r_c(ln zeta) table
 constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
 constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
+constexpr int kFinWaves = kFinThreads / 64;  // row groups of the fixed reduction order
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
 constexpr int kSegAlign = 64;      // tile boundaries are multiples of 64 particles
 

@@ -423,6 +423,199 @@ __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& 
         if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
 }
 
+// ------------------------------------------------------------- finalize ----
+// The reduction of a step: one block per job of kFinCols columns of one fit.
+//   column sums over the fit's tile rows in one fixed order: row group g
+//   (g < kFinWaves) adds rows g, g + kFinWaves, ... in row order, then the
+//   groups are added in order;
+//   observable columns: smoothing (eq. myts), Delta and chi^2 (eqs. delta,
+//   chi) and the force table; cell columns: the cell means that become the
+//   priors (Sec. 2.3.1);
+//   the end of the step: chi^2 from the parts of the bin jobs and the step
+//   counters, prior schedule and assignment flag.
+struct Flags {
+    bool step, cells_mode, observe, init, correct, refresh;
+};
+
+__device__ __forceinline__ Flags flags_of(const FitDev& fd, G<const FitState> st, int32_t mode) {
+    Flags f;
+    f.step = (mode & kModeStep) != 0;
+    f.cells_mode = (mode & kModeCells) != 0;
+    f.observe = (mode & kModeObserve) != 0;
+    f.init = (mode & kModeInit) != 0;
+    f.correct = f.step && st->correct != 0;
+    f.refresh = f.cells_mode || (f.correct && fd.entropy == 0 && fd.prior_every > 0 &&
+                                 ((st->kstep + 1) % fd.prior_every) == 0);
+    return f;
+}
+
+// Row group g of one column: the sum of rows g, g + kFinWaves, ... in row
+// order (and of the matching count column for cells), U rows in flight (the
+// sum does not depend on U).
+template <int U>
+__device__ __forceinline__ void group_sum(const FitDev& fd, bool bins, int col, int n_tiles, int g,
+                                          double& acc, double& acc2) {
+    const size_t stride = (size_t)fd.row_len;
+    const int J = fd.J, C = fd.C;
+    if (bins) {
+        const G<const double> base = gmem<const double>(fd.partials) + col;
+        for (int t0 = g; t0 < n_tiles; t0 += U * kFinWaves) {
+            double v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int t = t0 + k * kFinWaves;
+                v[k] = (t < n_tiles) ? base[(size_t)t * stride] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) acc += v[k];
+        }
+    } else {
+        const G<const double> base = gmem<const double>(fd.partials) + J + col;
+        for (int t0 = g; t0 < n_tiles; t0 += U * kFinWaves) {
+            double v[U], w[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int t = t0 + k * kFinWaves;
+                v[k] = (t < n_tiles) ? base[(size_t)t * stride] : 0.0;
+                w[k] = (t < n_tiles) ? base[(size_t)t * stride + C] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                acc += v[k];
+                acc2 += w[k];
+            }
+        }
+    }
+}
+
+// Column epilogue of one job (one wave; lane = column offset): tot, tot2 are
+// the column sums. Returns this job's chi^2 part (lane 0, bin jobs).
+template <typename T>
+__device__ __forceinline__ double column_epilogue(const FitDev& fd, bool bins, int col0,
+                                                  const Flags& f, double tot, double tot2,
+                                                  double yt0, double sg, double Yj, int lane) {
+    const int col = col0 + lane;
+    double d2 = 0.0;
+    if (bins && col < fd.J) {
+        if (f.observe) {
+            gmem(fd.obs_out)[col] = tot;
+        } else {
+            gmem(fd.yv)[col] = tot;
+            const double yt = f.init ? tot : yt0 + fd.q * (tot - yt0);
+            gmem(fd.ytil)[col] = yt;
+            const double d = (yt - Yj) / sg;
+            gmem(fd.delta)[col] = d;
+            gmem<T>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
+            d2 = d * d;
+        }
+    } else if (!bins && col < fd.C && tot2 > 0.0) {
+        gmem<T>(fd.ucell)[col] = (T)(tot / tot2);
+    }
+    if (bins && !f.observe) {
+        // chi^2 of these columns: fixed-order butterfly over the wave
+        for (int off = 32; off >= 1; off >>= 1) d2 += __shfl_xor(d2, off, 64);
+        if (lane == 0) gmem(fd.chi2_part)[col0 / kFinCols] = d2;
+    }
+    return d2;
+}
+
+// chi^2 from the parts of the bin jobs (one wave): lane l adds parts l,
+// l + 64, ... in order, then a fixed-order butterfly over the wave.
+__device__ __forceinline__ double chi2_of_parts(const double* parts, int n, int lane) {
+    double c = 0.0;
+    for (int b = lane; b < n; b += 64) c += parts[b];
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    return c;
+}
+
+// The end of the step for one fit (one thread).
+__device__ __forceinline__ void end_step(const FitDev& fd, G<FitState> gst, const Flags& f,
+                                         double chi2) {
+    if (!f.cells_mode) {
+        gst->chi2 = chi2;
+        if (!isfinite(chi2)) gst->error |= 1;
+        if (f.step) gmem(fd.chi2_hist)[gst->tstep % kHistCap] = chi2;
+    }
+    if (f.step) {
+        gst->tstep += 1;
+        gst->steps_left -= 1;
+        if (f.correct) gst->kstep += 1;
+        gst->assign_pending = f.refresh ? 1 : 0;
+    }
+    if (f.cells_mode) gst->assign_pending = 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
+                                                         const FinJob* __restrict__ jobs,
+                                                         int32_t mode) {
+    __shared__ double part[kFinWaves][kFinCols];
+    __shared__ double part2[kFinWaves][kFinCols];
+    __shared__ int last;
+    const FinJob jb = jobs[blockIdx.x];
+    const FitDev& fd = fits[jb.fit];
+    FitState* st = fd.st;
+    const G<FitState> gst = gmem(fd.st);
+    const bool step = (mode & kModeStep) != 0;
+    const bool cells_mode = (mode & kModeCells) != 0;
+    const bool observe = (mode & kModeObserve) != 0;
+    const bool bins = jb.kind == 0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = jb.col0 + lane;
+    const bool in = col < (bins ? fd.J : fd.C);
+
+    // observable columns: the rows and the smoothing inputs are requested
+    // before the fit's state is known (their latency overlaps its load)
+    double acc = 0.0, acc2 = 0.0;
+    double yt0 = 0.0, sg = 1.0, Yj = 0.0;
+    if (bins && !cells_mode && in) {
+        group_sum<16>(fd, true, col, jb.n_tiles, wave, acc, acc2);
+        if (wave == 0 && !observe) {
+            yt0 = gmem(fd.ytil)[col];
+            sg = gmem(fd.sigma)[col];
+            Yj = gmem(fd.Y)[col];
+        }
+    }
+    if (step && gst->steps_left <= 0) return;  // uniform: the fit is idle
+    const Flags f = flags_of(fd, gst, mode);
+    if (bins && cells_mode) return;
+    if (!bins && !f.refresh) return;
+    // cell columns, read only on refresh steps
+    if (!bins && in) group_sum<8>(fd, false, col, jb.n_tiles, wave, acc, acc2);
+    part[wave][lane] = acc;
+    part2[wave][lane] = acc2;
+    __syncthreads();
+    if (wave == 0) {
+        double tot = 0.0, tot2 = 0.0;
+        for (int w = 0; w < kFinWaves; ++w) {
+            tot += part[w][lane];
+            tot2 += part2[w][lane];
+        }
+        (void)column_epilogue<T>(fd, bins, jb.col0, f, tot, tot2, yt0, sg, Yj, lane);
+    }
+    // the last job of this fit ends the step; in observe mode the same
+    // hand-over runs on a separate counter and changes no state
+    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
+                            (f.refresh ? (uint32_t)fd.n_cell_jobs : 0u);
+    uint32_t* ticket = observe ? &st->mticket : &st->ticket;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(ticket, 1u);
+        last = (prev == n_part - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last || wave != 0) return;
+    __threadfence();
+    const double chi2 =
+        cells_mode ? 0.0 : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
+    if (lane != 0) return;
+    *ticket = 0u;
+    if (observe) return;
+    end_step(fd, gst, f, chi2);
+}
+
 // ------------------------------------------------------------- step --------
 template <typename T, typename A, int BLOCK, int KIN>
 __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
@@ -575,155 +768,6 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             row[J + j] = tb.csum[j];
             row[J + C + j] = (double)tb.ccnt[j];
         }
-}
-
-// ------------------------------------------------------------- finalize ----
-// One block per job of kFinCols columns of one fit: the column sums over the
-// fit's tile rows in a fixed order (wave w takes rows w, w + 16, ...; the
-// waves are then added in order), then for observable columns the smoothing
-// (eq. myts), Delta and chi^2 (eqs. delta, chi) and the force table, and for
-// cell columns the cell means that become the priors (Sec. 2.3.1). The last
-// block of a fit to finish (ticket) ends the step: chi^2 from the parts of
-// the bin jobs and the step counters, prior schedule and assignment flag.
-template <typename T>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
-                                                         const FinJob* __restrict__ jobs,
-                                                         int32_t mode) {
-    constexpr int kWaves = kFinThreads / 64;
-    constexpr int U = 16;  // rows in flight per lane
-    __shared__ double part[kWaves][kFinCols];
-    __shared__ double part2[kWaves][kFinCols];
-    __shared__ int last;
-    const FinJob jb = jobs[blockIdx.x];
-    const FitDev& fd = fits[jb.fit];
-    FitState* st = fd.st;
-    const G<FitState> gst = gmem(fd.st);
-    const bool step = (mode & kModeStep) != 0;
-    const bool cells_mode = (mode & kModeCells) != 0;
-    const bool observe = (mode & kModeObserve) != 0;
-    const bool init = (mode & kModeInit) != 0;
-    const bool bins = jb.kind == 0;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int col = jb.col0 + lane;
-    const int J = fd.J, C = fd.C;
-    const size_t stride = (size_t)fd.row_len;
-
-    // observable columns: the rows and the smoothing inputs are requested
-    // before the fit's state is known (their latency overlaps its load)
-    double acc = 0.0, acc2 = 0.0;
-    double yt0 = 0.0, sg = 1.0, Yj = 0.0;
-    if (bins && !cells_mode) {
-        if (col < J) {
-            const G<const double> base = gmem<const double>(fd.partials) + col;
-            for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
-                double v[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int t = t0 + k * kWaves;
-                    v[k] = (t < jb.n_tiles) ? base[(size_t)t * stride] : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k) acc += v[k];
-            }
-            if (wave == 0 && !observe) {
-                yt0 = gmem(fd.ytil)[col];
-                sg = gmem(fd.sigma)[col];
-                Yj = gmem(fd.Y)[col];
-            }
-        }
-    }
-    if (step && gst->steps_left <= 0) return;  // uniform: the fit is idle
-    const bool correct = step && gst->correct != 0;
-    const bool refresh = cells_mode || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
-                                        ((gst->kstep + 1) % fd.prior_every) == 0);
-    if (bins && cells_mode) return;
-    if (!bins && !refresh) return;
-    if (!bins && col < C) {
-        // cell columns, read only on refresh steps
-        const G<const double> base = gmem<const double>(fd.partials) + J + col;
-        for (int t0 = wave; t0 < jb.n_tiles; t0 += U * kWaves) {
-            double v[U], w[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int t = t0 + k * kWaves;
-                v[k] = (t < jb.n_tiles) ? base[(size_t)t * stride] : 0.0;
-                w[k] = (t < jb.n_tiles) ? base[(size_t)t * stride + C] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                acc += v[k];
-                acc2 += w[k];
-            }
-        }
-    }
-    part[wave][lane] = acc;
-    part2[wave][lane] = acc2;
-    __syncthreads();
-    if (wave == 0) {
-        double tot = 0.0, tot2 = 0.0;
-        for (int w = 0; w < kWaves; ++w) {
-            tot += part[w][lane];
-            tot2 += part2[w][lane];
-        }
-        double d2 = 0.0;
-        if (bins && col < J) {
-            if (observe) {
-                gmem(fd.obs_out)[col] = tot;
-            } else {
-                gmem(fd.yv)[col] = tot;
-                const double yt = init ? tot : yt0 + fd.q * (tot - yt0);
-                gmem(fd.ytil)[col] = yt;
-                const double d = (yt - Yj) / sg;
-                gmem(fd.delta)[col] = d;
-                gmem<T>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
-                d2 = d * d;
-            }
-        } else if (!bins && col < C && tot2 > 0.0) {
-            gmem<T>(fd.ucell)[col] = (T)(tot / tot2);
-        }
-        if (bins && !observe) {
-            // chi^2 of these columns: fixed-order butterfly over the wave
-            for (int off = 32; off >= 1; off >>= 1) d2 += __shfl_xor(d2, off, 64);
-            if (lane == 0) gmem(fd.chi2_part)[jb.col0 / kFinCols] = d2;
-        }
-    }
-    // the last job of this fit ends the step; in observe mode the same
-    // hand-over runs on a separate counter and changes no state
-    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
-                            (refresh ? (uint32_t)fd.n_cell_jobs : 0u);
-    uint32_t* ticket = observe ? &st->mticket : &st->ticket;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(ticket, 1u);
-        last = (prev == n_part - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!last || wave != 0) return;
-    __threadfence();
-    double chi2 = 0.0;
-    if (!cells_mode) {
-        // lane l adds parts l, l + 64, ... in order, then a fixed-order
-        // butterfly over the wave
-        for (int b = lane; b < fd.n_bin_jobs; b += 64) chi2 += gmem(fd.chi2_part)[b];
-        for (int off = 32; off >= 1; off >>= 1) chi2 += __shfl_xor(chi2, off, 64);
-    }
-    if (lane != 0) return;
-    *ticket = 0u;
-    if (observe) return;
-    if (!cells_mode) {
-        gst->chi2 = chi2;
-        if (!isfinite(chi2)) gst->error |= 1;
-        if (step) gmem(fd.chi2_hist)[gst->tstep % kHistCap] = chi2;
-    }
-    if (step) {
-        gst->tstep += 1;
-        gst->steps_left -= 1;
-        if (correct) gst->kstep += 1;
-        gst->assign_pending = refresh ? 1 : 0;
-    }
-    if (cells_mode) gst->assign_pending = 1;
 }
 
 // ------------------------------------------------------------- assign ------

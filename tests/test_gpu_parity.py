@@ -366,3 +366,4 @@ def test_fp32_vs_fp64_state_per_observable(oracle, Fit):
     fs.close()
     assert rows[0][1] <= 1e-5 and rows[0][3] <= 1e-5
     assert rows[-1][1] <= 1e-3 and rows[-1][3] <= 1e-3
+
