@@ -207,7 +207,7 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=500, help="workload 5: trace length")
     ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
-    ap.add_argument("--steps-per-launch", type=int, default=32)
+    ap.add_argument("--steps-per-launch", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB float32 device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -136,16 +136,38 @@ struct HostPot {
         return m;
     }
     double ecirc(double r) const { return r > 0 ? phi(r) + 0.5 * GM(r) / r : phi(0.0); }
-    // ln of the radius of the circular orbit with energy E (phi(0) < E < 0),
-    // by bisection in ln r
-    double ln_rc(double E) const {
-        double lo = -60.0, hi = 60.0;  // ln r bracket
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (ecirc(std::exp(mid)) < E) lo = mid; else hi = mid;
-            if (hi - lo < 1e-15) break;
+    // r dE_c/dr with E_c = Phi + G M(<r) / (2 r): G M / (2 r) + (G M)' / 2,
+    // (G M)' = 2 G M a r / (r + a)^3 (Hernquist) + G M200 / f(c) r / (r_s^2 (1 + r/r_s)^2)
+    double decirc_dlnr(double r) const {
+        const double ra = r + a;
+        double d = 0.5 * GM(r) / r + GMh * a * r / (ra * ra * ra);
+        if (GM200 > 0) {
+            const double q1 = 1.0 + r / rs;
+            d += 0.5 * GM200 / fc * r / (rs * rs * q1 * q1);
         }
-        return 0.5 * (lo + hi);
+        return d;
+    }
+    // ln of the radius of the circular orbit with energy E (phi(0) < E < 0):
+    // Newton steps in ln r from the guess x0 inside a bracket that every
+    // evaluation narrows (E_c increases with r); a step that leaves the
+    // bracket is replaced by bisection
+    double ln_rc(double E, double x0) const {
+        double lo = -60.0, hi = 60.0;
+        double x = std::min(std::max(x0, lo), hi);
+        for (int it = 0; it < 200; ++it) {
+            const double r = std::exp(x);
+            const double f = ecirc(r) - E;
+            if (f < 0) lo = x; else hi = x;
+            if (f == 0 || hi - lo < 1e-15) break;
+            double xn = x - f / decirc_dlnr(r);
+            if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+            if (std::fabs(xn - x) < 4e-16 * std::max(1.0, std::fabs(x))) {
+                x = xn;
+                break;
+            }
+            x = xn;
+        }
+        return x;
     }
 };
 
@@ -287,10 +309,17 @@ std::vector<unsigned char> as_bytes(const std::vector<double>& v) {
     return out;
 }
 
+// A copy ordered on the context's stream, complete on return (host
+// buffers may be reused at once).
+hipError_t copy_sync(hipStream_t s, void* dst, const void* src, size_t n, hipMemcpyKind kind) {
+    hipError_t e = hipMemcpyAsync(dst, src, n, kind, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
 m2m_status upload(m2m_ctx* c, size_t off, const std::vector<double>& v) {
     std::vector<unsigned char> b = c->f64 ? as_bytes<double>(v) : as_bytes<float>(v);
     if (b.empty()) return M2M_OK;
-    M2M_HIP(c, hipMemcpy(c->ws + off, b.data(), b.size(), hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->ws + off, b.data(), b.size(), hipMemcpyHostToDevice));
     return M2M_OK;
 }
 
@@ -324,7 +353,7 @@ m2m_status sync(m2m_ctx* c) {
 
 m2m_status read_state(m2m_ctx* c, FitState& s) {
     M2M_HIP(c, hipStreamSynchronize(c->stream));
-    M2M_HIP(c, hipMemcpy(&s, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, &s, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
     return M2M_OK;
 }
 
@@ -593,10 +622,12 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     for (int k = 0; k <= f.n_v; ++k) ve[k] = lin_edge(L.v_min, L.v_max, L.n_v, k);
     std::vector<double> lct(kLcTable);
     const double phi0 = hp.phi(0.0);
+    double guess = std::log(hp.a) + kLz0 * 0.5;  // small zeta: r_c ~ a sqrt(zeta)
     for (int k = 0; k < kLcTable; ++k) {
         const double lz = kLz0 + (kLz1 - kLz0) * k / (kLcTable - 1);
         const double E = phi0 / (1.0 + std::exp(lz));
-        lct[k] = hp.ln_rc(E);
+        lct[k] = hp.ln_rc(E, guess);
+        guess = lct[k];
     }
     std::vector<double> ones(w.C, 1.0);
     c->Vp.assign(std::max(f.n_R, 1), 0.0);
@@ -619,9 +650,9 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     fin_jobs(w, 0, count, jb);
     c->n_tiles = (int)tl.size();
     c->n_jobs = (int)jb.size();
-    if (hipMemcpy(c->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->jobs, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->fd_dev, &f, sizeof(FitDev), hipMemcpyHostToDevice) != hipSuccess)
+    if (copy_sync(c->stream, c->tiles, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        copy_sync(c->stream, c->jobs, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        copy_sync(c->stream, c->fd_dev, &f, sizeof(FitDev), hipMemcpyHostToDevice) != hipSuccess)
         return bail(M2M_EDEVICE);
     *out = c;
     return M2M_OK;
@@ -648,8 +679,8 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     }
     m2m_status s = sync(c);
     if (s != M2M_OK) return s;
-    M2M_HIP(c, hipMemcpy(c->fd.Y, Y, sizeof(double) * J, hipMemcpyHostToDevice));
-    M2M_HIP(c, hipMemcpy(c->fd.sigma, sigma, sizeof(double) * J, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->fd.Y, Y, sizeof(double) * J, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->fd.sigma, sigma, sizeof(double) * J, hipMemcpyHostToDevice));
     c->Vp = V;
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
@@ -703,7 +734,7 @@ m2m_status m2m_get_weights(m2m_ctx* c, void* dst, int32_t dst_is_device) {
         s = sync(c);
     } else {
         const size_t sz = c->f64 ? 8 : 4;
-        M2M_HIP(c, hipMemcpy(dst, c->fd.u, sz * (size_t)c->n, hipMemcpyDeviceToHost));
+        M2M_HIP(c, copy_sync(c->stream, dst, c->fd.u, sz * (size_t)c->n, hipMemcpyDeviceToHost));
         if (c->f64) {
             double* d = static_cast<double*>(dst);
             for (int64_t i = 0; i < c->n; ++i) d[i] *= scale;
@@ -724,9 +755,9 @@ m2m_status m2m_get_observables(m2m_ctx* c, double* y, double* y_tilde, double* d
     m2m_status s = read_state(c, st);
     if (s != M2M_OK) return s;
     const size_t J = (size_t)c->w.J;
-    if (y) M2M_HIP(c, hipMemcpy(y, c->fd.yv, 8 * J, hipMemcpyDeviceToHost));
-    if (y_tilde) M2M_HIP(c, hipMemcpy(y_tilde, c->fd.ytil, 8 * J, hipMemcpyDeviceToHost));
-    if (delta) M2M_HIP(c, hipMemcpy(delta, c->fd.delta, 8 * J, hipMemcpyDeviceToHost));
+    if (y) M2M_HIP(c, copy_sync(c->stream, y, c->fd.yv, 8 * J, hipMemcpyDeviceToHost));
+    if (y_tilde) M2M_HIP(c, copy_sync(c->stream, y_tilde, c->fd.ytil, 8 * J, hipMemcpyDeviceToHost));
+    if (delta) M2M_HIP(c, copy_sync(c->stream, delta, c->fd.delta, 8 * J, hipMemcpyDeviceToHost));
     if (chi2) *chi2 = st.chi2;
     if (st.error & 1) return fail(c, M2M_ENONFINITE, "chi^2 became non-finite");
     return M2M_OK;
@@ -739,7 +770,7 @@ m2m_status m2m_get_chi2_history(m2m_ctx* c, double* out, int32_t max, int32_t* n
     m2m_status s = read_state(c, st);
     if (s != M2M_OK) return s;
     std::vector<double> ring(kHistCap);
-    M2M_HIP(c, hipMemcpy(ring.data(), c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, ring.data(), c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
     const int64_t have = std::min<int64_t>(st.tstep, kHistCap);
     const int64_t take = std::min<int64_t>(have, max);
     for (int64_t k = 0; k < take; ++k) {
@@ -767,7 +798,7 @@ m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, dou
                            kModeObserve, c->stream));
     M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, c->stream));
     if ((s = sync(c)) != M2M_OK) return s;
-    M2M_HIP(c, hipMemcpy(y, c->fd.obs_out, 8 * (size_t)c->w.J, hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, y, c->fd.obs_out, 8 * (size_t)c->w.J, hipMemcpyDeviceToHost));
     if (tmp && (s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return s;
     return M2M_OK;
 }
@@ -802,22 +833,22 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
                   c->targets ? 1 : 0, c->ytil_init ? 1 : 0, 0, 0};
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
-    M2M_HIP(c, hipMemcpy(p, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, p, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
     p += sizeof(FitState);
     double* const dev[5] = {c->fd.ytil, c->fd.yv, c->fd.delta, c->fd.Y, c->fd.sigma};
     for (double* d : dev) {
-        M2M_HIP(c, hipMemcpy(p, d, 8 * J, hipMemcpyDeviceToHost));
+        M2M_HIP(c, copy_sync(c->stream, p, d, 8 * J, hipMemcpyDeviceToHost));
         p += 8 * J;
     }
     std::memcpy(p, c->Vp.data(), 8 * nR);
     p += 8 * nR;
     std::memcpy(p, c->sp.data(), 8 * nR);
     p += 8 * nR;
-    M2M_HIP(c, hipMemcpy(p, c->fd.ucell, sz * C, hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, p, c->fd.ucell, sz * C, hipMemcpyDeviceToHost));
     p += sz * C;
-    M2M_HIP(c, hipMemcpy(p, c->fd.rp, sz * J, hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, p, c->fd.rp, sz * J, hipMemcpyDeviceToHost));
     p += sz * J;
-    M2M_HIP(c, hipMemcpy(p, c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
+    M2M_HIP(c, copy_sync(c->stream, p, c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
     *bytes = need;
     return M2M_OK;
 }
@@ -844,11 +875,11 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     st.mticket = 0;
     st.steps_left = 0;
     st.assign_pending = 0;
-    M2M_HIP(c, hipMemcpy(c->st, &st, sizeof st, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->st, &st, sizeof st, hipMemcpyHostToDevice));
     p += sizeof(FitState);
     double* const dev[5] = {c->fd.ytil, c->fd.yv, c->fd.delta, c->fd.Y, c->fd.sigma};
     for (double* d : dev) {
-        M2M_HIP(c, hipMemcpy(d, p, 8 * J, hipMemcpyHostToDevice));
+        M2M_HIP(c, copy_sync(c->stream, d, p, 8 * J, hipMemcpyHostToDevice));
         p += 8 * J;
     }
     std::vector<double> V(nR), S(nR);
@@ -859,11 +890,11 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     c->Vp = V;
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
-    M2M_HIP(c, hipMemcpy(c->fd.ucell, p, (c->f64 ? 8 : 4) * C, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->fd.ucell, p, (c->f64 ? 8 : 4) * C, hipMemcpyHostToDevice));
     p += (c->f64 ? 8 : 4) * C;
-    M2M_HIP(c, hipMemcpy(c->fd.rp, p, (c->f64 ? 8 : 4) * J, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->fd.rp, p, (c->f64 ? 8 : 4) * J, hipMemcpyHostToDevice));
     p += (c->f64 ? 8 : 4) * J;
-    M2M_HIP(c, hipMemcpy(c->fd.chi2_hist, p, 8 * (size_t)kHistCap, hipMemcpyHostToDevice));
+    M2M_HIP(c, copy_sync(c->stream, c->fd.chi2_hist, p, 8 * (size_t)kHistCap, hipMemcpyHostToDevice));
     c->targets = h.targets != 0;
     c->ytil_init = h.ytil_init != 0;
     return M2M_OK;

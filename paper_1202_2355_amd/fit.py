@@ -44,33 +44,42 @@ class Fit:
         self.params = dict(params)
         tdt = _torch_dtype(dtype)
         self.n = int(particles["x"].shape[0]) if hasattr(particles["x"], "shape") else len(particles["x"])
-        # the eight state arrays back to back in one allocation (each start
-        # 256-byte aligned): a state about the size of the 256 MB Infinity
-        # Cache streams up to 1.2x faster packed than spread over separate
-        # allocations, whose placement leaves cache sets unevenly used
-        esz = 8 if dtype == "f64" else 4
-        stride = (self.n * esz + 255) // 256 * 256 // esz
-        self._buf = torch.empty(8 * stride, dtype=tdt, device=device)
-        self.t = {}
-        for f, k in enumerate((*FIELDS, "u", "uh")):
-            self.t[k] = self._buf[f * stride:f * stride + self.n]
-        for k in FIELDS:
-            v = particles[k]
-            src = (v if torch.is_tensor(v) else torch.as_tensor(np.asarray(v)))
-            self.t[k].copy_(src.reshape(-1))
-        for k, v in (("u", u), ("uh", u_prior)):
-            if v is None:
-                self.t[k].fill_(1.0)
-            else:
-                self.t[k].copy_((v if torch.is_tensor(v) else torch.as_tensor(np.asarray(v))).reshape(-1))
+        # every device operation of this fit (the state copies below, the
+        # library's work) is ordered on one stream
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.J = A.m2m_num_observables(self.layout)
         self.n_R = self.layout["n_R"] if self.layout["kin"] != "none" else 0
+        ws_bytes = A.m2m_workspace_bytes(self.layout, self.params, self.n, dtype)
+        with torch.cuda.stream(self.stream):
+            # the eight state arrays back to back in one allocation (each start
+            # 256-byte aligned): a state about the size of the 256 MB Infinity
+            # Cache streams up to 1.2x faster packed than spread over separate
+            # allocations, whose placement leaves cache sets unevenly used
+            esz = 8 if dtype == "f64" else 4
+            stride = (self.n * esz + 255) // 256 * 256 // esz
+            self._buf = torch.empty(8 * stride, dtype=tdt, device=device)
+            self.t = {}
+            for f, k in enumerate((*FIELDS, "u", "uh")):
+                self.t[k] = self._buf[f * stride:f * stride + self.n]
+            for k in FIELDS:
+                v = particles[k]
+                src = (v if torch.is_tensor(v) else torch.as_tensor(np.asarray(v)))
+                self.t[k].copy_(src.reshape(-1))
+            for k, v in (("u", u), ("uh", u_prior)):
+                if v is None:
+                    self.t[k].fill_(1.0)
+                else:
+                    self.t[k].copy_((v if torch.is_tensor(v) else torch.as_tensor(np.asarray(v))).reshape(-1))
+            # the library's workspace comes from torch's caching allocator, so
+            # that creating and closing fits allocates no device memory directly
+            # (no device-wide synchronization while other fits run)
+            self._ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=device)
         ctx = C.c_void_p()
         ptrs = [C.c_void_p(self.t[k].data_ptr()) for k in (*FIELDS, "u", "uh")]
         st = A.lib().m2m_create(C.byref(A.potential(potential)), C.byref(A.obs_layout(self.layout)),
                                 C.byref(A.params(self.params)), self.n, A.DTYPE[dtype], *ptrs,
-                                None, 0, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+                                C.c_void_p(self._ws.data_ptr()), C.c_size_t(ws_bytes),
+                                C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         A.check(st, "m2m_create")
         self.ctx = ctx
 

@@ -1,11 +1,13 @@
 """Continuous-batching server of M2M fit requests.
 
 A request is a target data set plus a potential (the mass-to-light and halo
-scans of the paper's applications, Sec. 6): the server draws the request's
+scans of the paper's applications, Sec. 6). The server draws the request's
 initial particle model on the device, keeps its particles and weights
 resident, and admits it into the running batch as soon as a slot and the
 HBM budget allow (footprint: particle state plus the library workspace).
-Every loop iteration enqueues a few batched steps, then retires the fits
+Each loop turn admits the requests prepared in the previous turn, enqueues
+a number of batched steps on the batch stream, prepares the next waiting
+requests on a setup stream while those steps run, then retires the fits
 that finished and copies their weights to the host. Latency is measured from
 a request's arrival to its weights being on the host.
 """
@@ -48,10 +50,15 @@ def footprint_bytes(req: Request, dtype: str) -> int:
 
 
 class Server:
-    def __init__(self, datasets, hbm_budget: int, max_fits: int = 64, steps_per_launch: int = 32,
-                 dtype: str = "f32", keep_weights: bool = False, initial_model=None):
+    def __init__(self, datasets, hbm_budget: int, max_fits: int = 64, steps_per_launch: int = 64,
+                 dtype: str = "f32", keep_weights: bool = False, initial_model=None,
+                 max_prepared: int = 4):
         """datasets: list of dicts with Y and sigma (and V_p, sigma_p for
-        Gauss-Hermite layouts). initial_model(req) -> dict of device tensors."""
+        Gauss-Hermite layouts). initial_model(req) -> dict of device tensors.
+
+        The batch runs on a stream of its own; new requests are prepared
+        (initial model drawn, context created, targets set) on a second
+        stream while the batch runs, and admitted at the next loop turn."""
         self.datasets = datasets
         self.budget = int(hbm_budget)
         self.max_fits = max_fits
@@ -59,27 +66,41 @@ class Server:
         self.dtype = dtype
         self.keep = keep_weights
         self.initial_model = initial_model
-        self.stream = torch.cuda.current_stream()
+        self.max_prepared = max_prepared
+        self.stream = torch.cuda.Stream()
+        self.setup = torch.cuda.Stream()
         self.batch = Batch(max_fits=max_fits, hbm_budget=self.budget, stream=self.stream)
         self.live = {}
+        self.prepared = deque()
 
-    def _admit(self, req: Request, now: float, it: int = -1) -> bool:
-        if self.batch.active >= self.max_fits:
+    def _prepared_bytes(self) -> int:
+        return sum(footprint_bytes(r, self.dtype) for _, r in self.prepared)
+
+    def _prepare(self, req: Request) -> bool:
+        """Draw the request's model and create its context on the setup
+        stream; False if the HBM budget does not allow it now."""
+        need = footprint_bytes(req, self.dtype)
+        if self.batch.footprint + self._prepared_bytes() + need > self.budget:
             return False
-        if self.batch.footprint + footprint_bytes(req, self.dtype) > self.budget:
-            return False
-        parts = self.initial_model(req)
-        fit = Fit(req.potential, req.layout, req.params, parts, dtype=self.dtype, stream=self.stream)
-        del parts
-        d = self.datasets[req.dataset]
-        fit.set_targets(d["Y"], d["sigma"], d.get("V_p"), d.get("sigma_p"))
-        if not self.batch.admit(fit, req.steps):
-            fit.close()
-            return False
-        req.t_admit = now
-        req.it_admit = it
-        self.live[id(fit)] = (fit, req)
+        with torch.cuda.stream(self.setup):
+            parts = self.initial_model(req)
+            fit = Fit(req.potential, req.layout, req.params, parts, dtype=self.dtype,
+                      stream=self.setup)
+            del parts
+            d = self.datasets[req.dataset]
+            fit.set_targets(d["Y"], d["sigma"], d.get("V_p"), d.get("sigma_p"))
+        self.prepared.append((fit, req))
         return True
+
+    def _admit(self, now: float, it: int) -> None:
+        while self.prepared and self.batch.active < self.max_fits:
+            fit, req = self.prepared[0]
+            if not self.batch.admit(fit, req.steps):
+                break
+            self.prepared.popleft()
+            req.t_admit = now
+            req.it_admit = it
+            self.live[id(fit)] = (fit, req)
 
     def run(self, requests, realtime: bool = True, log=None):
         """Serve ``requests`` (sorted by arrival). Returns the metrics dict."""
@@ -90,15 +111,18 @@ class Server:
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         sim_now = 0.0
         it = 0
-        while pending or waiting or self.batch.active:
+        while pending or waiting or self.prepared or self.batch.active:
             it += 1
             now = clock() if realtime else sim_now
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            while waiting and self._admit(waiting[0], now, it):
-                waiting.popleft()
+            self._admit(now, it)
             if self.batch.active:
                 self.batch.run(self.spl)
+            # while the batch runs: prepare the next requests
+            while waiting and len(self.prepared) < self.max_prepared and self._prepare(waiting[0]):
+                waiting.popleft()
+            if self.batch.active:
                 fin, _ = self.batch.poll()
                 t = clock() if realtime else now
                 for fit in fin:
@@ -112,8 +136,9 @@ class Server:
                     done.append(req)
                 if log and fin:
                     print(f"[serve] t={now:.3f}s done={len(done)} active={self.batch.active} "
-                          f"waiting={len(waiting)}", file=log, flush=True)
-            elif pending:
+                          f"prepared={len(self.prepared)} waiting={len(waiting)}", file=log,
+                          flush=True)
+            elif pending and not self.prepared:
                 if realtime:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
                 else:
@@ -144,4 +169,6 @@ class Server:
                 pass
             fit.close()
         self.live.clear()
+        while self.prepared:
+            self.prepared.popleft()[0].close()
         self.batch.close()
