@@ -59,11 +59,13 @@ typedef struct {
     double v_min, v_max;
 } orc_layout;
 
-/* entropy: 0 = mass-neutral S+ with moving priors, 1 = weight entropy */
+/* entropy: 0 = mass-neutral S+ with moving priors, 1 = weight entropy;
+ * smooth: 1 = thin-plate smoothing of the prior grid with GCV (Sec. 2.3.2) */
 typedef struct {
     double dt, eps, mu, alpha, mass;
     int32_t entropy, n_E, n_x, prior_every;
     double E_lo, E_hi;
+    int32_t smooth, pad;
 } orc_params;
 
 typedef struct {
@@ -80,6 +82,7 @@ typedef struct {
     uint8_t *flag;   /* optional: particle came within `band` of an edge */
     double band;
     int32_t nthreads;
+    double *ucell;   /* n_E n_x prior grid, kept between refreshes (empty cells keep theirs) */
 } orc_model;
 
 #define ORC_MAXK 80  /* at most 1 radial + 64 kinematic entries per particle */
@@ -446,7 +449,159 @@ int orc_init(orc_model *m) {
     return 0;
 }
 
-/* new priors: uhat_i = mean of u over the (E, x) cell of particle i */
+/* ------------------------------------------------------------- smoothing
+ * Thin-plate smoothing of the prior grid (Sec. 2.3.2, eq. smooth_grid), written
+ * out as its definition: the smoothed grid w minimizes
+ *   sum_c (w_c - w0_c)^2 + lambda w^T P w,
+ * where w^T P w is the sum over the grid of the finite-difference thin-plate
+ * terms (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 in the grid's own units
+ * (cell widths hE = (E_hi - E_lo)/n_E and hx = 1/n_x), with reflecting
+ * boundaries. With those boundaries the sum equals |Lap w|^2 for the discrete
+ * Laplacian Lap = L_E (x) I + I (x) L_x (summation by parts), so P = Lap Lap.
+ * Hence w = (I + lambda P)^-1 w0, solved here densely (Cholesky). lambda
+ * minimizes the generalized cross validation score
+ *   GCV(lambda) = (|w0 - A w0|^2 / n) / (1 - tr(A)/n)^2,  A = (I + lambda P)^-1,
+ * searched over p = log10(lambda) in three stages: steps of 0.25 over
+ * [p_lo, p_hi], then 65 points over the two steps around the best point,
+ * then 65 points over the two sub-steps around the best one (first minimum
+ * on ties). p_lo = -2 log10(G_hi) - 4, p_hi = -2 log10(G_lo) + 4 with G_hi =
+ * 4/hE^2 + 4/hx^2 and G_lo the smaller of 4 sin^2(pi/(2n))/h^2 over the axes
+ * with more than one cell. The smoothed priors are floored at 1e-3 times the
+ * mean of w0 (a prior must stay positive). Dense: meant for small grids. */
+static int cholesky(double *A, int n) {  /* in place, lower triangle */
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0)) return 1;
+        d = sqrt(d);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / d;
+        }
+    }
+    return 0;
+}
+
+/* GCV score of lambda; the smoothed grid into w if w != NULL */
+static double gcv_dense(const double *P, const double *w0, int n, double lam, double *w,
+                        double *scratch /* 2 n^2 + n */) {
+    double *M = scratch, *Li = scratch + (size_t)n * n, *s = scratch + 2 * (size_t)n * n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) M[i * n + j] = (i == j ? 1.0 : 0.0) + lam * P[i * n + j];
+    if (cholesky(M, n)) return INFINITY;
+    /* solve L L^T s = w0 */
+    for (int i = 0; i < n; ++i) {
+        double v = w0[i];
+        for (int k = 0; k < i; ++k) v -= M[i * n + k] * s[k];
+        s[i] = v / M[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = s[i];
+        for (int k = i + 1; k < n; ++k) v -= M[k * n + i] * s[k];
+        s[i] = v / M[i * n + i];
+    }
+    /* tr(A) = tr(L^-T L^-1) = sum of squares of the entries of L^-1 */
+    double tr = 0.0;
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < j; ++i) Li[i * n + j] = 0.0;
+        for (int i = j; i < n; ++i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            for (int k = j; k < i; ++k) v -= M[i * n + k] * Li[k * n + j];
+            Li[i * n + j] = v / M[i * n + i];
+            tr += Li[i * n + j] * Li[i * n + j];
+        }
+    }
+    double rss = 0.0;
+    for (int i = 0; i < n; ++i) rss += (w0[i] - s[i]) * (w0[i] - s[i]);
+    if (w)
+        for (int i = 0; i < n; ++i) w[i] = s[i];
+    double den = 1.0 - tr / n;
+    return (rss / n) / (den * den);
+}
+
+/* smooth the n_E x n_x grid w (cell k n_x + l) in place; *lambda_out the
+ * chosen lambda (0 if the grid has one cell) */
+int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
+    const int nE = par->n_E, nx = par->n_x, n = nE * nx;
+    if (lambda_out) *lambda_out = 0.0;
+    if (n < 2) return 0;
+    const double hE = (par->E_hi - par->E_lo) / nE, hx = 1.0 / nx;
+    double *Lap = (double *)calloc((size_t)n * n, sizeof(double));
+    double *P = (double *)calloc((size_t)n * n, sizeof(double));
+    double *w0 = (double *)malloc(sizeof(double) * n);
+    double *scratch = (double *)malloc(sizeof(double) * (2 * (size_t)n * n + n));
+    if (!Lap || !P || !w0 || !scratch) return 1;
+    for (int c = 0; c < n; ++c) w0[c] = w[c];
+    /* discrete Laplacian with reflecting boundaries (the ghost value beyond
+     * an edge equals the edge cell) */
+    for (int k = 0; k < nE; ++k)
+        for (int l = 0; l < nx; ++l) {
+            const int c = k * nx + l;
+            if (k > 0) { Lap[c * n + c - nx] += 1.0 / (hE * hE); Lap[c * n + c] -= 1.0 / (hE * hE); }
+            if (k < nE - 1) { Lap[c * n + c + nx] += 1.0 / (hE * hE); Lap[c * n + c] -= 1.0 / (hE * hE); }
+            if (l > 0) { Lap[c * n + c - 1] += 1.0 / (hx * hx); Lap[c * n + c] -= 1.0 / (hx * hx); }
+            if (l < nx - 1) { Lap[c * n + c + 1] += 1.0 / (hx * hx); Lap[c * n + c] -= 1.0 / (hx * hx); }
+        }
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            const double a = Lap[i * n + k];
+            if (a == 0.0) continue;
+            for (int j = 0; j < n; ++j) P[i * n + j] += a * Lap[k * n + j];
+        }
+    /* search range */
+    double Ghi = 0.0, Glo = INFINITY;
+    if (nE > 1) {
+        Ghi += 4.0 / (hE * hE);
+        const double s = sin(M_PI / (2.0 * nE));
+        Glo = fmin(Glo, 4.0 * s * s / (hE * hE));
+    }
+    if (nx > 1) {
+        Ghi += 4.0 / (hx * hx);
+        const double s = sin(M_PI / (2.0 * nx));
+        Glo = fmin(Glo, 4.0 * s * s / (hx * hx));
+    }
+    const double plo = -2.0 * log10(Ghi) - 4.0, phi_ = -2.0 * log10(Glo) + 4.0;
+    const int K1 = (int)floor((phi_ - plo) / 0.25) + 1;
+    int best = 0;
+    double bg = INFINITY;
+    for (int i = 0; i < K1; ++i) {
+        const double g = gcv_dense(P, w0, n, pow(10.0, plo + 0.25 * i), NULL, scratch);
+        if (g < bg) { bg = g; best = i; }
+    }
+    double a = plo + 0.25 * (best > 0 ? best - 1 : 0);
+    double b = plo + 0.25 * (best < K1 - 1 ? best + 1 : K1 - 1);
+    for (int stage = 0; stage < 2; ++stage) {
+        int bi = 0;
+        bg = INFINITY;
+        for (int j = 0; j <= 64; ++j) {
+            const double g = gcv_dense(P, w0, n, pow(10.0, a + (b - a) * j / 64.0), NULL, scratch);
+            if (g < bg) { bg = g; bi = j; }
+        }
+        const double na = a + (b - a) * (bi > 0 ? bi - 1 : 0) / 64.0;
+        const double nb = a + (b - a) * (bi < 64 ? bi + 1 : 64) / 64.0;
+        if (stage == 1) { a = a + (b - a) * bi / 64.0; b = a; break; }
+        a = na;
+        b = nb;
+    }
+    const double lam = pow(10.0, a);
+    (void)gcv_dense(P, w0, n, lam, w, scratch);
+    double mean = 0.0;
+    for (int c = 0; c < n; ++c) mean += w0[c];
+    mean /= n;
+    for (int c = 0; c < n; ++c) w[c] = fmax(w[c], 1e-3 * mean);
+    if (lambda_out) *lambda_out = lam;
+    free(Lap);
+    free(P);
+    free(w0);
+    free(scratch);
+    return 0;
+}
+
+/* new priors: uhat_i = prior of the (E, x) cell of particle i, the mean of u
+ * over the cell (empty cells keep their previous prior), then optionally
+ * smoothed over the grid */
 int orc_refresh_priors(orc_model *m) {
     int C = m->par.n_E * m->par.n_x;
     double *sum = (double *)calloc(C, sizeof(double));
@@ -467,11 +622,19 @@ int orc_refresh_priors(orc_model *m) {
         sum[cell[i]] += m->u[i];
         cnt[cell[i]] += 1;
     }
-    for (int64_t i = 0; i < m->n; ++i) m->uhat[i] = sum[cell[i]] / (double)cnt[cell[i]];
+    double *grid = (double *)malloc(sizeof(double) * C);
+    for (int c = 0; c < C; ++c)
+        grid[c] = cnt[c] > 0 ? sum[c] / (double)cnt[c] : (m->ucell ? m->ucell[c] : 1.0);
+    int rc = 0;
+    if (m->par.smooth) rc = orc_smooth_grid(&m->par, grid, NULL);
+    if (m->ucell)
+        for (int c = 0; c < C; ++c) m->ucell[c] = grid[c];
+    for (int64_t i = 0; i < m->n; ++i) m->uhat[i] = grid[cell[i]];
+    free(grid);
     free(sum);
     free(cnt);
     free(cell);
-    return 0;
+    return rc;
 }
 
 /* n steps; correct = 0 advances and smooths without weight correction

@@ -43,7 +43,8 @@ class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("eps", C.c_double), ("mu", C.c_double),
                 ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
                 ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
-                ("E_lo", C.c_double), ("E_hi", C.c_double)]
+                ("E_lo", C.c_double), ("E_hi", C.c_double), ("smooth", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -56,7 +57,7 @@ class Model(C.Structure):
         ("Y", _dp), ("sigma", _dp), ("Vp", _dp), ("sp", _dp),
         ("ytilde", _dp), ("yraw", _dp), ("delta", _dp), ("chi2", C.c_double),
         ("kstep", C.c_int64), ("flag", C.POINTER(C.c_uint8)), ("band", C.c_double),
-        ("nthreads", C.c_int32)]
+        ("nthreads", C.c_int32), ("ucell", _dp)]
 
 
 _lib = None
@@ -94,6 +95,8 @@ def lib():
             C.POINTER(C.c_int32), _dp, _dp]
         L.orc_init.argtypes = [C.POINTER(Model)]
         L.orc_refresh_priors.argtypes = [C.POINTER(Model)]
+        L.orc_smooth_grid.restype = C.c_int
+        L.orc_smooth_grid.argtypes = [C.POINTER(Params), _dp, _dp]
         L.orc_steps.argtypes = [C.POINTER(Model), C.c_int32, C.c_int32, _dp]
         L.orc_cell_mass.argtypes = [C.POINTER(Potential), C.POINTER(Params), C.c_int64] + [
             _dp] * 7 + [C.c_double, _dp]
@@ -125,7 +128,20 @@ def layout(d: dict) -> Layout:
 def params(d: dict) -> Params:
     return Params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
                   entropy=ENTROPY[d["entropy"]], n_E=d["n_E"], n_x=d["n_x"],
-                  prior_every=d["prior_every"], E_lo=d["E_lo"], E_hi=d["E_hi"])
+                  prior_every=d["prior_every"], E_lo=d["E_lo"], E_hi=d["E_hi"],
+                  smooth=int(d.get("smooth", 0)), pad=0)
+
+
+def smooth_grid(par: dict, grid):
+    """Thin-plate smoothing of an n_E x n_x prior grid with the GCV-chosen
+    lambda (Sec. 2.3.2); returns (smoothed grid, lambda)."""
+    w = _f64(grid).copy().reshape(-1)
+    if w.size != int(par["n_E"]) * int(par["n_x"]):
+        raise ValueError("grid size does not match n_E * n_x")
+    lam = C.c_double()
+    if lib().orc_smooth_grid(C.byref(params(dict(par, smooth=1))), _p(w), C.byref(lam)) != 0:
+        raise RuntimeError("orc_smooth_grid failed")
+    return w, lam.value
 
 
 def J_of(lay: dict) -> int:
@@ -248,6 +264,8 @@ class OracleFit:
         m.flag = self.flag.ctypes.data_as(C.POINTER(C.c_uint8)) if track_flags else None
         m.band = band
         m.nthreads = nthreads
+        self.ucell = np.ones(int(par["n_E"]) * int(par["n_x"]))
+        m.ucell = _p(self.ucell)
         self.m = m
         if self.Y.size != self.J or self.sigma.size != self.J:
             raise ValueError("target length does not match the layout")

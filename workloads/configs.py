@@ -67,13 +67,14 @@ def J_of(layout: dict) -> int:
 
 
 def make_params(pot: Potential, dt=0.01, eps=0.1, mu=1e-2, alpha=2.1, mass=1.0,
-                entropy="mpr", n_E=20, n_x=10, prior_every=25):
+                entropy="mpr", n_E=20, n_x=10, prior_every=25, smooth=0):
     """Step parameters. alpha is the smoothing rate per unit time (the
     workloads' "alpha = 2.1 dt" is read as alpha dt = 0.021 at dt = 0.01).
-    The (E, x) grid spans E in [Phi(0), 0)."""
+    The (E, x) grid spans E in [Phi(0), 0). smooth = 1 smooths the prior grid
+    (thin-plate spline, lambda by GCV) at every refresh."""
     return dict(dt=float(dt), eps=float(eps), mu=float(mu), alpha=float(alpha),
                 mass=float(mass), entropy=entropy, n_E=int(n_E), n_x=int(n_x),
-                prior_every=int(prior_every), E_lo=-pot.psi0(), E_hi=0.0)
+                prior_every=int(prior_every), E_lo=-pot.psi0(), E_hi=0.0, smooth=int(smooth))
 
 
 @dataclass
