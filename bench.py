@@ -212,6 +212,8 @@ def main(argv=None):
                     help="also run one 256 MiB float32 device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smooth", action="store_true",
+                    help="workloads 1-3: thin-plate GCV smoothing of the prior grid at refreshes")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the M2M path here is a "
@@ -258,6 +260,8 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return 0
     wl = workload(args.workload)
+    if args.smooth:
+        wl.params = dict(wl.params, smooth=1)
     dtype = wl.state
     print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={LAUNCH[args.workload]}",
           file=sys.stderr, flush=True)
@@ -303,6 +307,7 @@ def main(argv=None):
         "config": {"workload": wl.name, "particles": wl.N, "observables": wl.J,
                    "kinematics": wl.layout["kin"], "prior_grid": [wl.params["n_E"], wl.params["n_x"]],
                    "prior_every": wl.params["prior_every"], "state": dtype,
+                   "prior_smoothing": bool(wl.params.get("smooth", 0)),
                    "launch": list(LAUNCH[args.workload])},
         "latency": {"p50_s": ms * 1e-3, "p99_s": ms * 1e-3,
                     "fit": f"one fit, {args.steps} steps, device time"},

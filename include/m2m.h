@@ -49,6 +49,20 @@
  *     both clamped into the grid; E = v^2/2 + Phi(r), x = |r x v| / L_c(E);
  *     x = 0 for E >= 0 and x = 1 for E <= Phi(0). Empty cells keep their
  *     previous prior (no particle reads them).
+ *   Prior smoothing (smooth = 1, eq. smooth_grid). The grid w0 of cell means
+ *     (previous priors for empty cells) is replaced by the minimizer of
+ *     |w - w0|^2 + lambda w^T P w, P the finite-difference thin-plate
+ *     penalty (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 on the grid in its
+ *     own units (cell widths (E_hi - E_lo)/n_E and 1/n_x) with reflecting
+ *     boundaries, which equals |Lap w|^2 for the grid Laplacian. lambda
+ *     minimizes the generalized cross validation score
+ *       GCV = (|w0 - A w0|^2/n) / (1 - tr(A)/n)^2,  A = (I + lambda P)^-1,
+ *     over log10 lambda: steps of 0.25 over [-2 log10(G_hi) - 4,
+ *     -2 log10(G_lo) + 4] (G_hi = 4/hE^2 + 4/hx^2, G_lo the smaller of
+ *     4 sin^2(pi/2n)/h^2 over axes with more than one cell), then 65 points
+ *     over the two steps around the best one, then 65 points over the two
+ *     sub-steps around the best one. Smoothed priors are floored at 1e-3
+ *     times the mean of w0.
  *
  * Memory and ownership
  *   Particle arrays (x, y, z, vx, vy, vz, u, u_prior) are device pointers in
@@ -128,6 +142,9 @@ typedef struct {
     int32_t n_E, n_x;    /* prior grid, n_E, n_x >= 1, n_E * n_x <= 4096 */
     int32_t prior_every; /* correction steps between prior refreshes; 0 = never */
     double E_lo, E_hi;   /* energy range of the grid, E_lo < E_hi */
+    int32_t smooth;      /* 1: smooth the prior grid at every refresh (Sec. 2.3.2, see
+                            "Prior smoothing"); needs n_E, n_x <= 128; 0: cell means */
+    int32_t reserved;    /* must be 0 */
 } m2m_params;
 
 /* Number of observables J of a layout (0 if the layout is invalid). */

@@ -45,7 +45,8 @@ class m2m_params(C.Structure):
     _fields_ = [("dt", C.c_double), ("eps", C.c_double), ("mu", C.c_double),
                 ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
                 ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
-                ("E_lo", C.c_double), ("E_hi", C.c_double)]
+                ("E_lo", C.c_double), ("E_hi", C.c_double), ("smooth", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -135,7 +136,7 @@ def params(d: dict) -> m2m_params:
     ent = ENTROPY[d["entropy"]] if isinstance(d["entropy"], str) else int(d["entropy"])
     return m2m_params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
                       entropy=ent, n_E=d["n_E"], n_x=d["n_x"], prior_every=d["prior_every"],
-                      E_lo=d["E_lo"], E_hi=d["E_hi"])
+                      E_lo=d["E_lo"], E_hi=d["E_hi"], smooth=int(d.get("smooth", 0)), reserved=0)
 
 
 # ---- thin wrappers with the C names ------------------------------------------

@@ -20,6 +20,8 @@ namespace {
 
 constexpr int kGraphSteps = 8;      // M2M steps per captured graph
 constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
+constexpr uint32_t kStateVersion = 2u;         // 2: with the FP64 prior grid
+constexpr double kPi = 3.14159265358979323846;
 
 // launch shape for contexts and batches created from now on
 int g_block = 1024, g_tiles_per_cu = 1;
@@ -85,6 +87,26 @@ int32_t num_obs(const m2m_obs_layout& L) {
     return L.n_r + L.n_R * kin_per_annulus(L);
 }
 
+// log10(lambda) search range of the prior smoothing and the number of
+// points of its first stage (steps of 0.25)
+void smooth_range(const m2m_params& P, double* plo, double* phi, int* k1) {
+    const double hE = (P.E_hi - P.E_lo) / P.n_E, hx = 1.0 / P.n_x;
+    double ghi = 0.0, glo = INFINITY;
+    if (P.n_E > 1) {
+        ghi += 4.0 / (hE * hE);
+        const double s = std::sin(kPi / (2.0 * P.n_E));
+        glo = std::min(glo, 4.0 * s * s / (hE * hE));
+    }
+    if (P.n_x > 1) {
+        ghi += 4.0 / (hx * hx);
+        const double s = std::sin(kPi / (2.0 * P.n_x));
+        glo = std::min(glo, 4.0 * s * s / (hx * hx));
+    }
+    *plo = -2.0 * std::log10(ghi) - 4.0;
+    *phi = -2.0 * std::log10(glo) + 4.0;
+    *k1 = (int)std::floor((*phi - *plo) / 0.25) + 1;
+}
+
 std::string check_params(const m2m_params* P) {
     if (!P) return "params is NULL";
     if (!(is_fin(P->dt) && P->dt > 0)) return "dt must be > 0";
@@ -96,6 +118,16 @@ std::string check_params(const m2m_params* P) {
     if (P->n_E < 1 || P->n_x < 1 || (int64_t)P->n_E * P->n_x > kMaxCells) return "need n_E, n_x >= 1 and n_E*n_x <= 4096";
     if (P->prior_every < 0) return "prior_every must be >= 0";
     if (!(is_fin(P->E_lo) && is_fin(P->E_hi) && P->E_hi > P->E_lo)) return "need E_lo < E_hi";
+    if (P->smooth != 0 && P->smooth != 1) return "smooth must be 0 or 1";
+    if (P->reserved != 0) return "reserved must be 0";
+    if (P->smooth && (P->n_E > kSmoothMaxSide || P->n_x > kSmoothMaxSide))
+        return "prior smoothing needs n_E, n_x <= 128";
+    if (P->smooth && P->n_E * P->n_x > 1) {
+        double plo, phi;
+        int k1;
+        smooth_range(*P, &plo, &phi, &k1);
+        if (k1 > kSmoothMaxPoints) return "prior smoothing: grid spacings too different";
+    }
     return "";
 }
 
@@ -190,6 +222,7 @@ constexpr double kLz1 = 20.7232658369464;   // ln 1e9
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
     size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
+    size_t cdata, gprior, dctE, dctx, muE, mux, sm_a, sm_b;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
     int seg_cap, row_len, nbj, ncj, J, C;
 };
@@ -244,6 +277,16 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.chi2p = take(8 * (size_t)w.nbj);
     w.partials = take(8 * (size_t)w.seg_cap * (size_t)w.row_len);
     w.cidx = take(2 * (size_t)n);
+    w.cdata = take(8 * (size_t)w.C);
+    w.gprior = take(8 * (size_t)w.C);
+    if (P.smooth) {
+        w.dctE = take(8 * (size_t)P.n_E * P.n_E);
+        w.dctx = take(8 * (size_t)P.n_x * P.n_x);
+        w.muE = take(8 * (size_t)P.n_E);
+        w.mux = take(8 * (size_t)P.n_x);
+        w.sm_a = take(8 * (size_t)w.C);
+        w.sm_b = take(8 * (size_t)w.C);
+    }
     w.total = o;
     return w;
 }
@@ -320,6 +363,13 @@ m2m_status upload(m2m_ctx* c, size_t off, const std::vector<double>& v) {
     std::vector<unsigned char> b = c->f64 ? as_bytes<double>(v) : as_bytes<float>(v);
     if (b.empty()) return M2M_OK;
     M2M_HIP(c, copy_sync(c->stream, c->ws + off, b.data(), b.size(), hipMemcpyHostToDevice));
+    return M2M_OK;
+}
+
+m2m_status upload64(m2m_ctx* c, size_t off, const std::vector<double>& v) {
+    if (v.empty()) return M2M_OK;
+    M2M_HIP(c, copy_sync(c->stream, c->ws + off, v.data(), v.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
     return M2M_OK;
 }
 
@@ -592,6 +642,20 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.ucell = b + w.ucell;
     f.lctab = b + w.lctab;
     f.cidx = reinterpret_cast<uint16_t*>(b + w.cidx);
+    f.cdata = reinterpret_cast<double*>(b + w.cdata);
+    f.gprior = reinterpret_cast<double*>(b + w.gprior);
+    f.smooth = c->par.smooth;
+    if (c->par.smooth) {
+        f.dctE = reinterpret_cast<double*>(b + w.dctE);
+        f.dctx = reinterpret_cast<double*>(b + w.dctx);
+        f.muE = reinterpret_cast<double*>(b + w.muE);
+        f.mux = reinterpret_cast<double*>(b + w.mux);
+        f.sm_a = reinterpret_cast<double*>(b + w.sm_a);
+        f.sm_b = reinterpret_cast<double*>(b + w.sm_b);
+        int k1 = 0;
+        smooth_range(c->par, &f.sm_plo, &f.sm_phi, &k1);
+        f.sm_k1 = k1;
+    }
     f.lz0 = kLz0;
     f.ilz = (kLcTable - 1) / (kLz1 - kLz0);
     const double dt = c->par.dt;
@@ -639,6 +703,33 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     if ((s = upload(c, w.vedge, ve)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.ucell, ones)) != M2M_OK) return bail(s);
+    if ((s = upload64(c, w.gprior, ones)) != M2M_OK) return bail(s);
+    if (c->par.smooth) {
+        // orthonormal DCT-II matrices and the eigenvalues 4 sin^2(pi k/2n)/h^2
+        // of minus the reflecting-boundary second difference of each axis
+        auto dct = [](int n) {
+            std::vector<double> m((size_t)n * n);
+            for (int k = 0; k < n; ++k)
+                for (int i = 0; i < n; ++i)
+                    m[(size_t)k * n + i] = std::sqrt((k == 0 ? 1.0 : 2.0) / n) *
+                                           std::cos(kPi * k * (2.0 * i + 1.0) / (2.0 * n));
+            return m;
+        };
+        auto eig = [](int n, double h) {
+            std::vector<double> v(n);
+            for (int k = 0; k < n; ++k) {
+                const double sn = std::sin(kPi * k / (2.0 * n));
+                v[k] = 4.0 * sn * sn / (h * h);
+            }
+            return v;
+        };
+        const double hE = (c->par.E_hi - c->par.E_lo) / c->par.n_E, hx = 1.0 / c->par.n_x;
+        if ((s = upload64(c, w.dctE, dct(c->par.n_E))) != M2M_OK ||
+            (s = upload64(c, w.dctx, dct(c->par.n_x))) != M2M_OK ||
+            (s = upload64(c, w.muE, eig(c->par.n_E, hE))) != M2M_OK ||
+            (s = upload64(c, w.mux, eig(c->par.n_x, hx))) != M2M_OK)
+            return bail(s);
+    }
     if ((s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return bail(s);
 
     // ---- tiles of this fit alone
@@ -818,7 +909,7 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
     const size_t J = (size_t)c->w.J, C = (size_t)c->w.C, nR = c->Vp.size();
     const size_t sz = c->f64 ? 8 : 4;
     const size_t need = sizeof(StateHeader) + sizeof(FitState) + 8 * (5 * J + 2 * nR) +
-                        sz * (C + J) + 8 * (size_t)kHistCap;
+                        sz * (C + J) + 8 * (size_t)kHistCap + 8 * C;
     if (!host_blob) {
         *bytes = need;
         return M2M_OK;
@@ -829,7 +920,7 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
     m2m_status s = flush_assign(c);
     if (s != M2M_OK) return s;
     unsigned char* p = static_cast<unsigned char*>(host_blob);
-    StateHeader h{kStateMagic, 1u, c->n, (int32_t)J, (int32_t)C, c->f64 ? 1 : 0, (int32_t)nR,
+    StateHeader h{kStateMagic, kStateVersion, c->n, (int32_t)J, (int32_t)C, c->f64 ? 1 : 0, (int32_t)nR,
                   c->targets ? 1 : 0, c->ytil_init ? 1 : 0, 0, 0};
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -849,6 +940,8 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
     M2M_HIP(c, copy_sync(c->stream, p, c->fd.rp, sz * J, hipMemcpyDeviceToHost));
     p += sz * J;
     M2M_HIP(c, copy_sync(c->stream, p, c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
+    p += 8 * (size_t)kHistCap;
+    M2M_HIP(c, copy_sync(c->stream, p, c->fd.gprior, 8 * C, hipMemcpyDeviceToHost));
     *bytes = need;
     return M2M_OK;
 }
@@ -863,7 +956,7 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     StateHeader h{};
     std::memcpy(&h, p, sizeof h);
     const size_t J = (size_t)c->w.J, C = (size_t)c->w.C, nR = c->Vp.size();
-    if (h.magic != kStateMagic || h.version != 1u || h.n != c->n || h.J != (int32_t)J ||
+    if (h.magic != kStateMagic || h.version != kStateVersion || h.n != c->n || h.J != (int32_t)J ||
         h.C != (int32_t)C || h.dtype != (c->f64 ? 1 : 0) || h.n_R != (int32_t)nR)
         return fail(c, M2M_EINVAL, "state blob does not match this context");
     p += sizeof h;
@@ -895,6 +988,8 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     M2M_HIP(c, copy_sync(c->stream, c->fd.rp, p, (c->f64 ? 8 : 4) * J, hipMemcpyHostToDevice));
     p += (c->f64 ? 8 : 4) * J;
     M2M_HIP(c, copy_sync(c->stream, c->fd.chi2_hist, p, 8 * (size_t)kHistCap, hipMemcpyHostToDevice));
+    p += 8 * (size_t)kHistCap;
+    M2M_HIP(c, copy_sync(c->stream, c->fd.gprior, p, 8 * C, hipMemcpyHostToDevice));
     c->targets = h.targets != 0;
     c->ytil_init = h.ytil_init != 0;
     return M2M_OK;

@@ -16,6 +16,8 @@ constexpr int kLcTable = 8192;     // entries of the ln r_c(ln zeta) table
 constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
 constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
 constexpr int kFinWaves = kFinThreads / 64;  // row groups of the fixed reduction order
+constexpr int kSmoothMaxSide = 128;   // prior smoothing: at most this many cells per axis
+constexpr int kSmoothMaxPoints = 256; // and at most this many first-stage search points
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
 constexpr int kSegAlign = 64;      // tile boundaries are multiples of 64 particles
 
@@ -58,7 +60,7 @@ struct FitDev {
     double *partials;        // tile rows of row_len doubles
     int32_t row_len;         // J + 2 C
     int32_t kpriv;           // private copies of the in-tile bins (power of 2)
-    int32_t pad2;
+    int32_t smooth;          // thin-plate smoothing of the prior grid at refreshes
     int32_t n_bin_jobs;      // ceil(J / kFinCols)
     int32_t n_cell_jobs;     // ceil(C / kFinCols)
     int32_t entropy;
@@ -67,6 +69,15 @@ struct FitDev {
     double E_lo, E_hi, E_scale;  // E_scale = n_E / (E_hi - E_lo)
     void *ucell, *lctab;         // C values; kLcTable values of ln r_c(ln zeta)
     uint16_t *cidx;              // n values: cell of each particle at the last refresh
+    // prior grid in FP64: cell data of the last refresh (means, or the
+    // previous prior of empty cells) and the current priors
+    double *cdata, *gprior;
+    // smoothing: orthonormal DCT-II matrices (n_E^2, n_x^2), eigenvalues of
+    // minus the reflecting-boundary second difference per axis (n_E, n_x),
+    // two n_E n_x scratch grids, the log10(lambda) search range
+    double *dctE, *dctx, *muE, *mux, *sm_a, *sm_b;
+    double sm_plo, sm_phi;
+    int32_t sm_k1, pad3;         // points of the first search stage
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
     // step constants
     double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0

@@ -508,8 +508,14 @@ __device__ __forceinline__ double column_epilogue(const FitDev& fd, bool bins, i
             gmem<T>(fd.rp)[col] = (T)(fd.foc_chi * d / sg);
             d2 = d * d;
         }
-    } else if (!bins && col < fd.C && tot2 > 0.0) {
-        gmem<T>(fd.ucell)[col] = (T)(tot / tot2);
+    } else if (!bins && col < fd.C) {
+        // the cell's data: the mean weight, or the previous prior if empty
+        const double d = (tot2 > 0.0) ? tot / tot2 : gmem(fd.gprior)[col];
+        gmem(fd.cdata)[col] = d;
+        if (!fd.smooth) {
+            gmem(fd.gprior)[col] = d;
+            gmem<T>(fd.ucell)[col] = (T)d;
+        }
     }
     if (bins && !f.observe) {
         // chi^2 of these columns: fixed-order butterfly over the wave
@@ -545,13 +551,135 @@ __device__ __forceinline__ void end_step(const FitDev& fd, G<FitState> gst, cons
     if (f.cells_mode) gst->assign_pending = 1;
 }
 
+// Thin-plate smoothing of the prior grid with the GCV-chosen lambda (Sec.
+// 2.3.2, eq. smooth_grid) by the block that ends a refresh step. On the grid
+// with reflecting boundaries the penalty is |Lap w|^2 and the orthonormal
+// 2-D DCT-II diagonalizes Lap (eigenvalues -(muE_k + mux_m)), so with
+// Gamma = muE_k + mux_m and the transformed data w^ the smoother is the
+// filter 1/(1 + lambda Gamma^2), and
+//   |w0 - A w0|^2 = sum (t/(1+t))^2 w^^2,  1 - tr(A)/n = sum t/(1+t) / n,
+// t = lambda Gamma^2. The log10(lambda) search: steps of 0.25 from sm_plo
+// (sm_k1 points), then 65 points over the two steps around the best, then
+// 65 points over the two sub-steps around the best (first minimum on
+// ties). Smoothed priors are floored at 1e-3 of the mean of the data.
+// buf: kFinThreads doubles of LDS; sidx, smean: LDS scalars.
+template <typename T>
+__device__ void smooth_priors(const FitDev& fd, double* buf, int* sidx, double* smean) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nE = fd.n_E, nx = fd.n_x, n = nE * nx;
+    const G<const double> w0 = gmem<const double>(fd.cdata);
+    const G<double> gp = gmem(fd.gprior);
+    const G<T> uc = gmem<T>(fd.ucell);
+    if (n < 2) {
+        if (tid == 0) {
+            gp[0] = w0[0];
+            uc[0] = (T)w0[0];
+        }
+        return;
+    }
+    const G<const double> CE = gmem<const double>(fd.dctE), CX = gmem<const double>(fd.dctx);
+    const G<const double> mE = gmem<const double>(fd.muE), mX = gmem<const double>(fd.mux);
+    const G<double> A = gmem(fd.sm_a), B = gmem(fd.sm_b);
+    if (wave == 0) {
+        double sm = 0.0;
+        for (int c = lane; c < n; c += 64) sm += w0[c];
+        for (int off = 32; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 64);
+        if (lane == 0) *smean = sm / n;
+    }
+    // forward transform: A = C_E w0, B = A C_x^T
+    for (int o = tid; o < n; o += kFinThreads) {
+        const int k = o / nx, l = o - k * nx;
+        double v = 0.0;
+        for (int i = 0; i < nE; ++i) v += CE[k * nE + i] * w0[i * nx + l];
+        A[o] = v;
+    }
+    __syncthreads();
+    for (int o = tid; o < n; o += kFinThreads) {
+        const int k = o / nx, m = o - k * nx;
+        double v = 0.0;
+        for (int j = 0; j < nx; ++j) v += A[k * nx + j] * CX[m * nx + j];
+        B[o] = v;
+    }
+    __syncthreads();
+    // GCV at npts values of log10(lambda): coarse p = a + 0.25 i, refined
+    // p = a + (b - a) i / 64; returns the index of the first minimum
+    auto stage = [&](bool coarse, double a, double b, int npts) -> int {
+        for (int i = wave; i < npts; i += kFinWaves) {
+            const double p = coarse ? a + 0.25 * i : a + (b - a) * i / 64.0;
+            const double lam = pow(10.0, p);
+            double rss = 0.0, den = 0.0;
+            for (int c = lane; c < n; c += 64) {
+                const int k = c / nx, m = c - k * nx;
+                const double g = mE[k] + mX[m];
+                const double t = lam * g * g;
+                const double r = t / (1.0 + t);
+                const double e = r * B[c];
+                rss += e * e;
+                den += r;
+            }
+            for (int off = 32; off >= 1; off >>= 1) {
+                rss += __shfl_xor(rss, off, 64);
+                den += __shfl_xor(den, off, 64);
+            }
+            if (lane == 0) buf[i] = (rss / n) / ((den / n) * (den / n));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int bi = 0;
+            double bg = buf[0];
+            for (int i = 1; i < npts; ++i)
+                if (buf[i] < bg) {
+                    bg = buf[i];
+                    bi = i;
+                }
+            *sidx = bi;
+        }
+        __syncthreads();
+        return *sidx;
+    };
+    const int K1 = fd.sm_k1;
+    const double plo = fd.sm_plo;
+    const int i1 = stage(true, plo, 0.0, K1);
+    double a = plo + 0.25 * (i1 > 0 ? i1 - 1 : 0);
+    double b = plo + 0.25 * (i1 < K1 - 1 ? i1 + 1 : K1 - 1);
+    const int i2 = stage(false, a, b, 65);
+    const double na = a + (b - a) * (i2 > 0 ? i2 - 1 : 0) / 64.0;
+    const double nb = a + (b - a) * (i2 < 64 ? i2 + 1 : 64) / 64.0;
+    const int i3 = stage(false, na, nb, 65);
+    const double lam = pow(10.0, na + (nb - na) * i3 / 64.0);
+    // filter, inverse transform (B = C_E^T A, w = B C_x), floor
+    for (int c = tid; c < n; c += kFinThreads) {
+        const int k = c / nx, m = c - k * nx;
+        const double g = mE[k] + mX[m];
+        A[c] = B[c] / (1.0 + lam * g * g);
+    }
+    __syncthreads();
+    for (int o = tid; o < n; o += kFinThreads) {
+        const int i = o / nx, m = o - i * nx;
+        double v = 0.0;
+        for (int k = 0; k < nE; ++k) v += CE[k * nE + i] * A[k * nx + m];
+        B[o] = v;
+    }
+    __syncthreads();
+    const double floor_v = 1e-3 * (*smean);
+    for (int o = tid; o < n; o += kFinThreads) {
+        const int i = o / nx, l = o - i * nx;
+        double v = 0.0;
+        for (int m = 0; m < nx; ++m) v += B[i * nx + m] * CX[m * nx + l];
+        v = fmax(v, floor_v);
+        gp[o] = v;
+        uc[o] = (T)v;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
                                                          const FinJob* __restrict__ jobs,
                                                          int32_t mode) {
     __shared__ double part[kFinWaves][kFinCols];
     __shared__ double part2[kFinWaves][kFinCols];
-    __shared__ int last;
+    __shared__ int last, sidx;
+    __shared__ double smean;
     const FinJob jb = jobs[blockIdx.x];
     const FitDev& fd = fits[jb.fit];
     FitState* st = fd.st;
@@ -606,8 +734,11 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
         last = (prev == n_part - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (!last || wave != 0) return;
+    if (!last) return;
     __threadfence();
+    // a refresh with smoothing: the whole block smooths the prior grid
+    if (fd.smooth && f.refresh) smooth_priors<T>(fd, &part[0][0], &sidx, &smean);
+    if (wave != 0) return;
     const double chi2 =
         cells_mode ? 0.0 : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
     if (lane != 0) return;

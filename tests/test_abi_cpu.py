@@ -42,6 +42,11 @@ def test_host_only_entry_points():
     assert _abi.m2m_num_observables(bad) == 0
     assert _abi.m2m_workspace_bytes(wl.layout, wl.params, wl.N) > 0
     assert _abi.m2m_workspace_bytes(wl.layout, wl.params, 0) == 0
+    # prior smoothing: grids of at most 128 cells per side
+    assert _abi.m2m_workspace_bytes(wl.layout, dict(wl.params, smooth=1), wl.N) > 0
+    assert _abi.m2m_workspace_bytes(wl.layout, dict(wl.params, smooth=1, n_E=200, n_x=2),
+                                    wl.N) == 0
+    assert _abi.m2m_workspace_bytes(wl.layout, dict(wl.params, smooth=2), wl.N) == 0
     b0 = _abi.m2m_get_launch()
     with pytest.raises(_abi.M2MError):
         _abi.m2m_set_launch(300, 4)

@@ -367,3 +367,61 @@ def test_fp32_vs_fp64_state_per_observable(oracle, Fit):
     assert rows[0][1] <= 1e-5 and rows[0][3] <= 1e-5
     assert rows[-1][1] <= 1e-3 and rows[-1][3] <= 1e-3
 
+
+
+def _clear_of_cell_edges(oracle, pot, par, parts, band):
+    """Particles whose (E, x) lie more than ``band`` (relative) from every
+    prior-cell edge, so that the GPU and the oracle bin them alike."""
+    _, E, xc = oracle.cells(pot, par, parts)
+    dE = (par["E_hi"] - par["E_lo"]) / par["n_E"]
+    te = (E - par["E_lo"]) / dE
+    tx = xc * par["n_x"]
+    amb = (np.abs(te - np.round(te)) * dE <= band * abs(par["E_lo"])) | (
+        np.abs(tx - np.round(tx)) <= band * par["n_x"])
+    return {k: v[~amb] for k, v in parts.items()}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_prior_smoothing_matches_oracle(oracle, Fit, dtype):
+    """Thin-plate GCV smoothing of the prior grid (Sec. 2.3.2): the GPU's
+    spectral smoother against the oracle's dense solve, on cell means of the
+    same particles (those clear of cell edges, so both bin them alike)."""
+    wl = workload(1)
+    par = dict(wl.params, smooth=1, n_E=16, n_x=8)
+    parts = cast(wl.initial_particles(n=30_011, seed=6), dtype)
+    parts = _clear_of_cell_edges(oracle, wl.potential, par, parts, 1e-5)
+    n = parts["x"].size
+    u = cast({"u": random_weights(n, 13, spread=0.5)}, dtype)["u"]
+    _say("prior smoothing", dtype, n)
+    f = Fit(wl.potential, wl.layout, par, parts, dtype=dtype, u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    C = par["n_E"] * par["n_x"]
+    grid = np.frombuffer(f.get_state()[-8 * C:], dtype=np.float64)
+    f.close()
+    J = oracle.J_of(wl.layout)
+    o = oracle.OracleFit(wl.potential, wl.layout, par, parts, np.ones(J), np.ones(J), u=u)
+    o.refresh_priors()
+    np.testing.assert_allclose(grid, o.ucell, rtol=1e-10)
+    np.testing.assert_allclose(uh, o.arr["uhat"], rtol=1e-6 if dtype == "f32" else 1e-12)
+
+
+def test_run_with_prior_smoothing_matches_oracle(oracle, Fit):
+    """120 FP32 steps with smoothed moving priors (four refreshes) against
+    the oracle, to the weight tolerance of the FP32 path."""
+    wl = workload(1)
+    par = dict(wl.params, smooth=1)
+    T = oracle_targets(oracle, wl)
+    n = 20_000
+    parts = cast(wl.initial_particles(n=n, seed=8), "f32")
+    _say("run with smoothing", n)
+    f = Fit(wl.potential, wl.layout, par, parts, dtype="f32")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    o = oracle.OracleFit(wl.potential, wl.layout, par, parts, T["Y"], T["sigma"], T["V_p"],
+                         T["sigma_p"], track_flags=True, band=1e-5, nthreads=8)
+    f.step(120)
+    o.step(120)
+    r2, rmax, rall, frac = weight_errors(f.particles()["u"], o.arr["u"], o.flag)
+    _say("run with smoothing: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    f.close()
+    assert r2 <= 1e-4 and rmax <= 1e-4
