@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 # launch shape (threads per block, tiles per CU) of the fused step kernel per
 # workload, as chosen by paper_1202_2355_amd.autotune
-LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (512, 6), 5: (512, 6)}
+LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (512, 12), 5: (512, 6)}
 
 SERVE_N_MIN = 100_000   # smallest fit of the serving trace (errors floored at its noise)
 METRIC = "particle-steps/sec (push+deposit+weight update) at 1 GPU; p50/p99 fit latency"

@@ -222,7 +222,7 @@ constexpr double kLz1 = 20.7232658369464;   // ln 1e9
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
     size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
-    size_t cdata, gprior, dctE, dctx, muE, mux, sm_a, sm_b;
+    size_t cdata, gprior;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
     int seg_cap, row_len, nbj, ncj, J, C;
 };
@@ -279,14 +279,6 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.cidx = take(2 * (size_t)n);
     w.cdata = take(8 * (size_t)w.C);
     w.gprior = take(8 * (size_t)w.C);
-    if (P.smooth) {
-        w.dctE = take(8 * (size_t)P.n_E * P.n_E);
-        w.dctx = take(8 * (size_t)P.n_x * P.n_x);
-        w.muE = take(8 * (size_t)P.n_E);
-        w.mux = take(8 * (size_t)P.n_x);
-        w.sm_a = take(8 * (size_t)w.C);
-        w.sm_b = take(8 * (size_t)w.C);
-    }
     w.total = o;
     return w;
 }
@@ -646,12 +638,6 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.gprior = reinterpret_cast<double*>(b + w.gprior);
     f.smooth = c->par.smooth;
     if (c->par.smooth) {
-        f.dctE = reinterpret_cast<double*>(b + w.dctE);
-        f.dctx = reinterpret_cast<double*>(b + w.dctx);
-        f.muE = reinterpret_cast<double*>(b + w.muE);
-        f.mux = reinterpret_cast<double*>(b + w.mux);
-        f.sm_a = reinterpret_cast<double*>(b + w.sm_a);
-        f.sm_b = reinterpret_cast<double*>(b + w.sm_b);
         int k1 = 0;
         smooth_range(c->par, &f.sm_plo, &f.sm_phi, &k1);
         f.sm_k1 = k1;
@@ -704,32 +690,6 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.ucell, ones)) != M2M_OK) return bail(s);
     if ((s = upload64(c, w.gprior, ones)) != M2M_OK) return bail(s);
-    if (c->par.smooth) {
-        // orthonormal DCT-II matrices and the eigenvalues 4 sin^2(pi k/2n)/h^2
-        // of minus the reflecting-boundary second difference of each axis
-        auto dct = [](int n) {
-            std::vector<double> m((size_t)n * n);
-            for (int k = 0; k < n; ++k)
-                for (int i = 0; i < n; ++i)
-                    m[(size_t)k * n + i] = std::sqrt((k == 0 ? 1.0 : 2.0) / n) *
-                                           std::cos(kPi * k * (2.0 * i + 1.0) / (2.0 * n));
-            return m;
-        };
-        auto eig = [](int n, double h) {
-            std::vector<double> v(n);
-            for (int k = 0; k < n; ++k) {
-                const double sn = std::sin(kPi * k / (2.0 * n));
-                v[k] = 4.0 * sn * sn / (h * h);
-            }
-            return v;
-        };
-        const double hE = (c->par.E_hi - c->par.E_lo) / c->par.n_E, hx = 1.0 / c->par.n_x;
-        if ((s = upload64(c, w.dctE, dct(c->par.n_E))) != M2M_OK ||
-            (s = upload64(c, w.dctx, dct(c->par.n_x))) != M2M_OK ||
-            (s = upload64(c, w.muE, eig(c->par.n_E, hE))) != M2M_OK ||
-            (s = upload64(c, w.mux, eig(c->par.n_x, hx))) != M2M_OK)
-            return bail(s);
-    }
     if ((s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return bail(s);
 
     // ---- tiles of this fit alone

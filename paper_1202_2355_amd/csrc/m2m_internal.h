@@ -18,6 +18,7 @@ constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
 constexpr int kFinWaves = kFinThreads / 64;  // row groups of the fixed reduction order
 constexpr int kSmoothMaxSide = 128;   // prior smoothing: at most this many cells per axis
 constexpr int kSmoothMaxPoints = 256; // and at most this many first-stage search points
+constexpr int kGcvSlots = 5;          // lambda points a wave scores in one pass over the cells
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
 constexpr int kSegAlign = 64;      // tile boundaries are multiples of 64 particles
 
@@ -72,10 +73,7 @@ struct FitDev {
     // prior grid in FP64: cell data of the last refresh (means, or the
     // previous prior of empty cells) and the current priors
     double *cdata, *gprior;
-    // smoothing: orthonormal DCT-II matrices (n_E^2, n_x^2), eigenvalues of
-    // minus the reflecting-boundary second difference per axis (n_E, n_x),
-    // two n_E n_x scratch grids, the log10(lambda) search range
-    double *dctE, *dctx, *muE, *mux, *sm_a, *sm_b;
+    // smoothing: the log10(lambda) search range
     double sm_plo, sm_phi;
     int32_t sm_k1, pad3;         // points of the first search stage
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta

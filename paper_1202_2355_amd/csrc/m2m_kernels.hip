@@ -551,20 +551,62 @@ __device__ __forceinline__ void end_step(const FitDev& fd, G<FitState> gst, cons
     if (f.cells_mode) gst->assign_pending = 1;
 }
 
+// GCV score (RSS/n) / (1 - tr(A)/n)^2 of the spectral smoother at P values
+// of lambda, summed by one wave over the n cells (Gamma^2 in g2, transformed
+// data in wh); 1 / (1 + t) is a hardware reciprocal refined by two Newton
+// steps (within an ulp or two), as the score only ranks the lambdas.
+template <int P>
+__device__ __forceinline__ void gcv_points(const double* g2, const double* wh, int n, int lane,
+                                           const double* lam, double* out) {
+    double rss[P], den[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) rss[j] = den[j] = 0.0;
+    for (int c = lane; c < n; c += 64) {
+        const double g = g2[c], w = wh[c];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const double t = lam[j] * g;
+            const double d = 1.0 + t;
+            double iv = __builtin_amdgcn_rcp(d);
+            iv = fma(iv, fma(-d, iv, 1.0), iv);
+            iv = fma(iv, fma(-d, iv, 1.0), iv);
+            const double r = t * iv;
+            const double e = r * w;
+            rss[j] = fma(e, e, rss[j]);
+            den[j] += r;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            rss[j] += __shfl_xor(rss[j], off, 64);
+            den[j] += __shfl_xor(den[j], off, 64);
+        }
+        out[j] = (rss[j] / n) / ((den[j] / n) * (den[j] / n));
+    }
+}
+
 // Thin-plate smoothing of the prior grid with the GCV-chosen lambda (Sec.
 // 2.3.2, eq. smooth_grid) by the block that ends a refresh step. On the grid
 // with reflecting boundaries the penalty is |Lap w|^2 and the orthonormal
-// 2-D DCT-II diagonalizes Lap (eigenvalues -(muE_k + mux_m)), so with
-// Gamma = muE_k + mux_m and the transformed data w^ the smoother is the
-// filter 1/(1 + lambda Gamma^2), and
+// 2-D DCT-II diagonalizes Lap: its basis along an axis of n cells is
+// s_k cos(pi k (2i+1) / 2n) (s_0 = sqrt(1/n), s_k = sqrt(2/n)) with
+// eigenvalues -(2 - 2 cos(pi k / n)) / h^2. With Gamma the sum of the two
+// axes' eigenvalue magnitudes and the transformed data w^ the smoother is the filter
+// 1/(1 + lambda Gamma^2), and
 //   |w0 - A w0|^2 = sum (t/(1+t))^2 w^^2,  1 - tr(A)/n = sum t/(1+t) / n,
 // t = lambda Gamma^2. The log10(lambda) search: steps of 0.25 from sm_plo
 // (sm_k1 points), then 65 points over the two steps around the best, then
 // 65 points over the two sub-steps around the best (first minimum on
 // ties). Smoothed priors are floored at 1e-3 of the mean of the data.
-// buf: kFinThreads doubles of LDS; sidx, smean: LDS scalars.
+// In LDS: the grids sa, sb (kMaxCells doubles each), buf (scores and
+// lambdas of a search stage) and per axis the table
+// cos(pi j / 2n), j < 4n, from which every basis value and eigenvalue is
+// read (the argument k (2i+1) is taken modulo 4n).
 template <typename T>
-__device__ void smooth_priors(const FitDev& fd, double* buf, int* sidx, double* smean) {
+__device__ void smooth_priors(const FitDev& fd, double* sa, double* sb, double* tE, double* tX,
+                              double* buf, int* sidx, double* smean) {
+    static_assert(2 * kSmoothMaxPoints <= kFinWaves * kFinCols, "GCV scores and lambdas in buf");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nE = fd.n_E, nx = fd.n_x, n = nE * nx;
     const G<const double> w0 = gmem<const double>(fd.cdata);
@@ -577,62 +619,104 @@ __device__ void smooth_priors(const FitDev& fd, double* buf, int* sidx, double* 
         }
         return;
     }
-    const G<const double> CE = gmem<const double>(fd.dctE), CX = gmem<const double>(fd.dctx);
-    const G<const double> mE = gmem<const double>(fd.muE), mX = gmem<const double>(fd.mux);
-    const G<double> A = gmem(fd.sm_a), B = gmem(fd.sm_b);
+    const int pE = 4 * nE, pX = 4 * nx;
+    for (int j = tid; j < pE; j += kFinThreads) tE[j] = cos(M_PI * j / (2.0 * nE));
+    for (int j = tid; j < pX; j += kFinThreads) tX[j] = cos(M_PI * j / (2.0 * nx));
+    for (int c = tid; c < n; c += kFinThreads) sb[c] = w0[c];
+    const double sE0 = sqrt(1.0 / nE), sE = sqrt(2.0 / nE);
+    const double sX0 = sqrt(1.0 / nx), sX = sqrt(2.0 / nx);
+    __syncthreads();
     if (wave == 0) {
         double sm = 0.0;
-        for (int c = lane; c < n; c += 64) sm += w0[c];
+        for (int c = lane; c < n; c += 64) sm += sb[c];
         for (int off = 32; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 64);
         if (lane == 0) *smean = sm / n;
     }
-    // forward transform: A = C_E w0, B = A C_x^T
+    // forward transform along E: sa[k][l] = s_k sum_i cos(pi k (2i+1)/2nE) w0[i][l]
     for (int o = tid; o < n; o += kFinThreads) {
         const int k = o / nx, l = o - k * nx;
         double v = 0.0;
-        for (int i = 0; i < nE; ++i) v += CE[k * nE + i] * w0[i * nx + l];
-        A[o] = v;
+        int idx = k % pE;  // k (2i + 1) mod 4 nE
+        const int inc = (2 * k) % pE;
+        for (int i = 0; i < nE; ++i) {
+            v += tE[idx] * sb[i * nx + l];
+            idx += inc;
+            if (idx >= pE) idx -= pE;
+        }
+        sa[o] = (k == 0 ? sE0 : sE) * v;
     }
     __syncthreads();
+    // along x: sb[k][m] = s_m sum_j cos(pi m (2j+1)/2nx) sa[k][j]
     for (int o = tid; o < n; o += kFinThreads) {
         const int k = o / nx, m = o - k * nx;
         double v = 0.0;
-        for (int j = 0; j < nx; ++j) v += A[k * nx + j] * CX[m * nx + j];
-        B[o] = v;
+        int idx = m % pX;
+        const int inc = (2 * m) % pX;
+        for (int j = 0; j < nx; ++j) {
+            v += tX[idx] * sa[k * nx + j];
+            idx += inc;
+            if (idx >= pX) idx -= pX;
+        }
+        sb[o] = (m == 0 ? sX0 : sX) * v;
     }
     __syncthreads();
-    // GCV at npts values of log10(lambda): coarse p = a + 0.25 i, refined
-    // p = a + (b - a) i / 64; returns the index of the first minimum
+    // Gamma^2 of every cell into sa: (2 - 2 cos(pi k/n)) / h^2 per axis
+    {
+        const double hE = (fd.E_hi - fd.E_lo) / nE, hx = 1.0 / nx;
+        for (int c = tid; c < n; c += kFinThreads) {
+            const int k = c / nx, m = c - k * nx;
+            const double g = (2.0 - 2.0 * tE[(2 * k) % pE]) / (hE * hE) +
+                             (2.0 - 2.0 * tX[(2 * m) % pX]) / (hx * hx);
+            sa[c] = g * g;
+        }
+    }
+    __syncthreads();
+    // GCV at npts values of log10(lambda) (coarse p = a + 0.25 i, refined
+    // p = a + (b - a) i / 64): wave w takes points w, w + 16, ..., up to
+    // kGcvSlots of them in one pass over the cells (independent division
+    // chains, one load of each cell per pass); wave 0 then finds the index
+    // of the first minimum
+    double* lams = buf + kSmoothMaxPoints;  // lambda of each point of the stage
     auto stage = [&](bool coarse, double a, double b, int npts) -> int {
-        for (int i = wave; i < npts; i += kFinWaves) {
-            const double p = coarse ? a + 0.25 * i : a + (b - a) * i / 64.0;
-            const double lam = pow(10.0, p);
-            double rss = 0.0, den = 0.0;
-            for (int c = lane; c < n; c += 64) {
-                const int k = c / nx, m = c - k * nx;
-                const double g = mE[k] + mX[m];
-                const double t = lam * g * g;
-                const double r = t / (1.0 + t);
-                const double e = r * B[c];
-                rss += e * e;
-                den += r;
+        for (int i = tid; i < npts; i += kFinThreads)
+            lams[i] = pow(10.0, coarse ? a + 0.25 * i : a + (b - a) * i / 64.0);
+        __syncthreads();
+        const int mine = wave < npts ? (npts - wave + kFinWaves - 1) / kFinWaves : 0;
+        for (int j0 = 0; j0 < mine; j0 += kGcvSlots) {
+            const int cnt = min(kGcvSlots, mine - j0);
+            double lam[kGcvSlots];
+#pragma unroll
+            for (int j = 0; j < kGcvSlots; ++j)
+                lam[j] = j < cnt ? lams[wave + (j0 + j) * kFinWaves] : 0.0;
+            double out[kGcvSlots];
+            switch (cnt) {
+                case 5: gcv_points<5>(sa, sb, n, lane, lam, out); break;
+                case 4: gcv_points<4>(sa, sb, n, lane, lam, out); break;
+                case 3: gcv_points<3>(sa, sb, n, lane, lam, out); break;
+                case 2: gcv_points<2>(sa, sb, n, lane, lam, out); break;
+                default: gcv_points<1>(sa, sb, n, lane, lam, out); break;
             }
-            for (int off = 32; off >= 1; off >>= 1) {
-                rss += __shfl_xor(rss, off, 64);
-                den += __shfl_xor(den, off, 64);
-            }
-            if (lane == 0) buf[i] = (rss / n) / ((den / n) * (den / n));
+            if (lane == 0)
+                for (int j = 0; j < cnt; ++j) buf[wave + (j0 + j) * kFinWaves] = out[j];
         }
         __syncthreads();
-        if (tid == 0) {
-            int bi = 0;
-            double bg = buf[0];
-            for (int i = 1; i < npts; ++i)
-                if (buf[i] < bg) {
+        if (wave == 0) {
+            int bi = npts;
+            double bg = 0.0;
+            for (int i = lane; i < npts; i += 64)
+                if (bi == npts || buf[i] < bg) {
                     bg = buf[i];
                     bi = i;
                 }
-            *sidx = bi;
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double og = __shfl_xor(bg, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (oi < npts && (bi == npts || og < bg || (og == bg && oi < bi))) {
+                    bg = og;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) *sidx = bi < npts ? bi : 0;
         }
         __syncthreads();
         return *sidx;
@@ -647,25 +731,33 @@ __device__ void smooth_priors(const FitDev& fd, double* buf, int* sidx, double* 
     const double nb = a + (b - a) * (i2 < 64 ? i2 + 1 : 64) / 64.0;
     const int i3 = stage(false, na, nb, 65);
     const double lam = pow(10.0, na + (nb - na) * i3 / 64.0);
-    // filter, inverse transform (B = C_E^T A, w = B C_x), floor
-    for (int c = tid; c < n; c += kFinThreads) {
-        const int k = c / nx, m = c - k * nx;
-        const double g = mE[k] + mX[m];
-        A[c] = B[c] / (1.0 + lam * g * g);
-    }
+    // filter into sa, inverse along E into sb, along x to the output
+    for (int c = tid; c < n; c += kFinThreads) sa[c] = sb[c] / (1.0 + lam * sa[c]);
     __syncthreads();
     for (int o = tid; o < n; o += kFinThreads) {
         const int i = o / nx, m = o - i * nx;
-        double v = 0.0;
-        for (int k = 0; k < nE; ++k) v += CE[k * nE + i] * A[k * nx + m];
-        B[o] = v;
+        double v = sE0 * sa[m];  // k = 0
+        const int inc = (2 * i + 1) % pE;
+        int idx = inc;            // k (2i + 1) mod 4 nE
+        for (int k = 1; k < nE; ++k) {
+            v += sE * tE[idx] * sa[k * nx + m];
+            idx += inc;
+            if (idx >= pE) idx -= pE;
+        }
+        sb[o] = v;
     }
     __syncthreads();
     const double floor_v = 1e-3 * (*smean);
     for (int o = tid; o < n; o += kFinThreads) {
         const int i = o / nx, l = o - i * nx;
-        double v = 0.0;
-        for (int m = 0; m < nx; ++m) v += B[i * nx + m] * CX[m * nx + l];
+        double v = sX0 * sb[i * nx];  // m = 0
+        const int inc = (2 * l + 1) % pX;
+        int idx = inc;
+        for (int m = 1; m < nx; ++m) {
+            v += sX * tX[idx] * sb[i * nx + m];
+            idx += inc;
+            if (idx >= pX) idx -= pX;
+        }
         v = fmax(v, floor_v);
         gp[o] = v;
         uc[o] = (T)v;
@@ -680,6 +772,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     __shared__ double part2[kFinWaves][kFinCols];
     __shared__ int last, sidx;
     __shared__ double smean;
+    __shared__ double sgrid[2][kMaxCells];  // prior smoothing: grids and cosine tables
+    __shared__ double stab[2][4 * kSmoothMaxSide];
     const FinJob jb = jobs[blockIdx.x];
     const FitDev& fd = fits[jb.fit];
     FitState* st = fd.st;
@@ -737,7 +831,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     if (!last) return;
     __threadfence();
     // a refresh with smoothing: the whole block smooths the prior grid
-    if (fd.smooth && f.refresh) smooth_priors<T>(fd, &part[0][0], &sidx, &smean);
+    if (fd.smooth && f.refresh)
+        smooth_priors<T>(fd, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0], &sidx, &smean);
     if (wave != 0) return;
     const double chi2 =
         cells_mode ? 0.0 : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
