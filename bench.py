@@ -141,7 +141,7 @@ def run_batch(args, Fit, torch, _abi):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     assert b.particles() == ntot
-    ms_step, ms_fin = b.profile(20)
+    ms_step, ms_fin = b.profile(16)
     for f in list(fits):
         b.cancel(f)
     # comparator: the same fits, each stepped by its own launches

@@ -209,11 +209,13 @@ m2m_status m2m_observe(m2m_ctx* ctx, const double* V_p, const double* sigma_p, d
 m2m_status m2m_get_state(m2m_ctx* ctx, void* host_blob, size_t* bytes);
 m2m_status m2m_set_state(m2m_ctx* ctx, const void* host_blob, size_t bytes);
 
-/* Timing by HIP events on the context's stream, back-to-back launches only:
- * runs n_steps steps as m2m_step does (they advance the fit), then n_steps
- * launches of the finalize reduction in a measuring mode that changes no
- * state. ms_finalize is the mean finalize time and ms_step the mean step time
- * minus it, i.e. the fused step kernel plus one launch gap (milliseconds).
+/* Timing by HIP events on the context's stream. With r = ceil(n_steps / 32)
+ * (n_steps 1..4096), runs r graphs of 32 steps as m2m_step does, then r
+ * graphs of 32 steps each followed by one more finalize reduction in a
+ * measuring mode that changes no state: 64 r steps in all, which advance
+ * the fit. With S and S2 the mean times per step of the two runs,
+ * ms_finalize = S2 - S is the reduction's cost where it runs and
+ * ms_step = S - ms_finalize that of the fused step kernel (milliseconds).
  * Synchronizes. Used to report achieved bandwidth against the roofline. */
 m2m_status m2m_profile_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct, double* ms_step,
                             double* ms_finalize);
@@ -264,8 +266,9 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
  * *n_active (may be NULL) the number still running. */
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
                           int32_t* n_active);
-/* Like m2m_profile_step for the batch (n_steps batched steps, then n_steps
- * measuring finalize launches over all fits). Synchronizes. */
+/* Like m2m_profile_step for the batch, with graphs of 8 batched steps:
+ * 16 ceil(n_steps / 8) steps in all, which count against the fits' steps
+ * (n_steps 1..4096). Synchronizes. */
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize);
 /* Particles of the admitted fits that still have steps left. Synchronizes. */
 int64_t m2m_batch_particles(m2m_batch* b);

@@ -18,7 +18,9 @@ using namespace m2m;
 
 namespace {
 
-constexpr int kGraphSteps = 8;      // M2M steps per captured graph
+constexpr int kGraphSteps = 32;     // M2M steps per captured graph of one fit
+constexpr int kBatchGraphSteps = 8; // of a batch (captured again when fits come and go)
+constexpr int kProfileMax = 4096;   // most steps one m2m_profile_step call times
 constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
 constexpr uint32_t kStateVersion = 2u;         // 2: with the FP64 prior grid
 constexpr double kPi = 3.14159265358979323846;
@@ -307,8 +309,9 @@ struct m2m_ctx {
     int n_jobs = 0;
     size_t lds = 0;
     int block = 256, kin = 0;
-    hipGraphExec_t graph_fin = nullptr;
     bool acc64 = true;
+    bool wt = false;  // write-through particle stores (kModeWriteThrough)
+    hipGraphExec_t graph_prof = nullptr;  // steps with an extra measuring reduction
     bool targets = false;
     bool ytil_init = false;
     std::vector<double> Vp, sp;  // current Gauss-Hermite centres (host)
@@ -422,7 +425,7 @@ m2m_status check_error(m2m_ctx* c) {
 // One M2M step: the step kernel over all tiles, then the finalize.
 hipError_t launch_one_step(m2m_ctx* c, hipStream_t s) {
     hipError_t e = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
-                               c->lds, kModeStep, s);
+                               c->lds, kModeStep | (c->wt ? kModeWriteThrough : 0), s);
     if (e == hipSuccess) e = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, s);
     return e;
 }
@@ -432,14 +435,14 @@ m2m_status run_direct(m2m_ctx* c, int steps) {
     return M2M_OK;
 }
 
-// Capture kGraphSteps repetitions of body(stream) on the capture stream and
+// Capture n repetitions of body(stream) on the capture stream and
 // instantiate them as one graph.
 template <typename F>
-hipError_t capture_steps(hipStream_t cap, F body, hipGraphExec_t* out) {
+hipError_t capture_steps(hipStream_t cap, int n, F body, hipGraphExec_t* out) {
     *out = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = body(cap);
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = body(cap);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
@@ -453,24 +456,27 @@ m2m_status ensure_graph(m2m_ctx* c) {
     if (c->graph) return M2M_OK;
     if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     const hipError_t e = capture_steps(
-        c->cap,
+        c->cap, kGraphSteps,
         [c](hipStream_t s) { return launch_one_step(c, s); }, &c->graph);
     if (e != hipSuccess) return hip_fail(c, e, "step graph");
     return M2M_OK;
 }
 
-// The reduction part of a step in a measuring mode that changes no state
-// (observe-mode finalize), as a graph like the steps.
-m2m_status ensure_measure_graph(m2m_ctx* c) {
-    if (c->graph_fin) return M2M_OK;
+// Steps as in the step graph, each followed by one more reduction in the
+// measuring mode that changes no state (m2m_profile_step).
+m2m_status ensure_prof_graph(m2m_ctx* c) {
+    if (c->graph_prof) return M2M_OK;
     if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     const hipError_t e = capture_steps(
-        c->cap,
+        c->cap, kGraphSteps,
         [c](hipStream_t s) {
-            return launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, s);
+            hipError_t r = launch_one_step(c, s);
+            if (r == hipSuccess)
+                r = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, s);
+            return r;
         },
-        &c->graph_fin);
-    if (e != hipSuccess) return hip_fail(c, e, "measure graph");
+        &c->graph_prof);
+    if (e != hipSuccess) return hip_fail(c, e, "profile graph");
     return M2M_OK;
 }
 
@@ -546,6 +552,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     const WsLayout& w = c->w;
     const int kpriv = private_copies(c->f64, w.J);
     c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
+    c->wt = (size_t)n * 8 * (c->f64 ? 8 : 4) <= kWriteThroughMax;
     c->lds = step_lds_bytes(c->f64, c->acc64, w.J, c->lay.n_r,
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
                             c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C);
@@ -957,40 +964,37 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
 
 m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double* ms_step,
                             double* ms_finalize) {
-    if (!c || n_steps < 1) return M2M_EINVAL;
+    if (!c) return M2M_EINVAL;
+    if (n_steps < 1 || n_steps > kProfileMax) return fail(c, M2M_EINVAL, "n_steps out of range");
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    m2m_status st = ensure_graph(c);
+    if (st == M2M_OK) st = ensure_prof_graph(c);
+    if (st != M2M_OK) return st;
+    // r replays of each graph: S per step with the plain steps, S2 with the
+    // extra reduction; the reduction then costs S2 - S where it runs, and the
+    // step kernel S - (S2 - S)
+    const int r = (n_steps + kGraphSteps - 1) / kGraphSteps;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
-    // (1) n whole steps as m2m_step runs them (graph replays)
+    if (e == hipSuccess) e = launch_poke(c->st, 2 * r * kGraphSteps, correct ? 1 : 0, c->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
-    if (e == hipSuccess) {
-        m2m_status st = m2m_step(c, n_steps, correct);
-        if (st != M2M_OK) e = hipErrorUnknown;
-    }
+    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(c->graph, c->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-    // (2) the same n reductions in measuring mode (no state changes),
-    // launched the same way
-    if (e == hipSuccess && ensure_measure_graph(c) != M2M_OK) e = hipErrorUnknown;
+    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(c->graph_prof, c->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
-    for (int k = 0; k + kGraphSteps <= n_steps && e == hipSuccess; k += kGraphSteps)
-        e = hipGraphLaunch(c->graph_fin, c->stream);
-    for (int k = 0; k < n_steps % kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, c->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    float t_all = 0.f, t_fin = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t_all, ev[0], ev[1]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&t_fin, ev[2], ev[3]);
+    float t1 = 0.f, t2 = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[1], ev[2]);
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return hip_fail(c, e, "profile");
-    const double fin = (double)t_fin / n_steps;
-    if (ms_step) *ms_step = (double)t_all / n_steps - fin;
-    if (ms_finalize) *ms_finalize = fin;
+    const double S = (double)t1 / (r * kGraphSteps), S2 = (double)t2 / (r * kGraphSteps);
+    if (ms_step) *ms_step = S - (S2 - S);
+    if (ms_finalize) *ms_finalize = S2 - S;
     return M2M_OK;
 }
 
@@ -999,7 +1003,7 @@ m2m_status m2m_destroy(m2m_ctx* c) {
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    if (c->graph_fin) (void)hipGraphExecDestroy(c->graph_fin);
+    if (c->graph_prof) (void)hipGraphExecDestroy(c->graph_prof);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own_ws) (void)hipFree(c->ws);
     delete c;
@@ -1028,7 +1032,7 @@ struct m2m_batch {
     int block = 256, kin = -1;
     bool acc64 = true;
     hipGraphExec_t graph = nullptr;
-    hipGraphExec_t graph_fin = nullptr;
+    hipGraphExec_t graph_prof = nullptr;  // steps with an extra measuring reduction
 };
 
 namespace {
@@ -1064,9 +1068,9 @@ m2m_status rebuild(m2m_batch* b) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
-    if (b->graph_fin) {
-        (void)hipGraphExecDestroy(b->graph_fin);
-        b->graph_fin = nullptr;
+    if (b->graph_prof) {
+        (void)hipGraphExecDestroy(b->graph_prof);
+        b->graph_prof = nullptr;
     }
     b->n_tiles = b->n_jobs = b->n_fits = 0;
     if (b->fits.empty()) {
@@ -1111,19 +1115,23 @@ m2m_status rebuild(m2m_batch* b) {
     b->n_jobs = (int)jb.size();
     b->n_fits = (int)fd.size();
     b->lds = lds;
-    // graphs of kGraphSteps steps over this composition, and of the same
-    // reductions in measuring mode (m2m_batch_profile)
+    // graphs of kBatchGraphSteps steps over this composition, and of the
+    // same steps each followed by a reduction in the measuring mode that
+    // changes no state (m2m_batch_profile)
     hipError_t e = capture_steps(
-        b->cap,
+        b->cap, kBatchGraphSteps,
         [b, f64](hipStream_t s) { return batch_step(b, f64, s); }, &b->graph);
     if (e == hipSuccess)
         e = capture_steps(
-            b->cap,
+            b->cap, kBatchGraphSteps,
             [b, f64](hipStream_t s) {
-                return launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
-                                       kModeObserve, s);
+                hipError_t r = batch_step(b, f64, s);
+                if (r == hipSuccess)
+                    r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
+                                        kModeObserve, s);
+                return r;
             },
-            &b->graph_fin);
+            &b->graph_prof);
     if (e != hipSuccess) return M2M_EDEVICE;
     b->dirty = false;
     return M2M_OK;
@@ -1192,7 +1200,7 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
     }
     if (b->fits.empty() || steps_per_launch == 0) return M2M_OK;
     const bool f64 = b->f64 == 1;
-    const int full = steps_per_launch / kGraphSteps, rem = steps_per_launch % kGraphSteps;
+    const int full = steps_per_launch / kBatchGraphSteps, rem = steps_per_launch % kBatchGraphSteps;
     for (int k = 0; k < full; ++k)
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
     for (int k = 0; k < rem; ++k)
@@ -1242,38 +1250,33 @@ m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_
 }
 
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize) {
-    if (!b || n_steps < 1) return M2M_EINVAL;
+    if (!b || n_steps < 1 || n_steps > kProfileMax) return M2M_EINVAL;
     if (b->dirty) {
         m2m_status s = rebuild(b);
         if (s != M2M_OK) return s;
     }
     if (b->fits.empty()) return M2M_ESTATE;
-    const bool f64 = b->f64 == 1;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // as m2m_profile_step: r replays of the plain and of the measuring graph
+    const int r = (n_steps + kBatchGraphSteps - 1) / kBatchGraphSteps;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) e = hipEventRecord(ev[0], b->stream);
-    if (e == hipSuccess && m2m_batch_run(b, n_steps) != M2M_OK) e = hipErrorUnknown;
+    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(b->graph, b->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
+    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(b->graph_prof, b->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
-    for (int k = 0; k + kGraphSteps <= n_steps && e == hipSuccess; k += kGraphSteps)
-        e = hipGraphLaunch(b->graph_fin, b->stream);
-    for (int k = 0; k < n_steps % kGraphSteps && e == hipSuccess; ++k) {
-        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeObserve,
-                            b->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(ev[3], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    float t_all = 0.f, t_fin = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t_all, ev[0], ev[1]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&t_fin, ev[2], ev[3]);
+    float t1 = 0.f, t2 = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[1], ev[2]);
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return M2M_EDEVICE;
-    const double fin = (double)t_fin / n_steps;
-    if (ms_step) *ms_step = (double)t_all / n_steps - fin;
-    if (ms_finalize) *ms_finalize = fin;
+    const double S = (double)t1 / (r * kBatchGraphSteps), S2 = (double)t2 / (r * kBatchGraphSteps);
+    if (ms_step) *ms_step = S - (S2 - S);
+    if (ms_finalize) *ms_finalize = S2 - S;
     return M2M_OK;
 }
 
@@ -1311,7 +1314,7 @@ m2m_status m2m_batch_destroy(m2m_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     for (m2m_ctx* c : b->fits) c->batch = nullptr;
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    if (b->graph_fin) (void)hipGraphExecDestroy(b->graph_fin);
+    if (b->graph_prof) (void)hipGraphExecDestroy(b->graph_prof);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->fits_dev) (void)hipFree(b->fits_dev);
     if (b->tiles_dev) (void)hipFree(b->tiles_dev);

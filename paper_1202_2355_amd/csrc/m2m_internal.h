@@ -28,7 +28,13 @@ enum : int32_t {
     kModeInit = 2,       // deposit the current state; finalize sets ytilde = y
     kModeObserve = 4,    // deposit the current state into obs_out only
     kModeCells = 8,      // accumulate the prior cells of the current state only
+    kModeWriteThrough = 16,  // step: particle stores write through L2 (small fits)
 };
+
+// Particle state up to this size is stepped with write-through stores: it
+// stays in the memory-side cache, and no dirty particle lines are left in L2
+// for the write-back at the end of the step kernel.
+constexpr size_t kWriteThroughMax = size_t(64) << 20;
 
 // Dynamic per-fit state, device resident, written only by the kernels (and by
 // the host between launches, on the fit's stream).

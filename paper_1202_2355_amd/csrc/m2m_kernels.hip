@@ -437,15 +437,32 @@ struct Flags {
     bool step, cells_mode, observe, init, correct, refresh;
 };
 
-__device__ __forceinline__ Flags flags_of(const FitDev& fd, G<const FitState> st, int32_t mode) {
+// The fit's counters as the launch found them: only the block that ends the
+// step writes them, from these values, so they are read once, up front.
+struct Snap {
+    int64_t kstep, tstep;
+    int32_t steps_left, correct, error;
+};
+
+__device__ __forceinline__ Snap snap_of(G<const FitState> st) {
+    Snap s;
+    s.kstep = st->kstep;
+    s.tstep = st->tstep;
+    s.steps_left = st->steps_left;
+    s.correct = st->correct;
+    s.error = st->error;
+    return s;
+}
+
+__device__ __forceinline__ Flags flags_of(const FitDev& fd, const Snap& ss, int32_t mode) {
     Flags f;
     f.step = (mode & kModeStep) != 0;
     f.cells_mode = (mode & kModeCells) != 0;
     f.observe = (mode & kModeObserve) != 0;
     f.init = (mode & kModeInit) != 0;
-    f.correct = f.step && st->correct != 0;
+    f.correct = f.step && ss.correct != 0;
     f.refresh = f.cells_mode || (f.correct && fd.entropy == 0 && fd.prior_every > 0 &&
-                                 ((st->kstep + 1) % fd.prior_every) == 0);
+                                 ((ss.kstep + 1) % fd.prior_every) == 0);
     return f;
 }
 
@@ -534,18 +551,19 @@ __device__ __forceinline__ double chi2_of_parts(const double* parts, int n, int 
     return c;
 }
 
-// The end of the step for one fit (one thread).
+// The end of the step for one fit (one thread): the new counters from the
+// launch's snapshot of them (stores only).
 __device__ __forceinline__ void end_step(const FitDev& fd, G<FitState> gst, const Flags& f,
-                                         double chi2) {
+                                         const Snap& ss, double chi2) {
     if (!f.cells_mode) {
         gst->chi2 = chi2;
-        if (!isfinite(chi2)) gst->error |= 1;
-        if (f.step) gmem(fd.chi2_hist)[gst->tstep % kHistCap] = chi2;
+        if (!isfinite(chi2)) gst->error = ss.error | 1;
+        if (f.step) gmem(fd.chi2_hist)[ss.tstep % kHistCap] = chi2;
     }
     if (f.step) {
-        gst->tstep += 1;
-        gst->steps_left -= 1;
-        if (f.correct) gst->kstep += 1;
+        gst->tstep = ss.tstep + 1;
+        gst->steps_left = ss.steps_left - 1;
+        if (f.correct) gst->kstep = ss.kstep + 1;
         gst->assign_pending = f.refresh ? 1 : 0;
     }
     if (f.cells_mode) gst->assign_pending = 1;
@@ -799,8 +817,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
             Yj = gmem(fd.Y)[col];
         }
     }
-    if (step && gst->steps_left <= 0) return;  // uniform: the fit is idle
-    const Flags f = flags_of(fd, gst, mode);
+    const Snap ss = snap_of(gst);
+    if (step && ss.steps_left <= 0) return;  // uniform: the fit is idle
+    const Flags f = flags_of(fd, ss, mode);
     if (bins && cells_mode) return;
     if (!bins && !f.refresh) return;
     // cell columns, read only on refresh steps
@@ -823,13 +842,15 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     uint32_t* ticket = observe ? &st->mticket : &st->ticket;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(ticket, 1u);
+        // release of this job's results (wave 0 wrote them) with the count;
+        // acquire of the others' for the last job, passed on to its block by
+        // the barrier below
+        const uint32_t prev =
+            __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == n_part - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     // a refresh with smoothing: the whole block smooths the prior grid
     if (fd.smooth && f.refresh)
         smooth_priors<T>(fd, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0], &sidx, &smean);
@@ -839,10 +860,18 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     if (lane != 0) return;
     *ticket = 0u;
     if (observe) return;
-    end_step(fd, gst, f, chi2);
+    end_step(fd, gst, f, ss, chi2);
 }
 
 // ------------------------------------------------------------- step --------
+// A particle store that writes through L2 (agent-scope relaxed atomic store):
+// the value reaches the memory-side cache at once instead of staying dirty in
+// L2 until the write-back at the end of the kernel.
+template <typename T>
+__device__ __forceinline__ void put_wt(G<T> p, T v) {
+    __hip_atomic_store((T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T, typename A, int BLOCK, int KIN>
 __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles, int32_t mode) {
@@ -886,6 +915,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     const bool assign = step && st->assign_pending != 0;
     const bool deposit_on = !cells_only;
     const bool push = step;
+    const bool wt = (mode & kModeWriteThrough) != 0;
     const Hot<T> h = hot_of<T>(fd);
     const int J = h.J, C = h.C, kp = h.kp;
 
@@ -968,7 +998,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
             atomicAdd(&tb.ccnt[c], 1u);
             CI[i] = (uint16_t)c;
         }
-        if (push) {
+        if (push && wt) {
+            put_wt(X + i, x);
+            put_wt(Y + i, y);
+            put_wt(Z + i, z);
+            put_wt(VX + i, vx);
+            put_wt(VY + i, vy);
+            put_wt(VZ + i, vz);
+            if (correct) put_wt(U + i, u);
+            if (assign) put_wt(UH + i, uh);
+        } else if (push) {
             X[i] = x;
             Y[i] = y;
             Z[i] = z;

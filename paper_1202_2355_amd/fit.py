@@ -131,7 +131,9 @@ class Fit:
         return y
 
     def profile_step(self, n_steps: int, correct: bool = True):
-        """Mean per-kernel durations (ms) of n_steps directly launched steps."""
+        """(step kernel, reduction) times in ms per step from HIP events around
+        graph replays with and without one extra measuring reduction per step;
+        runs 2 * 32 * ceil(n / 32) steps (batch: 2 * 8 * ceil(n / 8))."""
         a, b = C.c_double(), C.c_double()
         self._chk(A.lib().m2m_profile_step(self.ctx, int(n_steps), int(bool(correct)), C.byref(a),
                                            C.byref(b)), "m2m_profile_step")
