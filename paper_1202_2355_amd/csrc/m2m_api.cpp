@@ -378,12 +378,7 @@ m2m_status upload_gh(m2m_ctx* c, const std::vector<double>& V, const std::vector
 
 // Split [0, n) into `count` tiles of near-equal size with aligned boundaries.
 void split_tiles(int64_t n, int count, int fit, int row0, std::vector<Tile>& out) {
-    for (int t = 0; t < count; ++t) {
-        int64_t b = n * t / count, e = n * (t + 1) / count;
-        b = b / kSegAlign * kSegAlign;
-        e = (t == count - 1) ? n : e / kSegAlign * kSegAlign;
-        out.push_back(Tile{fit, row0 + t, b, e, count, 0});
-    }
+    for (int t = 0; t < count; ++t) out.push_back(tile_of(n, t, count, fit, row0));
 }
 
 void fin_jobs(const WsLayout& w, int fit, int n_rows, std::vector<FinJob>& out) {
@@ -424,9 +419,9 @@ m2m_status check_error(m2m_ctx* c) {
 
 // One M2M step: the step kernel over all tiles, then the finalize.
 hipError_t launch_one_step(m2m_ctx* c, hipStream_t s) {
-    hipError_t e = launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles,
+    hipError_t e = launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles,
                                c->lds, kModeStep | (c->wt ? kModeWriteThrough : 0), s);
-    if (e == hipSuccess) e = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeStep, s);
+    if (e == hipSuccess) e = launch_finalize1(c->f64, c->fd, c->n_tiles, kModeStep, s);
     return e;
 }
 
@@ -472,7 +467,7 @@ m2m_status ensure_prof_graph(m2m_ctx* c) {
         [c](hipStream_t s) {
             hipError_t r = launch_one_step(c, s);
             if (r == hipSuccess)
-                r = launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, s);
+                r = launch_finalize1(c->f64, c->fd, c->n_tiles, kModeObserve, s);
             return r;
         },
         &c->graph_prof);
@@ -743,9 +738,9 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     if (!c->ytil_init) {
-        M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+        M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
                                kModeInit, c->stream));
-        M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeInit, c->stream));
+        M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModeInit, c->stream));
         c->ytil_init = true;
     } else {
         M2M_HIP(c, launch_residuals(c->f64, c->fd_dev, c->stream));
@@ -774,9 +769,9 @@ m2m_status m2m_update_priors(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
-    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
                            kModeCells, c->stream));
-    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeCells, c->stream));
+    M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModeCells, c->stream));
     M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
     return M2M_OK;
 }
@@ -852,9 +847,9 @@ m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, dou
                 return fail(c, M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
         if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     }
-    M2M_HIP(c, launch_step(c->f64, c->acc64, c->block, c->kin, c->fd_dev, c->tiles, c->n_tiles, c->lds,
+    M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
                            kModeObserve, c->stream));
-    M2M_HIP(c, launch_finalize(c->f64, c->fd_dev, 1, c->jobs, c->n_jobs, kModeObserve, c->stream));
+    M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModeObserve, c->stream));
     if ((s = sync(c)) != M2M_OK) return s;
     M2M_HIP(c, copy_sync(c->stream, y, c->fd.obs_out, 8 * (size_t)c->w.J, hipMemcpyDeviceToHost));
     if (tmp && (s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return s;

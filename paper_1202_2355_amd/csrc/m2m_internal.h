@@ -99,6 +99,17 @@ struct Tile {
     int32_t pad;
 };
 
+// Tile t of count tiles over n particles (tile rows row0 + t of fit `fit`):
+// boundaries at n t / count rounded down to a multiple of kSegAlign, the
+// last tile ending at n. The host builds its tile tables with it, and the
+// one-fit step kernel finds its own tile with it.
+__host__ __device__ inline Tile tile_of(int64_t n, int t, int count, int fit, int row0) {
+    int64_t b = n * t / count, e = n * (t + 1) / count;
+    b = b / kSegAlign * kSegAlign;
+    e = (t == count - 1) ? n : e / kSegAlign * kSegAlign;
+    return Tile{fit, row0 + t, b, e, count, 0};
+}
+
 // One finalize block: kFinCols columns of one fit.
 struct FinJob {
     int32_t fit;
@@ -116,6 +127,12 @@ int kin_class(int kin, int gh_nmax);
 // the column jobs of the fits of the table (n_fits of them)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
                            int n_jobs, int32_t mode, hipStream_t s);
+// one fit, fd (a host copy of its description) passed by value: the step
+// over n_tiles tiles as tile_of splits it; the finalize jobs of that fit
+// (bin jobs, then cell jobs) over n_rows tile rows
+hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& fd, int n_tiles,
+                        size_t lds, int32_t mode, hipStream_t s);
+hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s);
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
                          hipStream_t s);
 hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double scale,

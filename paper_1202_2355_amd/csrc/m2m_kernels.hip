@@ -783,17 +783,13 @@ __device__ void smooth_priors(const FitDev& fd, double* sa, double* sb, double* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
-                                                         const FinJob* __restrict__ jobs,
-                                                         int32_t mode) {
+__device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb, int32_t mode) {
     __shared__ double part[kFinWaves][kFinCols];
     __shared__ double part2[kFinWaves][kFinCols];
     __shared__ int last, sidx;
     __shared__ double smean;
     __shared__ double sgrid[2][kMaxCells];  // prior smoothing: grids and cosine tables
     __shared__ double stab[2][4 * kSmoothMaxSide];
-    const FinJob jb = jobs[blockIdx.x];
-    const FitDev& fd = fits[jb.fit];
     FitState* st = fd.st;
     const G<FitState> gst = gmem(fd.st);
     const bool step = (mode & kModeStep) != 0;
@@ -863,6 +859,26 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
     end_step(fd, gst, f, ss, chi2);
 }
 
+// the jobs of the fits of a table (batches)
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
+                                                         const FinJob* __restrict__ jobs,
+                                                         int32_t mode) {
+    const FinJob jb = jobs[blockIdx.x];
+    finalize_job<T>(fits[jb.fit], jb, mode);
+}
+
+// one fit, its description passed by value: block b < n_bin_jobs takes bin
+// columns, the others cell columns, over n_rows tile rows
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int32_t n_rows,
+                                                          int32_t mode) {
+    const int b = blockIdx.x;
+    const bool bins = b < fd.n_bin_jobs;
+    const FinJob jb{0, bins ? 0 : 1, (bins ? b : b - fd.n_bin_jobs) * kFinCols, n_rows};
+    finalize_job<T>(fd, jb, mode);
+}
+
 // ------------------------------------------------------------- step --------
 // A particle store that writes through L2 (agent-scope relaxed atomic store):
 // the value reaches the memory-side cache at once instead of staying dirty in
@@ -873,11 +889,8 @@ __device__ __forceinline__ void put_wt(G<T> p, T v) {
 }
 
 template <typename T, typename A, int BLOCK, int KIN>
-__global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
-                                                const Tile* __restrict__ tiles, int32_t mode) {
+__device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const Tile tl = tiles[blockIdx.x];
-    const FitDev& fd = fits[tl.fit];
     const bool step = (mode & kModeStep) != 0;
 
     // particle arrays from the tile start (32-bit offsets within the tile);
@@ -1035,6 +1048,21 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
         }
 }
 
+// the tiles of the fits of a table (batches)
+template <typename T, typename A, int BLOCK, int KIN>
+__global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
+                                                const Tile* __restrict__ tiles, int32_t mode) {
+    const Tile tl = tiles[blockIdx.x];
+    step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
+}
+
+// one fit, its description passed by value; block t takes tile t of the
+// fit split into gridDim.x tiles
+template <typename T, typename A, int BLOCK, int KIN>
+__global__ __launch_bounds__(BLOCK) void k_step1(const FitDev fd, int32_t mode) {
+    step_tile<T, A, BLOCK, KIN>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0), mode);
+}
+
 // ------------------------------------------------------------- assign ------
 template <typename T>
 __global__ __launch_bounds__(256) void k_assign(const FitDev* __restrict__ fits,
@@ -1103,25 +1131,48 @@ __global__ __launch_bounds__(256) void k_residuals(const FitDev* __restrict__ fi
     }
 }
 
+// one != nullptr: k_step1 over that fit (host copy passed by value), else
+// k_step over the tables
 template <typename T, typename A, int BLOCK, int KIN>
-hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, int n_tiles, size_t lds,
-                         int32_t mode, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
-                       tiles, mode);
+hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* one, int n_tiles,
+                         size_t lds, int32_t mode, hipStream_t s) {
+    if (one)
+        hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, *one,
+                           mode);
+    else
+        hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                           tiles, mode);
     return hipGetLastError();
 }
 
 template <typename T, typename A, int BLOCK>
-hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, int n_tiles,
-                           size_t lds, int32_t mode, hipStream_t s) {
+hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, const FitDev* one,
+                           int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
     switch (kin) {
-        case kKinNone: return launch_step_t<T, A, BLOCK, kKinNone>(fits, tiles, n_tiles, lds, mode, s);
-        case kKinV2: return launch_step_t<T, A, BLOCK, kKinV2>(fits, tiles, n_tiles, lds, mode, s);
-        case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, n_tiles, lds, mode, s);
-        case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, n_tiles, lds, mode, s);
-        case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, n_tiles, lds, mode, s);
+        case kKinNone: return launch_step_t<T, A, BLOCK, kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinV2: return launch_step_t<T, A, BLOCK, kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step_any(bool f64, bool acc64, int block, int kin, const FitDev* fits,
+                           const Tile* tiles, const FitDev* one, int n_tiles, size_t lds,
+                           int32_t mode, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (f64) return launch_step_kin<double, double, 256>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    if (acc64) {
+        if (block == 256) return launch_step_kin<float, double, 256>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+        if (block == 512) return launch_step_kin<float, double, 512>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+        if (block == 1024) return launch_step_kin<float, double, 1024>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    } else {
+        if (block == 256) return launch_step_kin<float, float, 256>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+        if (block == 512) return launch_step_kin<float, float, 512>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+        if (block == 1024) return launch_step_kin<float, float, 1024>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -1156,18 +1207,12 @@ int kin_class(int kin, int gh_nmax) {
 
 hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* fits,
                        const Tile* tiles, int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
-    if (n_tiles <= 0) return hipSuccess;
-    if (f64) return launch_step_kin<double, double, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
-    if (acc64) {
-        if (block == 256) return launch_step_kin<float, double, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
-        if (block == 512) return launch_step_kin<float, double, 512>(kin, fits, tiles, n_tiles, lds, mode, s);
-        if (block == 1024) return launch_step_kin<float, double, 1024>(kin, fits, tiles, n_tiles, lds, mode, s);
-    } else {
-        if (block == 256) return launch_step_kin<float, float, 256>(kin, fits, tiles, n_tiles, lds, mode, s);
-        if (block == 512) return launch_step_kin<float, float, 512>(kin, fits, tiles, n_tiles, lds, mode, s);
-        if (block == 1024) return launch_step_kin<float, float, 1024>(kin, fits, tiles, n_tiles, lds, mode, s);
-    }
-    return hipErrorInvalidValue;
+    return launch_step_any(f64, acc64, block, kin, fits, tiles, nullptr, n_tiles, lds, mode, s);
+}
+
+hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& fd, int n_tiles,
+                        size_t lds, int32_t mode, hipStream_t s) {
+    return launch_step_any(f64, acc64, block, kin, nullptr, nullptr, &fd, n_tiles, lds, mode, s);
 }
 
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
@@ -1180,6 +1225,18 @@ hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJo
         hipLaunchKernelGGL(k_finalize<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
                            mode);
     (void)n_fits;
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s) {
+    const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs;
+    if (n_jobs <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_finalize1<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fd, n_rows,
+                           mode);
+    else
+        hipLaunchKernelGGL(k_finalize1<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fd, n_rows,
+                           mode);
     return hipGetLastError();
 }
 
