@@ -10,7 +10,10 @@
  *   - weights: the paper's w_i with sum w = M initially (Sec. 3.2), carried
  *     as u_i = N w_i / M so that u_i = 1 at the start (flat priors,
  *     Sec. 2.2); w_i = u_i M / N.
- *   - model observables y_j = sum_i w_i K_j(z_i)          (Sec. 2.1, eq. obs)
+ *   - model observables y_j = sum_i w_i K_j(z_i)          (Sec. 2.1, eq. obs);
+ *     the density part is either top-hat radial mass bins or the spherical-
+ *     harmonic coefficients a_lm,k with cloud-in-cell radial weights
+ *     (Sec. 3.3, eq. alm)
  *   - time smoothing: the exponential kernel of eq. myts applied to a
  *     y that is constant over each step, i.e.
  *       ytilde <- ytilde + q (y - ytilde),  q = 1 - exp(-alpha dt),
@@ -47,7 +50,8 @@ typedef struct {
     double M200, c, r_s;          /* NFW; M200 = 0 means none */
 } orc_potential;
 
-/* kin: 0 none, 1 v_z^2 moment, 2 Gauss-Hermite b_1..b_gh_nmax, 3 LOSVD */
+/* kin: 0 none, 1 v_z^2 moment, 2 Gauss-Hermite b_1..b_gh_nmax, 3 LOSVD;
+ * dens: 0 n_r radial mass bins, 1 a_lm,k on a mesh of n_r radii, l <= l_max */
 typedef struct {
     int32_t n_r;
     double r_min, r_max;
@@ -57,6 +61,7 @@ typedef struct {
     int32_t gh_nmax;
     int32_t n_v;
     double v_min, v_max;
+    int32_t dens, l_max;
 } orc_layout;
 
 /* entropy: 0 = mass-neutral S+ with moving priors, 1 = weight entropy;
@@ -85,7 +90,7 @@ typedef struct {
     double *ucell;   /* n_E n_x prior grid, kept between refreshes (empty cells keep theirs) */
 } orc_model;
 
-#define ORC_MAXK 80  /* at most 1 radial + 64 kinematic entries per particle */
+#define ORC_MAXK 256  /* at most 2 x 81 density + 64 kinematic entries per particle */
 
 /* ------------------------------------------------------------- potential */
 static double nfw_fc(const orc_potential *p) {
@@ -147,12 +152,18 @@ double orc_lc(const orc_potential *p, double E) {
 }
 
 /* -------------------------------------------------------- observables */
+/* observables of the density part: n_r bins, or (l_max + 1)^2 coefficients
+ * at each of the n_r mesh radii */
+static int32_t dens_J(const orc_layout *L) {
+    return L->dens == 1 ? L->n_r * (L->l_max + 1) * (L->l_max + 1) : L->n_r;
+}
+
 int32_t orc_J(const orc_layout *L) {
     int32_t per = 0;
     if (L->kin == 1) per = 1;
     else if (L->kin == 2) per = L->gh_nmax;
     else if (L->kin == 3) per = L->n_v;
-    return L->n_r + L->n_R * per;
+    return dens_J(L) + L->n_R * per;
 }
 
 /* log edges e_k = lo (hi/lo)^(k/n), e_0 = lo, e_n = hi */
@@ -194,19 +205,55 @@ double orc_gh_u(int n, double nu) {
     return norm * orc_hermite(n, nu) * exp(-0.5 * nu * nu);
 }
 
+/* binomial coefficient C(n, k) */
+static double binom(int n, int k) {
+    return tgamma(n + 1.0) / (tgamma(k + 1.0) * tgamma(n - k + 1.0));
+}
+
+/* associated Legendre function with the Condon-Shortley phase,
+ *   P_l^m(x) = (-1)^m (1 - x^2)^(m/2) d^m/dx^m P_l(x),  0 <= m <= l,
+ * with the Legendre polynomial written out as
+ *   P_l(x) = 2^-l sum_k (-1)^k C(l, k) C(2l - 2k, l) x^(l - 2k)
+ * and differentiated term by term. */
+double orc_plm(int l, int m, double x) {
+    double d = 0.0;
+    for (int k = 0; 2 * k <= l; ++k) {
+        int p = l - 2 * k;
+        if (p < m) continue;
+        double c = ldexp(binom(l, k) * binom(2 * l - 2 * k, l), -l) * (k % 2 ? -1.0 : 1.0);
+        d += c * tgamma(p + 1.0) / tgamma(p - m + 1.0) * pow(x, p - m);
+    }
+    return (m % 2 ? -1.0 : 1.0) * pow(1.0 - x * x, 0.5 * m) * d;
+}
+
+/* real orthonormal spherical harmonic of degree l and order m (-l..l) at
+ * cos(theta) = ct and azimuth phi:
+ *   m = 0: N_l0 P_l(ct),  m > 0: sqrt2 N_lm P_l^m(ct) cos(m phi),
+ *   m < 0: sqrt2 N_l|m| P_l^|m|(ct) sin(|m| phi),
+ *   N_lm = sqrt((2l + 1)/(4 pi) (l - m)!/(l + m)!) */
+double orc_ylm(int l, int m, double ct, double phi) {
+    int am = m < 0 ? -m : m;
+    double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * tgamma(l - am + 1.0) / tgamma(l + am + 1.0));
+    double P = orc_plm(l, am, ct);
+    if (m == 0) return N * P;
+    return sqrt(2.0) * N * P * (m > 0 ? cos(am * phi) : sin(am * phi));
+}
+
 typedef struct {
     int32_t nr, nR, nv;
     double *re, *Re, *ve;
 } edges_t;
 
+/* density edges: n_r + 1 bin edges, or the n_r mesh radii (n_r - 1 intervals),
+ * both log-spaced from r_min to r_max */
 static void edges_make(const orc_layout *L, edges_t *E) {
-    E->nr = L->n_r;
+    E->nr = L->dens == 1 ? L->n_r - 1 : L->n_r;
     E->nR = L->n_R;
     E->nv = (L->kin == 3) ? L->n_v : 0;
     E->re = (double *)malloc(sizeof(double) * (E->nr + 1));
     E->Re = (double *)malloc(sizeof(double) * (E->nR + 1));
     E->ve = (double *)malloc(sizeof(double) * (E->nv + 1));
-    for (int k = 0; k <= E->nr; ++k) E->re[k] = log_edge(L->r_min, L->r_max, E->nr, k);
+    for (int k = 0; k <= E->nr; ++k) E->re[k] = log_edge(L->r_min, L->r_max, E->nr, k);  /* mesh r_k */
     for (int k = 0; k <= E->nR; ++k) E->Re[k] = log_edge(L->R_min, L->R_max, E->nR, k);
     for (int k = 0; k <= E->nv; ++k) E->ve[k] = lin_edge(L->v_min, L->v_max, E->nv, k);
 }
@@ -226,18 +273,35 @@ static int near_edge(const double *e, int n, double v, double band, int absolute
 }
 
 /* The kernels K_j(z) that are non-zero for one phase-space point: writes
- * (index, value) pairs and returns their count. Observable order: n_r radial
- * mass bins (K = 1 for r in the bin), then per annulus p (R = sqrt(x^2+y^2),
- * line of sight z) its kinematic entries: v_z^2 (kin 1), 2 sqrt(pi) u_n(nu),
- * nu = (v_z - V_p)/sigma_p, n = 1..gh_nmax (kin 2, eq. lumghn), or K = 1 for
- * the LOSVD bin holding v_z (kin 3). A particle outside every range has no
- * kernel (selection function, Sec. 2.1). */
+ * (index, value) pairs and returns their count. Observable order: first the
+ * density part, then per annulus p (R = sqrt(x^2+y^2), line of sight z) its
+ * kinematic entries: v_z^2 (kin 1), 2 sqrt(pi) u_n(nu), nu = (v_z - V_p)/sigma_p,
+ * n = 1..gh_nmax (kin 2, eq. lumghn), or K = 1 for the LOSVD bin holding v_z
+ * (kin 3). The density part is n_r radial mass bins (K = 1 for r in the bin,
+ * dens 0) or the coefficients a_lm,k (dens 1, eq. alm): entry
+ * k (l_max + 1)^2 + l^2 + l + m holds gamma_k(r) Y_l^m(theta, phi), where
+ * gamma_k is the cloud-in-cell weight of mesh radius r_k, linear in r between
+ * the two mesh radii around r (r_k <= r < r_{k+1}: gamma_k = (r_{k+1} - r) /
+ * (r_{k+1} - r_k), gamma_{k+1} = 1 - gamma_k). A particle outside every range
+ * has no kernel (selection function, Sec. 2.1). */
 static int kernels(const orc_layout *L, const edges_t *E, const double *Vp, const double *sp,
                    double x, double y, double z, double vz, int *idx, double *val) {
     int cnt = 0;
     double r = sqrt(x * x + y * y + z * z);
     int k = find_bin(E->re, E->nr, r);
-    if (k >= 0) {
+    if (k >= 0 && L->dens == 1) {
+        int nlm = (L->l_max + 1) * (L->l_max + 1);
+        double g = (E->re[k + 1] - r) / (E->re[k + 1] - E->re[k]);
+        double ct = z / r, phi = atan2(y, x);
+        for (int l = 0; l <= L->l_max; ++l)
+            for (int m = -l; m <= l; ++m) {
+                double Y = orc_ylm(l, m, ct, phi);
+                idx[cnt] = k * nlm + l * l + l + m;
+                val[cnt++] = g * Y;
+                idx[cnt] = (k + 1) * nlm + l * l + l + m;
+                val[cnt++] = (1.0 - g) * Y;
+            }
+    } else if (k >= 0) {
         idx[cnt] = k;
         val[cnt++] = 1.0;
     }
@@ -245,19 +309,20 @@ static int kernels(const orc_layout *L, const edges_t *E, const double *Vp, cons
     double R = sqrt(x * x + y * y);
     int p = find_bin(E->Re, E->nR, R);
     if (p < 0) return cnt;
+    int j0 = dens_J(L);
     if (L->kin == 1) {
-        idx[cnt] = L->n_r + p;
+        idx[cnt] = j0 + p;
         val[cnt++] = vz * vz;
     } else if (L->kin == 2) {
         double nu = (vz - Vp[p]) / sp[p];
         for (int n = 1; n <= L->gh_nmax; ++n) {
-            idx[cnt] = L->n_r + p * L->gh_nmax + (n - 1);
+            idx[cnt] = j0 + p * L->gh_nmax + (n - 1);
             val[cnt++] = 2.0 * sqrt(M_PI) * orc_gh_u(n, nu);
         }
     } else if (L->kin == 3) {
         int b = find_bin(E->ve, E->nv, vz);
         if (b >= 0) {
-            idx[cnt] = L->n_r + p * L->n_v + b;
+            idx[cnt] = j0 + p * L->n_v + b;
             val[cnt++] = 1.0;
         }
     }
@@ -276,10 +341,18 @@ int orc_kernels(const orc_layout *L, const double *Vp, const double *sp, double 
     return n;
 }
 
+/* within `band` of an edge where a kernel jumps: every bin edge, or only
+ * the two ends of the a_lm mesh (the cloud-in-cell weights are continuous
+ * inside it) */
 static int particle_ambiguous(const orc_layout *L, const edges_t *E, double x, double y,
                               double z, double vz, double band) {
     double r = sqrt(x * x + y * y + z * z);
-    if (near_edge(E->re, E->nr, r, band, 0)) return 1;
+    if (L->dens == 1) {
+        double ends[2] = {E->re[0], E->re[E->nr]};
+        if (near_edge(ends, 1, r, band, 0)) return 1;
+    } else if (near_edge(E->re, E->nr, r, band, 0)) {
+        return 1;
+    }
     if (L->kin == 0 || L->n_R == 0) return 0;
     double R = sqrt(x * x + y * y);
     if (near_edge(E->Re, E->nR, R, band, 0)) return 1;

@@ -17,6 +17,7 @@ SRC = os.path.join(HERE, "m2m_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 KIN = {"none": 0, "v2": 1, "gh": 2, "losvd": 3}
+DENS = {"bins": 0, "alm": 1}
 ENTROPY = {"mpr": 0, "gwr": 1}
 
 
@@ -36,7 +37,8 @@ class Layout(C.Structure):
     _fields_ = [("n_r", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
                 ("n_R", C.c_int32), ("R_min", C.c_double), ("R_max", C.c_double),
                 ("kin", C.c_int32), ("gh_nmax", C.c_int32), ("n_v", C.c_int32),
-                ("v_min", C.c_double), ("v_max", C.c_double)]
+                ("v_min", C.c_double), ("v_max", C.c_double), ("dens", C.c_int32),
+                ("l_max", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -82,6 +84,10 @@ def lib():
         L.orc_hermite.argtypes = [C.c_int, C.c_double]
         L.orc_gh_u.restype = C.c_double
         L.orc_gh_u.argtypes = [C.c_int, C.c_double]
+        L.orc_plm.restype = C.c_double
+        L.orc_plm.argtypes = [C.c_int, C.c_int, C.c_double]
+        L.orc_ylm.restype = C.c_double
+        L.orc_ylm.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double]
         L.orc_kernels.restype = C.c_int
         L.orc_kernels.argtypes = [C.POINTER(Layout), _dp, _dp] + [C.c_double] * 4 + [
             C.POINTER(C.c_int32), _dp]
@@ -120,9 +126,12 @@ def potential(d) -> Potential:
 
 
 def layout(d: dict) -> Layout:
+    dens = d.get("dens", "bins")
     return Layout(n_r=d["n_r"], r_min=d["r_min"], r_max=d["r_max"], n_R=d["n_R"],
                   R_min=d["R_min"], R_max=d["R_max"], kin=KIN[d["kin"]], gh_nmax=d["gh_nmax"],
-                  n_v=d["n_v"], v_min=d["v_min"], v_max=d["v_max"])
+                  n_v=d["n_v"], v_min=d["v_min"], v_max=d["v_max"],
+                  dens=DENS[dens] if isinstance(dens, str) else int(dens),
+                  l_max=int(d.get("l_max", 0)))
 
 
 def params(d: dict) -> Params:
@@ -170,13 +179,24 @@ def gh_u(n: int, nu: float) -> float:
     return lib().orc_gh_u(int(n), float(nu))
 
 
+def plm(l: int, m: int, x: float) -> float:
+    """Associated Legendre function P_l^m(x) with the Condon-Shortley phase."""
+    return lib().orc_plm(int(l), int(m), float(x))
+
+
+def ylm(l: int, m: int, ct: float, phi: float) -> float:
+    """Real orthonormal spherical harmonic at cos(theta) = ct and azimuth phi."""
+    return lib().orc_ylm(int(l), int(m), float(ct), float(phi))
+
+
 def kernels(lay: dict, x, y, z, vz, V_p=None, sigma_p=None):
-    """Non-zero kernels of one point: dict {j: K_j}."""
+    """Non-zero kernels of one point: dict {j: K_j} (entries of a point on a
+    mesh radius with zero weight included)."""
     nR = max(lay["n_R"], 1)
     V = _f64(np.zeros(nR) if V_p is None else V_p)
     S = _f64(np.ones(nR) if sigma_p is None else sigma_p)
-    idx = np.zeros(128, dtype=np.int32)
-    val = np.zeros(128)
+    idx = np.zeros(512, dtype=np.int32)
+    val = np.zeros(512)
     n = lib().orc_kernels(C.byref(layout(lay)), _p(V), _p(S), float(x), float(y), float(z),
                           float(vz), idx.ctypes.data_as(C.POINTER(C.c_int32)), _p(val))
     return {int(idx[k]): float(val[k]) for k in range(n)}
