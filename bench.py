@@ -214,6 +214,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smooth", action="store_true",
                     help="workloads 1-3: thin-plate GCV smoothing of the prior grid at refreshes")
+    ap.add_argument("--alm", type=int, default=None, metavar="L",
+                    help="workloads 1-3: spherical-harmonic density observables a_lm (l <= L) "
+                         "on a 60-point radial mesh instead of the radial mass bins")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the M2M path here is a "
@@ -260,6 +263,9 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return 0
     wl = workload(args.workload)
+    if args.alm is not None:
+        from workloads import with_alm
+        wl = with_alm(wl, n_mesh=60, l_max=args.alm)
     if args.smooth:
         wl.params = dict(wl.params, smooth=1)
     dtype = wl.state
@@ -293,7 +299,7 @@ def main(argv=None):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": (tb * wl.N if tb is not None else None),
-            "kernel": "k_step (fused force of change + push + deposit)",
+            "kernel": "k_step1 (fused force of change + push + deposit)",
             "kernel_ms": ms_step, "finalize_ms": ms_fin,
             "bytes_per_particle_step": bpp}
     fit.close()
@@ -308,6 +314,8 @@ def main(argv=None):
                    "kinematics": wl.layout["kin"], "prior_grid": [wl.params["n_E"], wl.params["n_x"]],
                    "prior_every": wl.params["prior_every"], "state": dtype,
                    "prior_smoothing": bool(wl.params.get("smooth", 0)),
+                   "density": (f"alm l<={wl.layout['l_max']} on {wl.layout['n_r']} radii"
+                               if wl.layout.get("dens") == "alm" else "radial bins"),
                    "launch": list(LAUNCH[args.workload])},
         "latency": {"p50_s": ms * 1e-3, "p99_s": ms * 1e-3,
                     "fit": f"one fit, {args.steps} steps, device time"},

@@ -34,8 +34,20 @@
  *     optionally NFW: Phi = -G M200/f(c) ln(1 + r/r_s)/r,
  *     f(c) = ln(1+c) - c/(1+c). M200 = 0 means no halo.
  *   Observables, in this order (J = m2m_num_observables):
- *     n_r radial mass bins, K = 1 for r in [e_k, e_{k+1}),
- *       e_k = r_min (r_max/r_min)^(k/n_r) (e_0 = r_min, e_{n_r} = r_max);
+ *     the density part, one of
+ *       M2M_DENS_BINS: n_r radial mass bins, K = 1 for r in [e_k, e_{k+1}),
+ *         e_k = r_min (r_max/r_min)^(k/n_r) (e_0 = r_min, e_{n_r} = r_max);
+ *       M2M_DENS_ALM: the spherical-harmonic coefficients a_lm,k of Sec. 3.3
+ *         (eq. alm) on the n_r mesh radii r_k = r_min (r_max/r_min)^(k/(n_r-1)):
+ *         entry k (l_max+1)^2 + l^2 + l + m, 0 <= l <= l_max, -l <= m <= l,
+ *         K = gamma_k(r) Y_lm(theta, phi), with the real orthonormal harmonics
+ *         Y_l0 = N_l0 P_l(cos t), Y_lm = sqrt2 N_lm P_l^m(cos t) cos(m phi),
+ *         Y_l,-m = sqrt2 N_lm P_l^m(cos t) sin(m phi) (m > 0; P_l^m with the
+ *         Condon-Shortley phase, N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!),
+ *         cos t = z/r, phi the azimuth of (x, y)) and the cloud-in-cell
+ *         weights, linear in r: for r_k <= r < r_{k+1},
+ *         gamma_k = (r_{k+1} - r)/(r_{k+1} - r_k), gamma_{k+1} = 1 - gamma_k,
+ *         nothing outside [r_0, r_{n_r-1});
  *     then per projected annulus p (R = sqrt(x^2 + y^2), the same log edges
  *     on [R_min, R_max); the line of sight is z), contiguous:
  *       M2M_KIN_V2:    one entry, K = v_z^2;
@@ -111,6 +123,7 @@ typedef enum {
 typedef enum { M2M_F32 = 0, M2M_F64 = 1 } m2m_dtype;
 typedef enum { M2M_S_MPR = 0, M2M_S_GWR = 1 } m2m_entropy;
 typedef enum { M2M_KIN_NONE = 0, M2M_KIN_V2 = 1, M2M_KIN_GH = 2, M2M_KIN_LOSVD = 3 } m2m_kin;
+typedef enum { M2M_DENS_BINS = 0, M2M_DENS_ALM = 1 } m2m_dens;
 
 /* Fixed spherical potential (Sec. 3.1, eq. her; NFW halo optional). */
 typedef struct {
@@ -118,8 +131,8 @@ typedef struct {
     double M200, c, r_s;          /* NFW: M200 = 0 for none; else c > 0, r_s > 0 */
 } m2m_potential;
 
-/* Observable kernels K_j (Sec. 2.1; eq. lumghn). Radii are in length units,
- * velocities in velocity units. n_r >= 1; kin is an m2m_kin. */
+/* Observable kernels K_j (Sec. 2.1; eqs. alm, lumghn). Radii are in length
+ * units, velocities in velocity units. n_r >= 1; kin is an m2m_kin. */
 typedef struct {
     int32_t n_r;
     double r_min, r_max;  /* 0 < r_min < r_max */
@@ -129,6 +142,8 @@ typedef struct {
     int32_t gh_nmax;      /* M2M_KIN_GH: 1..8 */
     int32_t n_v;          /* M2M_KIN_LOSVD: 1..256 */
     double v_min, v_max;  /* M2M_KIN_LOSVD: v_min < v_max */
+    int32_t dens;         /* m2m_dens: density observables; M2M_DENS_ALM needs n_r >= 2 */
+    int32_t l_max;        /* M2M_DENS_ALM: 0..8 */
 } m2m_obs_layout;
 
 /* Step parameters (eqs. modFOC, myts, S+, entropy; Sec. 2.3.1, 4.1). */

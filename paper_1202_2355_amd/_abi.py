@@ -21,6 +21,8 @@ M2M_S_MPR, M2M_S_GWR = 0, 1
 M2M_KIN_NONE, M2M_KIN_V2, M2M_KIN_GH, M2M_KIN_LOSVD = 0, 1, 2, 3
 KIN = {"none": M2M_KIN_NONE, "v2": M2M_KIN_V2, "gh": M2M_KIN_GH, "losvd": M2M_KIN_LOSVD}
 ENTROPY = {"mpr": M2M_S_MPR, "gwr": M2M_S_GWR}
+M2M_DENS_BINS, M2M_DENS_ALM = 0, 1
+DENS = {"bins": M2M_DENS_BINS, "alm": M2M_DENS_ALM}
 DTYPE = {"f32": M2M_F32, "f64": M2M_F64}
 
 
@@ -38,7 +40,8 @@ class m2m_obs_layout(C.Structure):
     _fields_ = [("n_r", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
                 ("n_R", C.c_int32), ("R_min", C.c_double), ("R_max", C.c_double),
                 ("kin", C.c_int32), ("gh_nmax", C.c_int32), ("n_v", C.c_int32),
-                ("v_min", C.c_double), ("v_max", C.c_double)]
+                ("v_min", C.c_double), ("v_max", C.c_double), ("dens", C.c_int32),
+                ("l_max", C.c_int32)]
 
 
 class m2m_params(C.Structure):
@@ -126,10 +129,13 @@ def potential(d) -> m2m_potential:
 
 def obs_layout(d: dict) -> m2m_obs_layout:
     kin = KIN[d["kin"]] if isinstance(d["kin"], str) else int(d["kin"])
+    dens = d.get("dens", "bins")
     return m2m_obs_layout(n_r=d["n_r"], r_min=d["r_min"], r_max=d["r_max"], n_R=d["n_R"],
                           R_min=d["R_min"], R_max=d["R_max"], kin=kin,
                           gh_nmax=d.get("gh_nmax", 0), n_v=d.get("n_v", 0),
-                          v_min=d.get("v_min", 0.0), v_max=d.get("v_max", 0.0))
+                          v_min=d.get("v_min", 0.0), v_max=d.get("v_max", 0.0),
+                          dens=DENS[dens] if isinstance(dens, str) else int(dens),
+                          l_max=int(d.get("l_max", 0)))
 
 
 def params(d: dict) -> m2m_params:

@@ -79,14 +79,31 @@ std::string check_layout(const m2m_obs_layout* L) {
         if (L->n_v < 1 || L->n_v > kMaxLOSVD) return "n_v must be in 1..256";
         if (!(is_fin(L->v_min) && is_fin(L->v_max) && L->v_max > L->v_min)) return "need v_min < v_max";
     }
-    const int64_t J = (int64_t)L->n_r + (int64_t)(L->kin == M2M_KIN_NONE ? 0 : L->n_R) * kin_per_annulus(*L);
+    if (L->dens != M2M_DENS_BINS && L->dens != M2M_DENS_ALM) return "unknown dens";
+    if (L->dens == M2M_DENS_ALM) {
+        if (L->n_r < 2) return "the a_lm mesh needs n_r >= 2 radii";
+        if (L->l_max < 0 || L->l_max > kMaxLM) return "l_max must be in 0..8";
+    }
+    const int64_t nlm = L->dens == M2M_DENS_ALM ? (int64_t)(L->l_max + 1) * (L->l_max + 1) : 1;
+    const int64_t J = (int64_t)L->n_r * nlm +
+                      (int64_t)(L->kin == M2M_KIN_NONE ? 0 : L->n_R) * kin_per_annulus(*L);
     if (J > 16384) return "too many observables";
     return "";
 }
 
+// radial bins, or the intervals between the a_lm mesh radii
+int radial_intervals(const m2m_obs_layout& L) {
+    return L.dens == M2M_DENS_ALM ? L.n_r - 1 : L.n_r;
+}
+
+// observables of the density part: n_r bins, or (l_max + 1)^2 at each mesh radius
+int32_t dens_obs(const m2m_obs_layout& L) {
+    return L.dens == M2M_DENS_ALM ? L.n_r * (L.l_max + 1) * (L.l_max + 1) : L.n_r;
+}
+
 int32_t num_obs(const m2m_obs_layout& L) {
-    if (L.kin == M2M_KIN_NONE) return L.n_r;
-    return L.n_r + L.n_R * kin_per_annulus(L);
+    if (L.kin == M2M_KIN_NONE) return dens_obs(L);
+    return dens_obs(L) + L.n_R * kin_per_annulus(L);
 }
 
 // log10(lambda) search range of the prior smoothing and the number of
@@ -223,7 +240,7 @@ constexpr double kLz1 = 20.7232658369464;   // ln 1e9
 
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
-    size_t st, fd, tiles, jobs, redge2, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
+    size_t st, fd, tiles, jobs, redge2, rmesh, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
     size_t cdata, gprior;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
     int seg_cap, row_len, nbj, ncj, J, C;
@@ -262,6 +279,7 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     const int nR = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
     const int nv = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
     w.redge2 = take(sz * (size_t)(L.n_r + 1));
+    w.rmesh = take(sz * (size_t)(L.n_r + 1));
     w.Redge2 = take(sz * (size_t)(nR + 1));
     w.vedge = take(sz * (size_t)(nv + 1));
     w.Vp = take(sz * (size_t)std::max(nR, 1));
@@ -542,13 +560,13 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->f64 = dtype == M2M_F64;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->block = c->f64 ? 256 : g_block;
-    c->kin = kin_class(c->lay.kin, c->lay.gh_nmax);
+    c->kin = kin_class(c->lay.kin, c->lay.gh_nmax, c->lay.dens);
     c->w = plan(c->lay, c->par, n, c->f64);
     const WsLayout& w = c->w;
     const int kpriv = private_copies(c->f64, w.J);
     c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
     c->wt = (size_t)n * 8 * (c->f64 ? 8 : 4) <= kWriteThroughMax;
-    c->lds = step_lds_bytes(c->f64, c->acc64, w.J, c->lay.n_r,
+    c->lds = step_lds_bytes(c->f64, c->acc64, w.J, radial_intervals(c->lay),
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
                             c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C);
     if (c->lds > max_lds()) {
@@ -590,7 +608,10 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.rs = hp.GM200 > 0 ? hp.rs : 1.0;
     f.phi0 = hp.phi(0.0);
     const m2m_obs_layout& L = c->lay;
-    f.n_r = L.n_r;
+    const int n_int = radial_intervals(L);
+    f.n_r = n_int;
+    f.jk0 = dens_obs(L);
+    f.l_max = L.dens == M2M_DENS_ALM ? L.l_max : 0;
     f.n_R = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
     f.kin = L.kin;
     f.nk = kin_per_annulus(L);
@@ -599,7 +620,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.gh_nmax = L.kin == M2M_KIN_GH ? L.gh_nmax : 0;
     f.C = w.C;
     f.lr0 = std::log2(L.r_min * L.r_min);
-    f.lrs = L.n_r / std::log2((L.r_max * L.r_max) / (L.r_min * L.r_min));
+    f.lrs = n_int / std::log2((L.r_max * L.r_max) / (L.r_min * L.r_min));
     if (f.n_R > 0) {
         f.lR0 = std::log2(L.R_min * L.R_min);
         f.lRs = L.n_R / std::log2((L.R_max * L.R_max) / (L.R_min * L.R_min));
@@ -610,6 +631,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     }
     unsigned char* b = c->ws;
     f.redge2 = b + w.redge2;
+    f.rmesh = b + w.rmesh;
     f.Redge2 = b + w.Redge2;
     f.vedge = b + w.vedge;
     f.Vp = b + w.Vp;
@@ -662,9 +684,11 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->jobs = reinterpret_cast<FinJob*>(b + w.jobs);
 
     // ---- tables
-    std::vector<double> re2(L.n_r + 1), Re2(f.n_R + 1), ve(f.n_v + 1, 0.0);
-    for (int k = 0; k <= L.n_r; ++k) {
-        const double e = log_edge(L.r_min, L.r_max, L.n_r, k);
+    // radial bin edges, or the a_lm mesh radii (n_int + 1 of both)
+    std::vector<double> re2(n_int + 1), rm(n_int + 1), Re2(f.n_R + 1), ve(f.n_v + 1, 0.0);
+    for (int k = 0; k <= n_int; ++k) {
+        const double e = log_edge(L.r_min, L.r_max, n_int, k);
+        rm[k] = e;
         re2[k] = e * e;
     }
     for (int k = 0; k <= f.n_R; ++k) {
@@ -687,6 +711,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     m2m_status s = M2M_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(M2M_EDEVICE);
     if ((s = upload(c, w.redge2, re2)) != M2M_OK) return bail(s);
+    if ((s = upload(c, w.rmesh, rm)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.Redge2, Re2)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.vedge, ve)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);

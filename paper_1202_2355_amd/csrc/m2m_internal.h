@@ -11,6 +11,7 @@ namespace m2m {
 
 constexpr int kMaxGH = 8;          // largest Gauss-Hermite order
 constexpr int kMaxLOSVD = 256;     // largest LOSVD bin count
+constexpr int kMaxLM = 8;          // largest degree l of the a_lm density observables
 constexpr int kMaxCells = 4096;    // largest n_E * n_x
 constexpr int kLcTable = 8192;     // entries of the ln r_c(ln zeta) table
 constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
@@ -59,10 +60,13 @@ struct FitDev {
     double GMh, a, GMn, rs, phi0;
     // observables
     int32_t n_r, n_R, kin, nk, J, n_v, gh_nmax, C;
+    int32_t jk0;             // index of the first kinematic observable
+    int32_t l_max;           // a_lm degree; n_r then counts mesh intervals
     double lr0, lrs;         // radial bin guess: (log2(r^2) - lr0) * lrs
     double lR0, lRs;         // annulus bin guess
     double vmin, vidv;       // LOSVD bin guess: (v - vmin) * vidv
     void *redge2, *Redge2, *vedge, *Vp, *isp, *rp;  // tables in the state dtype
+    void* rmesh;             // a_lm mesh radii (n_r + 1, state dtype)
     double *Y, *sigma, *yv, *ytil, *delta, *obs_out;
     double *partials;        // tile rows of row_len doubles
     int32_t row_len;         // J + 2 C
@@ -123,7 +127,7 @@ struct FinJob {
 hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* fits,
                        const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
                        hipStream_t s);
-int kin_class(int kin, int gh_nmax);
+int kin_class(int kin, int gh_nmax, int dens);
 // the column jobs of the fits of the table (n_fits of them)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
                            int n_jobs, int32_t mode, hipStream_t s);

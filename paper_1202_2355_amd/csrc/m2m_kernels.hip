@@ -98,7 +98,7 @@ struct Tabs {
     A *sum, *comp;
     double* csum;
     uint32_t* ccnt;
-    T *rp, *re2, *Re2, *ve, *Vp, *isp;
+    T *rp, *re2, *Re2, *ve, *Vp, *isp, *rm;
 };
 
 template <typename T, typename A>
@@ -124,6 +124,8 @@ __device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, i
     t.Vp = p;
     p += n_R;
     t.isp = p;
+    p += n_R;
+    t.rm = p;  // a_lm mesh radii (n_r + 1)
     return t;
 }
 
@@ -133,6 +135,7 @@ __device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, i
 template <typename T>
 struct Hot {
     int n_r, n_R, nk, gh_nmax, n_v, J, C, kp, n_E, n_x;
+    int jk0, l_max, nlm;  // first kinematic observable; a_lm degree and (l_max + 1)^2
     T lr0, lrs, lR0, lRs, vmin, vidv;
     T r2lo, r2hi, R2lo, R2hi, vlo, vhi;  // range ends: squared radii, velocities
     T GMh, a, GMn, rs, irs, phi0;
@@ -154,6 +157,9 @@ __device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
     h.kp = fd.kpriv;
     h.n_E = fd.n_E;
     h.n_x = fd.n_x;
+    h.jk0 = fd.jk0;
+    h.l_max = fd.l_max;
+    h.nlm = (fd.l_max + 1) * (fd.l_max + 1);
     h.lr0 = T(fd.lr0);
     h.lrs = T(fd.lrs);
     h.lR0 = T(fd.lR0);
@@ -227,40 +233,131 @@ __device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
     return refine_bin<T>(v, e, n, g);
 }
 
-// kinds of kinematic observables, fixed at compile time in k_step
-enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4 };
+// kinds of kinematic observables, fixed at compile time in k_step; the bit
+// kKinAlm selects the spherical-harmonic density observables instead of
+// radial bins
+enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4, kKinAlm = 8 };
 
 template <int KIN>
 struct KinSlots {
-    static constexpr int n = (KIN == kKinGH4) ? 4 : (KIN == kKinGHN) ? kMaxGH : 1;
+    static constexpr int n = ((KIN & 7) == kKinGH4) ? 4 : ((KIN & 7) == kKinGHN) ? kMaxGH : 1;
 };
 
-// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1)
-// and kn kinematic entries j = jk + m with values k[m].
+// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1),
+// or with a_lm the mesh interval jr with the cloud-in-cell weight g of its
+// inner radius and the direction (cos, sin of the polar angle; cos, sin of
+// the azimuth); then kn kinematic entries j = jk + m with values k[m].
 template <typename T, int KIN>
 struct Kern {
     int jr, jk, kn;
     T k[KinSlots<KIN>::n];
+    T g, ct, st, cp, sp;
 };
+
+// ------------------------------------------------------- spherical harmonics
+// Real orthonormal harmonics Y_lm (Condon-Shortley phase) through the
+// normalized associated Legendre functions Pn_l^m = N_lm P_l^m,
+// N_lm = sqrt((2l + 1)/(4 pi) (l - m)!/(l + m)!):
+//   Pn_0^0 = 1/sqrt(4 pi),  Pn_m^m = -sqrt((2m + 1)/(2m)) sin(t) Pn_{m-1}^{m-1},
+//   Pn_{m+1}^m = sqrt(2m + 3) cos(t) Pn_m^m,
+//   Pn_l^m = a_lm (cos(t) Pn_{l-1}^m - b_lm Pn_{l-2}^m),
+//   a_lm = sqrt((4l^2 - 1)/(l^2 - m^2)),  b_lm = sqrt(((l-1)^2 - m^2)/(4(l-1)^2 - 1));
+// Y_l0 = Pn_l^0, Y_l,m = sqrt2 Pn_l^m cos(m phi), Y_l,-m = sqrt2 Pn_l^m sin(m phi).
+constexpr double csqrt(double x) {  // compile-time square root (Newton)
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+struct YlmCoef {
+    double mm[kMaxLM + 1], m1[kMaxLM + 1], a[kMaxLM + 1][kMaxLM + 1], b[kMaxLM + 1][kMaxLM + 1];
+};
+
+constexpr YlmCoef ylm_coef() {
+    YlmCoef c{};
+    for (int m = 0; m <= kMaxLM; ++m) {
+        c.mm[m] = m > 0 ? csqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.0;
+        c.m1[m] = csqrt(2.0 * m + 3.0);
+        for (int l = m + 2; l <= kMaxLM; ++l) {
+            const double ll = double(l) * l, mm2 = double(m) * m, l1 = double(l - 1) * (l - 1);
+            c.a[l][m] = csqrt((4.0 * ll - 1.0) / (ll - mm2));
+            c.b[l][m] = csqrt((l1 - mm2) / (4.0 * l1 - 1.0));
+        }
+    }
+    return c;
+}
+
+__constant__ YlmCoef kYlm = ylm_coef();
+
+// f(l^2 + l + m, Y_lm) for every 0 <= l <= lmax, -l <= m <= l, at the
+// direction (ct, st) = cos, sin of the polar angle and (cp, sp) of the azimuth
+template <typename T, typename F>
+__device__ __forceinline__ void ylm_walk(int lmax, T ct, T st, T cp, T sp, F&& f) {
+    T pmm = T(0.282094791773878143);  // 1/sqrt(4 pi)
+    T cm = T(1), sm = T(0);           // cos(m phi), sin(m phi)
+    for (int m = 0; m <= lmax; ++m) {
+        if (m > 0) {
+            pmm = -T(kYlm.mm[m]) * st * pmm;
+            const T c = cm * cp - sm * sp;
+            sm = sm * cp + cm * sp;
+            cm = c;
+        }
+        const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
+        auto emit = [&](int l, T pn) {
+            if (m == 0) {
+                f(l * l + l, pn);
+            } else {
+                f(l * l + l + m, pn * c2);
+                f(l * l + l - m, pn * s2);
+            }
+        };
+        emit(m, pmm);
+        if (m < lmax) {
+            T p2 = pmm, p1 = T(kYlm.m1[m]) * ct * pmm;
+            emit(m + 1, p1);
+            for (int l = m + 2; l <= lmax; ++l) {
+                const T p = T(kYlm.a[l][m]) * (ct * p1 - T(kYlm.b[l][m]) * p2);
+                emit(l, p);
+                p2 = p1;
+                p1 = p;
+            }
+        }
+    }
+}
 
 template <typename T, typename A, int KIN>
 __device__ __forceinline__ Kern<T, KIN> kernels(const Hot<T>& h, const Tabs<T, A>& tb, T x, T y,
                                                 T z, T vz) {
+    constexpr int KK = KIN & 7;
     Kern<T, KIN> o;
     const T R2 = x * x + y * y;
     const T r2 = R2 + z * z;
     o.jr = bin_of<T>(r2, tb.re2, h.n_r, (Mth<T>::log2_(r2) - h.lr0) * h.lrs, h.r2lo, h.r2hi);
+    if ((KIN & kKinAlm) && o.jr >= 0) {
+        // cloud-in-cell weight of the inner mesh radius (linear in r) and the
+        // direction; r >= r_min > 0 here
+        const T r = Mth<T>::sqrt_(r2);
+        const T r0 = tb.rm[o.jr], r1 = tb.rm[o.jr + 1];
+        o.g = (r1 - r) / (r1 - r0);
+        const T ir = Mth<T>::rcp_(r);
+        o.ct = z * ir;
+        const T R = Mth<T>::sqrt_(R2);
+        o.st = R * ir;
+        const T iR = R > T(0) ? Mth<T>::rcp_(R) : T(0);
+        o.cp = R > T(0) ? x * iR : T(1);
+        o.sp = y * iR;
+    }
     o.jk = -1;
     o.kn = 0;
-    if (KIN == kKinNone) return o;
+    if (KK == kKinNone) return o;
     const int p = bin_of<T>(R2, tb.Re2, h.n_R, (Mth<T>::log2_(R2) - h.lR0) * h.lRs, h.R2lo, h.R2hi);
     if (p < 0) return o;
-    const int base = h.n_r + p * h.nk;
-    if (KIN == kKinV2) {
+    const int base = h.jk0 + p * h.nk;
+    if (KK == kKinV2) {
         o.jk = base;
         o.kn = 1;
         o.k[0] = vz * vz;
-    } else if (KIN == kKinGH4 || KIN == kKinGHN) {
+    } else if (KK == kKinGH4 || KK == kKinGHN) {
         // 2 sqrt(pi) u_n(nu) = sqrt2 e^{-nu^2/2} H_n(nu) / sqrt(2^n n!) by the
         // normalized three-term recurrence
         constexpr int NS = KinSlots<KIN>::n;
@@ -269,11 +366,11 @@ __device__ __forceinline__ Kern<T, KIN> kernels(const Hot<T>& h, const Tabs<T, A
         T hm = T(1);
         T hc = T(1.41421356237309505) * nu;
         o.jk = base;
-        o.kn = (KIN == kKinGH4) ? 4 : h.gh_nmax;
+        o.kn = (KK == kKinGH4) ? 4 : h.gh_nmax;
         o.k[0] = g * hc;
 #pragma unroll
         for (int n = 1; n < NS; ++n) {
-            if (KIN == kKinGH4 || n < h.gh_nmax) {
+            if (KK == kKinGH4 || n < h.gh_nmax) {
                 const T hn = T(kGhA[n]) * nu * hc - T(kGhB[n]) * hm;
                 hm = hc;
                 hc = hn;
@@ -390,6 +487,19 @@ __device__ __forceinline__ float two_sum_err(float old, float v) {
     return (old - (t - bp)) + (v - bp);
 }
 
+// The a_lm part of a deposit of weight w: w g Y_lm at the inner mesh radius
+// of the interval, w (1 - g) Y_lm at the outer one; add(j, value).
+template <typename T, int KIN, typename Add>
+__device__ __forceinline__ void deposit_alm(const Hot<T>& h, const Kern<T, KIN>& kk, T w,
+                                            Add&& add) {
+    const int b0 = kk.jr * h.nlm, b1 = b0 + h.nlm;
+    const T wa = w * kk.g, wb = w * (T(1) - kk.g);
+    ylm_walk(h.l_max, kk.ct, kk.st, kk.cp, kk.sp, [&](int lm, T Y) {
+        add(b0 + lm, wa * Y);
+        add(b1 + lm, wb * Y);
+    });
+}
+
 template <typename T, int KIN>
 __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, float>& tb,
                                         const Kern<T, KIN>& kk, T u, int priv) {
@@ -401,11 +511,17 @@ __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, float>& t
     float v[NS], o_k[NS];
 #pragma unroll
     for (int m = 0; m < NS; ++m) v[m] = (float)(wf * kk.k[m]);
-    if (kk.jr >= 0) o_r = atomicAdd(&tb.sum[kk.jr * kp + priv], wf);
+    if ((KIN & kKinAlm) && kk.jr >= 0)
+        deposit_alm(h, kk, T(wf), [&](int j, T val) {
+            const float vf = (float)val;
+            const float o = atomicAdd(&tb.sum[j * kp + priv], vf);
+            atomicAdd(&tb.comp[j * kp + priv], two_sum_err(o, vf));
+        });
+    if (!(KIN & kKinAlm) && kk.jr >= 0) o_r = atomicAdd(&tb.sum[kk.jr * kp + priv], wf);
 #pragma unroll
     for (int m = 0; m < NS; ++m)
         if (m < kk.kn) o_k[m] = atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], v[m]);
-    if (kk.jr >= 0) atomicAdd(&tb.comp[kk.jr * kp + priv], two_sum_err(o_r, wf));
+    if (!(KIN & kKinAlm) && kk.jr >= 0) atomicAdd(&tb.comp[kk.jr * kp + priv], two_sum_err(o_r, wf));
 #pragma unroll
     for (int m = 0; m < NS; ++m)
         if (m < kk.kn) atomicAdd(&tb.comp[(kk.jk + m) * kp + priv], two_sum_err(o_k[m], v[m]));
@@ -417,7 +533,9 @@ __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& 
     constexpr int NS = KinSlots<KIN>::n;
     const int kp = h.kp;
     const T w = u * h.w0;
-    if (kk.jr >= 0) atomicAdd(&tb.sum[kk.jr * kp + priv], (double)w);
+    if ((KIN & kKinAlm) && kk.jr >= 0)
+        deposit_alm(h, kk, w, [&](int j, T val) { atomicAdd(&tb.sum[j * kp + priv], (double)val); });
+    if (!(KIN & kKinAlm) && kk.jr >= 0) atomicAdd(&tb.sum[kk.jr * kp + priv], (double)w);
 #pragma unroll
     for (int m = 0; m < NS; ++m)
         if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
@@ -948,6 +1066,10 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             }
         const G<const T> re2 = gmem<const T>(fd.redge2);
         for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.re2[j] = re2[j];
+        if (KIN & kKinAlm) {
+            const G<const T> rm = gmem<const T>(fd.rmesh);
+            for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.rm[j] = rm[j];
+        }
         const G<const T> Re2 = gmem<const T>(fd.Redge2);
         for (int j = threadIdx.x; j <= h.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
         const G<const T> ve = gmem<const T>(fd.vedge);
@@ -985,7 +1107,16 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
         if (correct) {
             // force of change at z^k with the residuals of step k
             const Kern<T, KIN> kk = kernels<T, A, KIN>(h, tb, x, y, z, vz);
-            T chi = (kk.jr >= 0) ? tb.rp[kk.jr] : T(0);
+            T chi = T(0);
+            if ((KIN & kKinAlm) && kk.jr >= 0) {
+                const int b0 = kk.jr * h.nlm, b1 = b0 + h.nlm;
+                const T g1 = T(1) - kk.g;
+                ylm_walk(h.l_max, kk.ct, kk.st, kk.cp, kk.sp, [&](int lm, T Y) {
+                    chi += Y * (kk.g * tb.rp[b0 + lm] + g1 * tb.rp[b1 + lm]);
+                });
+            } else if (kk.jr >= 0) {
+                chi = tb.rp[kk.jr];
+            }
 #pragma unroll
             for (int m = 0; m < KinSlots<KIN>::n; ++m)
                 if (m < kk.kn) chi += kk.k[m] * tb.rp[kk.jk + m];
@@ -1154,6 +1285,11 @@ hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, const
         case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
         case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
         case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinNone: return launch_step_t<T, A, BLOCK, kKinAlm | kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinV2: return launch_step_t<T, A, BLOCK, kKinAlm | kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinGH4: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinGHN: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinAlm | kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1181,7 +1317,7 @@ size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, in
     (void)acc64;  // FP64 sums and FP32 sum + compensation both take 8 bytes per bin copy
     const size_t sz = f64 ? 8 : 4;
     const size_t bins = (size_t)J * (size_t)kpriv * 8 + (size_t)C * 8 + (size_t)((C + 1) & ~1) * 4;
-    const size_t tabs = ((size_t)J + (size_t)(n_r + 1) + (size_t)(n_R + 1) + (size_t)(n_v + 1) +
+    const size_t tabs = ((size_t)J + 2 * (size_t)(n_r + 1) + (size_t)(n_R + 1) + (size_t)(n_v + 1) +
                          2 * (size_t)n_R) * sz;
     return ((bins + tabs + 15) / 16) * 16;
 }
@@ -1195,12 +1331,13 @@ int private_copies(bool f64, int J) {
     return k;
 }
 
-int kin_class(int kin, int gh_nmax) {
+int kin_class(int kin, int gh_nmax, int dens) {
+    const int alm = dens == 1 ? kKinAlm : 0;
     switch (kin) {
-        case 0: return kKinNone;
-        case 1: return kKinV2;
-        case 2: return gh_nmax == 4 ? kKinGH4 : kKinGHN;
-        case 3: return kKinLOSVD;
+        case 0: return alm | kKinNone;
+        case 1: return alm | kKinV2;
+        case 2: return alm | (gh_nmax == 4 ? kKinGH4 : kKinGHN);
+        case 3: return alm | kKinLOSVD;
         default: return -1;
     }
 }

@@ -47,6 +47,14 @@ def test_host_only_entry_points():
     assert _abi.m2m_workspace_bytes(wl.layout, dict(wl.params, smooth=1, n_E=200, n_x=2),
                                     wl.N) == 0
     assert _abi.m2m_workspace_bytes(wl.layout, dict(wl.params, smooth=2), wl.N) == 0
+    # spherical-harmonic density observables: (l_max + 1)^2 per mesh radius
+    alm = dict(wl.layout, n_r=60, dens="alm", l_max=4)
+    assert _abi.m2m_num_observables(alm) == 60 * 25 + 40 * 64
+    assert _abi.m2m_num_observables(dict(alm, l_max=9)) == 0
+    assert _abi.m2m_num_observables(dict(alm, l_max=-1)) == 0
+    assert _abi.m2m_num_observables(dict(alm, n_r=1)) == 0
+    assert _abi.m2m_num_observables(dict(alm, dens=2)) == 0
+    assert _abi.m2m_num_observables(dict(alm, n_r=200, l_max=8)) == 0  # J > 16384
     b0 = _abi.m2m_get_launch()
     with pytest.raises(_abi.M2MError):
         _abi.m2m_set_launch(300, 4)

@@ -425,3 +425,70 @@ def test_run_with_prior_smoothing_matches_oracle(oracle, Fit):
     _say("run with smoothing: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
     f.close()
     assert r2 <= 1e-4 and rmax <= 1e-4
+
+
+# ------------------------------------------------- spherical-harmonic density
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_alm_observe_matches_oracle(oracle, Fit, dtype):
+    """Density observables a_lm,k (Sec. 3.3, eq. alm) on the paper's 60-point
+    mesh with l <= 4, plus the Gauss-Hermite annuli, of one state."""
+    from workloads import with_alm
+    wl = with_alm(workload(2), n_mesh=60, l_max=4)
+    n = 50_003
+    _say("alm observe", wl.name, dtype, n, "J", wl.J)
+    parts = cast(wl.initial_particles(n=n, seed=202), dtype)
+    u = cast({"u": random_weights(n, 9)}, dtype)["u"]
+    V, S = _gh_centres(wl.layout["n_R"])
+    V, S = cast({"V": V, "S": S}, dtype).values()
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype, u=u)
+    y = f.observe(V, S)
+    band = BAND_F32 if dtype == "f32" else BAND_F64
+    yo, ya, yb = oracle.deposit(parts, u, wl.layout, mass=wl.params["mass"], V_p=V, sigma_p=S,
+                                band=band, nthreads=8, with_abs=True)
+    worst = assert_observables(y, yo, ya, yb, 1e-5 if dtype == "f32" else 1e-12, wl.name)
+    _say("alm observe", dtype, "max |dy|/sum|wK| =", worst)
+    # the monopole row carries the mass: sum_k a_00,k = Y_00 sum of the mass inside
+    nlm = 25
+    a00 = np.asarray(y)[:60 * nlm].reshape(60, nlm)[:, 0]
+    assert np.all(a00 >= -1e-12)
+    f.close()
+
+
+def test_alm_run_fp64_matches_oracle(oracle, Fit):
+    """FP64 state, workload 1 with its radial bins replaced by a_lm (l <= 2)
+    on a 30-point mesh: weights and chi^2 history after 100 steps."""
+    from workloads import with_alm
+    wl = with_alm(workload(1), n_mesh=30, l_max=2)
+    n = 20_003
+    _say("alm run fp64", wl.name, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 100, "f64", 1e-12)
+    f.step(100)
+    hist_o = o.step(100)
+    hist_g = f.chi2_history(100)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("alm run fp64: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    assert r2 <= 1e-10
+    assert rmax <= 1e-10
+    np.testing.assert_allclose(hist_g, hist_o, rtol=1e-9)
+    f.close()
+
+
+def test_alm_run_fp32_matches_oracle(oracle, Fit):
+    """FP32 state, workload 2 with a_lm (l <= 4) on 60 mesh radii: weights
+    after 50 steps."""
+    from workloads import with_alm
+    wl = with_alm(workload(2), n_mesh=60, l_max=4)
+    n = 30_001
+    _say("alm run fp32", wl.name, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 50, "f32", 1e-5)
+    f.step(50)
+    hist_o = o.step(50)
+    hist_g = f.chi2_history(50)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("alm run fp32: rel2", r2, "max(unflagged)", rmax, "max(all)", rall, "flagged", frac)
+    assert r2 <= 1e-4
+    assert rmax <= 1e-4
+    np.testing.assert_allclose(hist_g, hist_o, rtol=1e-4)
+    f.close()

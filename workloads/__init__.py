@@ -34,5 +34,7 @@ from .configs import (  # noqa: F401
     make_potential,
     J_of,
     rng,
+    with_alm,
 )
-from .targets import fit_gauss_hermite_centres, add_noise, floor_model_noise, make_targets  # noqa: F401
+from .targets import (  # noqa: F401
+    add_noise, density_length, fit_gauss_hermite_centres, floor_model_noise, make_targets)

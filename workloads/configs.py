@@ -33,6 +33,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
+from .targets import density_length
 from .dynamics import (
     EddingtonDF,
     HernquistTracer,
@@ -55,15 +56,27 @@ def make_potential(upsilon=1.0, M200=0.0, c=0.0, r200=100.0, G=1.0, M_star=1.0, 
 
 
 def make_layout(n_r, r_min, r_max, n_R=0, R_min=0.05, R_max=20.0, kin="none",
-                gh_nmax=0, n_v=0, v_min=0.0, v_max=0.0):
+                gh_nmax=0, n_v=0, v_min=0.0, v_max=0.0, dens="bins", l_max=0):
+    """Observable layout. dens = "bins": n_r radial mass bins on [r_min, r_max);
+    dens = "alm": spherical-harmonic coefficients a_lm,k, l <= l_max, on n_r
+    log-spaced mesh radii from r_min to r_max (cloud-in-cell weights)."""
     return dict(n_r=int(n_r), r_min=float(r_min), r_max=float(r_max), n_R=int(n_R),
                 R_min=float(R_min), R_max=float(R_max), kin=kin, gh_nmax=int(gh_nmax),
-                n_v=int(n_v), v_min=float(v_min), v_max=float(v_max))
+                n_v=int(n_v), v_min=float(v_min), v_max=float(v_max), dens=dens,
+                l_max=int(l_max))
 
 
 def J_of(layout: dict) -> int:
     per = {"none": 0, "v2": 1, "gh": layout["gh_nmax"], "losvd": layout["n_v"]}[layout["kin"]]
-    return layout["n_r"] + layout["n_R"] * per
+    return density_length(layout) + layout["n_R"] * per
+
+
+def with_alm(wl: "Workload", n_mesh: int = 60, l_max: int = 4) -> "Workload":
+    """The workload with its radial mass bins replaced by the spherical-harmonic
+    density coefficients a_lm,k (Sec. 3.3, eq. alm) on an n_mesh-point
+    log-spaced mesh over the same radial range (the paper uses 60 points)."""
+    lay = dict(wl.layout, n_r=int(n_mesh), dens="alm", l_max=int(l_max))
+    return wl.with_(name=f"{wl.name}_alm{l_max}", layout=lay)
 
 
 def make_params(pot: Potential, dt=0.01, eps=0.1, mu=1e-2, alpha=2.1, mass=1.0,

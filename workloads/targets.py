@@ -20,6 +20,14 @@ from .dynamics import hernquist_projected_mass
 SQRT2 = float(np.sqrt(2.0))
 
 
+def density_length(layout: dict) -> int:
+    """Observables of the density part: n_r radial bins, or (l_max + 1)^2
+    spherical-harmonic coefficients at each of the n_r mesh radii."""
+    if layout.get("dens", "bins") == "alm":
+        return layout["n_r"] * (layout.get("l_max", 0) + 1) ** 2
+    return layout["n_r"]
+
+
 def annulus_luminosity(layout: dict, M=1.0, a=1.0) -> np.ndarray:
     """l_p of a Hernquist(M, a) tracer in the layout's log annuli (closed form)."""
     n = layout["n_R"]
@@ -37,7 +45,7 @@ def fit_gauss_hermite_centres(observe, layout: dict, lum: np.ndarray,
     dh_2 = -d sigma/(sqrt2 sigma), so V += sqrt2 sigma h_1 and
     sigma *= 1 + sqrt2 h_2 cancel the current h_1, h_2 to first order.
     """
-    n_r, n_R, nmax = layout["n_r"], layout["n_R"], layout["gh_nmax"]
+    n_r, n_R, nmax = density_length(layout), layout["n_R"], layout["gh_nmax"]
     if nmax < 2:
         raise ValueError("Gauss-Hermite centres need b_1 and b_2")
     V = np.zeros(n_R)
@@ -61,14 +69,23 @@ def add_noise(Y_true: np.ndarray, layout: dict, s: float, g: np.random.Generator
 
     * radial mass and v^2 moments: sigma = s |Y_true| (floored at 1e-3 of the
       group's largest value, so empty bins still carry a finite error);
+    * spherical-harmonic coefficients a_lm,k: sigma = s |a_00,k| for every
+      (l, m) at mesh radius k, with the same floor (the errors of the
+      higher moments scale with the density there; the values of l > 0
+      are about zero for a spherical target);
     * Gauss-Hermite b_n: sigma = s l_p (b_n can vanish, l_p cannot);
     * LOSVD bins: sigma = s max(Y, 0.01 max_k Y_{p,k}) per annulus.
     """
     Y_true = np.asarray(Y_true, dtype=np.float64)
-    n_r, n_R, kin = layout["n_r"], layout["n_R"], layout["kin"]
+    n_r, n_R, kin = density_length(layout), layout["n_R"], layout["kin"]
     sig = np.empty_like(Y_true)
-    rad = np.abs(Y_true[:n_r])
-    sig[:n_r] = s * np.maximum(rad, 1e-3 * rad.max())
+    if layout.get("dens", "bins") == "alm":
+        nlm = (layout.get("l_max", 0) + 1) ** 2
+        a00 = np.abs(Y_true[:n_r].reshape(-1, nlm)[:, 0])
+        sig[:n_r] = np.repeat(s * np.maximum(a00, 1e-3 * a00.max()), nlm)
+    else:
+        rad = np.abs(Y_true[:n_r])
+        sig[:n_r] = s * np.maximum(rad, 1e-3 * rad.max())
     rest = Y_true[n_r:]
     if kin == "v2":
         a = np.abs(rest)
