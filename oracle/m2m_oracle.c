@@ -65,13 +65,27 @@ typedef struct {
 } orc_layout;
 
 /* entropy: 0 = mass-neutral S+ with moving priors, 1 = weight entropy;
- * smooth: 1 = thin-plate smoothing of the prior grid with GCV (Sec. 2.3.2) */
+ * smooth: 1 = thin-plate smoothing of the prior grid with GCV (Sec. 2.3.2);
+ * cells: bit 0 = a second grid for particles with L_z < 0 (rotating models,
+ * Sec. 5), bit 1 = energy bins linear in exp(E) (Sec. 5.2) */
 typedef struct {
     double dt, eps, mu, alpha, mass;
     int32_t entropy, n_E, n_x, prior_every;
     double E_lo, E_hi;
-    int32_t smooth, pad;
+    int32_t smooth, cells;
 } orc_params;
+
+/* cells of the prior grid: n_E n_x, twice that with the L_z split */
+static int n_cells(const orc_params *P) {
+    return P->n_E * P->n_x * ((P->cells & 1) ? 2 : 1);
+}
+
+/* position of E on the energy axis in bin units: (E - E_lo)/(E_hi - E_lo) n_E,
+ * or (exp E - exp E_lo)/(exp E_hi - exp E_lo) n_E */
+static double energy_coord(const orc_params *P, double E) {
+    if (P->cells & 2) return (exp(E) - exp(P->E_lo)) / (exp(P->E_hi) - exp(P->E_lo)) * P->n_E;
+    return (E - P->E_lo) / (P->E_hi - P->E_lo) * P->n_E;
+}
 
 typedef struct {
     int64_t n;
@@ -451,8 +465,10 @@ void orc_deposit(int64_t n, const double *x, const double *y, const double *z, c
  * [0, 1) in n_x equal bins; out-of-range values go to the end cells. For
  * E >= 0 there is no circular orbit and x is taken as 0; for E <= Phi(0)
  * L_c = 0 and x is taken as 1. Returns k * n_x + l. */
-int32_t orc_cell(const orc_potential *p, const orc_params *P, double x, double y, double z,
-                 double vx, double vy, double vz, double *Eout, double *xout) {
+/* cell of a phase-space point; also E, x and L_z / (|r| |v|) */
+static int32_t cell_of(const orc_potential *p, const orc_params *P, double x, double y, double z,
+                       double vx, double vy, double vz, double *Eout, double *xout,
+                       double *lzout) {
     double r = sqrt(x * x + y * y + z * z);
     double E = 0.5 * (vx * vx + vy * vy + vz * vz) + orc_phi(p, r);
     double lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
@@ -463,7 +479,7 @@ int32_t orc_cell(const orc_potential *p, const orc_params *P, double x, double y
         double Lc = orc_lc(p, E);
         xc = (Lc > 0.0) ? L / Lc : 1.0;
     }
-    int k = (int)floor((E - P->E_lo) / (P->E_hi - P->E_lo) * P->n_E);
+    int k = (int)floor(energy_coord(P, E));
     if (!(E - P->E_lo >= 0.0)) k = 0;
     if (k < 0) k = 0;
     if (k > P->n_E - 1) k = P->n_E - 1;
@@ -472,16 +488,30 @@ int32_t orc_cell(const orc_potential *p, const orc_params *P, double x, double y
     if (l > P->n_x - 1) l = P->n_x - 1;
     if (Eout) *Eout = E;
     if (xout) *xout = xc;
-    return k * P->n_x + l;
+    if (lzout) {
+        double rv = r * sqrt(vx * vx + vy * vy + vz * vz);
+        *lzout = rv > 0.0 ? lz / rv : 0.0;
+    }
+    int c = k * P->n_x + l;
+    if ((P->cells & 1) && lz < 0.0) c += P->n_E * P->n_x;
+    return c;
 }
 
-static int cell_ambiguous(const orc_params *P, double E, double xc, double band) {
+int32_t orc_cell(const orc_potential *p, const orc_params *P, double x, double y, double z,
+                 double vx, double vy, double vz, double *Eout, double *xout) {
+    return cell_of(p, P, x, y, z, vx, vy, vz, Eout, xout, NULL);
+}
+
+static int cell_ambiguous(const orc_params *P, double E, double xc, double lzr, double band) {
+    /* bin width in E at E: 1 / (d energy_coord / dE) */
     double dE = (P->E_hi - P->E_lo) / P->n_E;
-    double t = (E - P->E_lo) / dE;
+    if (P->cells & 2) dE = (exp(P->E_hi) - exp(P->E_lo)) / (P->n_E * exp(E));
+    double t = energy_coord(P, E);
     double fe = t - floor(t);
     if ((fe * dE <= band * fabs(P->E_lo) || (1.0 - fe) * dE <= band * fabs(P->E_lo)) &&
         t > 0.5 && t < P->n_E - 0.5)
         return 1;
+    if ((P->cells & 1) && fabs(lzr) <= band) return 1;
     double tx = xc * P->n_x;
     double fx = tx - floor(tx);
     if ((fx <= band * P->n_x || 1.0 - fx <= band * P->n_x) && tx > 0.5 && tx < P->n_x - 0.5)
@@ -528,7 +558,8 @@ int orc_init(orc_model *m) {
  *   sum_c (w_c - w0_c)^2 + lambda w^T P w,
  * where w^T P w is the sum over the grid of the finite-difference thin-plate
  * terms (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 in the grid's own units
- * (cell widths hE = (E_hi - E_lo)/n_E and hx = 1/n_x), with reflecting
+ * (cell widths hE = (E_hi - E_lo)/n_E, or (exp E_hi - exp E_lo)/n_E for
+ * energy bins linear in exp(E), and hx = 1/n_x), with reflecting
  * boundaries. With those boundaries the sum equals |Lap w|^2 for the discrete
  * Laplacian Lap = L_E (x) I + I (x) L_x (summation by parts), so P = Lap Lap.
  * Hence w = (I + lambda P)^-1 w0, solved here densely (Cholesky). lambda
@@ -600,7 +631,10 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
     const int nE = par->n_E, nx = par->n_x, n = nE * nx;
     if (lambda_out) *lambda_out = 0.0;
     if (n < 2) return 0;
-    const double hE = (par->E_hi - par->E_lo) / nE, hx = 1.0 / nx;
+    /* cell width along the energy axis, in the variable the bins are linear in */
+    const double hE = (par->cells & 2) ? (exp(par->E_hi) - exp(par->E_lo)) / nE
+                                        : (par->E_hi - par->E_lo) / nE;
+    const double hx = 1.0 / nx;
     double *Lap = (double *)calloc((size_t)n * n, sizeof(double));
     double *P = (double *)calloc((size_t)n * n, sizeof(double));
     double *w0 = (double *)malloc(sizeof(double) * n);
@@ -676,7 +710,7 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
  * over the cell (empty cells keep their previous prior), then optionally
  * smoothed over the grid */
 int orc_refresh_priors(orc_model *m) {
-    int C = m->par.n_E * m->par.n_x;
+    int C = n_cells(&m->par);
     double *sum = (double *)calloc(C, sizeof(double));
     int64_t *cnt = (int64_t *)calloc(C, sizeof(int64_t));
     int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * m->n);
@@ -685,10 +719,10 @@ int orc_refresh_priors(orc_model *m) {
 #pragma omp parallel for num_threads(T) schedule(static)
 #endif
     for (int64_t i = 0; i < m->n; ++i) {
-        double E, xc;
-        cell[i] = orc_cell(&m->pot, &m->par, m->x[i], m->y[i], m->z[i], m->vx[i], m->vy[i],
-                           m->vz[i], &E, &xc);
-        if (m->flag && cell_ambiguous(&m->par, E, xc, m->band)) m->flag[i] = 1;
+        double E, xc, lzr;
+        cell[i] = cell_of(&m->pot, &m->par, m->x[i], m->y[i], m->z[i], m->vx[i], m->vy[i],
+                          m->vz[i], &E, &xc, &lzr);
+        if (m->flag && cell_ambiguous(&m->par, E, xc, lzr, m->band)) m->flag[i] = 1;
     }
     /* cell sums in particle order */
     for (int64_t i = 0; i < m->n; ++i) {
@@ -699,7 +733,10 @@ int orc_refresh_priors(orc_model *m) {
     for (int c = 0; c < C; ++c)
         grid[c] = cnt[c] > 0 ? sum[c] / (double)cnt[c] : (m->ucell ? m->ucell[c] : 1.0);
     int rc = 0;
-    if (m->par.smooth) rc = orc_smooth_grid(&m->par, grid, NULL);
+    /* each n_E x n_x grid (both halves with the L_z split) is smoothed alone */
+    if (m->par.smooth)
+        for (int c0 = 0; c0 < C && rc == 0; c0 += m->par.n_E * m->par.n_x)
+            rc = orc_smooth_grid(&m->par, grid + c0, NULL);
     if (m->ucell)
         for (int c = 0; c < C; ++c) m->ucell[c] = grid[c];
     for (int64_t i = 0; i < m->n; ++i) m->uhat[i] = grid[cell[i]];
@@ -774,7 +811,7 @@ int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) 
 void orc_cell_mass(const orc_potential *p, const orc_params *P, int64_t n, const double *x,
                    const double *y, const double *z, const double *vx, const double *vy,
                    const double *vz, const double *u, double mass, double *out) {
-    int C = P->n_E * P->n_x;
+    int C = n_cells(P);
     for (int c = 0; c < C; ++c) out[c] = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t c = orc_cell(p, P, x[i], y[i], z[i], vx[i], vy[i], vz[i], NULL, NULL);

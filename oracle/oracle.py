@@ -46,7 +46,7 @@ class Params(C.Structure):
                 ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
                 ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
                 ("E_lo", C.c_double), ("E_hi", C.c_double), ("smooth", C.c_int32),
-                ("pad", C.c_int32)]
+                ("cells", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -138,7 +138,12 @@ def params(d: dict) -> Params:
     return Params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
                   entropy=ENTROPY[d["entropy"]], n_E=d["n_E"], n_x=d["n_x"],
                   prior_every=d["prior_every"], E_lo=d["E_lo"], E_hi=d["E_hi"],
-                  smooth=int(d.get("smooth", 0)), pad=0)
+                  smooth=int(d.get("smooth", 0)), cells=int(d.get("cells", 0)))
+
+
+def n_cells(par: dict) -> int:
+    """Cells of the prior grid: n_E n_x, twice that with the L_z split (cells bit 0)."""
+    return int(par["n_E"]) * int(par["n_x"]) * (2 if int(par.get("cells", 0)) & 1 else 1)
 
 
 def smooth_grid(par: dict, grid):
@@ -236,7 +241,7 @@ def cells(pot, par: dict, parts: dict):
 
 def cell_mass(pot, par: dict, parts: dict, u, mass=1.0):
     x, y, z, vx, vy, vz = (_f64(parts[k]) for k in ("x", "y", "z", "vx", "vy", "vz"))
-    out = np.zeros(par["n_E"] * par["n_x"])
+    out = np.zeros(n_cells(par))
     lib().orc_cell_mass(C.byref(potential(pot)), C.byref(params(par)), x.size, _p(x), _p(y),
                         _p(z), _p(vx), _p(vy), _p(vz), _p(_f64(u)), float(mass), _p(out))
     return out
@@ -284,7 +289,7 @@ class OracleFit:
         m.flag = self.flag.ctypes.data_as(C.POINTER(C.c_uint8)) if track_flags else None
         m.band = band
         m.nthreads = nthreads
-        self.ucell = np.ones(int(par["n_E"]) * int(par["n_x"]))
+        self.ucell = np.ones(n_cells(par))
         m.ucell = _p(self.ucell)
         self.m = m
         if self.Y.size != self.J or self.sigma.size != self.J:
