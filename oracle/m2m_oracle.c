@@ -35,7 +35,11 @@
  *     prior_every correction steps) new priors from z^{k+1}.
  *
  * The Hernquist potential is eq. her (Sec. 3.1); the optional NFW halo is
- *   Phi = -G M200 / f(c) ln(1 + r/r_s) / r,  f(c) = ln(1+c) - c/(1+c).
+ *   Phi = -G M200 / f(c) ln(1 + r/r_s) / r,  f(c) = ln(1+c) - c/(1+c),
+ * and the optional logarithmic halo (Sec. 5, eq. log_halo)
+ *   Phi_D = v0^2/2 ln(r0^2 + R^2 + z^2/q^2),  R^2 = x^2 + y^2.
+ * With it the potential is axisymmetric (q != 1) and grows without bound;
+ * circular orbits, and so L_c(E), are taken in the equatorial plane.
  */
 #include <math.h>
 #include <stdint.h>
@@ -48,6 +52,7 @@
 typedef struct {
     double G, M_star, a, upsilon; /* Hernquist mass is M_star * upsilon */
     double M200, c, r_s;          /* NFW; M200 = 0 means none */
+    double v0, r0, q;             /* logarithmic halo (Sec. 5); v0 = 0 means none */
 } orc_potential;
 
 /* kin: 0 none, 1 v_z^2 moment, 2 Gauss-Hermite b_1..b_gh_nmax, 3 LOSVD;
@@ -111,13 +116,31 @@ static double nfw_fc(const orc_potential *p) {
     return log(1.0 + p->c) - p->c / (1.0 + p->c);
 }
 
-double orc_phi(const orc_potential *p, double r) {
+/* the spherical part (Hernquist + NFW) at radius r */
+static double phi_sph(const orc_potential *p, double r) {
     double phi = -p->G * p->M_star * p->upsilon / (r + p->a);
     if (p->M200 > 0.0) {
         double k = p->G * p->M200 / nfw_fc(p);
         phi += (r > 0.0) ? -k * log1p(r / p->r_s) / r : -k / p->r_s;
     }
     return phi;
+}
+
+static double halo_phi(const orc_potential *p, double R2, double z2) {
+    if (p->v0 == 0.0) return 0.0;
+    return 0.5 * p->v0 * p->v0 * log(p->r0 * p->r0 + R2 + z2 / (p->q * p->q));
+}
+
+/* Phi at (x, y, z) */
+double orc_phi3(const orc_potential *p, double x, double y, double z) {
+    double R2 = x * x + y * y, z2 = z * z;
+    return phi_sph(p, sqrt(R2 + z2)) + halo_phi(p, R2, z2);
+}
+
+/* Phi on the equatorial plane at radius r (the whole potential when it is
+ * spherical) */
+double orc_phi(const orc_potential *p, double r) {
+    return phi_sph(p, r) + halo_phi(p, r * r, 0.0);
 }
 
 double orc_mass(const orc_potential *p, double r) {
@@ -129,30 +152,46 @@ double orc_mass(const orc_potential *p, double r) {
     return m;
 }
 
-/* g = -grad Phi = -G M(<r) r_vec / r^3 ; zero at the centre by symmetry */
+/* g = -grad Phi: -G M(<r) r_vec / r^3 of the spherical part (zero at the
+ * centre by symmetry) and -v0^2 (x, y, z/q^2) / (r0^2 + R^2 + z^2/q^2) of the
+ * logarithmic halo */
 void orc_accel(const orc_potential *p, double x, double y, double z, double *g) {
     double r = sqrt(x * x + y * y + z * z);
-    if (r == 0.0) {
-        g[0] = g[1] = g[2] = 0.0;
-        return;
+    g[0] = g[1] = g[2] = 0.0;
+    if (r > 0.0) {
+        double s = -p->G * orc_mass(p, r) / (r * r * r);
+        g[0] = s * x;
+        g[1] = s * y;
+        g[2] = s * z;
     }
-    double s = -p->G * orc_mass(p, r) / (r * r * r);
-    g[0] = s * x;
-    g[1] = s * y;
-    g[2] = s * z;
+    if (p->v0 != 0.0) {
+        double q2 = p->q * p->q;
+        double D = p->r0 * p->r0 + x * x + y * y + z * z / q2;
+        double k = -p->v0 * p->v0 / D;
+        g[0] += k * x;
+        g[1] += k * y;
+        g[2] += k * z / q2;
+    }
 }
 
-/* energy of the circular orbit of radius r: Phi(r) + v_c^2/2, v_c^2 = G M / r */
+/* squared circular speed at radius r in the equatorial plane, r dPhi/dR */
+static double vc2(const orc_potential *p, double r) {
+    double v = r > 0.0 ? p->G * orc_mass(p, r) / r : 0.0;
+    if (p->v0 != 0.0) v += p->v0 * p->v0 * r * r / (p->r0 * p->r0 + r * r);
+    return v;
+}
+
+/* energy of the circular orbit of radius r: Phi(r) + v_c^2/2 */
 static double circ_energy(const orc_potential *p, double r) {
-    if (r == 0.0) return orc_phi(p, 0.0);
-    return orc_phi(p, r) + 0.5 * p->G * orc_mass(p, r) / r;
+    return orc_phi(p, r) + 0.5 * vc2(p, r);
 }
 
 /* L_c(E): angular momentum of the circular orbit of energy E, by bisection
- * of circ_energy(r) = E. 0 for E <= Phi(0), +inf for E >= 0. */
+ * of circ_energy(r) = E. 0 for E <= Phi(0); +inf for E >= 0 when the
+ * potential vanishes at infinity (no logarithmic halo). */
 double orc_lc(const orc_potential *p, double E) {
     if (E <= orc_phi(p, 0.0)) return 0.0;
-    if (E >= 0.0) return INFINITY;
+    if (p->v0 == 0.0 && E >= 0.0) return INFINITY;
     double lo = 0.0, hi = 1.0;
     while (circ_energy(p, hi) < E && hi < 1e300) hi *= 2.0;
     /* halve until the bracket is a few ulps wide (or stops shrinking) */
@@ -162,7 +201,7 @@ double orc_lc(const orc_potential *p, double E) {
         if (circ_energy(p, mid) < E) lo = mid; else hi = mid;
     }
     double rc = 0.5 * (lo + hi);
-    return sqrt(p->G * orc_mass(p, rc) * rc);
+    return rc * sqrt(vc2(p, rc));
 }
 
 /* -------------------------------------------------------- observables */
@@ -470,11 +509,11 @@ static int32_t cell_of(const orc_potential *p, const orc_params *P, double x, do
                        double vx, double vy, double vz, double *Eout, double *xout,
                        double *lzout) {
     double r = sqrt(x * x + y * y + z * z);
-    double E = 0.5 * (vx * vx + vy * vy + vz * vz) + orc_phi(p, r);
+    double E = 0.5 * (vx * vx + vy * vy + vz * vz) + orc_phi3(p, x, y, z);
     double lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
     double L = sqrt(lx * lx + ly * ly + lz * lz);
     double xc;
-    if (E >= 0.0) xc = 0.0;
+    if (p->v0 == 0.0 && E >= 0.0) xc = 0.0;
     else {
         double Lc = orc_lc(p, E);
         xc = (Lc > 0.0) ? L / Lc : 1.0;
@@ -627,7 +666,8 @@ static double gcv_dense(const double *P, const double *w0, int n, double lam, do
 
 /* smooth the n_E x n_x grid w (cell k n_x + l) in place; *lambda_out the
  * chosen lambda (0 if the grid has one cell) */
-int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
+/* lambda_in > 0: smooth with that lambda instead of searching for it */
+static int smooth_grid(const orc_params *par, double *w, double lambda_in, double *lambda_out) {
     const int nE = par->n_E, nx = par->n_x, n = nE * nx;
     if (lambda_out) *lambda_out = 0.0;
     if (n < 2) return 0;
@@ -670,7 +710,7 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
         Glo = fmin(Glo, 4.0 * s * s / (hx * hx));
     }
     const double plo = -2.0 * log10(Ghi) - 4.0, phi_ = -2.0 * log10(Glo) + 4.0;
-    const int K1 = (int)floor((phi_ - plo) / 0.25) + 1;
+    const int K1 = lambda_in > 0.0 ? 0 : (int)floor((phi_ - plo) / 0.25) + 1;
     int best = 0;
     double bg = INFINITY;
     for (int i = 0; i < K1; ++i) {
@@ -679,7 +719,7 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
     }
     double a = plo + 0.25 * (best > 0 ? best - 1 : 0);
     double b = plo + 0.25 * (best < K1 - 1 ? best + 1 : K1 - 1);
-    for (int stage = 0; stage < 2; ++stage) {
+    for (int stage = 0; stage < 2 && K1 > 0; ++stage) {
         int bi = 0;
         bg = INFINITY;
         for (int j = 0; j <= 64; ++j) {
@@ -692,7 +732,7 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
         a = na;
         b = nb;
     }
-    const double lam = pow(10.0, a);
+    const double lam = lambda_in > 0.0 ? lambda_in : pow(10.0, a);
     (void)gcv_dense(P, w0, n, lam, w, scratch);
     double mean = 0.0;
     for (int c = 0; c < n; ++c) mean += w0[c];
@@ -704,6 +744,15 @@ int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
     free(w0);
     free(scratch);
     return 0;
+}
+
+int orc_smooth_grid(const orc_params *par, double *w, double *lambda_out) {
+    return smooth_grid(par, w, 0.0, lambda_out);
+}
+
+/* the smoothed grid at a given lambda > 0 (tests of the lambda search) */
+int orc_smooth_grid_at(const orc_params *par, double *w, double lambda) {
+    return smooth_grid(par, w, lambda > 0.0 ? lambda : 1e-300, NULL);
 }
 
 /* new priors: uhat_i = prior of the (E, x) cell of particle i, the mean of u

@@ -30,7 +30,8 @@ def build(force: bool = True) -> str:
 
 
 class Potential(C.Structure):
-    _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")]
+    _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s",
+                                          "v0", "r0", "q")]
 
 
 class Layout(C.Structure):
@@ -73,6 +74,8 @@ def lib():
         L = C.CDLL(LIB)
         L.orc_phi.restype = C.c_double
         L.orc_phi.argtypes = [C.POINTER(Potential), C.c_double]
+        L.orc_phi3.restype = C.c_double
+        L.orc_phi3.argtypes = [C.POINTER(Potential), C.c_double, C.c_double, C.c_double]
         L.orc_mass.restype = C.c_double
         L.orc_mass.argtypes = [C.POINTER(Potential), C.c_double]
         L.orc_lc.restype = C.c_double
@@ -103,6 +106,8 @@ def lib():
         L.orc_refresh_priors.argtypes = [C.POINTER(Model)]
         L.orc_smooth_grid.restype = C.c_int
         L.orc_smooth_grid.argtypes = [C.POINTER(Params), _dp, _dp]
+        L.orc_smooth_grid_at.restype = C.c_int
+        L.orc_smooth_grid_at.argtypes = [C.POINTER(Params), _dp, C.c_double]
         L.orc_steps.argtypes = [C.POINTER(Model), C.c_int32, C.c_int32, _dp]
         L.orc_cell_mass.argtypes = [C.POINTER(Potential), C.POINTER(Params), C.c_int64] + [
             _dp] * 7 + [C.c_double, _dp]
@@ -122,7 +127,8 @@ def _f64(a):
 
 def potential(d) -> Potential:
     d = d.as_dict() if hasattr(d, "as_dict") else d
-    return Potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")})
+    return Potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")},
+                     v0=float(d.get("v0", 0.0)), r0=float(d.get("r0", 1.0)), q=float(d.get("q", 1.0)))
 
 
 def layout(d: dict) -> Layout:
@@ -158,12 +164,26 @@ def smooth_grid(par: dict, grid):
     return w, lam.value
 
 
+def smooth_grid_at(par: dict, grid, lam: float):
+    """The same smoothing with a given lambda (no search)."""
+    w = _f64(grid).copy().reshape(-1)
+    if w.size != int(par["n_E"]) * int(par["n_x"]):
+        raise ValueError("grid size does not match n_E * n_x")
+    if lib().orc_smooth_grid_at(C.byref(params(dict(par, smooth=1))), _p(w), float(lam)) != 0:
+        raise RuntimeError("orc_smooth_grid_at failed")
+    return w
+
+
 def J_of(lay: dict) -> int:
     return int(lib().orc_J(C.byref(layout(lay))))
 
 
 def phi(pot, r: float) -> float:
     return lib().orc_phi(C.byref(potential(pot)), float(r))
+
+
+def phi3(pot, x: float, y: float, z: float) -> float:
+    return lib().orc_phi3(C.byref(potential(pot)), float(x), float(y), float(z))
 
 
 def lc(pot, E: float) -> float:
