@@ -32,7 +32,11 @@
  *     the cell priors from z^{k+1}; they act from the next step on.
  *   Potential. Hernquist (eq. her) of mass M_star*upsilon and scale a, plus
  *     optionally NFW: Phi = -G M200/f(c) ln(1 + r/r_s)/r,
- *     f(c) = ln(1+c) - c/(1+c). M200 = 0 means no halo.
+ *     f(c) = ln(1+c) - c/(1+c) (M200 = 0: none), plus optionally the
+ *     logarithmic halo Phi_D = v0^2/2 ln(r0^2 + R^2 + z^2/q^2) (v0 = 0:
+ *     none), flattened along z for q != 1. With the logarithmic halo every
+ *     energy above Phi(0) is bound, and L_c(E) is the angular momentum of the
+ *     circular orbit of energy E in the equatorial plane.
  *   Observables, in this order (J = m2m_num_observables):
  *     the density part, one of
  *       M2M_DENS_BINS: n_r radial mass bins, K = 1 for r in [e_k, e_{k+1}),
@@ -57,11 +61,17 @@
  *       M2M_KIN_LOSVD: n_v entries, K = 1 for v_z in the k-th of n_v equal
  *                      bins of [v_min, v_max).
  *     A particle outside a range has no kernel there (selection function).
- *   Prior cells. k = floor((E - E_lo)/(E_hi - E_lo) n_E), l = floor(x n_x),
- *     both clamped into the grid; E = v^2/2 + Phi(r), x = |r x v| / L_c(E);
- *     x = 0 for E >= 0 and x = 1 for E <= Phi(0). Empty cells keep their
- *     previous prior (no particle reads them).
- *   Prior smoothing (smooth = 1, eq. smooth_grid). The grid w0 of cell means
+ *   Prior cells. k = floor((E - E_lo)/(E_hi - E_lo) n_E), or with
+ *     M2M_CELLS_EXP_E k = floor((exp E - exp E_lo)/(exp E_hi - exp E_lo) n_E),
+ *     l = floor(x n_x), both clamped into the grid; cell k n_x + l, and with
+ *     M2M_CELLS_LZ cell n_E n_x + k n_x + l for particles with L_z < 0
+ *     (C = 2 n_E n_x cells, at most 4096); E = v^2/2 + Phi(x, y, z),
+ *     x = |r x v| / L_c(E); x = 1 for E <= Phi(0), and without the
+ *     logarithmic halo x = 0 for E >= 0.
+ *     Empty cells keep their previous prior (no particle reads them).
+ *   Prior smoothing (smooth = 1, eq. smooth_grid). Each n_E x n_x grid (both
+ *     halves with M2M_CELLS_LZ) is smoothed alone, with the cell width along
+ *     energy measured in exp E with M2M_CELLS_EXP_E. The grid w0 of cell means
  *     (previous priors for empty cells) is replaced by the minimizer of
  *     |w - w0|^2 + lambda w^T P w, P the finite-difference thin-plate
  *     penalty (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 on the grid in its
@@ -124,11 +134,16 @@ typedef enum { M2M_F32 = 0, M2M_F64 = 1 } m2m_dtype;
 typedef enum { M2M_S_MPR = 0, M2M_S_GWR = 1 } m2m_entropy;
 typedef enum { M2M_KIN_NONE = 0, M2M_KIN_V2 = 1, M2M_KIN_GH = 2, M2M_KIN_LOSVD = 3 } m2m_kin;
 typedef enum { M2M_DENS_BINS = 0, M2M_DENS_ALM = 1 } m2m_dens;
+/* prior-grid options for rotating models (Sec. 5): a second n_E x n_x grid
+ * for particles with L_z < 0; energy bins linear in exp(E) */
+typedef enum { M2M_CELLS_LZ = 1, M2M_CELLS_EXP_E = 2 } m2m_cells;
 
-/* Fixed spherical potential (Sec. 3.1, eq. her; NFW halo optional). */
+/* Fixed potential (Sec. 3.1, eq. her; NFW halo optional; logarithmic halo
+ * of Sec. 5, eq. log_halo, optional). */
 typedef struct {
     double G, M_star, a, upsilon; /* Hernquist mass M_star*upsilon, scale a > 0 */
     double M200, c, r_s;          /* NFW: M200 = 0 for none; else c > 0, r_s > 0 */
+    double v0, r0, q;             /* logarithmic halo: v0 = 0 for none; else r0 > 0, q > 0 */
 } m2m_potential;
 
 /* Observable kernels K_j (Sec. 2.1; eqs. alm, lumghn). Radii are in length
@@ -159,7 +174,8 @@ typedef struct {
     double E_lo, E_hi;   /* energy range of the grid, E_lo < E_hi */
     int32_t smooth;      /* 1: smooth the prior grid at every refresh (Sec. 2.3.2, see
                             "Prior smoothing"); needs n_E, n_x <= 128; 0: cell means */
-    int32_t reserved;    /* must be 0 */
+    int32_t cells;       /* m2m_cells flags of the prior grid (Sec. 5); 0: n_E x n_x
+                            cells linear in E */
 } m2m_params;
 
 /* Number of observables J of a layout (0 if the layout is invalid). */

@@ -33,7 +33,8 @@ class M2MError(RuntimeError):
 
 
 class m2m_potential(C.Structure):
-    _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")]
+    _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s",
+                                          "v0", "r0", "q")]
 
 
 class m2m_obs_layout(C.Structure):
@@ -49,7 +50,7 @@ class m2m_params(C.Structure):
                 ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
                 ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
                 ("E_lo", C.c_double), ("E_hi", C.c_double), ("smooth", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("cells", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -124,7 +125,9 @@ def check(status: int, where: str, ctx=None):
 
 def potential(d) -> m2m_potential:
     d = d.as_dict() if hasattr(d, "as_dict") else d
-    return m2m_potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")})
+    return m2m_potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")},
+                         v0=float(d.get("v0", 0.0)), r0=float(d.get("r0", 1.0)),
+                         q=float(d.get("q", 1.0)))
 
 
 def obs_layout(d: dict) -> m2m_obs_layout:
@@ -142,7 +145,8 @@ def params(d: dict) -> m2m_params:
     ent = ENTROPY[d["entropy"]] if isinstance(d["entropy"], str) else int(d["entropy"])
     return m2m_params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
                       entropy=ent, n_E=d["n_E"], n_x=d["n_x"], prior_every=d["prior_every"],
-                      E_lo=d["E_lo"], E_hi=d["E_hi"], smooth=int(d.get("smooth", 0)), reserved=0)
+                      E_lo=d["E_lo"], E_hi=d["E_hi"], smooth=int(d.get("smooth", 0)),
+                      cells=int(d.get("cells", 0)))
 
 
 # ---- thin wrappers with the C names ------------------------------------------

@@ -108,8 +108,20 @@ int32_t num_obs(const m2m_obs_layout& L) {
 
 // log10(lambda) search range of the prior smoothing and the number of
 // points of its first stage (steps of 0.25)
+// cell width of the prior grid along energy, in the variable the energy bins
+// are linear in (E, or exp E)
+double energy_width(const m2m_params& P) {
+    if (P.cells & M2M_CELLS_EXP_E) return (std::exp(P.E_hi) - std::exp(P.E_lo)) / P.n_E;
+    return (P.E_hi - P.E_lo) / P.n_E;
+}
+
+// cells of the prior grid: n_E n_x, twice that with the L_z split
+int n_cells(const m2m_params& P) {
+    return P.n_E * P.n_x * ((P.cells & M2M_CELLS_LZ) ? 2 : 1);
+}
+
 void smooth_range(const m2m_params& P, double* plo, double* phi, int* k1) {
-    const double hE = (P.E_hi - P.E_lo) / P.n_E, hx = 1.0 / P.n_x;
+    const double hE = energy_width(P), hx = 1.0 / P.n_x;
     double ghi = 0.0, glo = INFINITY;
     if (P.n_E > 1) {
         ghi += 4.0 / (hE * hE);
@@ -138,7 +150,8 @@ std::string check_params(const m2m_params* P) {
     if (P->prior_every < 0) return "prior_every must be >= 0";
     if (!(is_fin(P->E_lo) && is_fin(P->E_hi) && P->E_hi > P->E_lo)) return "need E_lo < E_hi";
     if (P->smooth != 0 && P->smooth != 1) return "smooth must be 0 or 1";
-    if (P->reserved != 0) return "reserved must be 0";
+    if (P->cells & ~(M2M_CELLS_LZ | M2M_CELLS_EXP_E)) return "unknown cells flags";
+    if (n_cells(*P) > kMaxCells) return "need n_E*n_x <= 2048 with the L_z split";
     if (P->smooth && (P->n_E > kSmoothMaxSide || P->n_x > kSmoothMaxSide))
         return "prior smoothing needs n_E, n_x <= 128";
     if (P->smooth && P->n_E * P->n_x > 1) {
@@ -158,6 +171,9 @@ std::string check_potential(const m2m_potential* p) {
     if (!(is_fin(p->M200) && p->M200 >= 0)) return "M200 must be >= 0";
     if (p->M200 > 0 && !(is_fin(p->c) && p->c > 0 && is_fin(p->r_s) && p->r_s > 0))
         return "NFW needs c > 0 and r_s > 0";
+    if (!(is_fin(p->v0) && p->v0 >= 0)) return "v0 must be >= 0";
+    if (p->v0 > 0 && !(is_fin(p->r0) && p->r0 > 0 && is_fin(p->q) && p->q > 0))
+        return "the logarithmic halo needs r0 > 0 and q > 0";
     return "";
 }
 
@@ -165,6 +181,7 @@ std::string check_potential(const m2m_potential* p) {
 // (independent host evaluation, FP64: bin edges and the L_c(E) table)
 struct HostPot {
     double GMh, a, GM200, c, rs, fc;
+    double v02, r02;  // logarithmic halo v0^2, r0^2 (v02 = 0: none)
     explicit HostPot(const m2m_potential& p) {
         GMh = p.G * p.M_star * p.upsilon;
         a = p.a;
@@ -172,10 +189,14 @@ struct HostPot {
         c = p.c;
         rs = p.r_s;
         fc = p.M200 > 0 ? std::log1p(c) - c / (1.0 + c) : 1.0;
+        v02 = p.v0 > 0 ? p.v0 * p.v0 : 0.0;
+        r02 = p.v0 > 0 ? p.r0 * p.r0 : 1.0;
     }
+    // on the equatorial plane at radius r (the whole potential if spherical)
     double phi(double r) const {
         double v = -GMh / (r + a);
         if (GM200 > 0) v += (r > 0) ? -GM200 / fc * std::log1p(r / rs) / r : -GM200 / (fc * rs);
+        if (v02 > 0) v += 0.5 * v02 * std::log(r02 + r * r);
         return v;
     }
     double GM(double r) const {  // G M(<r)
@@ -186,15 +207,27 @@ struct HostPot {
         }
         return m;
     }
-    double ecirc(double r) const { return r > 0 ? phi(r) + 0.5 * GM(r) / r : phi(0.0); }
-    // r dE_c/dr with E_c = Phi + G M(<r) / (2 r): G M / (2 r) + (G M)' / 2,
-    // (G M)' = 2 G M a r / (r + a)^3 (Hernquist) + G M200 / f(c) r / (r_s^2 (1 + r/r_s)^2)
+    // squared circular speed in the equatorial plane, r dPhi/dr
+    double vc2(double r) const {
+        double v = r > 0 ? GM(r) / r : 0.0;
+        if (v02 > 0) v += v02 * r * r / (r02 + r * r);
+        return v;
+    }
+    double ecirc(double r) const { return phi(r) + 0.5 * vc2(r); }
+    // r dE_c/dr with E_c = Phi + v_c^2 / 2: for the spherical parts
+    // G M / (2 r) + (G M)' / 2, (G M)' = 2 G M a r / (r + a)^3 (Hernquist) +
+    // G M200 / f(c) r / (r_s^2 (1 + r/r_s)^2); for the logarithmic halo
+    // v0^2 r^2 (2 r0^2 + r^2) / (r0^2 + r^2)^2
     double decirc_dlnr(double r) const {
         const double ra = r + a;
         double d = 0.5 * GM(r) / r + GMh * a * r / (ra * ra * ra);
         if (GM200 > 0) {
             const double q1 = 1.0 + r / rs;
             d += 0.5 * GM200 / fc * r / (rs * rs * q1 * q1);
+        }
+        if (v02 > 0) {
+            const double s = r02 + r * r;
+            d += v02 * r * r * (2.0 * r02 + r * r) / (s * s);
         }
         return d;
     }
@@ -237,6 +270,7 @@ double lin_edge(double lo, double hi, int n, int k) {
 // ln zeta range of the L_c table: zeta = (E - Phi0) / (-E)
 constexpr double kLz0 = -16.1180956509583;  // ln 1e-7
 constexpr double kLz1 = 20.7232658369464;   // ln 1e9
+constexpr double kLzHalo1 = 3.68887945411394;  // ln 40: with the logarithmic halo, zeta <= 40
 
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
@@ -261,7 +295,7 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     WsLayout w{};
     const size_t sz = f64 ? 8 : 4;
     w.J = num_obs(L);
-    w.C = P.n_E * P.n_x;
+    w.C = n_cells(P);
     w.row_len = w.J + 2 * w.C;
     w.nbj = (w.J + kFinCols - 1) / kFinCols;
     w.ncj = (w.C + kFinCols - 1) / kFinCols;
@@ -655,6 +689,16 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.E_lo = c->par.E_lo;
     f.E_hi = c->par.E_hi;
     f.E_scale = c->par.n_E / (c->par.E_hi - c->par.E_lo);
+    f.cell_flags = c->par.cells;
+    f.cell_half = c->par.n_E * c->par.n_x;
+    if (c->par.cells & M2M_CELLS_EXP_E) {
+        f.cell_e0 = std::exp(c->par.E_lo);
+        f.cell_es = c->par.n_E / (std::exp(c->par.E_hi) - std::exp(c->par.E_lo));
+    } else {
+        f.cell_e0 = c->par.E_lo;
+        f.cell_es = f.E_scale;
+    }
+    f.sm_hE = energy_width(c->par);
     f.ucell = b + w.ucell;
     f.lctab = b + w.lctab;
     f.cidx = reinterpret_cast<uint16_t*>(b + w.cidx);
@@ -666,8 +710,14 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
         smooth_range(c->par, &f.sm_plo, &f.sm_phi, &k1);
         f.sm_k1 = k1;
     }
+    // L_c table over ln zeta: zeta = (E - Phi(0)) / (-E), or with the
+    // logarithmic halo (nothing escapes) zeta = (E - Phi(0)) / v0^2
+    const double lz1 = hp.v02 > 0 ? kLzHalo1 : kLz1;
     f.lz0 = kLz0;
-    f.ilz = (kLcTable - 1) / (kLz1 - kLz0);
+    f.ilz = (kLcTable - 1) / (lz1 - kLz0);
+    f.hv2 = hp.v02;
+    f.hr02 = hp.r02;
+    f.hiq2 = hp.v02 > 0 ? 1.0 / (c->pot.q * c->pot.q) : 1.0;
     const double dt = c->par.dt;
     f.dt = dt;
     f.w0 = c->par.mass / (double)n;
@@ -700,8 +750,8 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     const double phi0 = hp.phi(0.0);
     double guess = std::log(hp.a) + kLz0 * 0.5;  // small zeta: r_c ~ a sqrt(zeta)
     for (int k = 0; k < kLcTable; ++k) {
-        const double lz = kLz0 + (kLz1 - kLz0) * k / (kLcTable - 1);
-        const double E = phi0 / (1.0 + std::exp(lz));
+        const double lz = kLz0 + (lz1 - kLz0) * k / (kLcTable - 1);
+        const double E = hp.v02 > 0 ? phi0 + hp.v02 * std::exp(lz) : phi0 / (1.0 + std::exp(lz));
         lct[k] = hp.ln_rc(E, guess);
         guess = lct[k];
     }

@@ -1,0 +1,567 @@
+// Device helpers shared by the HIP kernels of the M2M step: global-memory
+// views, elementary functions, LDS tables, per-tile constants, binning,
+// spherical harmonics, the potential and the in-tile accumulation.
+// Included by m2m_kernels.hip and by the step-kernel units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "m2m_internal.h"
+
+namespace m2m {
+namespace {
+
+// ------------------------------------------------------------- memory ------
+// Device arrays reached through pointers stored in the fit table are seen
+// through the global address space: accesses compile to global (not flat)
+// loads and stores, which do not also wait on the LDS counter, so loads in
+// flight overlap the LDS work of the particle loop.
+template <typename T>
+using G = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ G<T> gmem(T* p) {
+    return (G<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ G<T> gmem(void* p) {
+    return (G<T>)static_cast<T*>(p);
+}
+
+// ------------------------------------------------------------- math --------
+// FP32: the hardware transcendental and reciprocal instructions (about 1 ulp;
+// arguments here are never denormal). FP64: the correctly rounded library.
+template <typename T>
+struct Mth;
+
+template <>
+struct Mth<float> {
+    __device__ static float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+    __device__ static float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+    __device__ static float log2_(float x) { return __builtin_amdgcn_logf(x); }
+    __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static float log1p_(float x) { return log1pf(x); }
+    __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+    static constexpr float nfw_series_max = 0.1f;
+};
+
+template <>
+struct Mth<double> {
+    __device__ static double exp_(double x) { return exp(x); }
+    __device__ static double log_(double x) { return log(x); }
+    __device__ static double log2_(double x) { return log2(x); }
+    __device__ static double sqrt_(double x) { return sqrt(x); }
+    __device__ static double log1p_(double x) { return log1p(x); }
+    __device__ static double rcp_(double x) { return 1.0 / x; }
+    static constexpr double nfw_series_max = 1e-3;
+};
+
+// normalized Hermite recurrence coefficients: H_{n+1} = a_n nu H_n - b_n H_{n-1}
+// with a_n = sqrt(2/(n+1)), b_n = sqrt(n/(n+1)), n = 1..7
+__constant__ double kGhA[kMaxGH] = {0.0,
+                                   1.0,                   // sqrt(2/2)
+                                   0.81649658092772603,   // sqrt(2/3)
+                                   0.70710678118654752,   // sqrt(2/4)
+                                   0.63245553203367587,   // sqrt(2/5)
+                                   0.57735026918962576,   // sqrt(2/6)
+                                   0.53452248382484880,   // sqrt(2/7)
+                                   0.5};                  // sqrt(2/8)
+__constant__ double kGhB[kMaxGH] = {0.0,
+                                   0.70710678118654752,   // sqrt(1/2)
+                                   0.81649658092772603,   // sqrt(2/3)
+                                   0.86602540378443865,   // sqrt(3/4)
+                                   0.89442719099991588,   // sqrt(4/5)
+                                   0.91287092917527690,   // sqrt(5/6)
+                                   0.92582009977255146,   // sqrt(6/7)
+                                   0.93541434669348535};  // sqrt(7/8)
+
+// ------------------------------------------------------------- LDS ---------
+// In-tile bins: FP64 sums (A = double), or FP32 sums with an FP32 array of
+// their compensation (A = float). They are kept in kpriv private copies,
+// interleaved (copy g of bin j at j * kpriv + g); lane l adds into copy
+// l mod kpriv. Then the prior-cell sums of the tile (FP64 weight sums and
+// integer counts), then the tables. The 8-byte arrays come first so that
+// they are aligned.
+template <typename T, typename A>
+struct Tabs {
+    A *sum, *comp;
+    double* csum;
+    uint32_t* ccnt;
+    T *rp, *re2, *Re2, *ve, *Vp, *isp, *rm;
+};
+
+template <typename T, typename A>
+__device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, int n_r, int n_R,
+                                            int n_v, int C) {
+    Tabs<T, A> t;
+    A* q = reinterpret_cast<A*>(raw);
+    t.sum = q;
+    q += J * kp;
+    t.comp = q;
+    if (sizeof(A) == 4) q += J * kp;
+    t.csum = reinterpret_cast<double*>(q);
+    t.ccnt = reinterpret_cast<uint32_t*>(t.csum + C);
+    T* p = reinterpret_cast<T*>(t.ccnt + ((C + 1) & ~1));  // 8-byte aligned
+    t.rp = p;
+    p += J;
+    t.re2 = p;
+    p += n_r + 1;
+    t.Re2 = p;
+    p += n_R + 1;
+    t.ve = p;
+    p += n_v + 1;
+    t.Vp = p;
+    p += n_R;
+    t.isp = p;
+    p += n_R;
+    t.rm = p;  // a_lm mesh radii (n_r + 1)
+    return t;
+}
+
+// ------------------------------------------------------------- per tile ----
+// What the particle loop reads of its fit, loaded once per tile (uniform
+// values) instead of from the fit table inside the loop.
+template <typename T>
+struct Hot {
+    int n_r, n_R, nk, gh_nmax, n_v, J, C, kp, n_E, n_x;
+    int jk0, l_max, nlm;  // first kinematic observable; a_lm degree and (l_max + 1)^2
+    T lr0, lrs, lR0, lRs, vmin, vidv;
+    T r2lo, r2hi, R2lo, R2hi, vlo, vhi;  // range ends: squared radii, velocities
+    T GMh, a, GMn, rs, irs, phi0;
+    T dt, hdt, w0, foc_mu, foc_cs;
+    T E_lo, E_scale, lz0, ilz;  // E_lo, E_scale: offset and scale of the cells' energy coordinate
+    int cell_flags, cell_half;
+    int halo;                // logarithmic halo present
+    T hv2, hr02, hiq2, iv2;  // its v0^2, r0^2, 1/q^2 and 1/v0^2
+    G<const T> lctab;
+};
+
+template <typename T>
+__device__ __forceinline__ Hot<T> hot_of(const FitDev& fd) {
+    Hot<T> h;
+    h.n_r = fd.n_r;
+    h.n_R = fd.n_R;
+    h.nk = fd.nk;
+    h.gh_nmax = fd.gh_nmax;
+    h.n_v = fd.n_v;
+    h.J = fd.J;
+    h.C = fd.C;
+    h.kp = fd.kpriv;
+    h.n_E = fd.n_E;
+    h.n_x = fd.n_x;
+    h.jk0 = fd.jk0;
+    h.l_max = fd.l_max;
+    h.nlm = (fd.l_max + 1) * (fd.l_max + 1);
+    h.lr0 = T(fd.lr0);
+    h.lrs = T(fd.lrs);
+    h.lR0 = T(fd.lR0);
+    h.lRs = T(fd.lRs);
+    h.vmin = T(fd.vmin);
+    h.vidv = T(fd.vidv);
+    const G<const T> re2 = gmem<const T>(fd.redge2);
+    const G<const T> Re2 = gmem<const T>(fd.Redge2);
+    const G<const T> ve = gmem<const T>(fd.vedge);
+    h.r2lo = re2[0];
+    h.r2hi = re2[fd.n_r];
+    h.R2lo = Re2[0];
+    h.R2hi = Re2[fd.n_R];
+    h.vlo = ve[0];
+    h.vhi = ve[fd.n_v];
+    h.GMh = T(fd.GMh);
+    h.a = T(fd.a);
+    h.GMn = T(fd.GMn);
+    h.rs = T(fd.rs);
+    h.irs = T(1.0 / fd.rs);
+    h.phi0 = T(fd.phi0);
+    h.dt = T(fd.dt);
+    h.hdt = T(0.5 * fd.dt);
+    h.w0 = T(fd.w0);
+    h.foc_mu = T(fd.foc_mu);
+    h.foc_cs = T(fd.foc_cs);
+    h.E_lo = T(fd.cell_e0);
+    h.E_scale = T(fd.cell_es);
+    h.cell_flags = fd.cell_flags;
+    h.cell_half = fd.cell_half;
+    h.halo = fd.hv2 > 0.0;
+    h.hv2 = T(fd.hv2);
+    h.hr02 = T(fd.hr02);
+    h.hiq2 = T(fd.hiq2);
+    h.iv2 = T(fd.hv2 > 0.0 ? 1.0 / fd.hv2 : 0.0);
+    h.lz0 = T(fd.lz0);
+    h.ilz = T(fd.ilz);
+    h.lctab = gmem<const T>(fd.lctab);
+    return h;
+}
+
+// ------------------------------------------------------------- binning -----
+// k with e[k] <= v < e[k+1] for ascending e[0..n], decided by comparison with
+// the stored edges (v is known to lie in [e[0], e[n])).
+template <typename T>
+__device__ __forceinline__ int refine_bin(T v, const T* e, int n, T g) {
+    g = fmin(fmax(g, T(0)), T(n - 1));
+    int k = (int)g;
+    if (v < e[k]) {
+        --k;
+        if (k > 0 && v < e[k]) --k;
+    } else if (v >= e[k + 1]) {
+        ++k;
+        if (k < n - 1 && v >= e[k + 1]) ++k;
+    }
+    if (!(v >= e[k] && v < e[k + 1])) {  // the guess was off by more than 2
+        int lo = 0, hi = n;               // invariant e[lo] <= v < e[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (v >= e[mid]) lo = mid; else hi = mid;
+        }
+        k = lo;
+    }
+    return k;
+}
+
+// Bin of v, or -1 outside [lo, hi). The arithmetic position g of v in bin
+// units is accurate to a few 1e-6, so a point more than 1e-4 of a bin from
+// both edges is in bin floor(g); only points closer to an edge are compared
+// with the stored edges.
+template <typename T>
+__device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
+    if (!(v >= lo) || !(v < hi)) return -1;
+    const T gc = fmin(fmax(g, T(0)), T(n));
+    const int k = min((int)gc, n - 1);
+    const T fr = g - T(k);
+    if (fr > T(1e-4) && fr < T(1) - T(1e-4)) return k;
+    return refine_bin<T>(v, e, n, g);
+}
+
+// kinds of kinematic observables, fixed at compile time in k_step; the bit
+// kKinAlm selects the spherical-harmonic density observables instead of
+// radial bins
+enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4, kKinAlm = 8 };
+
+template <int KIN>
+struct KinSlots {
+    static constexpr int n = ((KIN & 7) == kKinGH4) ? 4 : ((KIN & 7) == kKinGHN) ? kMaxGH : 1;
+};
+
+// Non-zero kernels K_j of one phase-space point: the radial bin jr (K = 1),
+// or with a_lm the mesh interval jr with the cloud-in-cell weight g of its
+// inner radius and the direction (cos, sin of the polar angle; cos, sin of
+// the azimuth); then kn kinematic entries j = jk + m with values k[m].
+template <typename T, int KIN>
+struct Kern {
+    int jr, jk, kn;
+    T k[KinSlots<KIN>::n];
+    T g, ct, st, cp, sp;
+};
+
+// ------------------------------------------------------- spherical harmonics
+// Real orthonormal harmonics Y_lm (Condon-Shortley phase) through the
+// normalized associated Legendre functions Pn_l^m = N_lm P_l^m,
+// N_lm = sqrt((2l + 1)/(4 pi) (l - m)!/(l + m)!):
+//   Pn_0^0 = 1/sqrt(4 pi),  Pn_m^m = -sqrt((2m + 1)/(2m)) sin(t) Pn_{m-1}^{m-1},
+//   Pn_{m+1}^m = sqrt(2m + 3) cos(t) Pn_m^m,
+//   Pn_l^m = a_lm (cos(t) Pn_{l-1}^m - b_lm Pn_{l-2}^m),
+//   a_lm = sqrt((4l^2 - 1)/(l^2 - m^2)),  b_lm = sqrt(((l-1)^2 - m^2)/(4(l-1)^2 - 1));
+// Y_l0 = Pn_l^0, Y_l,m = sqrt2 Pn_l^m cos(m phi), Y_l,-m = sqrt2 Pn_l^m sin(m phi).
+constexpr double csqrt(double x) {  // compile-time square root (Newton)
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 64; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+
+struct YlmCoef {
+    double mm[kMaxLM + 1], m1[kMaxLM + 1], a[kMaxLM + 1][kMaxLM + 1], b[kMaxLM + 1][kMaxLM + 1];
+};
+
+constexpr YlmCoef ylm_coef() {
+    YlmCoef c{};
+    for (int m = 0; m <= kMaxLM; ++m) {
+        c.mm[m] = m > 0 ? csqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.0;
+        c.m1[m] = csqrt(2.0 * m + 3.0);
+        for (int l = m + 2; l <= kMaxLM; ++l) {
+            const double ll = double(l) * l, mm2 = double(m) * m, l1 = double(l - 1) * (l - 1);
+            c.a[l][m] = csqrt((4.0 * ll - 1.0) / (ll - mm2));
+            c.b[l][m] = csqrt((l1 - mm2) / (4.0 * l1 - 1.0));
+        }
+    }
+    return c;
+}
+
+__constant__ YlmCoef kYlm = ylm_coef();
+
+// f(l^2 + l + m, Y_lm) for every 0 <= l <= lmax, -l <= m <= l, at the
+// direction (ct, st) = cos, sin of the polar angle and (cp, sp) of the azimuth
+template <typename T, typename F>
+__device__ __forceinline__ void ylm_walk(int lmax, T ct, T st, T cp, T sp, F&& f) {
+    T pmm = T(0.282094791773878143);  // 1/sqrt(4 pi)
+    T cm = T(1), sm = T(0);           // cos(m phi), sin(m phi)
+    for (int m = 0; m <= lmax; ++m) {
+        if (m > 0) {
+            pmm = -T(kYlm.mm[m]) * st * pmm;
+            const T c = cm * cp - sm * sp;
+            sm = sm * cp + cm * sp;
+            cm = c;
+        }
+        const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
+        auto emit = [&](int l, T pn) {
+            if (m == 0) {
+                f(l * l + l, pn);
+            } else {
+                f(l * l + l + m, pn * c2);
+                f(l * l + l - m, pn * s2);
+            }
+        };
+        emit(m, pmm);
+        if (m < lmax) {
+            T p2 = pmm, p1 = T(kYlm.m1[m]) * ct * pmm;
+            emit(m + 1, p1);
+            for (int l = m + 2; l <= lmax; ++l) {
+                const T p = T(kYlm.a[l][m]) * (ct * p1 - T(kYlm.b[l][m]) * p2);
+                emit(l, p);
+                p2 = p1;
+                p1 = p;
+            }
+        }
+    }
+}
+
+template <typename T, typename A, int KIN>
+__device__ __forceinline__ Kern<T, KIN> kernels(const Hot<T>& h, const Tabs<T, A>& tb, T x, T y,
+                                                T z, T vz) {
+    constexpr int KK = KIN & 7;
+    Kern<T, KIN> o;
+    const T R2 = x * x + y * y;
+    const T r2 = R2 + z * z;
+    o.jr = bin_of<T>(r2, tb.re2, h.n_r, (Mth<T>::log2_(r2) - h.lr0) * h.lrs, h.r2lo, h.r2hi);
+    if ((KIN & kKinAlm) && o.jr >= 0) {
+        // cloud-in-cell weight of the inner mesh radius (linear in r) and the
+        // direction; r >= r_min > 0 here
+        const T r = Mth<T>::sqrt_(r2);
+        const T r0 = tb.rm[o.jr], r1 = tb.rm[o.jr + 1];
+        o.g = (r1 - r) / (r1 - r0);
+        const T ir = Mth<T>::rcp_(r);
+        o.ct = z * ir;
+        const T R = Mth<T>::sqrt_(R2);
+        o.st = R * ir;
+        const T iR = R > T(0) ? Mth<T>::rcp_(R) : T(0);
+        o.cp = R > T(0) ? x * iR : T(1);
+        o.sp = y * iR;
+    }
+    o.jk = -1;
+    o.kn = 0;
+    if (KK == kKinNone) return o;
+    const int p = bin_of<T>(R2, tb.Re2, h.n_R, (Mth<T>::log2_(R2) - h.lR0) * h.lRs, h.R2lo, h.R2hi);
+    if (p < 0) return o;
+    const int base = h.jk0 + p * h.nk;
+    if (KK == kKinV2) {
+        o.jk = base;
+        o.kn = 1;
+        o.k[0] = vz * vz;
+    } else if (KK == kKinGH4 || KK == kKinGHN) {
+        // 2 sqrt(pi) u_n(nu) = sqrt2 e^{-nu^2/2} H_n(nu) / sqrt(2^n n!) by the
+        // normalized three-term recurrence
+        constexpr int NS = KinSlots<KIN>::n;
+        const T nu = (vz - tb.Vp[p]) * tb.isp[p];
+        const T g = T(1.41421356237309505) * Mth<T>::exp_(T(-0.5) * nu * nu);
+        T hm = T(1);
+        T hc = T(1.41421356237309505) * nu;
+        o.jk = base;
+        o.kn = (KK == kKinGH4) ? 4 : h.gh_nmax;
+        o.k[0] = g * hc;
+#pragma unroll
+        for (int n = 1; n < NS; ++n) {
+            if (KK == kKinGH4 || n < h.gh_nmax) {
+                const T hn = T(kGhA[n]) * nu * hc - T(kGhB[n]) * hm;
+                hm = hc;
+                hc = hn;
+                o.k[n] = g * hc;
+            }
+        }
+    } else {
+        const int b = bin_of<T>(vz, tb.ve, h.n_v, (vz - h.vmin) * h.vidv, h.vlo, h.vhi);
+        if (b >= 0) {
+            o.jk = base + b;
+            o.kn = 1;
+            o.k[0] = T(1);
+        }
+    }
+    return o;
+}
+
+// ------------------------------------------------------------- potential ---
+template <typename T>
+__device__ __forceinline__ T phi_of(const Hot<T>& h, T r) {
+    T p = -h.GMh / (r + h.a);
+    if (h.GMn > T(0)) {
+        const T q = r * h.irs;
+        const T l = (q > T(1e-4)) ? Mth<T>::log1p_(q) / q : T(1) - q * (T(0.5) - q * T(1.0 / 3.0));
+        p -= h.GMn * h.irs * l;
+    }
+    return p;
+}
+
+// the logarithmic halo v0^2/2 ln(r0^2 + R^2 + z^2/q^2) at R^2, z^2
+template <typename T>
+__device__ __forceinline__ T halo_phi(const Hot<T>& h, T R2, T z2) {
+    return T(0.5) * h.hv2 * Mth<T>::log_(h.hr02 + R2 + z2 * h.hiq2);
+}
+
+// s(r) with g = -s(r) * (x, y, z) for the spherical parts: G M(<r) / r^3
+template <typename T>
+__device__ __forceinline__ T accel_of(const Hot<T>& h, T r) {
+    if (!(r > T(0))) return T(0);
+    const T ra = r + h.a;
+    T s = h.GMh * Mth<T>::rcp_(r * ra * ra);
+    if (h.GMn > T(0)) {
+        const T q = r * h.irs;
+        T m;
+        if (q < T(Mth<T>::nfw_series_max)) {
+            // ln(1+q) - q/(1+q) = sum_{k>=2} (-1)^k (k-1) q^k / k
+            m = q * q *
+                (T(0.5) -
+                 q * (T(2.0 / 3.0) -
+                      q * (T(0.75) - q * (T(0.8) - q * (T(5.0 / 6.0) - q * (T(6.0 / 7.0) - q * T(0.875)))))));
+        } else {
+            m = Mth<T>::log1p_(q) - q * Mth<T>::rcp_(T(1) + q);
+        }
+        s += h.GMn * m * Mth<T>::rcp_(r * r * r);
+    }
+    return s;
+}
+
+// Prior cell (k, l) -> k n_x + l of one phase-space point.
+template <typename T>
+__device__ __forceinline__ int cell_of(const Hot<T>& h, T x, T y, T z, T vx, T vy, T vz) {
+    const T R2 = x * x + y * y;
+    const T r = Mth<T>::sqrt_(R2 + z * z);
+    T E = T(0.5) * (vx * vx + vy * vy + vz * vz) + phi_of<T>(h, r);
+    if (h.halo) E += halo_phi<T>(h, R2, z * z);
+    const T lx = y * vz - z * vy, ly = z * vx - x * vz, lz = x * vy - y * vx;
+    const T L = Mth<T>::sqrt_(lx * lx + ly * ly + lz * lz);
+    T xc;
+    if (!h.halo && !(E < T(0))) {
+        xc = T(0);  // unbound: no circular orbit
+    } else if (!(E > h.phi0)) {
+        xc = T(1);
+    } else {
+        // radius of the circular orbit of energy E (in the equatorial plane)
+        // from the table of ln r_c(ln zeta), zeta = (E - Phi(0)) / (-E), or
+        // (E - Phi(0)) / v0^2 with the logarithmic halo; in FP64 refined by
+        // Newton steps on E_c(r) = Phi(r) + r Phi'(r) / 2 = E
+        const T zeta = h.halo ? (E - h.phi0) * h.iv2 : (E - h.phi0) / (-E);
+        const T t = (Mth<T>::log_(zeta) - h.lz0) * h.ilz;
+        const T tc = fmin(fmax(t, T(0)), T(kLcTable - 2));
+        const int i = (int)tc;
+        const T f = t - T(i);  // extrapolates linearly beyond the table
+        T rc = Mth<T>::exp_(h.lctab[i] + f * (h.lctab[i + 1] - h.lctab[i]));
+        if (sizeof(T) == 8) {
+            for (int it = 0; it < 2; ++it) {
+                T s = accel_of<T>(h, rc);
+                T Ec = phi_of<T>(h, rc);
+                const T ra = rc + h.a;
+                T dEc = T(0.5) * s * rc + h.GMh * h.a / (ra * ra * ra);
+                if (h.GMn > T(0)) {
+                    const T q1 = T(1) + rc * h.irs;
+                    dEc += T(0.5) * h.GMn * h.irs * h.irs / (q1 * q1);
+                }
+                if (h.halo) {
+                    const T d = h.hr02 + rc * rc;
+                    s += h.hv2 / d;
+                    Ec += halo_phi<T>(h, rc * rc, T(0));
+                    dEc += h.hv2 * rc * (T(2) * h.hr02 + rc * rc) / (d * d);
+                }
+                Ec += T(0.5) * s * rc * rc;
+                const T rn = rc - (Ec - E) / dEc;
+                rc = (rn > T(0)) ? rn : T(0.5) * rc;
+            }
+        }
+        T sc = accel_of<T>(h, rc);
+        if (h.halo) sc += h.hv2 * Mth<T>::rcp_(h.hr02 + rc * rc);
+        const T Lc = rc * rc * Mth<T>::sqrt_(sc);  // r v_c, v_c^2 = r dPhi/dr
+        xc = (Lc > T(0)) ? L / Lc : T(1);
+    }
+    // energy coordinate in bin units, linear in E or in exp(E); below E_lo
+    // (or NaN) it clamps into bin 0
+    const T ec = (h.cell_flags & 2) ? Mth<T>::exp_(E) : E;
+    const T te = fmin((ec - h.E_lo) * h.E_scale, T(h.n_E));
+    int k = (te >= T(0)) ? (int)te : 0;
+    k = min(k, h.n_E - 1);
+    const T tx = fmin(xc * T(h.n_x), T(h.n_x));
+    int l = (tx >= T(0)) ? (int)tx : 0;
+    l = min(l, h.n_x - 1);
+    return k * h.n_x + l + (((h.cell_flags & 1) && lz < T(0)) ? h.cell_half : 0);
+}
+
+// ------------------------------------------------------------- accumulate --
+// Add the kernels of one particle (weight w) into its private bin copies.
+// FP64 bins: one FP64 LDS atomic add per kernel (gfx950 runs these about six
+// times faster than FP32 LDS atomic adds). FP32 bins: every add returns the
+// value it replaced, and the exact rounding error of the add (TwoSum) goes
+// into the compensation array; all adds of the particle are issued before
+// their errors are formed. The error terms are exact only if every value is
+// rounded where the source rounds it: FP contraction is off in this part (a
+// product fused into the error's add would differ from the value added).
+__device__ __forceinline__ float two_sum_err(float old, float v) {
+#pragma clang fp contract(off)
+    const float t = old + v;  // the value the add stored
+    const float bp = t - old;
+    return (old - (t - bp)) + (v - bp);
+}
+
+// The a_lm part of a deposit of weight w: w g Y_lm at the inner mesh radius
+// of the interval, w (1 - g) Y_lm at the outer one; add(j, value).
+template <typename T, int KIN, typename Add>
+__device__ __forceinline__ void deposit_alm(const Hot<T>& h, const Kern<T, KIN>& kk, T w,
+                                            Add&& add) {
+    const int b0 = kk.jr * h.nlm, b1 = b0 + h.nlm;
+    const T wa = w * kk.g, wb = w * (T(1) - kk.g);
+    ylm_walk(h.l_max, kk.ct, kk.st, kk.cp, kk.sp, [&](int lm, T Y) {
+        add(b0 + lm, wa * Y);
+        add(b1 + lm, wb * Y);
+    });
+}
+
+template <typename T, int KIN>
+__device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, float>& tb,
+                                        const Kern<T, KIN>& kk, T u, int priv) {
+#pragma clang fp contract(off)
+    constexpr int NS = KinSlots<KIN>::n;
+    const int kp = h.kp;
+    const float wf = (float)(u * h.w0);
+    float o_r = 0.f;
+    float v[NS], o_k[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) v[m] = (float)(wf * kk.k[m]);
+    if ((KIN & kKinAlm) && kk.jr >= 0)
+        deposit_alm(h, kk, T(wf), [&](int j, T val) {
+            const float vf = (float)val;
+            const float o = atomicAdd(&tb.sum[j * kp + priv], vf);
+            atomicAdd(&tb.comp[j * kp + priv], two_sum_err(o, vf));
+        });
+    if (!(KIN & kKinAlm) && kk.jr >= 0) o_r = atomicAdd(&tb.sum[kk.jr * kp + priv], wf);
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+        if (m < kk.kn) o_k[m] = atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], v[m]);
+    if (!(KIN & kKinAlm) && kk.jr >= 0) atomicAdd(&tb.comp[kk.jr * kp + priv], two_sum_err(o_r, wf));
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+        if (m < kk.kn) atomicAdd(&tb.comp[(kk.jk + m) * kp + priv], two_sum_err(o_k[m], v[m]));
+}
+
+template <typename T, int KIN>
+__device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& tb,
+                                        const Kern<T, KIN>& kk, T u, int priv) {
+    constexpr int NS = KinSlots<KIN>::n;
+    const int kp = h.kp;
+    const T w = u * h.w0;
+    if ((KIN & kKinAlm) && kk.jr >= 0)
+        deposit_alm(h, kk, w, [&](int j, T val) { atomicAdd(&tb.sum[j * kp + priv], (double)val); });
+    if (!(KIN & kKinAlm) && kk.jr >= 0) atomicAdd(&tb.sum[kk.jr * kp + priv], (double)w);
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+        if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
+}
+
+
+}  // namespace
+}  // namespace m2m

@@ -78,15 +78,21 @@ struct FitDev {
     // priors
     int32_t n_E, n_x, prior_every, pad1;
     double E_lo, E_hi, E_scale;  // E_scale = n_E / (E_hi - E_lo)
+    // energy coordinate of the cells: (e - cell_e0) * cell_es with e = E, or
+    // e = exp(E) (cell_flags bit 1); bit 0: particles with L_z < 0 take cell
+    // cell_half + k n_x + l
+    double cell_e0, cell_es;
+    int32_t cell_flags, cell_half;
     void *ucell, *lctab;         // C values; kLcTable values of ln r_c(ln zeta)
     uint16_t *cidx;              // n values: cell of each particle at the last refresh
     // prior grid in FP64: cell data of the last refresh (means, or the
     // previous prior of empty cells) and the current priors
     double *cdata, *gprior;
-    // smoothing: the log10(lambda) search range
-    double sm_plo, sm_phi;
+    // smoothing: the log10(lambda) search range, the cell width along energy
+    double sm_plo, sm_phi, sm_hE;
     int32_t sm_k1, pad3;         // points of the first search stage
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
+    double hv2, hr02, hiq2;      // logarithmic halo: v0^2 (0: none), r0^2, 1/q^2
     // step constants
     double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
     double *chi2_hist;
@@ -131,6 +137,14 @@ int kin_class(int kin, int gh_nmax, int dens);
 // the column jobs of the fits of the table (n_fits of them)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
                            int n_jobs, int32_t mode, hipStream_t s);
+// the step kernel of one particle-state / in-tile-sum type pair (one == nullptr:
+// over the fit and tile tables, else over that one fit); m2m_step_*.hip
+hipError_t launch_step_f64(int block, int kin, const FitDev* fits, const Tile* tiles,
+                           const FitDev* one, int n_tiles, size_t lds, int32_t mode, hipStream_t s);
+hipError_t launch_step_f32d(int block, int kin, const FitDev* fits, const Tile* tiles,
+                            const FitDev* one, int n_tiles, size_t lds, int32_t mode, hipStream_t s);
+hipError_t launch_step_f32f(int block, int kin, const FitDev* fits, const Tile* tiles,
+                            const FitDev* one, int n_tiles, size_t lds, int32_t mode, hipStream_t s);
 // one fit, fd (a host copy of its description) passed by value: the step
 // over n_tiles tiles as tile_of splits it; the finalize jobs of that fit
 // (bin jobs, then cell jobs) over n_rows tile rows

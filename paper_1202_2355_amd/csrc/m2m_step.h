@@ -1,0 +1,248 @@
+// The fused step kernel (k_step for batches, k_step1 for one fit) and its
+// compile-time dispatch; each step unit (m2m_step_*.hip) instantiates it for
+// one particle-state / accumulator type pair.
+#pragma once
+
+#include "m2m_device.h"
+
+namespace m2m {
+namespace {
+
+// ------------------------------------------------------------- step --------
+// A particle store that writes through L2 (agent-scope relaxed atomic store):
+// the value reaches the memory-side cache at once instead of staying dirty in
+// L2 until the write-back at the end of the kernel.
+template <typename T>
+__device__ __forceinline__ void put_wt(G<T> p, T v) {
+    __hip_atomic_store((T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, typename A, int BLOCK, int KIN>
+__device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int32_t mode) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const bool step = (mode & kModeStep) != 0;
+
+    // particle arrays from the tile start (32-bit offsets within the tile);
+    // the first particle of every lane is requested before anything else so
+    // that its latency overlaps the set-up below
+    const G<T> __restrict__ X = gmem<T>(fd.x) + tl.begin;
+    const G<T> __restrict__ Y = gmem<T>(fd.y) + tl.begin;
+    const G<T> __restrict__ Z = gmem<T>(fd.z) + tl.begin;
+    const G<T> __restrict__ VX = gmem<T>(fd.vx) + tl.begin;
+    const G<T> __restrict__ VY = gmem<T>(fd.vy) + tl.begin;
+    const G<T> __restrict__ VZ = gmem<T>(fd.vz) + tl.begin;
+    const G<T> __restrict__ U = gmem<T>(fd.u) + tl.begin;
+    const G<T> __restrict__ UH = gmem<T>(fd.uh) + tl.begin;
+    const G<uint16_t> __restrict__ CI = gmem(fd.cidx) + tl.begin;
+    const int len = (int)(tl.end - tl.begin);
+    int i = threadIdx.x;
+    T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
+    if (i < len) {
+        nx = X[i];
+        ny = Y[i];
+        nz = Z[i];
+        nvx = VX[i];
+        nvy = VY[i];
+        nvz = VZ[i];
+        nu = U[i];
+        if (step) nh = UH[i];
+    }
+
+    const G<const FitState> st = gmem<const FitState>(fd.st);
+    if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
+    const bool cells_only = (mode & kModeCells) != 0;
+    const bool correct = step && st->correct != 0;
+    const bool refresh = cells_only || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
+                                        ((st->kstep + 1) % fd.prior_every) == 0);
+    const bool assign = step && st->assign_pending != 0;
+    const bool deposit_on = !cells_only;
+    const bool push = step;
+    const bool wt = (mode & kModeWriteThrough) != 0;
+    const Hot<T> h = hot_of<T>(fd);
+    const int J = h.J, C = h.C, kp = h.kp;
+
+    Tabs<T, A> tb = carve<T, A>(lds_raw, J, kp, h.n_r, h.n_R, h.n_v, C);
+    const int priv = threadIdx.x & (kp - 1);
+    {
+        const G<const T> rp = gmem<const T>(fd.rp);
+        for (int j = threadIdx.x; j < J; j += BLOCK) tb.rp[j] = rp[j];
+        for (int j = threadIdx.x; j < J * kp; j += BLOCK) {
+            tb.sum[j] = A(0);
+            if (sizeof(A) == 4) tb.comp[j] = A(0);
+        }
+        if (refresh)
+            for (int j = threadIdx.x; j < C; j += BLOCK) {
+                tb.csum[j] = 0.0;
+                tb.ccnt[j] = 0u;
+            }
+        const G<const T> re2 = gmem<const T>(fd.redge2);
+        for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.re2[j] = re2[j];
+        if (KIN & kKinAlm) {
+            const G<const T> rm = gmem<const T>(fd.rmesh);
+            for (int j = threadIdx.x; j <= h.n_r; j += BLOCK) tb.rm[j] = rm[j];
+        }
+        const G<const T> Re2 = gmem<const T>(fd.Redge2);
+        for (int j = threadIdx.x; j <= h.n_R; j += BLOCK) tb.Re2[j] = Re2[j];
+        const G<const T> ve = gmem<const T>(fd.vedge);
+        for (int j = threadIdx.x; j <= h.n_v; j += BLOCK) tb.ve[j] = ve[j];
+        const G<const T> Vp = gmem<const T>(fd.Vp);
+        const G<const T> isp = gmem<const T>(fd.isp);
+        for (int j = threadIdx.x; j < h.n_R; j += BLOCK) {
+            tb.Vp[j] = Vp[j];
+            tb.isp[j] = isp[j];
+        }
+    }
+    const G<double> row = gmem(fd.partials) + (size_t)tl.row * (size_t)fd.row_len;
+    const G<const T> __restrict__ ucell = gmem<const T>(fd.ucell);
+    const bool need_uh = correct || assign;
+    __syncthreads();
+
+    // software pipeline: the loads of the next particle are in flight while
+    // the current one is computed
+    for (; i < len; i += BLOCK) {
+        T x = nx, y = ny, z = nz, vx = nvx, vy = nvy, vz = nvz, u = nu, uh = nh;
+        const int inext = i + BLOCK;
+        if (inext < len) {
+            nx = X[inext];
+            ny = Y[inext];
+            nz = Z[inext];
+            nvx = VX[inext];
+            nvy = VY[inext];
+            nvz = VZ[inext];
+            nu = U[inext];
+            if (need_uh) nh = UH[inext];
+        }
+        // the prior of the particle's cell at the last refresh (same
+        // phase-space point: no push in between)
+        if (assign) uh = ucell[min((int)CI[i], C - 1)];
+        if (correct) {
+            // force of change at z^k with the residuals of step k
+            const Kern<T, KIN> kk = kernels<T, A, KIN>(h, tb, x, y, z, vz);
+            T chi = T(0);
+            if ((KIN & kKinAlm) && kk.jr >= 0) {
+                const int b0 = kk.jr * h.nlm, b1 = b0 + h.nlm;
+                const T g1 = T(1) - kk.g;
+                ylm_walk(h.l_max, kk.ct, kk.st, kk.cp, kk.sp, [&](int lm, T Y) {
+                    chi += Y * (kk.g * tb.rp[b0 + lm] + g1 * tb.rp[b1 + lm]);
+                });
+            } else if (kk.jr >= 0) {
+                chi = tb.rp[kk.jr];
+            }
+#pragma unroll
+            for (int m = 0; m < KinSlots<KIN>::n; ++m)
+                if (m < kk.kn) chi += kk.k[m] * tb.rp[kk.jk + m];
+            const T lr = Mth<T>::log_(u * Mth<T>::rcp_(uh));
+            u = u * Mth<T>::exp_(-h.foc_mu * (lr + h.foc_cs) - chi);
+        }
+        if (push) {
+            x += h.hdt * vx;
+            y += h.hdt * vy;
+            z += h.hdt * vz;
+            const T R2 = x * x + y * y, z2 = z * z;
+            T s = accel_of<T>(h, Mth<T>::sqrt_(R2 + z2)) * h.dt;
+            T sz = s;
+            if (h.halo) {  // logarithmic halo: -v0^2 (x, y, z/q^2) / (r0^2 + R^2 + z^2/q^2)
+                const T sh = h.hv2 * Mth<T>::rcp_(h.hr02 + R2 + z2 * h.hiq2) * h.dt;
+                s += sh;
+                sz += sh * h.hiq2;
+            }
+            vx -= s * x;
+            vy -= s * y;
+            vz -= sz * z;
+            x += h.hdt * vx;
+            y += h.hdt * vy;
+            z += h.hdt * vz;
+        }
+        if (deposit_on) deposit<T, KIN>(h, tb, kernels<T, A, KIN>(h, tb, x, y, z, vz), u, priv);
+        if (refresh) {
+            const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
+            atomicAdd(&tb.csum[c], (double)u);
+            atomicAdd(&tb.ccnt[c], 1u);
+            CI[i] = (uint16_t)c;
+        }
+        if (push && wt) {
+            put_wt(X + i, x);
+            put_wt(Y + i, y);
+            put_wt(Z + i, z);
+            put_wt(VX + i, vx);
+            put_wt(VY + i, vy);
+            put_wt(VZ + i, vz);
+            if (correct) put_wt(U + i, u);
+            if (assign) put_wt(UH + i, uh);
+        } else if (push) {
+            X[i] = x;
+            Y[i] = y;
+            Z[i] = z;
+            VX[i] = vx;
+            VY[i] = vy;
+            VZ[i] = vz;
+            if (correct) U[i] = u;
+            if (assign) UH[i] = uh;
+        }
+    }
+    __syncthreads();
+    if (deposit_on)
+        for (int j = threadIdx.x; j < J; j += BLOCK) {
+            double t = 0.0;
+            for (int g = 0; g < kp; ++g) {
+                t += (double)tb.sum[j * kp + g];
+                if (sizeof(A) == 4) t += (double)tb.comp[j * kp + g];
+            }
+            row[j] = t;
+        }
+    if (refresh)
+        for (int j = threadIdx.x; j < C; j += BLOCK) {
+            row[J + j] = tb.csum[j];
+            row[J + C + j] = (double)tb.ccnt[j];
+        }
+}
+
+// the tiles of the fits of a table (batches)
+template <typename T, typename A, int BLOCK, int KIN>
+__global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
+                                                const Tile* __restrict__ tiles, int32_t mode) {
+    const Tile tl = tiles[blockIdx.x];
+    step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
+}
+
+// one fit, its description passed by value; block t takes tile t of the
+// fit split into gridDim.x tiles
+template <typename T, typename A, int BLOCK, int KIN>
+__global__ __launch_bounds__(BLOCK) void k_step1(const FitDev fd, int32_t mode) {
+    step_tile<T, A, BLOCK, KIN>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0), mode);
+}
+
+
+template <typename T, typename A, int BLOCK, int KIN>
+hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* one, int n_tiles,
+                         size_t lds, int32_t mode, hipStream_t s) {
+    if (one)
+        hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, *one,
+                           mode);
+    else
+        hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                           tiles, mode);
+    return hipGetLastError();
+}
+
+template <typename T, typename A, int BLOCK>
+hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, const FitDev* one,
+                           int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
+    switch (kin) {
+        case kKinNone: return launch_step_t<T, A, BLOCK, kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinV2: return launch_step_t<T, A, BLOCK, kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinNone: return launch_step_t<T, A, BLOCK, kKinAlm | kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinV2: return launch_step_t<T, A, BLOCK, kKinAlm | kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinGH4: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinGHN: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinAlm | kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+
+}  // namespace
+}  // namespace m2m

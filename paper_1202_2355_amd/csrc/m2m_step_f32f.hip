@@ -1,0 +1,15 @@
+// Step kernels with float particle state and float in-tile sums.
+#include "m2m_step.h"
+
+namespace m2m {
+
+hipError_t launch_step_f32f(int block, int kin, const FitDev* fits, const Tile* tiles,
+                        const FitDev* one, int n_tiles, size_t lds, int32_t mode,
+                        hipStream_t s) {
+    if (block == 256) return launch_step_kin<float, float, 256>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    if (block == 512) return launch_step_kin<float, float, 512>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    if (block == 1024) return launch_step_kin<float, float, 1024>(kin, fits, tiles, one, n_tiles, lds, mode, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace m2m

@@ -492,3 +492,173 @@ def test_alm_run_fp32_matches_oracle(oracle, Fit):
     assert rmax <= 1e-4
     np.testing.assert_allclose(hist_g, hist_o, rtol=1e-4)
     f.close()
+
+
+# ------------------------------------------------ prior-grid options (Sec. 5)
+def _dirty_cells(oracle, pot, par, parts, cell, flagged, band):
+    """Cells a flagged particle may fall into: the oracle's cells of the
+    particle with its speed, its radius and its azimuthal velocity moved by
+    four bands either way (so across any nearby E, x or L_z = 0 edge)."""
+    C = oracle.n_cells(par)
+    dirty = np.zeros(C, bool)
+    dirty[cell[flagged]] = True
+    q = {k: v[flagged] for k, v in parts.items()}
+    d = 4.0 * band
+    vt = np.sqrt(q["vx"] ** 2 + q["vy"] ** 2 + q["vz"] ** 2)
+    R = np.maximum(np.hypot(q["x"], q["y"]), 1e-300)
+    ex, ey = -q["y"] / R, q["x"] / R   # azimuthal unit vector
+    variants = []
+    for s in (1.0 + d, 1.0 - d):
+        variants.append(dict(q, vx=q["vx"] * s, vy=q["vy"] * s, vz=q["vz"] * s))
+        variants.append(dict(q, x=q["x"] * s, y=q["y"] * s, z=q["z"] * s))
+    for s in (d, -d):
+        variants.append(dict(q, vx=q["vx"] + s * vt * ex, vy=q["vy"] + s * vt * ey))
+    for v in variants:
+        c, _, _ = oracle.cells(pot, par, v)
+        dirty[c] = True
+    return dirty
+
+
+def _oracle_priors(oracle, wl, par, parts, u, band):
+    J = oracle.J_of(wl.layout)
+    o = oracle.OracleFit(wl.potential, wl.layout, par, parts, np.ones(J), np.ones(J), u=u,
+                         track_flags=True, band=band, nthreads=8)
+    o.refresh_priors()
+    return o
+
+
+@pytest.mark.parametrize("cells", [1, 2, 3])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_prior_refresh_with_cell_options_matches_oracle(oracle, Fit, dtype, cells):
+    """Cells split by the sign of L_z (bit 0) and energy bins linear in
+    exp(E) (bit 1): priors of every cell none of whose particles the oracle
+    flags as near an edge (or near L_z = 0)."""
+    wl = workload(3)
+    par = dict(wl.params, cells=cells, n_E=32, n_x=16)
+    n = 40_001
+    _say("cell options", cells, dtype, n)
+    parts = cast(wl.initial_particles(n=n, seed=15), dtype)
+    u = cast({"u": random_weights(n, 19, spread=0.5)}, dtype)["u"]
+    f = Fit(wl.potential, wl.layout, par, parts, dtype=dtype, u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    f.close()
+    o = _oracle_priors(oracle, wl, par, parts, u, 1e-5 if dtype == "f32" else 1e-12)
+    cell, _, _ = oracle.cells(wl.potential, par, parts)
+    band = 1e-5 if dtype == "f32" else 1e-12
+    ok = ~_dirty_cells(oracle, wl.potential, par, parts, cell, o.flag != 0, band)[cell]
+    _say("cell options", cells, dtype, "clean fraction", ok.mean())
+    # exp(E) bins are wide at low E, so their cells are populous and one
+    # flagged member excludes many particles
+    assert ok.mean() > 0.5
+    np.testing.assert_allclose(uh[ok], o.arr["uhat"][ok], rtol=1e-6 if dtype == "f32" else 1e-13)
+    if cells & 1:
+        half = par["n_E"] * par["n_x"]
+        assert (cell >= half).any() and (cell < half).any()
+
+
+def test_prior_smoothing_with_cell_options_matches_oracle(oracle, Fit):
+    """Smoothing of both L_z halves, each alone, with energy bins linear in
+    exp(E) (FP64 state, particles clear of every cell edge). lambda is the
+    first minimum of GCV on a grid whose last stage steps log10(lambda) by
+    1/4096; on a flat minimum scores of neighbouring points can agree to
+    rounding, and the GPU's spectral scores and the oracle's dense ones may
+    then pick neighbours. So every smoothed cell must lie within the oracle's
+    values at its lambda and one last-stage step either side, widened by the
+    rounding of the oracle's dense Cholesky solve of (I + lambda P), whose
+    condition number is 1 + lambda G_max^2 (G_max = 4/hE^2 + 4/hx^2 bounds
+    the grid Laplacian; narrow exp(E) cells make it large). The GPU's
+    spectral solve has no such loss."""
+    wl = workload(1)
+    par = dict(wl.params, smooth=1, n_E=16, n_x=8, cells=3)
+    parts = wl.initial_particles(n=30_011, seed=16)
+    u = random_weights(parts["x"].size, 23, spread=0.5)
+    o = _oracle_priors(oracle, wl, par, parts, u, 1e-9)
+    keep = o.flag == 0
+    parts = {k: v[keep] for k, v in parts.items()}
+    u = u[keep]
+    _say("smoothing with cell options", parts["x"].size)
+    f = Fit(wl.potential, wl.layout, par, parts, dtype="f64", u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    C = oracle.n_cells(par)
+    grid = np.frombuffer(f.get_state()[-8 * C:], dtype=np.float64)
+    f.close()
+    # the data of each half: cell means, 1 (the initial prior) where empty
+    cell, _, _ = oracle.cells(wl.potential, par, parts)
+    sums = np.bincount(cell, weights=u, minlength=C)
+    cnts = np.bincount(cell, minlength=C)
+    data = np.where(cnts > 0, sums / np.maximum(cnts, 1), 1.0)
+    half = par["n_E"] * par["n_x"]
+    step = 10.0 ** (1.0 / 4096)
+    hE = (np.exp(par["E_hi"]) - np.exp(par["E_lo"])) / par["n_E"]
+    gmax = 4.0 / hE ** 2 + 4.0 * par["n_x"] ** 2
+    for h in range(2):
+        d = data[h * half:(h + 1) * half]
+        w, lam = oracle.smooth_grid(par, d)
+        lo = np.minimum.reduce([w, oracle.smooth_grid_at(par, d, lam / step),
+                                oracle.smooth_grid_at(par, d, lam * step)])
+        hi = np.maximum.reduce([w, oracle.smooth_grid_at(par, d, lam / step),
+                                oracle.smooth_grid_at(par, d, lam * step)])
+        g = grid[h * half:(h + 1) * half]
+        slack = max(1e-12, 8 * np.finfo(float).eps * (1.0 + lam * gmax ** 2)) * np.abs(w)
+        _say("half", h, "lambda", lam, "max |gpu - oracle| / |oracle|",
+             float(np.max(np.abs(g - w) / np.abs(w))))
+        assert np.all(g >= lo - slack) and np.all(g <= hi + slack)
+    np.testing.assert_array_equal(uh, grid[cell])
+
+
+# ---------------------------------------------- logarithmic halo (Sec. 5)
+def _halo_workload(oracle, wlid, q=0.7):
+    """The workload in its potential plus a flattened logarithmic halo, the
+    prior grid's energies spanning [Phi(0), Phi(r = 20)) of the total."""
+    from dataclasses import replace
+    wl = workload(wlid)
+    pot = replace(wl.potential, v0=0.8, r0=2.5, q=q)
+    par = dict(wl.params, E_lo=oracle.phi(pot, 0.0), E_hi=oracle.phi(pot, 20.0))
+    return wl.with_(name=wl.name + "_halo", potential=pot, params=par)
+
+
+def test_halo_run_fp64_matches_oracle(oracle, Fit):
+    """FP64 state in a flattened logarithmic halo: positions, weights and the
+    chi^2 history after 100 steps with two prior refreshes."""
+    wl = _halo_workload(oracle, 1)
+    n = 20_003
+    _say("halo run fp64", wl.name, n)
+    T, parts, f, o = _run_pair(oracle, Fit, wl, n, 100, "f64", 1e-12)
+    f.step(100)
+    hist_o = o.step(100)
+    hist_g = f.chi2_history(100)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("halo run fp64: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(st[k], o.arr[k], rtol=0, atol=1e-9)
+    assert r2 <= 1e-10
+    assert rmax <= 1e-10
+    np.testing.assert_allclose(hist_g, hist_o, rtol=1e-9)
+    f.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_halo_prior_refresh_matches_oracle(oracle, Fit, dtype):
+    """Priors in the halo potential: energies include the halo, circularity
+    against equatorial circular orbits (every energy is bound)."""
+    wl = _halo_workload(oracle, 3)
+    par = dict(wl.params, n_E=32, n_x=16)
+    n = 40_001
+    _say("halo priors", dtype, n)
+    parts = cast(wl.initial_particles(n=n, seed=25), dtype)
+    u = cast({"u": random_weights(n, 29, spread=0.5)}, dtype)["u"]
+    f = Fit(wl.potential, wl.layout, par, parts, dtype=dtype, u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    f.close()
+    band = 1e-5 if dtype == "f32" else 1e-12
+    o = _oracle_priors(oracle, wl, par, parts, u, band)
+    cell, E, xc = oracle.cells(wl.potential, par, parts)
+    assert (E > 0).any()   # bound energies above 0 exist in the halo
+    ok = ~_dirty_cells(oracle, wl.potential, par, parts, cell, o.flag != 0, band)[cell]
+    _say("halo priors", dtype, "clean fraction", ok.mean())
+    assert ok.mean() > 0.5
+    np.testing.assert_allclose(uh[ok], o.arr["uhat"][ok], rtol=1e-6 if dtype == "f32" else 1e-13)

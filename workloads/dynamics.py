@@ -31,7 +31,10 @@ import numpy as np
 # --------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Potential:
-    """Hernquist(G*M_star*upsilon, a) [+ NFW(G*M200, c, r_s)] potential."""
+    """Hernquist(G*M_star*upsilon, a) [+ NFW(G*M200, c, r_s)] potential, and
+    optionally the logarithmic halo v0^2/2 ln(r0^2 + R^2 + z^2/q^2) (v0 > 0).
+    The samplers here use the spherical parts only; the halo is carried for
+    the fits (it makes every orbit bound, so psi/psi0 ignore it)."""
 
     G: float = 1.0
     M_star: float = 1.0
@@ -40,6 +43,9 @@ class Potential:
     M200: float = 0.0
     c: float = 0.0
     r_s: float = 0.0
+    v0: float = 0.0
+    r0: float = 1.0
+    q: float = 1.0
 
     @property
     def has_nfw(self) -> bool:
@@ -82,7 +88,7 @@ class Potential:
 
     def as_dict(self) -> dict:
         return dict(G=self.G, M_star=self.M_star, a=self.a, upsilon=self.upsilon,
-                    M200=self.M200, c=self.c, r_s=self.r_s)
+                    M200=self.M200, c=self.c, r_s=self.r_s, v0=self.v0, r0=self.r0, q=self.q)
 
 
 # --------------------------------------------------------------------------
