@@ -403,7 +403,8 @@ def test_prior_smoothing_matches_oracle(oracle, Fit, dtype):
     o = oracle.OracleFit(wl.potential, wl.layout, par, parts, np.ones(J), np.ones(J), u=u)
     o.refresh_priors()
     np.testing.assert_allclose(grid, o.ucell, rtol=1e-10)
-    np.testing.assert_allclose(uh, o.arr["uhat"], rtol=1e-6 if dtype == "f32" else 1e-12)
+    # each particle's prior is its cell's value on that grid: the same bound
+    np.testing.assert_allclose(uh, o.arr["uhat"], rtol=1e-6 if dtype == "f32" else 1e-10)
 
 
 def test_run_with_prior_smoothing_matches_oracle(oracle, Fit):
