@@ -222,7 +222,8 @@ __device__ __forceinline__ void gcv_points(const double* g2, const double* wh, i
 // cos(pi j / 2n), j < 4n, from which every basis value and eigenvalue is
 // read (the argument k (2i+1) is taken modulo 4n).
 template <typename T>
-__device__ void smooth_priors(const FitDev& fd, int base, double* sa, double* sb, double* tE,
+__device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double* sa, double* sb,
+                                              double* tE,
                               double* tX, double* buf, int* sidx, double* smean) {
     static_assert(2 * kSmoothMaxPoints <= kFinWaves * kFinCols, "GCV scores and lambdas in buf");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -449,11 +450,15 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     if (!last) return;
     // a refresh with smoothing: the whole block smooths the prior grid
     if (fd.smooth && f.refresh)
-        for (int base = 0; base < fd.C; base += fd.cell_half) {
-            smooth_priors<T>(fd, base, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0], &sidx,
-                             &smean);
+    {
+        // each n_E x n_x grid alone: the first, then the L_z < 0 half if split
+        smooth_priors<T>(fd, 0, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0], &sidx, &smean);
+        if (fd.C > fd.cell_half) {
             __syncthreads();
+            smooth_priors<T>(fd, fd.cell_half, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0],
+                             &sidx, &smean);
         }
+    }
     if (wave != 0) return;
     const double chi2 =
         cells_mode ? 0.0 : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
