@@ -40,6 +40,9 @@
  *   Phi_D = v0^2/2 ln(r0^2 + R^2 + z^2/q^2),  R^2 = x^2 + y^2.
  * With it the potential is axisymmetric (q != 1) and grows without bound;
  * circular orbits, and so L_c(E), are taken in the equatorial plane.
+ * Optionally the stellar part is computed from the particles themselves (a
+ * multipole expansion rebuilt every scf_every steps, see "self-consistent
+ * potential" below); the prior cells then keep the analytic potential.
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,6 +56,12 @@ typedef struct {
     double G, M_star, a, upsilon; /* Hernquist mass is M_star * upsilon */
     double M200, c, r_s;          /* NFW; M200 = 0 means none */
     double v0, r0, q;             /* logarithmic halo (Sec. 5); v0 = 0 means none */
+    /* self-consistent stellar potential (Sec. 2.1, Sec. 5): scf_nr = 0 means
+     * none (the Hernquist part is used); else the multipole expansion of the
+     * particles up to degree scf_lmax with node values at scf_nr radii
+     * log-spaced over [scf_rmin, scf_rmax], rebuilt every scf_every steps */
+    double scf_rmin, scf_rmax;
+    int32_t scf_lmax, scf_nr, scf_every;
 } orc_potential;
 
 /* kin: 0 none, 1 v_z^2 moment, 2 Gauss-Hermite b_1..b_gh_nmax, 3 LOSVD;
@@ -107,6 +116,8 @@ typedef struct {
     double band;
     int32_t nthreads;
     double *ucell;   /* n_E n_x prior grid, kept between refreshes (empty cells keep theirs) */
+    double *scf;     /* self-consistent potential: node table (scf_nr x (scf_lmax+1)^2 x 2) */
+    int64_t tstep;   /* steps of any kind taken (the expansion's schedule) */
 } orc_model;
 
 #define ORC_MAXK 256  /* at most 2 x 81 density + 64 kinematic entries per particle */
@@ -290,6 +301,167 @@ double orc_ylm(int l, int m, double ct, double phi) {
     double P = orc_plm(l, am, ct);
     if (m == 0) return N * P;
     return sqrt(2.0) * N * P * (m > 0 ? cos(am * phi) : sin(am * phi));
+}
+
+/* ------------------------------------------------- self-consistent potential
+ * The stellar potential computed from the particles as they move (Sec. 2.1;
+ * in Sec. 5 from a spherical-harmonic decomposition of the model's light at a
+ * constant mass-to-light ratio). The particles' masses are
+ * m_i = upsilon w_i = upsilon u_i M / N. Poisson's equation in spherical
+ * harmonics (the multipole expansion of the point masses), truncated at
+ * l <= scf_lmax:
+ *   Phi_*(x) = sum_lm Phi_lm(r) Y_lm(theta, phi),
+ *   Phi_lm(r) = -4 pi G / (2l + 1) [r^-(l+1) A_lm(r) + r^l B_lm(r)],
+ *   A_lm(r) = sum_{r_i < r} m_i r_i^l Y_lm(x_i),
+ *   B_lm(r) = sum_{r_i >= r} m_i r_i^-(l+1) Y_lm(x_i).
+ * It is taken exactly at the nodes rho_k (k < scf_nr, log-spaced over
+ * [scf_rmin, scf_rmax]) together with its slope
+ *   r dPhi_lm/dr = -4 pi G / (2l + 1) [-(l+1) r^-(l+1) A_lm + l r^l B_lm]
+ * (the terms of dA/dr and dB/dr cancel). Between nodes Phi_lm is the cubic
+ * Hermite interpolant of these values and slopes in s = ln r; inside rho_0 it
+ * is the regular r^l (c0 + c1 r^2), beyond the last node c0 r^-(l+1) + c1 r^l,
+ * each with the value and slope of its end node. Table entry
+ * (k (scf_lmax+1)^2 + l^2 + l + m) 2 holds Phi_lm(rho_k), the next one
+ * r dPhi_lm/dr there. */
+static int nthreads_of(int32_t want);
+
+static double scf_node(const orc_potential *p, int k) {
+    if (k == 0) return p->scf_rmin;
+    if (k == p->scf_nr - 1) return p->scf_rmax;
+    return p->scf_rmin * pow(p->scf_rmax / p->scf_rmin, (double)k / (double)(p->scf_nr - 1));
+}
+
+void orc_scf_table(const orc_potential *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *u, double mass, double *tab, int32_t nthreads) {
+    const int L = p->scf_lmax, K = p->scf_nr, nlm = (L + 1) * (L + 1);
+    /* per particle: r and m_i Y_lm(x_i) */
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *mY = (double *)malloc(sizeof(double) * (size_t)n * nlm);
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+        double ct = r[i] > 0.0 ? z[i] / r[i] : 1.0, ph = atan2(y[i], x[i]);
+        double mi = p->upsilon * u[i] * mass / (double)n;
+        for (int l = 0; l <= L; ++l)
+            for (int m = -l; m <= l; ++m) mY[i * nlm + l * l + l + m] = mi * orc_ylm(l, m, ct, ph);
+    }
+    int T = nthreads_of(nthreads);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(T) schedule(static)
+#endif
+    for (int k = 0; k < K; ++k) {
+        double rho = scf_node(p, k);
+        for (int l = 0; l <= L; ++l)
+            for (int m = -l; m <= l; ++m) {
+                int lm = l * l + l + m;
+                double A = 0.0, B = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    if (r[i] < rho)
+                        A += pow(r[i], l) * mY[i * nlm + lm];
+                    else
+                        B += pow(r[i], -(l + 1)) * mY[i * nlm + lm];
+                }
+                double c = -4.0 * M_PI * p->G / (2.0 * l + 1.0);
+                double ra = pow(rho, -(l + 1)), rb = pow(rho, l);
+                tab[(k * nlm + lm) * 2] = c * (ra * A + rb * B);
+                tab[(k * nlm + lm) * 2 + 1] = c * (-(l + 1) * ra * A + l * rb * B);
+            }
+    }
+    free(mY);
+    free(r);
+}
+
+/* Phi_lm(r) and r dPhi_lm/dr at radius r from the node table */
+static void scf_radial(const orc_potential *p, const double *tab, int nlm, int l, int lm, double r,
+                       double *f, double *d) {
+    const int K = p->scf_nr;
+    const double r0 = scf_node(p, 0), r1 = scf_node(p, K - 1);
+    if (r < r0) {
+        double P = tab[lm * 2], D = tab[lm * 2 + 1], v = r / r0, vl = pow(v, l);
+        double c = 0.5 * (D - l * P);
+        *f = vl * (P + c * (v * v - 1.0));
+        *d = vl * (l * P + c * ((l + 2) * v * v - l));
+        return;
+    }
+    if (r >= r1) {
+        const double *t = tab + ((K - 1) * nlm + lm) * 2;
+        double P = t[0], D = t[1], v = r / r1;
+        double cA = (l * P - D) / (2.0 * l + 1.0), cB = ((l + 1) * P + D) / (2.0 * l + 1.0);
+        double va = pow(v, -(l + 1)), vb = pow(v, l);
+        *f = cA * va + cB * vb;
+        *d = -(l + 1) * cA * va + l * cB * vb;
+        return;
+    }
+    int k = 0;
+    while (k < K - 2 && scf_node(p, k + 1) <= r) ++k;
+    const double *t0 = tab + (k * nlm + lm) * 2, *t1 = tab + ((k + 1) * nlm + lm) * 2;
+    double s0 = log(scf_node(p, k)), h = log(scf_node(p, k + 1)) - s0;
+    double t = (log(r) - s0) / h, t2 = t * t, t3 = t2 * t;
+    *f = (2 * t3 - 3 * t2 + 1) * t0[0] + h * (t3 - 2 * t2 + t) * t0[1] + (-2 * t3 + 3 * t2) * t1[0] +
+         h * (t3 - t2) * t1[1];
+    *d = ((6 * t2 - 6 * t) * t0[0] + h * (3 * t2 - 4 * t + 1) * t0[1] + (-6 * t2 + 6 * t) * t1[0] +
+          h * (3 * t2 - 2 * t) * t1[1]) / h;
+}
+
+double orc_scf_phi(const orc_potential *p, const double *tab, double x, double y, double z) {
+    const int L = p->scf_lmax, nlm = (L + 1) * (L + 1);
+    double r = sqrt(x * x + y * y + z * z);
+    double ct = r > 0.0 ? z / r : 1.0, ph = atan2(y, x), phi = 0.0;
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) {
+            double f, d;
+            scf_radial(p, tab, nlm, l, l * l + l + m, r, &f, &d);
+            phi += f * orc_ylm(l, m, ct, ph);
+        }
+    return phi;
+}
+
+/* g = -grad Phi_* in spherical components: dPhi/dr, (1/r) dPhi/dtheta with
+ *   dP_l^m/dtheta = (l cos(theta) P_l^m - (l + m) P_{l-1}^m) / sin(theta),
+ * and (1/(r sin(theta))) dPhi/dphi. Zero at the centre (where the direction is
+ * undefined); on the z axis the direction is tilted by 1e-9 rad. */
+void orc_scf_accel(const orc_potential *p, const double *tab, double x, double y, double z,
+                   double *g) {
+    const int L = p->scf_lmax, nlm = (L + 1) * (L + 1);
+    double r = sqrt(x * x + y * y + z * z);
+    g[0] = g[1] = g[2] = 0.0;
+    if (!(r > 0.0)) return;
+    double R = sqrt(x * x + y * y);
+    if (R == 0.0) {
+        x = r * 1e-9;
+        R = x;
+    }
+    double ct = z / r, st = R / r, cp = x / R, sp = y / R, ph = atan2(y, x);
+    double dr = 0.0, dth = 0.0, dps = 0.0;
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double f, d;
+            scf_radial(p, tab, nlm, l, l * l + l + m, r, &f, &d);
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * tgamma(l - am + 1.0) /
+                            tgamma(l + am + 1.0));
+            double P = orc_plm(l, am, ct);
+            double Pm1 = (l - 1 >= am) ? orc_plm(l - 1, am, ct) : 0.0;
+            double dP = (l * ct * P - (l + am) * Pm1) / st;
+            double T, dT; /* the azimuthal factor and its phi derivative */
+            if (m == 0) {
+                T = 1.0;
+                dT = 0.0;
+            } else if (m > 0) {
+                T = sqrt(2.0) * cos(am * ph);
+                dT = -sqrt(2.0) * am * sin(am * ph);
+            } else {
+                T = sqrt(2.0) * sin(am * ph);
+                dT = sqrt(2.0) * am * cos(am * ph);
+            }
+            dr += d / r * N * P * T;
+            dth += f * N * dP * T;
+            dps += f * N * P / st * dT;
+        }
+    /* grad = dr rhat + dth/r thetahat + dps/r phihat */
+    double gt = dth / r, gp = dps / r;
+    g[0] = -(dr * st * cp + gt * ct * cp - gp * sp);
+    g[1] = -(dr * st * sp + gt * ct * sp + gp * cp);
+    g[2] = -(dr * ct - gt * st);
 }
 
 typedef struct {
@@ -588,7 +760,28 @@ int orc_init(orc_model *m) {
     deposit_model(m, m->yraw);
     for (int j = 0; j < m->J; ++j) m->ytilde[j] = m->yraw[j];
     residuals(m);
+    if (m->pot.scf_nr > 0) {
+        if (!m->scf) return 1;
+        orc_scf_table(&m->pot, m->n, m->x, m->y, m->z, m->u, m->par.mass, m->scf, m->nthreads);
+    }
     return 0;
+}
+
+/* the whole acceleration of the fit: with the self-consistent potential the
+ * expansion replaces the Hernquist part */
+static void accel_total(const orc_model *m, double x, double y, double z, double *g) {
+    if (m->pot.scf_nr == 0) {
+        orc_accel(&m->pot, x, y, z, g);
+        return;
+    }
+    orc_potential d = m->pot;
+    d.M_star = 0.0;
+    orc_accel(&d, x, y, z, g);
+    double gs[3];
+    orc_scf_accel(&m->pot, m->scf, x, y, z, gs);
+    g[0] += gs[0];
+    g[1] += gs[1];
+    g[2] += gs[2];
 }
 
 /* ------------------------------------------------------------- smoothing
@@ -830,7 +1023,7 @@ int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) 
             m->x[i] += 0.5 * dt * m->vx[i];
             m->y[i] += 0.5 * dt * m->vy[i];
             m->z[i] += 0.5 * dt * m->vz[i];
-            orc_accel(&m->pot, m->x[i], m->y[i], m->z[i], g);
+            accel_total(m, m->x[i], m->y[i], m->z[i], g);
             m->vx[i] += dt * g[0];
             m->vy[i] += dt * g[1];
             m->vz[i] += dt * g[2];
@@ -849,6 +1042,10 @@ int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) 
             if (P->entropy == 0 && P->prior_every > 0 && m->kstep % P->prior_every == 0)
                 orc_refresh_priors(m);
         }
+        /* the self-consistent potential from z^{k+1} and the new weights */
+        m->tstep += 1;
+        if (m->pot.scf_nr > 0 && m->tstep % m->pot.scf_every == 0)
+            orc_scf_table(&m->pot, m->n, m->x, m->y, m->z, m->u, P->mass, m->scf, m->nthreads);
         if (chi2_hist) chi2_hist[s] = m->chi2;
     }
     free(rj);

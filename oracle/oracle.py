@@ -31,7 +31,8 @@ def build(force: bool = True) -> str:
 
 class Potential(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s",
-                                          "v0", "r0", "q")]
+                                          "v0", "r0", "q", "scf_rmin", "scf_rmax")] + [
+        ("scf_lmax", C.c_int32), ("scf_nr", C.c_int32), ("scf_every", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -60,7 +61,7 @@ class Model(C.Structure):
         ("Y", _dp), ("sigma", _dp), ("Vp", _dp), ("sp", _dp),
         ("ytilde", _dp), ("yraw", _dp), ("delta", _dp), ("chi2", C.c_double),
         ("kstep", C.c_int64), ("flag", C.POINTER(C.c_uint8)), ("band", C.c_double),
-        ("nthreads", C.c_int32), ("ucell", _dp)]
+        ("nthreads", C.c_int32), ("ucell", _dp), ("scf", _dp), ("tstep", C.c_int64)]
 
 
 _lib = None
@@ -113,6 +114,11 @@ def lib():
             _dp] * 7 + [C.c_double, _dp]
         L.orc_push.argtypes = [C.POINTER(Potential), C.c_double, C.c_int64] + [_dp] * 6 + [
             C.c_int32]
+        L.orc_scf_table.argtypes = [C.POINTER(Potential), C.c_int64] + [_dp] * 4 + [
+            C.c_double, _dp, C.c_int32]
+        L.orc_scf_phi.restype = C.c_double
+        L.orc_scf_phi.argtypes = [C.POINTER(Potential), _dp] + [C.c_double] * 3
+        L.orc_scf_accel.argtypes = [C.POINTER(Potential), _dp] + [C.c_double] * 3 + [_dp]
         _lib = L
     return _lib
 
@@ -128,7 +134,40 @@ def _f64(a):
 def potential(d) -> Potential:
     d = d.as_dict() if hasattr(d, "as_dict") else d
     return Potential(**{k: float(d[k]) for k in ("G", "M_star", "a", "upsilon", "M200", "c", "r_s")},
-                     v0=float(d.get("v0", 0.0)), r0=float(d.get("r0", 1.0)), q=float(d.get("q", 1.0)))
+                     v0=float(d.get("v0", 0.0)), r0=float(d.get("r0", 1.0)), q=float(d.get("q", 1.0)),
+                     scf_rmin=float(d.get("scf_rmin", 0.0)), scf_rmax=float(d.get("scf_rmax", 0.0)),
+                     scf_lmax=int(d.get("scf_lmax", 0)), scf_nr=int(d.get("scf_nr", 0)),
+                     scf_every=int(d.get("scf_every", 1)))
+
+
+def scf_size(pot) -> int:
+    """Entries of the self-consistent potential's node table (0 without it)."""
+    P = potential(pot)
+    return P.scf_nr * (P.scf_lmax + 1) ** 2 * 2
+
+
+def scf_table(pot, parts: dict, u=None, mass=1.0, nthreads=1):
+    """Node table of the particles' multipole potential: array (scf_nr,
+    (scf_lmax+1)^2, 2) of Phi_lm(rho_k) and r dPhi_lm/dr there."""
+    P = potential(pot)
+    x, y, z = (_f64(parts[k]) for k in ("x", "y", "z"))
+    u = _f64(np.ones(x.size) if u is None else u)
+    tab = np.zeros(scf_size(pot))
+    lib().orc_scf_table(C.byref(P), x.size, _p(x), _p(y), _p(z), _p(u), float(mass), _p(tab),
+                        int(nthreads))
+    return tab.reshape(P.scf_nr, (P.scf_lmax + 1) ** 2, 2)
+
+
+def scf_phi(pot, tab, x, y, z) -> float:
+    t = _f64(tab).reshape(-1)
+    return lib().orc_scf_phi(C.byref(potential(pot)), _p(t), float(x), float(y), float(z))
+
+
+def scf_accel(pot, tab, x, y, z):
+    t = _f64(tab).reshape(-1)
+    g = np.zeros(3)
+    lib().orc_scf_accel(C.byref(potential(pot)), _p(t), float(x), float(y), float(z), _p(g))
+    return g
 
 
 def layout(d: dict) -> Layout:
@@ -311,6 +350,9 @@ class OracleFit:
         m.nthreads = nthreads
         self.ucell = np.ones(n_cells(par))
         m.ucell = _p(self.ucell)
+        self.scf = np.zeros(max(scf_size(pot), 1))
+        m.scf = _p(self.scf)
+        m.tstep = 0
         self.m = m
         if self.Y.size != self.J or self.sigma.size != self.J:
             raise ValueError("target length does not match the layout")
