@@ -85,6 +85,23 @@
  *     over the two steps around the best one, then 65 points over the two
  *     sub-steps around the best one. Smoothed priors are floored at 1e-3
  *     times the mean of w0.
+ *   Self-consistent potential (scf_nr > 0). The stellar potential is the
+ *     multipole expansion of the particles, m_i = upsilon u_i M / N:
+ *       Phi_*(x) = sum_lm Phi_lm(r) Y_lm(theta, phi)  (l <= scf_lmax, the
+ *       real harmonics above),
+ *       Phi_lm(r) = -4 pi G / (2l+1) [r^-(l+1) A_lm(r) + r^l B_lm(r)],
+ *       A_lm(r) = sum_{r_i < r} m_i r_i^l Y_lm(x_i),
+ *       B_lm(r) = sum_{r_i >= r} m_i r_i^-(l+1) Y_lm(x_i),
+ *     exact with its slope r dPhi_lm/dr at the nodes
+ *     rho_k = scf_rmin (scf_rmax/scf_rmin)^(k/(scf_nr-1)); between nodes
+ *     Phi_lm is the cubic Hermite interpolant of value and slope in ln r,
+ *     inside rho_0 r^l (c0 + c1 r^2), beyond the last node
+ *     c0 r^-(l+1) + c1 r^l, each matching the end node. The force is its
+ *     exact gradient (zero at r = 0). The expansion is built from the
+ *     particles and weights when the targets are first set (or by
+ *     m2m_refresh_potential) and rebuilt after the push of every step k with
+ *     (k + 1) % scf_every == 0, counting steps of every kind from 0, from
+ *     z^{k+1} and the weights after that step; it acts from the next step on.
  *
  * Memory and ownership
  *   Particle arrays (x, y, z, vx, vy, vz, u, u_prior) are device pointers in
@@ -176,6 +193,18 @@ typedef struct {
                             "Prior smoothing"); needs n_E, n_x <= 128; 0: cell means */
     int32_t cells;       /* m2m_cells flags of the prior grid (Sec. 5); 0: n_E x n_x
                             cells linear in E */
+    /* Self-consistent stellar potential (Sec. 2.1: a potential computed from
+     * the particles as they move; Sec. 5: from a spherical-harmonic
+     * decomposition of the light at constant M/L). scf_nr = 0: none, the
+     * Hernquist part of m2m_potential is the stars. Otherwise the stars are
+     * the multipole expansion of the particles' masses upsilon w_i to degree
+     * scf_lmax, known at scf_nr nodes log-spaced over [scf_rmin, scf_rmax]
+     * (see "Self-consistent potential"); the NFW and logarithmic halos stay
+     * analytic, and the prior cells keep the analytic potential. */
+    int32_t scf_lmax;    /* 0..8 */
+    int32_t scf_nr;      /* 0, or 2..64 nodes */
+    double scf_rmin, scf_rmax; /* 0 < scf_rmin < scf_rmax */
+    int32_t scf_every;   /* steps between rebuilds of the expansion, >= 1 */
 } m2m_params;
 
 /* Number of observables J of a layout (0 if the layout is invalid). */
@@ -212,6 +241,19 @@ m2m_status m2m_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct);
 /* Recompute the cell priors from the current state now (Sec. 2.3.1) and
  * assign them; asynchronous. EINVAL unless entropy is M2M_S_MPR. */
 m2m_status m2m_update_priors(m2m_ctx* ctx);
+
+/* Rebuild the self-consistent stellar potential (Sec. 2.1, Sec. 5) from the
+ * current particles and weights now; asynchronous. It acts from the next
+ * step on. Call it after changing the particle arrays between steps.
+ * EINVAL unless params.scf_nr > 0, ESTATE inside a batch. */
+m2m_status m2m_refresh_potential(m2m_ctx* ctx);
+
+/* The node table of the self-consistent potential into out (host memory,
+ * max >= scf_nr (scf_lmax+1)^2 2 doubles): entry (k (scf_lmax+1)^2 + l^2 +
+ * l + m) 2 is Phi_lm(rho_k), the next one r dPhi_lm/dr at rho_k.
+ * Synchronizes the stream. EINVAL without the expansion or if max is too
+ * small, ESTATE inside a batch. */
+m2m_status m2m_get_potential(m2m_ctx* ctx, double* out, int32_t max);
 
 /* Weights w_i = u_i M / N into dst (n values of the context's dtype), on the
  * device (dst_is_device = 1) or the host. Synchronizes the stream. */

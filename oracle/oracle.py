@@ -17,6 +17,7 @@ SRC = os.path.join(HERE, "m2m_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 KIN = {"none": 0, "v2": 1, "gh": 2, "losvd": 3}
+SCF_KEYS = ("scf_lmax", "scf_nr", "scf_rmin", "scf_rmax", "scf_every")
 DENS = {"bins": 0, "alm": 1}
 ENTROPY = {"mpr": 0, "gwr": 1}
 
@@ -338,6 +339,8 @@ class OracleFit:
         m.n = n
         for k in ("x", "y", "z", "vx", "vy", "vz", "u", "uhat"):
             setattr(m, k, _p(self.arr[k]))
+        pot = pot.as_dict() if hasattr(pot, "as_dict") else dict(pot)
+        pot.update({k: par[k] for k in SCF_KEYS if k in par})  # the expansion may come with par
         m.pot = potential(pot)
         m.lay = layout(lay)
         m.par = params(par)

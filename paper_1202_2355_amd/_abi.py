@@ -50,7 +50,8 @@ class m2m_params(C.Structure):
                 ("alpha", C.c_double), ("mass", C.c_double), ("entropy", C.c_int32),
                 ("n_E", C.c_int32), ("n_x", C.c_int32), ("prior_every", C.c_int32),
                 ("E_lo", C.c_double), ("E_hi", C.c_double), ("smooth", C.c_int32),
-                ("cells", C.c_int32)]
+                ("cells", C.c_int32), ("scf_lmax", C.c_int32), ("scf_nr", C.c_int32),
+                ("scf_rmin", C.c_double), ("scf_rmax", C.c_double), ("scf_every", C.c_int32)]
 
 
 _vp = C.c_void_p
@@ -69,6 +70,8 @@ SIGNATURES = {
     "m2m_set_targets": (_st, [_vp, _i32, _dp, _dp, _dp, _dp]),
     "m2m_step": (_st, [_vp, _i32, _i32]),
     "m2m_update_priors": (_st, [_vp]),
+    "m2m_refresh_potential": (_st, [_vp]),
+    "m2m_get_potential": (_st, [_vp, _dp, _i32]),
     "m2m_get_weights": (_st, [_vp, _vp, _i32]),
     "m2m_get_observables": (_st, [_vp, _dp, _dp, _dp, _dp]),
     "m2m_get_chi2_history": (_st, [_vp, _dp, _i32, C.POINTER(_i32)]),
@@ -146,7 +149,10 @@ def params(d: dict) -> m2m_params:
     return m2m_params(dt=d["dt"], eps=d["eps"], mu=d["mu"], alpha=d["alpha"], mass=d["mass"],
                       entropy=ent, n_E=d["n_E"], n_x=d["n_x"], prior_every=d["prior_every"],
                       E_lo=d["E_lo"], E_hi=d["E_hi"], smooth=int(d.get("smooth", 0)),
-                      cells=int(d.get("cells", 0)))
+                      cells=int(d.get("cells", 0)), scf_lmax=int(d.get("scf_lmax", 0)),
+                      scf_nr=int(d.get("scf_nr", 0)), scf_rmin=float(d.get("scf_rmin", 0.0)),
+                      scf_rmax=float(d.get("scf_rmax", 0.0)),
+                      scf_every=int(d.get("scf_every", 1)))
 
 
 # ---- thin wrappers with the C names ------------------------------------------

@@ -154,6 +154,14 @@ std::string check_params(const m2m_params* P) {
     if (n_cells(*P) > kMaxCells) return "need n_E*n_x <= 2048 with the L_z split";
     if (P->smooth && (P->n_E > kSmoothMaxSide || P->n_x > kSmoothMaxSide))
         return "prior smoothing needs n_E, n_x <= 128";
+    if (P->scf_nr != 0) {
+        if (P->scf_nr < 2 || P->scf_nr > kMaxScfNodes) return "scf_nr must be 0 or 2..64";
+        if (P->scf_lmax < 0 || P->scf_lmax > kMaxLM) return "scf_lmax must be 0..8";
+        if (!(is_fin(P->scf_rmin) && is_fin(P->scf_rmax) && P->scf_rmin > 0 &&
+              P->scf_rmax > P->scf_rmin))
+            return "need 0 < scf_rmin < scf_rmax";
+        if (P->scf_every < 1) return "scf_every must be >= 1";
+    }
     if (P->smooth && P->n_E * P->n_x > 1) {
         double plo, phi;
         int k1;
@@ -275,10 +283,15 @@ constexpr double kLzHalo1 = 3.68887945411394;  // ln 40: with the logarithmic ha
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
     size_t st, fd, tiles, jobs, redge2, rmesh, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
-    size_t cdata, gprior;
+    size_t cdata, gprior, scf_rho, scf_sum, scf_tab;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
-    int seg_cap, row_len, nbj, ncj, J, C;
+    int seg_cap, row_len, nbj, ncj, npj, J, C, P;  // P: interval sums of the expansion
 };
+
+// entries of the node table of the self-consistent potential
+size_t scf_table_len(const m2m_params& P) {
+    return P.scf_nr > 0 ? (size_t)P.scf_nr * (size_t)((P.scf_lmax + 1) * (P.scf_lmax + 1)) * 2 : 0;
+}
 
 int seg_cap_of(int64_t n, int row_len) {
     // at least ~1024 particles per tile, and partial rows of at most
@@ -296,9 +309,11 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     const size_t sz = f64 ? 8 : 4;
     w.J = num_obs(L);
     w.C = n_cells(P);
-    w.row_len = w.J + 2 * w.C;
+    w.P = (int)scf_table_len(P);  // 2 K nlm interval sums, as many as table entries
+    w.row_len = w.J + 2 * w.C + w.P;
     w.nbj = (w.J + kFinCols - 1) / kFinCols;
     w.ncj = (w.C + kFinCols - 1) / kFinCols;
+    w.npj = (w.P + kFinCols - 1) / kFinCols;
     w.seg_cap = seg_cap_of(n, w.row_len);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -309,7 +324,7 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.st = take(sizeof(FitState));
     w.fd = take(sizeof(FitDev));
     w.tiles = take(sizeof(Tile) * (size_t)w.seg_cap);
-    w.jobs = take(sizeof(FinJob) * (size_t)(w.nbj + w.ncj));
+    w.jobs = take(sizeof(FinJob) * (size_t)(w.nbj + w.ncj + w.npj));
     const int nR = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
     const int nv = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
     w.redge2 = take(sz * (size_t)(L.n_r + 1));
@@ -333,6 +348,9 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.cidx = take(2 * (size_t)n);
     w.cdata = take(8 * (size_t)w.C);
     w.gprior = take(8 * (size_t)w.C);
+    w.scf_rho = take(8 * (size_t)std::max(P.scf_nr, 1));
+    w.scf_sum = take(8 * (size_t)std::max(w.P, 1));
+    w.scf_tab = take(8 * (size_t)std::max(w.P, 1));
     w.total = o;
     return w;
 }
@@ -436,6 +454,7 @@ void split_tiles(int64_t n, int count, int fit, int row0, std::vector<Tile>& out
 void fin_jobs(const WsLayout& w, int fit, int n_rows, std::vector<FinJob>& out) {
     for (int b = 0; b < w.nbj; ++b) out.push_back(FinJob{fit, 0, b * kFinCols, n_rows});
     for (int b = 0; b < w.ncj; ++b) out.push_back(FinJob{fit, 1, b * kFinCols, n_rows});
+    for (int b = 0; b < w.npj; ++b) out.push_back(FinJob{fit, 2, b * kFinCols, n_rows});
 }
 
 m2m_status sync(m2m_ctx* c) {
@@ -466,6 +485,16 @@ m2m_status check_error(m2m_ctx* c) {
     m2m_status r = read_state(c, s);
     if (r != M2M_OK) return r;
     if (s.error & 1) return fail(c, M2M_ENONFINITE, "chi^2 became non-finite");
+    return M2M_OK;
+}
+
+// Rebuild the self-consistent potential from the current state: the step
+// kernel deposits the interval sums only, the finalize reduces them and
+// writes the node table.
+m2m_status refresh_potential(m2m_ctx* c) {
+    M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
+                           kModePot, c->stream));
+    M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModePot, c->stream));
     return M2M_OK;
 }
 
@@ -594,7 +623,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->f64 = dtype == M2M_F64;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->block = c->f64 ? 256 : g_block;
-    c->kin = kin_class(c->lay.kin, c->lay.gh_nmax, c->lay.dens);
+    c->kin = kin_class(c->lay.kin, c->lay.gh_nmax, c->lay.dens, c->par.scf_nr > 0);
     c->w = plan(c->lay, c->par, n, c->f64);
     const WsLayout& w = c->w;
     const int kpriv = private_copies(c->f64, w.J);
@@ -602,7 +631,8 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->wt = (size_t)n * 8 * (c->f64 ? 8 : 4) <= kWriteThroughMax;
     c->lds = step_lds_bytes(c->f64, c->acc64, w.J, radial_intervals(c->lay),
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
-                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C);
+                            c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C,
+                            c->par.scf_nr, c->par.scf_lmax);
     if (c->lds > max_lds()) {
         delete c;
         return M2M_EUNSUPPORTED;
@@ -682,6 +712,20 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.kpriv = kpriv;
     f.n_bin_jobs = w.nbj;
     f.n_cell_jobs = w.ncj;
+    f.n_pot_jobs = w.npj;
+    f.scf_nr = c->par.scf_nr;
+    f.scf_lmax = c->par.scf_nr > 0 ? c->par.scf_lmax : 0;
+    f.scf_every = std::max(c->par.scf_every, 1);
+    f.scf_col0 = w.J + 2 * w.C;
+    f.scf_P = w.P;
+    if (c->par.scf_nr > 0) {
+        f.scf_ls0 = std::log(c->par.scf_rmin);
+        f.scf_ih = (c->par.scf_nr - 1) / std::log(c->par.scf_rmax / c->par.scf_rmin);
+    }
+    f.scf_c = c->pot.G * c->pot.upsilon * c->par.mass / (double)n;
+    f.scf_rho = reinterpret_cast<double*>(b + w.scf_rho);
+    f.scf_sum = reinterpret_cast<double*>(b + w.scf_sum);
+    f.scf_tab = reinterpret_cast<double*>(b + w.scf_tab);
     f.entropy = c->par.entropy;
     f.n_E = c->par.n_E;
     f.n_x = c->par.n_x;
@@ -765,6 +809,13 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     if ((s = upload(c, w.Redge2, Re2)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.vedge, ve)) != M2M_OK) return bail(s);
     if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);
+    if (c->par.scf_nr > 0) {
+        // nodes of the self-consistent potential, FP64
+        std::vector<double> rho(c->par.scf_nr);
+        for (int k = 0; k < c->par.scf_nr; ++k)
+            rho[k] = log_edge(c->par.scf_rmin, c->par.scf_rmax, c->par.scf_nr - 1, k);
+        if ((s = upload64(c, w.scf_rho, rho)) != M2M_OK) return bail(s);
+    }
     if ((s = upload(c, w.ucell, ones)) != M2M_OK) return bail(s);
     if ((s = upload64(c, w.gprior, ones)) != M2M_OK) return bail(s);
     if ((s = upload_gh(c, c->Vp, c->sp)) != M2M_OK) return bail(s);
@@ -813,6 +864,7 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
     c->sp = S;
     if ((s = upload_gh(c, V, S)) != M2M_OK) return s;
     if (!c->ytil_init) {
+        if (c->par.scf_nr > 0 && (s = refresh_potential(c)) != M2M_OK) return s;
         M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
                                kModeInit, c->stream));
         M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModeInit, c->stream));
@@ -838,6 +890,25 @@ m2m_status m2m_step(m2m_ctx* c, int32_t n_steps, int32_t correct) {
         for (int k = 0; k < full; ++k) M2M_HIP(c, hipGraphLaunch(c->graph, c->stream));
     }
     return run_direct(c, rem);
+}
+
+m2m_status m2m_refresh_potential(m2m_ctx* c) {
+    if (!c) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (c->par.scf_nr <= 0) return fail(c, M2M_EINVAL, "the fit has no self-consistent potential");
+    return refresh_potential(c);
+}
+
+m2m_status m2m_get_potential(m2m_ctx* c, double* out, int32_t max) {
+    if (!c || !out) return M2M_EINVAL;
+    if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    const size_t ST = scf_table_len(c->par);
+    if (ST == 0) return fail(c, M2M_EINVAL, "the fit has no self-consistent potential");
+    if (max < 0 || (size_t)max < ST) return fail(c, M2M_EINVAL, "output too small");
+    m2m_status s = sync(c);
+    if (s != M2M_OK) return s;
+    M2M_HIP(c, copy_sync(c->stream, out, c->fd.scf_tab, 8 * ST, hipMemcpyDeviceToHost));
+    return M2M_OK;
 }
 
 m2m_status m2m_update_priors(m2m_ctx* c) {
@@ -945,8 +1016,9 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     const size_t J = (size_t)c->w.J, C = (size_t)c->w.C, nR = c->Vp.size();
     const size_t sz = c->f64 ? 8 : 4;
+    const size_t ST = scf_table_len(c->par);
     const size_t need = sizeof(StateHeader) + sizeof(FitState) + 8 * (5 * J + 2 * nR) +
-                        sz * (C + J) + 8 * (size_t)kHistCap + 8 * C;
+                        sz * (C + J) + 8 * (size_t)kHistCap + 8 * C + 8 * ST;
     if (!host_blob) {
         *bytes = need;
         return M2M_OK;
@@ -979,6 +1051,8 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
     M2M_HIP(c, copy_sync(c->stream, p, c->fd.chi2_hist, 8 * (size_t)kHistCap, hipMemcpyDeviceToHost));
     p += 8 * (size_t)kHistCap;
     M2M_HIP(c, copy_sync(c->stream, p, c->fd.gprior, 8 * C, hipMemcpyDeviceToHost));
+    p += 8 * C;
+    if (ST > 0) M2M_HIP(c, copy_sync(c->stream, p, c->fd.scf_tab, 8 * ST, hipMemcpyDeviceToHost));
     *bytes = need;
     return M2M_OK;
 }
@@ -1027,6 +1101,9 @@ m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     M2M_HIP(c, copy_sync(c->stream, c->fd.chi2_hist, p, 8 * (size_t)kHistCap, hipMemcpyHostToDevice));
     p += 8 * (size_t)kHistCap;
     M2M_HIP(c, copy_sync(c->stream, c->fd.gprior, p, 8 * C, hipMemcpyHostToDevice));
+    p += 8 * C;
+    const size_t ST = scf_table_len(c->par);
+    if (ST > 0) M2M_HIP(c, copy_sync(c->stream, c->fd.scf_tab, p, 8 * ST, hipMemcpyHostToDevice));
     c->targets = h.targets != 0;
     c->ytil_init = h.ytil_init != 0;
     return M2M_OK;

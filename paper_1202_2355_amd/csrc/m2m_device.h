@@ -89,6 +89,7 @@ struct Tabs {
     double* csum;
     uint32_t* ccnt;
     T *rp, *re2, *Re2, *ve, *Vp, *isp, *rm;
+    unsigned char* end;  // first byte after the tables
 };
 
 template <typename T, typename A>
@@ -116,6 +117,7 @@ __device__ __forceinline__ Tabs<T, A> carve(unsigned char* raw, int J, int kp, i
     t.isp = p;
     p += n_R;
     t.rm = p;  // a_lm mesh radii (n_r + 1)
+    t.end = reinterpret_cast<unsigned char*>(p + n_r + 1);
     return t;
 }
 
@@ -235,8 +237,10 @@ __device__ __forceinline__ int bin_of(T v, const T* e, int n, T g, T lo, T hi) {
 
 // kinds of kinematic observables, fixed at compile time in k_step; the bit
 // kKinAlm selects the spherical-harmonic density observables instead of
-// radial bins
-enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4, kKinAlm = 8 };
+// radial bins,
+// kKinScf the self-consistent stellar potential
+enum : int { kKinNone = 0, kKinV2 = 1, kKinGH4 = 2, kKinGHN = 3, kKinLOSVD = 4, kKinAlm = 8,
+             kKinScf = 16 };
 
 template <int KIN>
 struct KinSlots {
@@ -271,6 +275,10 @@ constexpr double csqrt(double x) {  // compile-time square root (Newton)
 
 struct YlmCoef {
     double mm[kMaxLM + 1], m1[kMaxLM + 1], a[kMaxLM + 1][kMaxLM + 1], b[kMaxLM + 1][kMaxLM + 1];
+    // theta derivatives: d Pn_l^m / dt = l cos(t) Qn_l^m - e_lm Qn_{l-1}^m with
+    // Qn = Pn / sin(t) (m >= 1), e_lm = sqrt((2l + 1)(l^2 - m^2) / (2l - 1));
+    // d Pn_l^0 / dt = sqrt(l (l + 1)) Pn_l^1 = s_l sin(t) Qn_l^1
+    double e[kMaxLM + 1][kMaxLM + 1], s[kMaxLM + 1];
 };
 
 constexpr YlmCoef ylm_coef() {
@@ -283,6 +291,9 @@ constexpr YlmCoef ylm_coef() {
             c.a[l][m] = csqrt((4.0 * ll - 1.0) / (ll - mm2));
             c.b[l][m] = csqrt((l1 - mm2) / (4.0 * l1 - 1.0));
         }
+        for (int l = m + 1; l <= kMaxLM; ++l)
+            c.e[l][m] = csqrt((2.0 * l + 1.0) * (double(l) * l - double(m) * m) / (2.0 * l - 1.0));
+        c.s[m] = csqrt(double(m) * (m + 1.0));
     }
     return c;
 }
@@ -407,11 +418,12 @@ __device__ __forceinline__ T halo_phi(const Hot<T>& h, T R2, T z2) {
 }
 
 // s(r) with g = -s(r) * (x, y, z) for the spherical parts: G M(<r) / r^3
-template <typename T>
+// (without the Hernquist stars for STARS = false)
+template <typename T, bool STARS = true>
 __device__ __forceinline__ T accel_of(const Hot<T>& h, T r) {
     if (!(r > T(0))) return T(0);
     const T ra = r + h.a;
-    T s = h.GMh * Mth<T>::rcp_(r * ra * ra);
+    T s = STARS ? h.GMh * Mth<T>::rcp_(r * ra * ra) : T(0);
     if (h.GMn > T(0)) {
         const T q = r * h.irs;
         T m;
@@ -561,6 +573,230 @@ __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& 
     for (int m = 0; m < NS; ++m)
         if (m < kk.kn) atomicAdd(&tb.sum[(kk.jk + m) * kp + priv], (double)(w * kk.k[m]));
 }
+
+
+// ------------------------------------------------ self-consistent potential
+// The stellar potential of the particles as a multipole expansion,
+//   Phi_*(x) = sum_lm Phi_lm(r) Y_lm(theta, phi),
+//   Phi_lm(r) = -4 pi G / (2l + 1) [r^-(l+1) A_lm(r) + r^l B_lm(r)],
+//   A_lm(r) = sum_{r_i < r} m_i r_i^l Y_lm(x_i),  B_lm(r) = sum_{r_i >= r} m_i r_i^-(l+1) Y_lm(x_i),
+// known at the nodes rho_k with the slope r dPhi_lm/dr (node table). The step
+// kernel deposits u r^l Y_lm into the interval of each particle (0 below
+// rho_0, k + 1 for rho_k <= r < rho_{k+1}, K beyond the last node) for
+// intervals 0..K-1, and u r^-(l+1) Y_lm for intervals 1..K; the finalize
+// forms the prefix and suffix sums at the nodes. Between nodes Phi_lm is the
+// cubic Hermite interpolant in s = ln r; inside rho_0 the regular
+// r^l (c0 + c1 r^2), beyond the last node c0 r^-(l+1) + c1 r^l, each with the
+// value and slope of its end node.
+template <typename T>
+struct Scf {
+    int K, L, nlm;
+    T ls0, ih;       // ln rho_0, 1 / node spacing in ln r
+    const T* rho;    // K node radii (LDS)
+    const T* tab;    // K x nlm x (Phi, r dPhi/dr) (LDS)
+    double* bins;    // 2 K nlm interval sums (LDS)
+};
+
+// LDS bytes of the expansion: sums, node table and node radii
+__host__ __device__ inline size_t scf_lds_bytes(int K, int L, size_t sz) {
+    const size_t nlm = (size_t)(L + 1) * (size_t)(L + 1);
+    return 8 * 2 * (size_t)K * nlm + sz * ((size_t)K * nlm * 2 + (size_t)K) + 8;
+}
+
+template <typename T>
+__device__ __forceinline__ int scf_interval(const Scf<T>& s, T r) {
+    if (!(r >= s.rho[0])) return 0;
+    if (r >= s.rho[s.K - 1]) return s.K;
+    int k = (int)((Mth<T>::log_(r) - s.ls0) * s.ih);
+    k = min(max(k, 0), s.K - 2);
+    if (r < s.rho[k]) --k;  // the guess is within one interval
+    else if (r >= s.rho[k + 1]) ++k;
+    return k + 1;
+}
+
+// direction cosines of (x, y, z): cos, sin of the polar angle and of the
+// azimuth (the +x azimuth on the z axis, the +z pole at the centre)
+template <typename T>
+__device__ __forceinline__ void scf_dir(T x, T y, T z, T r, T R, T& ct, T& st, T& cp, T& sp) {
+    const T ir = r > T(0) ? Mth<T>::rcp_(r) : T(0);
+    ct = r > T(0) ? z * ir : T(1);
+    st = R * ir;
+    const T iR = R > T(0) ? Mth<T>::rcp_(R) : T(0);
+    cp = R > T(0) ? x * iR : T(1);
+    sp = y * iR;
+}
+
+// deposit of one particle of weight u into the interval sums
+template <typename T>
+__device__ __forceinline__ void scf_deposit(const Scf<T>& s, T x, T y, T z, T u) {
+    const T R2 = x * x + y * y;
+    const T r = Mth<T>::sqrt_(R2 + z * z), R = Mth<T>::sqrt_(R2);
+    T ct, st, cp, sp;
+    scf_dir<T>(x, y, z, r, R, ct, st, cp, sp);
+    const int q = scf_interval<T>(s, r);
+    const T ir = r > T(0) ? Mth<T>::rcp_(r) : T(0);
+    double* const A = q < s.K ? s.bins + q * s.nlm : nullptr;
+    double* const B = q > 0 ? s.bins + (s.K + q - 1) * s.nlm : nullptr;
+    T pmm = T(0.282094791773878143);  // 1/sqrt(4 pi)
+    T cm = T(1), sm = T(0);
+    T rm = u, irm = u * ir;  // u r^m, u r^-(m+1)
+    for (int m = 0; m <= s.L; ++m) {
+        if (m > 0) {
+            pmm = -T(kYlm.mm[m]) * st * pmm;
+            const T c = cm * cp - sm * sp;
+            sm = sm * cp + cm * sp;
+            cm = c;
+            rm *= r;
+            irm *= ir;
+        }
+        const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
+        T p2 = T(0), p1 = pmm, rl = rm, irl = irm;
+        for (int l = m; l <= s.L; ++l) {
+            if (l == m + 1) {
+                p2 = p1;
+                p1 = T(kYlm.m1[m]) * ct * pmm;
+            } else if (l > m + 1) {
+                const T p = T(kYlm.a[l][m]) * (ct * p1 - T(kYlm.b[l][m]) * p2);
+                p2 = p1;
+                p1 = p;
+            }
+            if (l > m) {
+                rl *= r;
+                irl *= ir;
+            }
+            const int j = l * l + l;
+            if (m == 0) {
+                if (A) atomicAdd(&A[j], (double)(rl * p1));
+                if (B) atomicAdd(&B[j], (double)(irl * p1));
+            } else {
+                const T yc = p1 * c2, ys = p1 * s2;
+                if (A) {
+                    atomicAdd(&A[j + m], (double)(rl * yc));
+                    atomicAdd(&A[j - m], (double)(rl * ys));
+                }
+                if (B) {
+                    atomicAdd(&B[j + m], (double)(irl * yc));
+                    atomicAdd(&B[j - m], (double)(irl * ys));
+                }
+            }
+        }
+    }
+}
+
+// g = -grad Phi_* at (x, y, z): dPhi/dr, (1/r) dPhi/dtheta and
+// (1/(r sin theta)) dPhi/dphi, with Qn = Pn / sin(theta) carried by the
+// same recurrences as Pn (no division on the axis); zero at the centre
+template <typename T>
+__device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx, T& gy, T& gz) {
+    gx = gy = gz = T(0);
+    const T R2 = x * x + y * y, r2 = R2 + z * z;
+    if (!(r2 > T(0))) return;
+    const T r = Mth<T>::sqrt_(r2), R = Mth<T>::sqrt_(R2);
+    T ct, st, cp, sp;
+    scf_dir<T>(x, y, z, r, R, ct, st, cp, sp);
+    const int nlm = s.nlm;
+    // radial region: 0 core (node 0), 1 between nodes k0 and k0 + 1, 2 beyond
+    // the last node (node k0 = K - 1)
+    const int q = scf_interval<T>(s, r);
+    const int reg = q == 0 ? 0 : (q == s.K ? 2 : 1);
+    const int k0 = q == 0 ? 0 : q - 1;
+    T v = T(1), iv = T(1), v2 = T(1);
+    T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0);
+    if (reg == 1) {
+        const T t = fmin(fmax((Mth<T>::log_(r) - s.ls0) * s.ih - T(k0), T(0)), T(1));
+        const T t2 = t * t, t3 = t2 * t, h = Mth<T>::rcp_(s.ih);
+        w0 = T(2) * t3 - T(3) * t2 + T(1);
+        w1 = h * (t3 - T(2) * t2 + t);
+        w2 = T(3) * t2 - T(2) * t3;
+        w3 = h * (t3 - t2);
+        e0 = (T(6) * t2 - T(6) * t) * s.ih;
+        e1 = T(3) * t2 - T(4) * t + T(1);
+        e2 = -e0;
+        e3 = T(3) * t2 - T(2) * t;
+    } else {
+        v = r * Mth<T>::rcp_(s.rho[k0]);
+        iv = Mth<T>::rcp_(v);
+        v2 = v * v;
+    }
+    // Phi_lm and r dPhi_lm/dr at r; vl = v^l, ivl = v^-(l+1)
+    auto radial = [&](int l, int lm, T vl, T ivl, T& f, T& d) {
+        const T* t0 = s.tab + (k0 * nlm + lm) * 2;
+        const T P0 = t0[0], D0 = t0[1];
+        const T fl = T(l);
+        if (reg == 1) {
+            const T P1 = t0[2 * nlm], D1 = t0[2 * nlm + 1];
+            f = w0 * P0 + w1 * D0 + w2 * P1 + w3 * D1;
+            d = e0 * P0 + e1 * D0 + e2 * P1 + e3 * D1;
+        } else if (reg == 0) {
+            const T c = T(0.5) * (D0 - fl * P0);
+            f = vl * (P0 + c * (v2 - T(1)));
+            d = vl * (fl * P0 + c * ((fl + T(2)) * v2 - fl));
+        } else {
+            const T i21 = Mth<T>::rcp_(T(2) * fl + T(1));
+            const T cA = (fl * P0 - D0) * i21, cB = ((fl + T(1)) * P0 + D0) * i21;
+            f = cA * ivl + cB * vl;
+            d = (fl * cB * vl - (fl + T(1)) * cA * ivl);
+        }
+    };
+    T fr = T(0), fth = T(0), fph = T(0);
+    T pmm = T(0.282094791773878143);  // Pn_m^m (m = 0: 1/sqrt(4 pi))
+    T cm = T(1), sm = T(0), vm = T(1), ivm = iv;
+    for (int m = 0; m <= s.L; ++m) {
+        T qmm = T(0);  // Qn_m^m
+        if (m > 0) {
+            qmm = -T(kYlm.mm[m]) * pmm;
+            pmm = st * qmm;
+            const T c = cm * cp - sm * sp;
+            sm = sm * cp + cm * sp;
+            cm = c;
+            vm *= v;
+            ivm *= iv;
+        }
+        const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
+        // column m: X_l = Pn_l^0 for m = 0, Qn_l^m for m >= 1
+        T x2 = T(0), x1 = (m == 0) ? pmm : qmm, vl = vm, ivl = ivm;
+        for (int l = m; l <= s.L; ++l) {
+            if (l == m + 1) {
+                x2 = x1;
+                x1 = T(kYlm.m1[m]) * ct * x1;
+            } else if (l > m + 1) {
+                const T xn = T(kYlm.a[l][m]) * (ct * x1 - T(kYlm.b[l][m]) * x2);
+                x2 = x1;
+                x1 = xn;
+            }
+            if (l > m) {
+                vl *= v;
+                ivl *= iv;
+            }
+            const int j = l * l + l;
+            if (m == 0) {
+                T f, d;
+                radial(l, j, vl, ivl, f, d);
+                fr += d * x1;
+            } else {
+                const T pn = st * x1;
+                const T dth = T(l) * ct * x1 - (l > m ? T(kYlm.e[l][m]) * x2 : T(0));
+                T fp, dp, fm, dm;
+                radial(l, j + m, vl, ivl, fp, dp);
+                radial(l, j - m, vl, ivl, fm, dm);
+                fr += (dp * c2 + dm * s2) * pn;
+                fth += (fp * c2 + fm * s2) * dth;
+                fph += T(m) * x1 * (fm * c2 - fp * s2);
+                if (m == 1) {  // the theta derivative of the m = 0 term of degree l
+                    T f0, d0;
+                    radial(l, j, vl, ivl, f0, d0);
+                    fth += f0 * T(kYlm.s[l]) * pn;
+                }
+            }
+        }
+    }
+    const T ir = Mth<T>::rcp_(r);
+    const T gr = fr * ir, gt = fth * ir, gp = fph * ir;
+    gx = -(gr * st * cp + gt * ct * cp - gp * sp);
+    gy = -(gr * st * sp + gt * ct * sp + gp * cp);
+    gz = -(gr * ct - gt * st);
+}
+
 
 
 }  // namespace

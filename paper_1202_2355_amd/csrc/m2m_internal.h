@@ -22,6 +22,7 @@ constexpr int kSmoothMaxPoints = 256; // and at most this many first-stage searc
 constexpr int kGcvSlots = 5;          // lambda points a wave scores in one pass over the cells
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
 constexpr int kSegAlign = 64;      // tile boundaries are multiples of 64 particles
+constexpr int kMaxScfNodes = 64;   // largest node count of the self-consistent potential
 
 // kernel launch modes (bit set)
 enum : int32_t {
@@ -30,6 +31,7 @@ enum : int32_t {
     kModeObserve = 4,    // deposit the current state into obs_out only
     kModeCells = 8,      // accumulate the prior cells of the current state only
     kModeWriteThrough = 16,  // step: particle stores write through L2 (small fits)
+    kModePot = 32,       // rebuild the self-consistent potential from the current state only
 };
 
 // Particle state up to this size is stepped with write-through stores: it
@@ -69,7 +71,7 @@ struct FitDev {
     void* rmesh;             // a_lm mesh radii (n_r + 1, state dtype)
     double *Y, *sigma, *yv, *ytil, *delta, *obs_out;
     double *partials;        // tile rows of row_len doubles
-    int32_t row_len;         // J + 2 C
+    int32_t row_len;         // J + 2 C (+ scf_P)
     int32_t kpriv;           // private copies of the in-tile bins (power of 2)
     int32_t smooth;          // thin-plate smoothing of the prior grid at refreshes
     int32_t n_bin_jobs;      // ceil(J / kFinCols)
@@ -93,6 +95,17 @@ struct FitDev {
     int32_t sm_k1, pad3;         // points of the first search stage
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
     double hv2, hr02, hiq2;      // logarithmic halo: v0^2 (0: none), r0^2, 1/q^2
+    // self-consistent stellar potential (scf_nr = 0: none): a multipole
+    // expansion to degree scf_lmax with node values at scf_nr radii
+    // log-spaced from scf_rho[0]; the tile rows carry its scf_P interval sums
+    // from column scf_col0 (after the cell columns), reduced by n_pot_jobs
+    // finalize jobs on the steps that rebuild it (every scf_every steps)
+    int32_t scf_nr, scf_lmax, scf_every, scf_col0, scf_P, n_pot_jobs;
+    double scf_ls0, scf_ih;      // ln rho_0, 1 / node spacing in ln r
+    double scf_c;                // G upsilon M / N: Phi scale per unit weight u
+    double *scf_rho;             // node radii (FP64)
+    double *scf_sum;             // interval sums of the last rebuild (scf_P)
+    double *scf_tab;             // nodes x (l, m): Phi_lm(rho_k), r dPhi_lm/dr there
     // step constants
     double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
     double *chi2_hist;
@@ -123,7 +136,7 @@ __host__ __device__ inline Tile tile_of(int64_t n, int t, int count, int fit, in
 // One finalize block: kFinCols columns of one fit.
 struct FinJob {
     int32_t fit;
-    int32_t kind;  // 0: observable columns, 1: cell columns
+    int32_t kind;  // 0: observable columns, 1: cell columns, 2: potential columns
     int32_t col0;
     int32_t n_tiles;  // rows of the fit to reduce
 };
@@ -133,7 +146,6 @@ struct FinJob {
 hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* fits,
                        const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
                        hipStream_t s);
-int kin_class(int kin, int gh_nmax, int dens);
 // the column jobs of the fits of the table (n_fits of them)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
                            int n_jobs, int32_t mode, hipStream_t s);
@@ -158,7 +170,9 @@ hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double sc
 hipError_t launch_poke(FitState* st, int32_t steps_left, int32_t correct, hipStream_t s);
 hipError_t launch_gather(const FitDev* fits, int n, int32_t* out, hipStream_t s);
 hipError_t launch_residuals(bool f64, const FitDev* fit, hipStream_t s);
-size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C);
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C,
+                      int scf_nr, int scf_lmax);
+int kin_class(int kin, int gh_nmax, int dens, bool scf);
 int private_copies(bool f64, int J);
 
 }  // namespace m2m

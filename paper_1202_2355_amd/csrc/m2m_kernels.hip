@@ -33,7 +33,7 @@ namespace {
 //   the end of the step: chi^2 from the parts of the bin jobs and the step
 //   counters, prior schedule and assignment flag.
 struct Flags {
-    bool step, cells_mode, observe, init, correct, refresh;
+    bool step, cells_mode, observe, init, correct, refresh, pot_mode, pot;
 };
 
 // The fit's counters as the launch found them: only the block that ends the
@@ -62,6 +62,11 @@ __device__ __forceinline__ Flags flags_of(const FitDev& fd, const Snap& ss, int3
     f.correct = f.step && ss.correct != 0;
     f.refresh = f.cells_mode || (f.correct && fd.entropy == 0 && fd.prior_every > 0 &&
                                  ((ss.kstep + 1) % fd.prior_every) == 0);
+    // the self-consistent potential is rebuilt (kModePot alone, or every
+    // scf_every steps)
+    f.pot_mode = (mode & kModePot) != 0;
+    f.pot = fd.scf_nr > 0 &&
+            (f.pot_mode || (f.step && ((ss.tstep + 1) % fd.scf_every) == 0));
     return f;
 }
 
@@ -383,6 +388,42 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
     }
 }
 
+// The node table of the self-consistent potential from the reduced interval
+// sums (one thread per (l, m)): at node k, A_lm = the sums u r^l Y_lm of
+// intervals 0..k (particles inside rho_k), B_lm = the sums u r^-(l+1) Y_lm of
+// intervals k+1..K (at or outside rho_k), and
+//   Phi_lm = -4 pi c / (2l + 1) [rho^-(l+1) A_lm + rho^l B_lm],
+//   r dPhi_lm/dr = -4 pi c / (2l + 1) [-(l+1) rho^-(l+1) A_lm + l rho^l B_lm],
+// c = G upsilon M / N (the mass of a particle per unit weight, times G).
+__device__ __forceinline__ void build_scf_table(const FitDev& fd) {
+    const int K = fd.scf_nr, L = fd.scf_lmax, nlm = (L + 1) * (L + 1);
+    const int lm = threadIdx.x;
+    if (lm >= nlm) return;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    const G<const double> a = gmem<const double>(fd.scf_sum);
+    const G<const double> b = a + (size_t)K * nlm;  // interval q >= 1 at (q - 1) nlm
+    const G<const double> rho = gmem<const double>(fd.scf_rho);
+    const G<double> tab = gmem(fd.scf_tab);
+    const double c = -4.0 * M_PI * fd.scf_c / (2.0 * l + 1.0);
+    double A = 0.0;
+    for (int k = 0; k < K; ++k) {
+        A += a[(size_t)k * nlm + lm];
+        tab[((size_t)k * nlm + lm) * 2] = A;  // A_lm(rho_k) for now
+    }
+    double B = 0.0;
+    for (int k = K - 1; k >= 0; --k) {
+        B += b[(size_t)k * nlm + lm];  // interval k + 1
+        const double Ak = tab[((size_t)k * nlm + lm) * 2];
+        const double r = rho[k];
+        double rl = 1.0;
+        for (int i = 0; i < l; ++i) rl *= r;
+        const double ra = 1.0 / (rl * r);
+        tab[((size_t)k * nlm + lm) * 2] = c * (ra * Ak + rl * B);
+        tab[((size_t)k * nlm + lm) * 2 + 1] = c * (-(l + 1.0) * ra * Ak + l * rl * B);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb, int32_t mode) {
     __shared__ double part[kFinWaves][kFinCols];
@@ -396,17 +437,18 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     const bool step = (mode & kModeStep) != 0;
     const bool cells_mode = (mode & kModeCells) != 0;
     const bool observe = (mode & kModeObserve) != 0;
-    const bool bins = jb.kind == 0;
+    const bool pot_mode = (mode & kModePot) != 0;
+    const bool bins = jb.kind == 0, pots = jb.kind == 2;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = jb.col0 + lane;
-    const bool in = col < (bins ? fd.J : fd.C);
+    const bool in = col < (bins ? fd.J : pots ? fd.scf_P : fd.C);
 
     // observable columns: the rows and the smoothing inputs are requested
     // before the fit's state is known (their latency overlaps its load)
     double acc = 0.0, acc2 = 0.0;
     double yt0 = 0.0, sg = 1.0, Yj = 0.0;
-    if (bins && !cells_mode && in) {
+    if (bins && !cells_mode && !pot_mode && in) {
         group_sum<16>(fd, true, col, jb.n_tiles, wave, acc, acc2);
         if (wave == 0 && !observe) {
             yt0 = gmem(fd.ytil)[col];
@@ -417,10 +459,13 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     const Snap ss = snap_of(gst);
     if (step && ss.steps_left <= 0) return;  // uniform: the fit is idle
     const Flags f = flags_of(fd, ss, mode);
-    if (bins && cells_mode) return;
-    if (!bins && !f.refresh) return;
-    // cell columns, read only on refresh steps
-    if (!bins && in) group_sum<8>(fd, false, col, jb.n_tiles, wave, acc, acc2);
+    if (bins && (cells_mode || pot_mode)) return;
+    if (jb.kind == 1 && !f.refresh) return;
+    if (pots && !f.pot) return;
+    // cell columns, read only on refresh steps; potential columns only on
+    // the steps that rebuild it
+    if (jb.kind == 1 && in) group_sum<8>(fd, false, col, jb.n_tiles, wave, acc, acc2);
+    if (pots && in) group_sum<16>(fd, true, fd.scf_col0 + col, jb.n_tiles, wave, acc, acc2);
     part[wave][lane] = acc;
     part2[wave][lane] = acc2;
     __syncthreads();
@@ -430,12 +475,18 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
             tot += part[w][lane];
             tot2 += part2[w][lane];
         }
-        (void)column_epilogue<T>(fd, bins, jb.col0, f, tot, tot2, yt0, sg, Yj, lane);
+        if (pots) {
+            if (in) gmem(fd.scf_sum)[col] = tot;
+        } else {
+            (void)column_epilogue<T>(fd, bins, jb.col0, f, tot, tot2, yt0, sg, Yj, lane);
+        }
     }
     // the last job of this fit ends the step; in observe mode the same
     // hand-over runs on a separate counter and changes no state
-    const uint32_t n_part = (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
-                            (f.refresh ? (uint32_t)fd.n_cell_jobs : 0u);
+    const uint32_t n_part = pot_mode ? (uint32_t)fd.n_pot_jobs
+                                     : (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
+                                           (f.refresh ? (uint32_t)fd.n_cell_jobs : 0u) +
+                                           (f.pot ? (uint32_t)fd.n_pot_jobs : 0u);
     uint32_t* ticket = observe ? &st->mticket : &st->ticket;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -459,12 +510,15 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
                              &sidx, &smean);
         }
     }
+    // the node table of the self-consistent potential from the new sums
+    if (f.pot) build_scf_table(fd);
     if (wave != 0) return;
-    const double chi2 =
-        cells_mode ? 0.0 : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
+    const double chi2 = (cells_mode || pot_mode)
+                            ? 0.0
+                            : chi2_of_parts(static_cast<const double*>(fd.chi2_part), fd.n_bin_jobs, lane);
     if (lane != 0) return;
     *ticket = 0u;
-    if (observe) return;
+    if (observe || pot_mode) return;
     end_step(fd, gst, f, ss, chi2);
 }
 
@@ -478,13 +532,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restri
 }
 
 // one fit, its description passed by value: block b < n_bin_jobs takes bin
-// columns, the others cell columns, over n_rows tile rows
+// columns, then n_cell_jobs blocks cell columns, then n_pot_jobs blocks the
+// columns of the self-consistent potential, over n_rows tile rows
 template <typename T>
 __global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int32_t n_rows,
                                                           int32_t mode) {
     const int b = blockIdx.x;
-    const bool bins = b < fd.n_bin_jobs;
-    const FinJob jb{0, bins ? 0 : 1, (bins ? b : b - fd.n_bin_jobs) * kFinCols, n_rows};
+    const int nb = fd.n_bin_jobs, nc = fd.n_cell_jobs;
+    const int kind = b < nb ? 0 : (b < nb + nc ? 1 : 2);
+    const int base = kind == 0 ? 0 : (kind == 1 ? nb : nb + nc);
+    const FinJob jb{0, kind, (b - base) * kFinCols, n_rows};
     finalize_job<T>(fd, jb, mode);
 }
 
@@ -572,13 +629,15 @@ static hipError_t launch_step_any(bool f64, bool acc64, int block, int kin, cons
 }
 
 
-size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C) {
+size_t step_lds_bytes(bool f64, bool acc64, int J, int n_r, int n_R, int n_v, int kpriv, int C,
+                      int scf_nr, int scf_lmax) {
     (void)acc64;  // FP64 sums and FP32 sum + compensation both take 8 bytes per bin copy
     const size_t sz = f64 ? 8 : 4;
     const size_t bins = (size_t)J * (size_t)kpriv * 8 + (size_t)C * 8 + (size_t)((C + 1) & ~1) * 4;
     const size_t tabs = ((size_t)J + 2 * (size_t)(n_r + 1) + (size_t)(n_R + 1) + (size_t)(n_v + 1) +
                          2 * (size_t)n_R) * sz;
-    return ((bins + tabs + 15) / 16) * 16;
+    const size_t scf = scf_nr > 0 ? scf_lds_bytes(scf_nr, scf_lmax, sz) : 0;
+    return ((bins + tabs + scf + 15) / 16) * 16;
 }
 
 // Private bin copies: as many as fit in 48 KiB of LDS, at most 8.
@@ -590,8 +649,8 @@ int private_copies(bool f64, int J) {
     return k;
 }
 
-int kin_class(int kin, int gh_nmax, int dens) {
-    const int alm = dens == 1 ? kKinAlm : 0;
+int kin_class(int kin, int gh_nmax, int dens, bool scf) {
+    const int alm = (dens == 1 ? kKinAlm : 0) | (scf ? kKinScf : 0);
     switch (kin) {
         case 0: return alm | kKinNone;
         case 1: return alm | kKinV2;
@@ -625,7 +684,7 @@ hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJo
 }
 
 hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s) {
-    const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs;
+    const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs + fd.n_pot_jobs;
     if (n_jobs <= 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(k_finalize1<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fd, n_rows,

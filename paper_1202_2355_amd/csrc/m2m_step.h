@@ -51,11 +51,16 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     const G<const FitState> st = gmem<const FitState>(fd.st);
     if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
     const bool cells_only = (mode & kModeCells) != 0;
+    const bool pot_only = (mode & kModePot) != 0;
+    // the steps that rebuild the self-consistent potential deposit into its
+    // interval sums after the push
+    const bool scf_dep = (KIN & kKinScf) &&
+                         (pot_only || (step && ((st->tstep + 1) % fd.scf_every) == 0));
     const bool correct = step && st->correct != 0;
     const bool refresh = cells_only || (correct && fd.entropy == 0 && fd.prior_every > 0 &&
                                         ((st->kstep + 1) % fd.prior_every) == 0);
     const bool assign = step && st->assign_pending != 0;
-    const bool deposit_on = !cells_only;
+    const bool deposit_on = !cells_only && !pot_only;
     const bool push = step;
     const bool wt = (mode & kModeWriteThrough) != 0;
     const Hot<T> h = hot_of<T>(fd);
@@ -91,6 +96,32 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             tb.Vp[j] = Vp[j];
             tb.isp[j] = isp[j];
         }
+    }
+    // the self-consistent potential: interval sums, node table and radii
+    // after the tables
+    Scf<T> sc{};
+    if (KIN & kKinScf) {
+        double* sb = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(tb.end) + 7) &
+                                               ~uintptr_t(7));
+        sc.K = fd.scf_nr;
+        sc.L = fd.scf_lmax;
+        sc.nlm = (fd.scf_lmax + 1) * (fd.scf_lmax + 1);
+        sc.ls0 = T(fd.scf_ls0);
+        sc.ih = T(fd.scf_ih);
+        const int nt = sc.K * sc.nlm * 2;
+        T* tt = reinterpret_cast<T*>(sb + nt);
+        T* rr = tt + nt;
+        sc.bins = sb;
+        sc.tab = tt;
+        sc.rho = rr;
+        if (push) {
+            const G<const double> stab = gmem<const double>(fd.scf_tab);
+            for (int j = threadIdx.x; j < nt; j += BLOCK) tt[j] = T(stab[j]);
+        }
+        const G<const double> srho = gmem<const double>(fd.scf_rho);
+        for (int j = threadIdx.x; j < sc.K; j += BLOCK) rr[j] = T(srho[j]);
+        if (scf_dep)
+            for (int j = threadIdx.x; j < nt; j += BLOCK) sb[j] = 0.0;
     }
     const G<double> row = gmem(fd.partials) + (size_t)tl.row * (size_t)fd.row_len;
     const G<const T> __restrict__ ucell = gmem<const T>(fd.ucell);
@@ -139,7 +170,9 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             y += h.hdt * vy;
             z += h.hdt * vz;
             const T R2 = x * x + y * y, z2 = z * z;
-            T s = accel_of<T>(h, Mth<T>::sqrt_(R2 + z2)) * h.dt;
+            // with the self-consistent potential the expansion takes the
+            // place of the Hernquist stars
+            T s = accel_of<T, (KIN & kKinScf) == 0>(h, Mth<T>::sqrt_(R2 + z2)) * h.dt;
             T sz = s;
             if (h.halo) {  // logarithmic halo: -v0^2 (x, y, z/q^2) / (r0^2 + R^2 + z^2/q^2)
                 const T sh = h.hv2 * Mth<T>::rcp_(h.hr02 + R2 + z2 * h.hiq2) * h.dt;
@@ -149,11 +182,19 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             vx -= s * x;
             vy -= s * y;
             vz -= sz * z;
+            if (KIN & kKinScf) {
+                T gx, gy, gz;
+                scf_accel<T>(sc, x, y, z, gx, gy, gz);
+                vx += h.dt * gx;
+                vy += h.dt * gy;
+                vz += h.dt * gz;
+            }
             x += h.hdt * vx;
             y += h.hdt * vy;
             z += h.hdt * vz;
         }
         if (deposit_on) deposit<T, KIN>(h, tb, kernels<T, A, KIN>(h, tb, x, y, z, vz), u, priv);
+        if ((KIN & kKinScf) && scf_dep) scf_deposit<T>(sc, x, y, z, u);
         if (refresh) {
             const int c = cell_of<T>(h, x, y, z, vx, vy, vz);
             atomicAdd(&tb.csum[c], (double)u);
@@ -195,6 +236,8 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             row[J + j] = tb.csum[j];
             row[J + C + j] = (double)tb.ccnt[j];
         }
+    if ((KIN & kKinScf) && scf_dep)
+        for (int j = threadIdx.x; j < fd.scf_P; j += BLOCK) row[fd.scf_col0 + j] = sc.bins[j];
 }
 
 // the tiles of the fits of a table (batches)
@@ -225,20 +268,31 @@ hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* on
     return hipGetLastError();
 }
 
+// kinds of observables with the compile-time bits HI (a_lm, self-consistent
+// potential) set
+template <typename T, typename A, int BLOCK, int HI>
+hipError_t launch_step_lo(int lo, const FitDev* fits, const Tile* tiles, const FitDev* one,
+                          int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
+    switch (lo) {
+        case kKinNone: return launch_step_t<T, A, BLOCK, HI | kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinV2: return launch_step_t<T, A, BLOCK, HI | kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGH4: return launch_step_t<T, A, BLOCK, HI | kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinGHN: return launch_step_t<T, A, BLOCK, HI | kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinLOSVD: return launch_step_t<T, A, BLOCK, HI | kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, typename A, int BLOCK>
 hipError_t launch_step_kin(int kin, const FitDev* fits, const Tile* tiles, const FitDev* one,
                            int n_tiles, size_t lds, int32_t mode, hipStream_t s) {
-    switch (kin) {
-        case kKinNone: return launch_step_t<T, A, BLOCK, kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinV2: return launch_step_t<T, A, BLOCK, kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinGH4: return launch_step_t<T, A, BLOCK, kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinGHN: return launch_step_t<T, A, BLOCK, kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinAlm | kKinNone: return launch_step_t<T, A, BLOCK, kKinAlm | kKinNone>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinAlm | kKinV2: return launch_step_t<T, A, BLOCK, kKinAlm | kKinV2>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinAlm | kKinGH4: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGH4>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinAlm | kKinGHN: return launch_step_t<T, A, BLOCK, kKinAlm | kKinGHN>(fits, tiles, one, n_tiles, lds, mode, s);
-        case kKinAlm | kKinLOSVD: return launch_step_t<T, A, BLOCK, kKinAlm | kKinLOSVD>(fits, tiles, one, n_tiles, lds, mode, s);
+    const int lo = kin & 7;
+    switch (kin & ~7) {
+        case 0: return launch_step_lo<T, A, BLOCK, 0>(lo, fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm: return launch_step_lo<T, A, BLOCK, kKinAlm>(lo, fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinScf: return launch_step_lo<T, A, BLOCK, kKinScf>(lo, fits, tiles, one, n_tiles, lds, mode, s);
+        case kKinAlm | kKinScf:
+            return launch_step_lo<T, A, BLOCK, kKinAlm | kKinScf>(lo, fits, tiles, one, n_tiles, lds, mode, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -98,6 +98,20 @@ class Fit:
     def update_priors(self):
         self._chk(A.lib().m2m_update_priors(self.ctx), "m2m_update_priors")
 
+    def refresh_potential(self):
+        """Rebuild the self-consistent stellar potential from the current
+        particles and weights (params scf_nr > 0)."""
+        self._chk(A.lib().m2m_refresh_potential(self.ctx), "m2m_refresh_potential")
+
+    def potential_table(self) -> np.ndarray:
+        """Node table of the self-consistent potential: array (scf_nr,
+        (scf_lmax+1)^2, 2) of Phi_lm(rho_k) and r dPhi_lm/dr there."""
+        K, L = int(self.params.get("scf_nr", 0)), int(self.params.get("scf_lmax", 0))
+        out = np.zeros(max(K * (L + 1) ** 2 * 2, 1))
+        self._chk(A.lib().m2m_get_potential(self.ctx, _dp(out), int(out.size)),
+                  "m2m_get_potential")
+        return out.reshape(K, (L + 1) ** 2, 2)
+
     def weights(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.float64 if self.dtype == "f64" else np.float32)
         self._chk(A.lib().m2m_get_weights(self.ctx, out.ctypes.data_as(C.c_void_p), 0),

@@ -35,6 +35,7 @@ from .configs import (  # noqa: F401
     J_of,
     rng,
     with_alm,
+    with_scf,
 )
 from .targets import (  # noqa: F401
     add_noise, density_length, fit_gauss_hermite_centres, floor_model_noise, make_targets)

@@ -79,6 +79,17 @@ def with_alm(wl: "Workload", n_mesh: int = 60, l_max: int = 4) -> "Workload":
     return wl.with_(name=f"{wl.name}_alm{l_max}", layout=lay)
 
 
+def with_scf(wl: "Workload", l_max: int = 4, n_nodes: int = 32, r_min: float = 0.02,
+             r_max: float = 100.0, every: int = 10) -> "Workload":
+    """The workload with its stellar potential computed from the particles (a
+    multipole expansion to degree l_max with n_nodes log-spaced nodes over
+    [r_min, r_max], rebuilt every `every` steps; Sec. 2.1, Sec. 5) instead of
+    the analytic Hernquist part."""
+    par = dict(wl.params, scf_lmax=int(l_max), scf_nr=int(n_nodes), scf_rmin=float(r_min),
+               scf_rmax=float(r_max), scf_every=int(every))
+    return wl.with_(name=f"{wl.name}_scf{l_max}", params=par)
+
+
 def make_params(pot: Potential, dt=0.01, eps=0.1, mu=1e-2, alpha=2.1, mass=1.0,
                 entropy="mpr", n_E=20, n_x=10, prior_every=25, smooth=0):
     """Step parameters. alpha is the smoothing rate per unit time (the
