@@ -219,6 +219,11 @@ def main(argv=None):
     ap.add_argument("--alm", type=int, default=None, metavar="L",
                     help="workloads 1-3: spherical-harmonic density observables a_lm (l <= L) "
                          "on a 60-point radial mesh instead of the radial mass bins")
+    ap.add_argument("--scf", type=int, default=None, metavar="L",
+                    help="workloads 1-3: the stellar potential from the particles, a multipole "
+                         "expansion (l <= L, 32 nodes on [0.02, 100]) instead of the Hernquist part")
+    ap.add_argument("--scf-every", type=int, default=10,
+                    help="with --scf: steps between rebuilds of the expansion")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the M2M path here is a "
@@ -270,6 +275,10 @@ def main(argv=None):
         wl = with_alm(wl, n_mesh=60, l_max=args.alm)
     if args.smooth:
         wl.params = dict(wl.params, smooth=1)
+    if args.scf is not None:
+        from workloads import with_scf
+        wl = with_scf(wl, l_max=args.scf, n_nodes=32, r_min=0.02, r_max=100.0,
+                      every=args.scf_every)
     dtype = wl.state
     print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={LAUNCH[args.workload]}",
           file=sys.stderr, flush=True)
@@ -318,6 +327,10 @@ def main(argv=None):
                    "prior_smoothing": bool(wl.params.get("smooth", 0)),
                    "density": (f"alm l<={wl.layout['l_max']} on {wl.layout['n_r']} radii"
                                if wl.layout.get("dens") == "alm" else "radial bins"),
+                   "stellar_potential": (
+                       f"multipole l<={wl.params['scf_lmax']}, {wl.params['scf_nr']} nodes, "
+                       f"rebuilt every {wl.params['scf_every']} steps"
+                       if wl.params.get("scf_nr", 0) else "analytic"),
                    "launch": list(LAUNCH[args.workload])},
         "latency": {"p50_s": ms * 1e-3, "p99_s": ms * 1e-3,
                     "fit": f"one fit, {args.steps} steps, device time"},

@@ -95,9 +95,10 @@
  *     exact with its slope r dPhi_lm/dr at the nodes
  *     rho_k = scf_rmin (scf_rmax/scf_rmin)^(k/(scf_nr-1)); between nodes
  *     Phi_lm is the cubic Hermite interpolant of value and slope in ln r,
- *     inside rho_0 r^l (c0 + c1 r^2), beyond the last node
- *     c0 r^-(l+1) + c1 r^l, each matching the end node. The force is its
- *     exact gradient (zero at r = 0). The expansion is built from the
+ *     inside rho_0 r^l (c0 + c1 r^2), beyond the last node the decaying
+ *     c0 r^-(l+1) + c1 r^-(l+3), each matching value and slope at the end
+ *     node. The force is its exact gradient (zero at r = 0). Particles with
+ *     a non-finite radius add nothing to the expansion. The expansion is built from the
  *     particles and weights when the targets are first set (or by
  *     m2m_refresh_potential) and rebuilt after the push of every step k with
  *     (k + 1) % scf_every == 0, counting steps of every kind from 0, from

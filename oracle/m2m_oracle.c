@@ -319,8 +319,11 @@ double orc_ylm(int l, int m, double ct, double phi) {
  *   r dPhi_lm/dr = -4 pi G / (2l + 1) [-(l+1) r^-(l+1) A_lm + l r^l B_lm]
  * (the terms of dA/dr and dB/dr cancel). Between nodes Phi_lm is the cubic
  * Hermite interpolant of these values and slopes in s = ln r; inside rho_0 it
- * is the regular r^l (c0 + c1 r^2), beyond the last node c0 r^-(l+1) + c1 r^l,
- * each with the value and slope of its end node. Table entry
+ * is the regular r^l (c0 + c1 r^2), beyond the last node the decaying
+ * c0 r^-(l+1) + c1 r^-(l+3) (the potential of a bounded mass falls off; the
+ * form is exact when no mass lies beyond the last node), each with the value
+ * and slope of its end node. Particles with a non-finite radius add nothing.
+ * Table entry
  * (k (scf_lmax+1)^2 + l^2 + l + m) 2 holds Phi_lm(rho_k), the next one
  * r dPhi_lm/dr there. */
 static int nthreads_of(int32_t want);
@@ -355,6 +358,7 @@ void orc_scf_table(const orc_potential *p, int64_t n, const double *x, const dou
                 int lm = l * l + l + m;
                 double A = 0.0, B = 0.0;
                 for (int64_t i = 0; i < n; ++i) {
+                    if (!isfinite(r[i])) continue;
                     if (r[i] < rho)
                         A += pow(r[i], l) * mY[i * nlm + lm];
                     else
@@ -385,10 +389,10 @@ static void scf_radial(const orc_potential *p, const double *tab, int nlm, int l
     if (r >= r1) {
         const double *t = tab + ((K - 1) * nlm + lm) * 2;
         double P = t[0], D = t[1], v = r / r1;
-        double cA = (l * P - D) / (2.0 * l + 1.0), cB = ((l + 1) * P + D) / (2.0 * l + 1.0);
-        double va = pow(v, -(l + 1)), vb = pow(v, l);
-        *f = cA * va + cB * vb;
-        *d = -(l + 1) * cA * va + l * cB * vb;
+        double b = -0.5 * (D + (l + 1) * P), a = P - b;
+        double va = pow(v, -(l + 1)), iv2 = 1.0 / (v * v);
+        *f = va * (a + b * iv2);
+        *d = -va * ((l + 1) * a + (l + 3) * b * iv2);
         return;
     }
     int k = 0;

@@ -44,6 +44,7 @@ struct Mth<float> {
     __device__ static float log1p_(float x) { return log1pf(x); }
     __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static constexpr float nfw_series_max = 0.1f;
+    static constexpr float max_ = 3.40282347e38f;  // largest finite value
 };
 
 template <>
@@ -55,6 +56,7 @@ struct Mth<double> {
     __device__ static double log1p_(double x) { return log1p(x); }
     __device__ static double rcp_(double x) { return 1.0 / x; }
     static constexpr double nfw_series_max = 1e-3;
+    static constexpr double max_ = 1.7976931348623157e308;
 };
 
 // normalized Hermite recurrence coefficients: H_{n+1} = a_n nu H_n - b_n H_{n-1}
@@ -586,8 +588,9 @@ __device__ __forceinline__ void deposit(const Hot<T>& h, const Tabs<T, double>& 
 // intervals 0..K-1, and u r^-(l+1) Y_lm for intervals 1..K; the finalize
 // forms the prefix and suffix sums at the nodes. Between nodes Phi_lm is the
 // cubic Hermite interpolant in s = ln r; inside rho_0 the regular
-// r^l (c0 + c1 r^2), beyond the last node c0 r^-(l+1) + c1 r^l, each with the
-// value and slope of its end node.
+// r^l (c0 + c1 r^2), beyond the last node the decaying c0 r^-(l+1) +
+// c1 r^-(l+3), each with the value and slope of its end node. A particle
+// with a non-finite radius deposits nothing.
 template <typename T>
 struct Scf {
     int K, L, nlm;
@@ -633,6 +636,7 @@ __device__ __forceinline__ void scf_deposit(const Scf<T>& s, T x, T y, T z, T u)
     const T r = Mth<T>::sqrt_(R2 + z * z), R = Mth<T>::sqrt_(R2);
     T ct, st, cp, sp;
     scf_dir<T>(x, y, z, r, R, ct, st, cp, sp);
+    if (!(r <= Mth<T>::max_)) return;  // inf or NaN
     const int q = scf_interval<T>(s, r);
     const T ir = r > T(0) ? Mth<T>::rcp_(r) : T(0);
     double* const A = q < s.K ? s.bins + q * s.nlm : nullptr;
@@ -700,7 +704,9 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
     const int q = scf_interval<T>(s, r);
     const int reg = q == 0 ? 0 : (q == s.K ? 2 : 1);
     const int k0 = q == 0 ? 0 : q - 1;
-    T v = T(1), iv = T(1), v2 = T(1);
+    // v = r / rho_k0 in the core and beyond the last node; the powers carried
+    // through the walk are v^l (core) or v^-(l+1) (beyond), both <= 1
+    T v = T(1), v2 = T(1), mul = T(1), pw0 = T(1);
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0);
     if (reg == 1) {
         const T t = fmin(fmax((Mth<T>::log_(r) - s.ls0) * s.ih - T(k0), T(0)), T(1));
@@ -715,11 +721,17 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
         e3 = T(3) * t2 - T(2) * t;
     } else {
         v = r * Mth<T>::rcp_(s.rho[k0]);
-        iv = Mth<T>::rcp_(v);
-        v2 = v * v;
+        if (reg == 0) {
+            v2 = v * v;
+            mul = v;
+        } else {
+            mul = Mth<T>::rcp_(v);
+            v2 = mul * mul;  // 1 / v^2 beyond the last node
+            pw0 = mul;
+        }
     }
-    // Phi_lm and r dPhi_lm/dr at r; vl = v^l, ivl = v^-(l+1)
-    auto radial = [&](int l, int lm, T vl, T ivl, T& f, T& d) {
+    // Phi_lm and r dPhi_lm/dr at r; pw = v^l (core) or v^-(l+1) (beyond)
+    auto radial = [&](int l, int lm, T pw, T& f, T& d) {
         const T* t0 = s.tab + (k0 * nlm + lm) * 2;
         const T P0 = t0[0], D0 = t0[1];
         const T fl = T(l);
@@ -729,18 +741,19 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
             d = e0 * P0 + e1 * D0 + e2 * P1 + e3 * D1;
         } else if (reg == 0) {
             const T c = T(0.5) * (D0 - fl * P0);
-            f = vl * (P0 + c * (v2 - T(1)));
-            d = vl * (fl * P0 + c * ((fl + T(2)) * v2 - fl));
+            f = pw * (P0 + c * (v2 - T(1)));
+            d = pw * (fl * P0 + c * ((fl + T(2)) * v2 - fl));
         } else {
-            const T i21 = Mth<T>::rcp_(T(2) * fl + T(1));
-            const T cA = (fl * P0 - D0) * i21, cB = ((fl + T(1)) * P0 + D0) * i21;
-            f = cA * ivl + cB * vl;
-            d = (fl * cB * vl - (fl + T(1)) * cA * ivl);
+            // a v^-(l+1) + b v^-(l+3) with value P0 and slope D0 at v = 1
+            const T b = T(-0.5) * (D0 + (fl + T(1)) * P0);
+            const T a = P0 - b;
+            f = pw * (a + b * v2);
+            d = -pw * ((fl + T(1)) * a + (fl + T(3)) * b * v2);
         }
     };
     T fr = T(0), fth = T(0), fph = T(0);
     T pmm = T(0.282094791773878143);  // Pn_m^m (m = 0: 1/sqrt(4 pi))
-    T cm = T(1), sm = T(0), vm = T(1), ivm = iv;
+    T cm = T(1), sm = T(0), pwm = pw0;
     for (int m = 0; m <= s.L; ++m) {
         T qmm = T(0);  // Qn_m^m
         if (m > 0) {
@@ -749,12 +762,11 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
             const T c = cm * cp - sm * sp;
             sm = sm * cp + cm * sp;
             cm = c;
-            vm *= v;
-            ivm *= iv;
+            pwm *= mul;
         }
         const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
         // column m: X_l = Pn_l^0 for m = 0, Qn_l^m for m >= 1
-        T x2 = T(0), x1 = (m == 0) ? pmm : qmm, vl = vm, ivl = ivm;
+        T x2 = T(0), x1 = (m == 0) ? pmm : qmm, pw = pwm;
         for (int l = m; l <= s.L; ++l) {
             if (l == m + 1) {
                 x2 = x1;
@@ -764,27 +776,24 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
                 x2 = x1;
                 x1 = xn;
             }
-            if (l > m) {
-                vl *= v;
-                ivl *= iv;
-            }
+            if (l > m) pw *= mul;
             const int j = l * l + l;
             if (m == 0) {
                 T f, d;
-                radial(l, j, vl, ivl, f, d);
+                radial(l, j, pw, f, d);
                 fr += d * x1;
             } else {
                 const T pn = st * x1;
                 const T dth = T(l) * ct * x1 - (l > m ? T(kYlm.e[l][m]) * x2 : T(0));
                 T fp, dp, fm, dm;
-                radial(l, j + m, vl, ivl, fp, dp);
-                radial(l, j - m, vl, ivl, fm, dm);
+                radial(l, j + m, pw, fp, dp);
+                radial(l, j - m, pw, fm, dm);
                 fr += (dp * c2 + dm * s2) * pn;
                 fth += (fp * c2 + fm * s2) * dth;
                 fph += T(m) * x1 * (fm * c2 - fp * s2);
                 if (m == 1) {  // the theta derivative of the m = 0 term of degree l
                     T f0, d0;
-                    radial(l, j, vl, ivl, f0, d0);
+                    radial(l, j, pw, f0, d0);
                     fth += f0 * T(kYlm.s[l]) * pn;
                 }
             }

@@ -101,8 +101,10 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     // after the tables
     Scf<T> sc{};
     if (KIN & kKinScf) {
-        double* sb = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(tb.end) + 7) &
-                                               ~uintptr_t(7));
+        // 8-byte aligned offset from the LDS base (pointer arithmetic on the
+        // base, so that the compiler keeps LDS loads and atomics)
+        const int off = (int)(tb.end - lds_raw + 7) & ~7;
+        double* sb = reinterpret_cast<double*>(lds_raw + off);
         sc.K = fd.scf_nr;
         sc.L = fd.scf_lmax;
         sc.nlm = (fd.scf_lmax + 1) * (fd.scf_lmax + 1);

@@ -55,6 +55,17 @@ def test_host_only_entry_points():
     assert _abi.m2m_num_observables(dict(alm, n_r=1)) == 0
     assert _abi.m2m_num_observables(dict(alm, dens=2)) == 0
     assert _abi.m2m_num_observables(dict(alm, n_r=200, l_max=8)) == 0  # J > 16384
+    # self-consistent potential: 2..64 nodes, degree 0..8, 0 < r_min < r_max,
+    # rebuilt every >= 1 steps; its interval sums and node table add to the
+    # workspace
+    scf = dict(wl.params, scf_lmax=4, scf_nr=32, scf_rmin=0.02, scf_rmax=100.0, scf_every=10)
+    w0 = _abi.m2m_workspace_bytes(wl.layout, wl.params, wl.N)
+    assert _abi.m2m_workspace_bytes(wl.layout, scf, wl.N) > w0
+    for bad in (dict(scf_nr=1), dict(scf_nr=65), dict(scf_lmax=9), dict(scf_lmax=-1),
+                dict(scf_rmin=0.0), dict(scf_rmax=0.01), dict(scf_every=0),
+                dict(scf_rmin=float("nan"))):
+        assert _abi.m2m_workspace_bytes(wl.layout, dict(scf, **bad), wl.N) == 0, bad
+    assert _abi.m2m_workspace_bytes(wl.layout, dict(scf, scf_nr=0, scf_lmax=99), wl.N) == w0
     b0 = _abi.m2m_get_launch()
     with pytest.raises(_abi.M2MError):
         _abi.m2m_set_launch(300, 4)

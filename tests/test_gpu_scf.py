@@ -171,3 +171,29 @@ def test_scf_batch_equals_alone(oracle, Fit):
         _assert_table(f.potential_table(), alone[k][1], 1e-6, "scf batch table")
         f.close()
     b.close()
+
+
+def test_long_fp32_run_with_mass_beyond_the_last_node_stays_finite(oracle, Fit):
+    """l <= 4 with the last node at r = 20 (a tenth of the mass beyond it):
+    after 300 steps every particle is finite and chi^2 stays near that of the
+    same run in the analytic potential (the expansion decays beyond the last
+    node instead of growing like r^l)."""
+    base = workload(2)
+    wl = with_scf(base, l_max=4, n_nodes=24, r_min=0.02, r_max=20.0, every=5)
+    T = oracle_targets(oracle, base)
+    n = 100_003
+    _say("scf long fp32", n)
+    parts = cast(base.initial_particles(n=n, seed=53), "f32")
+    chi = {}
+    for name, w in (("analytic", base), ("scf", wl)):
+        f = Fit(w.potential, w.layout, w.params, parts, dtype="f32")
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        f.step(300)
+        st = f.particles()
+        assert all(np.all(np.isfinite(st[k])) for k in ("x", "y", "z", "vx", "vy", "vz")), name
+        chi[name] = f.observables()["chi2"]
+        if name == "scf":
+            assert np.all(np.isfinite(f.potential_table()))
+        f.close()
+    _say("scf long fp32 chi2", chi)
+    assert chi["scf"] < 3.0 * chi["analytic"]

@@ -136,6 +136,46 @@ def test_potential_and_force_are_continuous_across_nodes():
         assert np.linalg.norm(ga - gb) < 1e-6 * np.linalg.norm(ga)
 
 
+def test_beyond_the_last_node_the_form_is_exact_for_mass_inside():
+    """With all mass inside the last node the decaying form is the exact
+    exterior multipole: it approaches the direct sum far out."""
+    rng = np.random.default_rng(15)
+    P, parts = _cloud(rng, 1000, 0.0, 5.0)
+    u = rng.uniform(0.5, 1.5, len(P))
+    p = _pot(lmax=8, nr=16, rmin=0.1, rmax=10.0)
+    tab = O.scf_table(p, parts, u)
+    for r in (25.0, 60.0, 400.0):
+        for d in _dirs(rng, 3):
+            X = r * d
+            ref = _direct(P, u, 1.0, X)
+            assert abs(O.scf_phi(p, tab, *X) - ref) < 1e-7 * abs(ref), r
+
+
+def test_beyond_the_last_node_the_potential_decays():
+    """With mass beyond the last node (a wide cloud), Phi_* and the force
+    still fall off outside it: r |Phi| and r^2 |g| stay bounded."""
+    rng = np.random.default_rng(16)
+    P, parts = _cloud(rng, 2000, 0.0, 300.0)
+    p = _pot(lmax=4, nr=20, rmin=0.1, rmax=50.0)
+    tab = O.scf_table(p, parts)
+    d = _dirs(rng, 1)[0]
+    rs = np.geomspace(60.0, 1e8, 25)
+    rp = np.array([r * abs(O.scf_phi(p, tab, *(r * d))) for r in rs])
+    rg = np.array([r * r * np.linalg.norm(O.scf_accel(p, tab, *(r * d))) for r in rs])
+    assert rp.max() < 2.0 * rp[0] and rg.max() < 3.0 * rg[0]
+    assert np.all(np.isfinite(rp)) and np.all(np.isfinite(rg))
+
+
+def test_particles_with_a_non_finite_radius_add_nothing():
+    rng = np.random.default_rng(17)
+    P, parts = _cloud(rng, 300, 0.0, 10.0)
+    p = _pot(lmax=2, nr=10)
+    tab = O.scf_table(p, parts)
+    bad = {k: np.append(v, [np.nan, np.inf]) for k, v in parts.items()}
+    u = np.ones(302) * 302 / 300  # the same mass per finite particle
+    assert np.allclose(O.scf_table(p, bad, u), tab, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("lmax", [0, 4])
 def test_hernquist_realization_reproduces_the_analytic_potential(lmax):
     """10^5 particles: about 800 lie inside r = 0.1, so the force there is
