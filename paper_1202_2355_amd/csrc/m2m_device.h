@@ -301,6 +301,11 @@ constexpr YlmCoef ylm_coef() {
 }
 
 __constant__ YlmCoef kYlm = ylm_coef();
+constexpr YlmCoef kYlmC = ylm_coef();  // the same, folded where the indices are constant
+
+// coefficient of the harmonics recurrences: from the folded copy when the
+// degree is fixed at compile time (LMAX >= 0), else from constant memory
+#define M2M_YC(LMAX, field) ((LMAX) >= 0 ? kYlmC.field : kYlm.field)
 
 // f(l^2 + l + m, Y_lm) for every 0 <= l <= lmax, -l <= m <= l, at the
 // direction (ct, st) = cos, sin of the polar angle and (cp, sp) of the azimuth
@@ -596,14 +601,17 @@ struct Scf {
     int K, L, nlm;
     T ls0, ih;       // ln rho_0, 1 / node spacing in ln r
     const T* rho;    // K node radii (LDS)
-    const T* tab;    // K x nlm x (Phi, r dPhi/dr) (LDS)
+    // per interval q = 0..K and (l, m): (Phi, r dPhi/dr) at the inner and the
+    // outer end node (LDS; the core and the outer interval repeat their one
+    // node), one 4-vector per entry
+    const T* tab;
     double* bins;    // 2 K nlm interval sums (LDS)
 };
 
-// LDS bytes of the expansion: sums, node table and node radii
+// LDS bytes of the expansion: sums, interval table and node radii
 __host__ __device__ inline size_t scf_lds_bytes(int K, int L, size_t sz) {
     const size_t nlm = (size_t)(L + 1) * (size_t)(L + 1);
-    return 8 * 2 * (size_t)K * nlm + sz * ((size_t)K * nlm * 2 + (size_t)K) + 8;
+    return 8 * 2 * (size_t)K * nlm + sz * ((size_t)(K + 1) * nlm * 4 + (size_t)K) + 32;
 }
 
 template <typename T>
@@ -689,9 +697,29 @@ __device__ __forceinline__ void scf_deposit(const Scf<T>& s, T x, T y, T z, T u)
 
 // g = -grad Phi_* at (x, y, z): dPhi/dr, (1/r) dPhi/dtheta and
 // (1/(r sin theta)) dPhi/dphi, with Qn = Pn / sin(theta) carried by the
-// same recurrences as Pn (no division on the axis); zero at the centre
-template <typename T>
+// same recurrences as Pn (no division on the axis); zero at the centre.
+// Phi_lm and r dPhi_lm/dr at r are linear in the four table values of the
+// particle's interval: Hermite weights between nodes; in the core and
+// beyond the last node the form u^n (P + (sg D - n P)(u^2 - 1)/2), u = v,
+// n = l, sg = 1 inside rho_0 and u = 1/v, n = l + 1, sg = -1 beyond the last
+// node (v = r over the end node), whose weights depend on l.
+template <typename T, int VEC>
+struct ScfQuad;
+template <>
+struct ScfQuad<float, 4> {
+    using type = float4;
+};
+template <>
+struct ScfQuad<double, 4> {
+    using type = double4;
+};
+
+// LMAX >= 0: the degree is LMAX, fixed at compile time (loops unrolled,
+// coefficients folded); LMAX < 0: the fit's degree s.L
+template <typename T, int LMAX>
 __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx, T& gy, T& gz) {
+    using Q4 = typename ScfQuad<T, 4>::type;
+    const int L = LMAX >= 0 ? LMAX : s.L;
     gx = gy = gz = T(0);
     const T R2 = x * x + y * y, r2 = R2 + z * z;
     if (!(r2 > T(0))) return;
@@ -699,17 +727,15 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
     T ct, st, cp, sp;
     scf_dir<T>(x, y, z, r, R, ct, st, cp, sp);
     const int nlm = s.nlm;
-    // radial region: 0 core (node 0), 1 between nodes k0 and k0 + 1, 2 beyond
-    // the last node (node k0 = K - 1)
     const int q = scf_interval<T>(s, r);
-    const int reg = q == 0 ? 0 : (q == s.K ? 2 : 1);
-    const int k0 = q == 0 ? 0 : q - 1;
-    // v = r / rho_k0 in the core and beyond the last node; the powers carried
-    // through the walk are v^l (core) or v^-(l+1) (beyond), both <= 1
-    T v = T(1), v2 = T(1), mul = T(1), pw0 = T(1);
+    const bool outer = q == 0 || q == s.K;
+    const Q4* const row = reinterpret_cast<const Q4*>(s.tab) + q * nlm;
+    // interior: Hermite weights of (P0, D0, P1, D1) for the value (w) and the
+    // slope (e); outer: u, sg, the offset of n over l, and the first power
     T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), e0 = T(0), e1 = T(0), e2 = T(0), e3 = T(0);
-    if (reg == 1) {
-        const T t = fmin(fmax((Mth<T>::log_(r) - s.ls0) * s.ih - T(k0), T(0)), T(1));
+    T u = T(1), sg = T(1), dn = T(0), qh = T(0), u2 = T(1), pw0 = T(1);
+    if (!outer) {
+        const T t = fmin(fmax((Mth<T>::log_(r) - s.ls0) * s.ih - T(q - 1), T(0)), T(1));
         const T t2 = t * t, t3 = t2 * t, h = Mth<T>::rcp_(s.ih);
         w0 = T(2) * t3 - T(3) * t2 + T(1);
         w1 = h * (t3 - T(2) * t2 + t);
@@ -720,82 +746,83 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
         e2 = -e0;
         e3 = T(3) * t2 - T(2) * t;
     } else {
-        v = r * Mth<T>::rcp_(s.rho[k0]);
-        if (reg == 0) {
-            v2 = v * v;
-            mul = v;
-        } else {
-            mul = Mth<T>::rcp_(v);
-            v2 = mul * mul;  // 1 / v^2 beyond the last node
-            pw0 = mul;
-        }
+        const T v = r * Mth<T>::rcp_(s.rho[q == 0 ? 0 : s.K - 1]);
+        u = q == 0 ? v : Mth<T>::rcp_(v);
+        sg = q == 0 ? T(1) : T(-1);
+        dn = q == 0 ? T(0) : T(1);
+        pw0 = q == 0 ? T(1) : u;
+        u2 = u * u;
+        qh = T(0.5) * (u2 - T(1));
     }
-    // Phi_lm and r dPhi_lm/dr at r; pw = v^l (core) or v^-(l+1) (beyond)
+    // Phi_lm (f) and r dPhi_lm/dr (d) of entry lm, degree l, pw = u^n
     auto radial = [&](int l, int lm, T pw, T& f, T& d) {
-        const T* t0 = s.tab + (k0 * nlm + lm) * 2;
-        const T P0 = t0[0], D0 = t0[1];
-        const T fl = T(l);
-        if (reg == 1) {
-            const T P1 = t0[2 * nlm], D1 = t0[2 * nlm + 1];
-            f = w0 * P0 + w1 * D0 + w2 * P1 + w3 * D1;
-            d = e0 * P0 + e1 * D0 + e2 * P1 + e3 * D1;
-        } else if (reg == 0) {
-            const T c = T(0.5) * (D0 - fl * P0);
-            f = pw * (P0 + c * (v2 - T(1)));
-            d = pw * (fl * P0 + c * ((fl + T(2)) * v2 - fl));
-        } else {
-            // a v^-(l+1) + b v^-(l+3) with value P0 and slope D0 at v = 1
-            const T b = T(-0.5) * (D0 + (fl + T(1)) * P0);
-            const T a = P0 - b;
-            f = pw * (a + b * v2);
-            d = -pw * ((fl + T(1)) * a + (fl + T(3)) * b * v2);
-        }
+        const Q4 t = row[lm];
+        const T n = T(l) + dn;
+        const T g = n * qh + u2;
+        const T W0 = outer ? pw * (T(1) - n * qh) : w0;
+        const T W1 = outer ? pw * sg * qh : w1;
+        const T E0 = outer ? sg * pw * n * (T(1) - g) : e0;
+        const T E1 = outer ? pw * g : e1;
+        f = W0 * t.x + W1 * t.y + w2 * t.z + w3 * t.w;
+        d = E0 * t.x + E1 * t.y + e2 * t.z + e3 * t.w;
     };
     T fr = T(0), fth = T(0), fph = T(0);
     T pmm = T(0.282094791773878143);  // Pn_m^m (m = 0: 1/sqrt(4 pi))
     T cm = T(1), sm = T(0), pwm = pw0;
-    for (int m = 0; m <= s.L; ++m) {
+#pragma unroll
+    for (int m = 0; m <= (LMAX >= 0 ? LMAX : kMaxLM); ++m) {
+        if (m > L) break;
         T qmm = T(0);  // Qn_m^m
         if (m > 0) {
-            qmm = -T(kYlm.mm[m]) * pmm;
+            qmm = -T(M2M_YC(LMAX, mm[m])) * pmm;
             pmm = st * qmm;
             const T c = cm * cp - sm * sp;
             sm = sm * cp + cm * sp;
             cm = c;
-            pwm *= mul;
+            pwm *= u;
         }
         const T c2 = T(1.41421356237309505) * cm, s2 = T(1.41421356237309505) * sm;
-        // column m: X_l = Pn_l^0 for m = 0, Qn_l^m for m >= 1
+        // column m: X_l = Pn_l^0 for m = 0, Qn_l^m for m >= 1; along the m = 0
+        // column also Y_l = Qn_l^1, for d Pn_l^0 / dtheta = s_l sin(theta) Qn_l^1
         T x2 = T(0), x1 = (m == 0) ? pmm : qmm, pw = pwm;
-        for (int l = m; l <= s.L; ++l) {
+        T y2 = T(0), y1 = T(0);
+#pragma unroll
+        for (int l = m; l <= (LMAX >= 0 ? LMAX : kMaxLM); ++l) {
+            if (l > L) break;
             if (l == m + 1) {
                 x2 = x1;
-                x1 = T(kYlm.m1[m]) * ct * x1;
+                x1 = T(M2M_YC(LMAX, m1[m])) * ct * x1;
             } else if (l > m + 1) {
-                const T xn = T(kYlm.a[l][m]) * (ct * x1 - T(kYlm.b[l][m]) * x2);
+                const T xn = T(M2M_YC(LMAX, a[l][m])) * (ct * x1 - T(M2M_YC(LMAX, b[l][m])) * x2);
                 x2 = x1;
                 x1 = xn;
             }
-            if (l > m) pw *= mul;
+            if (l > m) pw *= u;
             const int j = l * l + l;
             if (m == 0) {
+                if (l == 1) {
+                    y1 = -T(M2M_YC(LMAX, mm[1])) * T(0.282094791773878143);
+                } else if (l == 2) {
+                    y2 = y1;
+                    y1 = T(M2M_YC(LMAX, m1[1])) * ct * y1;
+                } else if (l > 2) {
+                    const T yn = T(M2M_YC(LMAX, a[l][1])) * (ct * y1 - T(M2M_YC(LMAX, b[l][1])) * y2);
+                    y2 = y1;
+                    y1 = yn;
+                }
                 T f, d;
                 radial(l, j, pw, f, d);
                 fr += d * x1;
+                fth += f * T(M2M_YC(LMAX, s[l])) * st * y1;
             } else {
                 const T pn = st * x1;
-                const T dth = T(l) * ct * x1 - (l > m ? T(kYlm.e[l][m]) * x2 : T(0));
+                const T dth = T(l) * ct * x1 - (l > m ? T(M2M_YC(LMAX, e[l][m])) * x2 : T(0));
                 T fp, dp, fm, dm;
                 radial(l, j + m, pw, fp, dp);
                 radial(l, j - m, pw, fm, dm);
                 fr += (dp * c2 + dm * s2) * pn;
                 fth += (fp * c2 + fm * s2) * dth;
                 fph += T(m) * x1 * (fm * c2 - fp * s2);
-                if (m == 1) {  // the theta derivative of the m = 0 term of degree l
-                    T f0, d0;
-                    radial(l, j, pw, f0, d0);
-                    fth += f0 * T(kYlm.s[l]) * pn;
-                }
             }
         }
     }
@@ -805,8 +832,6 @@ __device__ __forceinline__ void scf_accel(const Scf<T>& s, T x, T y, T z, T& gx,
     gy = -(gr * st * sp + gt * ct * sp + gp * cp);
     gz = -(gr * ct - gt * st);
 }
-
-
 
 }  // namespace
 }  // namespace m2m

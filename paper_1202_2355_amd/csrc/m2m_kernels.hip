@@ -389,7 +389,7 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
 }
 
 // The node table of the self-consistent potential from the reduced interval
-// sums (one thread per (l, m)): at node k, A_lm = the sums u r^l Y_lm of
+// sums (one thread per node and (l, m)): at node k, A_lm = the sums u r^l Y_lm of
 // intervals 0..k (particles inside rho_k), B_lm = the sums u r^-(l+1) Y_lm of
 // intervals k+1..K (at or outside rho_k), and
 //   Phi_lm = -4 pi c / (2l + 1) [rho^-(l+1) A_lm + rho^l B_lm],
@@ -397,30 +397,26 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
 // c = G upsilon M / N (the mass of a particle per unit weight, times G).
 __device__ __forceinline__ void build_scf_table(const FitDev& fd) {
     const int K = fd.scf_nr, L = fd.scf_lmax, nlm = (L + 1) * (L + 1);
-    const int lm = threadIdx.x;
-    if (lm >= nlm) return;
-    int l = 0;
-    while ((l + 1) * (l + 1) <= lm) ++l;
     const G<const double> a = gmem<const double>(fd.scf_sum);
     const G<const double> b = a + (size_t)K * nlm;  // interval q >= 1 at (q - 1) nlm
     const G<const double> rho = gmem<const double>(fd.scf_rho);
     const G<double> tab = gmem(fd.scf_tab);
-    const double c = -4.0 * M_PI * fd.scf_c / (2.0 * l + 1.0);
-    double A = 0.0;
-    for (int k = 0; k < K; ++k) {
-        A += a[(size_t)k * nlm + lm];
-        tab[((size_t)k * nlm + lm) * 2] = A;  // A_lm(rho_k) for now
-    }
-    double B = 0.0;
-    for (int k = K - 1; k >= 0; --k) {
-        B += b[(size_t)k * nlm + lm];  // interval k + 1
-        const double Ak = tab[((size_t)k * nlm + lm) * 2];
+    // one thread per (node, l, m); A in ascending, B in descending interval order
+    for (int e = threadIdx.x; e < K * nlm; e += blockDim.x) {
+        const int k = e / nlm, lm = e - k * nlm;
+        int l = 0;
+        while ((l + 1) * (l + 1) <= lm) ++l;
+        double A = 0.0;
+        for (int q = 0; q <= k; ++q) A += a[(size_t)q * nlm + lm];
+        double B = 0.0;
+        for (int q = K; q > k; --q) B += b[(size_t)(q - 1) * nlm + lm];
         const double r = rho[k];
         double rl = 1.0;
         for (int i = 0; i < l; ++i) rl *= r;
         const double ra = 1.0 / (rl * r);
-        tab[((size_t)k * nlm + lm) * 2] = c * (ra * Ak + rl * B);
-        tab[((size_t)k * nlm + lm) * 2 + 1] = c * (-(l + 1.0) * ra * Ak + l * rl * B);
+        const double c = -4.0 * M_PI * fd.scf_c / (2.0 * l + 1.0);
+        tab[(size_t)e * 2] = c * (ra * A + rl * B);
+        tab[(size_t)e * 2 + 1] = c * (-(l + 1.0) * ra * A + l * rl * B);
     }
 }
 

@@ -97,33 +97,41 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             tb.isp[j] = isp[j];
         }
     }
-    // the self-consistent potential: interval sums, node table and radii
-    // after the tables
+    // the self-consistent potential: the interval table (32-byte aligned),
+    // interval sums and node radii after the tables; offsets from the LDS
+    // base, so that the compiler keeps LDS loads and atomics
     Scf<T> sc{};
     if (KIN & kKinScf) {
-        // 8-byte aligned offset from the LDS base (pointer arithmetic on the
-        // base, so that the compiler keeps LDS loads and atomics)
-        const int off = (int)(tb.end - lds_raw + 7) & ~7;
-        double* sb = reinterpret_cast<double*>(lds_raw + off);
+        const int off = (int)(tb.end - lds_raw + 31) & ~31;
         sc.K = fd.scf_nr;
         sc.L = fd.scf_lmax;
         sc.nlm = (fd.scf_lmax + 1) * (fd.scf_lmax + 1);
         sc.ls0 = T(fd.scf_ls0);
         sc.ih = T(fd.scf_ih);
-        const int nt = sc.K * sc.nlm * 2;
-        T* tt = reinterpret_cast<T*>(sb + nt);
-        T* rr = tt + nt;
-        sc.bins = sb;
+        const int K = sc.K, nlm = sc.nlm, ne = (K + 1) * nlm;
+        T* tt = reinterpret_cast<T*>(lds_raw + off);
+        double* sb = reinterpret_cast<double*>(tt + 4 * ne);
+        T* rr = reinterpret_cast<T*>(sb + 2 * K * nlm);
         sc.tab = tt;
+        sc.bins = sb;
         sc.rho = rr;
         if (push) {
+            // interval q: (Phi, r dPhi/dr) at its inner and outer node; the
+            // core (q = 0) and the outer interval (q = K) repeat their node
             const G<const double> stab = gmem<const double>(fd.scf_tab);
-            for (int j = threadIdx.x; j < nt; j += BLOCK) tt[j] = T(stab[j]);
+            for (int e = threadIdx.x; e < ne; e += BLOCK) {
+                const int qq = e / nlm, lm = e - qq * nlm;
+                const int ki = qq == 0 ? 0 : qq - 1, ko = qq == K ? K - 1 : qq;
+                tt[4 * e] = T(stab[(ki * nlm + lm) * 2]);
+                tt[4 * e + 1] = T(stab[(ki * nlm + lm) * 2 + 1]);
+                tt[4 * e + 2] = T(stab[(ko * nlm + lm) * 2]);
+                tt[4 * e + 3] = T(stab[(ko * nlm + lm) * 2 + 1]);
+            }
         }
         const G<const double> srho = gmem<const double>(fd.scf_rho);
-        for (int j = threadIdx.x; j < sc.K; j += BLOCK) rr[j] = T(srho[j]);
+        for (int j = threadIdx.x; j < K; j += BLOCK) rr[j] = T(srho[j]);
         if (scf_dep)
-            for (int j = threadIdx.x; j < nt; j += BLOCK) sb[j] = 0.0;
+            for (int j = threadIdx.x; j < 2 * K * nlm; j += BLOCK) sb[j] = 0.0;
     }
     const G<double> row = gmem(fd.partials) + (size_t)tl.row * (size_t)fd.row_len;
     const G<const T> __restrict__ ucell = gmem<const T>(fd.ucell);
@@ -186,7 +194,13 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             vz -= sz * z;
             if (KIN & kKinScf) {
                 T gx, gy, gz;
-                scf_accel<T>(sc, x, y, z, gx, gy, gz);
+                // the common degrees with their loops unrolled
+                if (sc.L == 4)
+                    scf_accel<T, 4>(sc, x, y, z, gx, gy, gz);
+                else if (sc.L == 2)
+                    scf_accel<T, 2>(sc, x, y, z, gx, gy, gz);
+                else
+                    scf_accel<T, -1>(sc, x, y, z, gx, gy, gz);
                 vx += h.dt * gx;
                 vy += h.dt * gy;
                 vz += h.dt * gz;
