@@ -79,13 +79,15 @@ def _scf_pair(oracle, Fit, wl, n, dtype, band, seed):
     return f, o
 
 
-def test_scf_run_fp64_matches_oracle(oracle, Fit):
-    """FP64 state, workload 1 in its own multipole potential (l <= 2, 16
-    nodes, rebuilt every 5 steps): 40 steps with a prior refresh."""
-    wl = with_scf(workload(1), l_max=2, n_nodes=16, r_min=0.05, r_max=50.0, every=5)
+@pytest.mark.parametrize("l_max", [2, 3, 4])
+def test_scf_run_fp64_matches_oracle(oracle, Fit, l_max):
+    """FP64 state, workload 1 in its own multipole potential (16 nodes,
+    rebuilt every 5 steps): 40 steps with a prior refresh. l <= 2 and 4 take
+    the force with unrolled loops, l <= 3 the one with the degree at run time."""
+    wl = with_scf(workload(1), l_max=l_max, n_nodes=16, r_min=0.05, r_max=50.0, every=5)
     wl = wl.with_(params=dict(wl.params, prior_every=20))
     n = 20_003
-    _say("scf run fp64", wl.name, n)
+    _say("scf run fp64", wl.name, l_max, n)
     f, o = _scf_pair(oracle, Fit, wl, n, "f64", 1e-12, seed=45)
     f.step(40)
     hist_o = o.step(40)
