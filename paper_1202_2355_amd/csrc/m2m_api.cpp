@@ -1204,7 +1204,8 @@ hipError_t batch_step(m2m_batch* b, bool f64, hipStream_t s) {
     hipError_t e = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
                                b->lds, kModeStep, s);
     if (e == hipSuccess)
-        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s);
+        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s,
+                            kin_scf(b->kin));
     return e;
 }
 
@@ -1275,7 +1276,7 @@ m2m_status rebuild(m2m_batch* b) {
                 hipError_t r = batch_step(b, f64, s);
                 if (r == hipSuccess)
                     r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
-                                        kModeObserve, s);
+                                        kModeObserve, s, kin_scf(b->kin));
                 return r;
             },
             &b->graph_prof);

@@ -95,7 +95,13 @@ struct FitDev {
     int32_t sm_k1, pad3;         // points of the first search stage
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
     double hv2, hr02, hiq2;      // logarithmic halo: v0^2 (0: none), r0^2, 1/q^2
-    // self-consistent stellar potential (scf_nr = 0: none): a multipole
+    // step constants
+    double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
+    double *chi2_hist;
+    double *chi2_part;           // one per bin job
+    FitState *st;
+    // self-consistent stellar potential (last, so that the fields before keep
+    // their offsets in the kernel arguments) (scf_nr = 0: none): a multipole
     // expansion to degree scf_lmax with node values at scf_nr radii
     // log-spaced from scf_rho[0]; the tile rows carry its scf_P interval sums
     // from column scf_col0 (after the cell columns), reduced by n_pot_jobs
@@ -106,11 +112,6 @@ struct FitDev {
     double *scf_rho;             // node radii (FP64)
     double *scf_sum;             // interval sums of the last rebuild (scf_P)
     double *scf_tab;             // nodes x (l, m): Phi_lm(rho_k), r dPhi_lm/dr there
-    // step constants
-    double dt, w0, foc_mu, foc_cs, foc_chi, q;  // foc_mu = eps dt mu, foc_chi = eps dt w0
-    double *chi2_hist;
-    double *chi2_part;           // one per bin job
-    FitState *st;
 };
 
 // One tile: a contiguous particle range of one fit, owned by one block.
@@ -147,8 +148,10 @@ hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* f
                        const Tile* tiles, int n_tiles, size_t lds_bytes, int32_t mode,
                        hipStream_t s);
 // the column jobs of the fits of the table (n_fits of them)
+// scf: the fits have the self-consistent potential (kin_scf of their kin class)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s);
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf);
+bool kin_scf(int kin);
 // the step kernel of one particle-state / in-tile-sum type pair (one == nullptr:
 // over the fit and tile tables, else over that one fit); m2m_step_*.hip
 hipError_t launch_step_f64(int block, int kin, const FitDev* fits, const Tile* tiles,

@@ -53,6 +53,7 @@ __device__ __forceinline__ Snap snap_of(G<const FitState> st) {
     return s;
 }
 
+template <bool SCF>
 __device__ __forceinline__ Flags flags_of(const FitDev& fd, const Snap& ss, int32_t mode) {
     Flags f;
     f.step = (mode & kModeStep) != 0;
@@ -64,8 +65,8 @@ __device__ __forceinline__ Flags flags_of(const FitDev& fd, const Snap& ss, int3
                                  ((ss.kstep + 1) % fd.prior_every) == 0);
     // the self-consistent potential is rebuilt (kModePot alone, or every
     // scf_every steps)
-    f.pot_mode = (mode & kModePot) != 0;
-    f.pot = fd.scf_nr > 0 &&
+    f.pot_mode = SCF && (mode & kModePot) != 0;
+    f.pot = SCF && fd.scf_nr > 0 &&
             (f.pot_mode || (f.step && ((ss.tstep + 1) % fd.scf_every) == 0));
     return f;
 }
@@ -420,7 +421,9 @@ __device__ __forceinline__ void build_scf_table(const FitDev& fd) {
     }
 }
 
-template <typename T>
+// SCF: the fit has the self-consistent potential (its potential jobs and the
+// node table are compiled in only then)
+template <typename T, bool SCF>
 __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb, int32_t mode) {
     __shared__ double part[kFinWaves][kFinCols];
     __shared__ double part2[kFinWaves][kFinCols];
@@ -433,8 +436,8 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     const bool step = (mode & kModeStep) != 0;
     const bool cells_mode = (mode & kModeCells) != 0;
     const bool observe = (mode & kModeObserve) != 0;
-    const bool pot_mode = (mode & kModePot) != 0;
-    const bool bins = jb.kind == 0, pots = jb.kind == 2;
+    const bool pot_mode = SCF && (mode & kModePot) != 0;
+    const bool bins = jb.kind == 0, pots = SCF && jb.kind == 2;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = jb.col0 + lane;
@@ -454,7 +457,7 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     }
     const Snap ss = snap_of(gst);
     if (step && ss.steps_left <= 0) return;  // uniform: the fit is idle
-    const Flags f = flags_of(fd, ss, mode);
+    const Flags f = flags_of<SCF>(fd, ss, mode);
     if (bins && (cells_mode || pot_mode)) return;
     if (jb.kind == 1 && !f.refresh) return;
     if (pots && !f.pot) return;
@@ -507,7 +510,7 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
         }
     }
     // the node table of the self-consistent potential from the new sums
-    if (f.pot) build_scf_table(fd);
+    if (SCF && f.pot) build_scf_table(fd);
     if (wave != 0) return;
     const double chi2 = (cells_mode || pot_mode)
                             ? 0.0
@@ -519,18 +522,18 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
 }
 
 // the jobs of the fits of a table (batches)
-template <typename T>
+template <typename T, bool SCF>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
                                                          const FinJob* __restrict__ jobs,
                                                          int32_t mode) {
     const FinJob jb = jobs[blockIdx.x];
-    finalize_job<T>(fits[jb.fit], jb, mode);
+    finalize_job<T, SCF>(fits[jb.fit], jb, mode);
 }
 
 // one fit, its description passed by value: block b < n_bin_jobs takes bin
 // columns, then n_cell_jobs blocks cell columns, then n_pot_jobs blocks the
 // columns of the self-consistent potential, over n_rows tile rows
-template <typename T>
+template <typename T, bool SCF>
 __global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int32_t n_rows,
                                                           int32_t mode) {
     const int b = blockIdx.x;
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int3
     const int kind = b < nb ? 0 : (b < nb + nc ? 1 : 2);
     const int base = kind == 0 ? 0 : (kind == 1 ? nb : nb + nc);
     const FinJob jb{0, kind, (b - base) * kFinCols, n_rows};
-    finalize_job<T>(fd, jb, mode);
+    finalize_job<T, SCF>(fd, jb, mode);
 }
 
 
@@ -667,27 +670,42 @@ hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& 
 }
 
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s) {
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf) {
     if (n_jobs <= 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL(k_finalize<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
-                           mode);
+    if (f64 && scf)
+        hipLaunchKernelGGL((k_finalize<double, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fits,
+                           jobs, mode);
+    else if (f64)
+        hipLaunchKernelGGL((k_finalize<double, false>), dim3(n_jobs), dim3(kFinThreads), 0, s,
+                           fits, jobs, mode);
+    else if (scf)
+        hipLaunchKernelGGL((k_finalize<float, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fits,
+                           jobs, mode);
     else
-        hipLaunchKernelGGL(k_finalize<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fits, jobs,
-                           mode);
+        hipLaunchKernelGGL((k_finalize<float, false>), dim3(n_jobs), dim3(kFinThreads), 0, s,
+                           fits, jobs, mode);
     (void)n_fits;
     return hipGetLastError();
 }
 
+bool kin_scf(int kin) { return (kin & kKinScf) != 0; }
+
 hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s) {
     const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs + fd.n_pot_jobs;
     if (n_jobs <= 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL(k_finalize1<double>, dim3(n_jobs), dim3(kFinThreads), 0, s, fd, n_rows,
-                           mode);
+    const bool scf = fd.scf_nr > 0;
+    if (f64 && scf)
+        hipLaunchKernelGGL((k_finalize1<double, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
+                           n_rows, mode);
+    else if (f64)
+        hipLaunchKernelGGL((k_finalize1<double, false>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
+                           n_rows, mode);
+    else if (scf)
+        hipLaunchKernelGGL((k_finalize1<float, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
+                           n_rows, mode);
     else
-        hipLaunchKernelGGL(k_finalize1<float>, dim3(n_jobs), dim3(kFinThreads), 0, s, fd, n_rows,
-                           mode);
+        hipLaunchKernelGGL((k_finalize1<float, false>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
+                           n_rows, mode);
     return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     const G<const FitState> st = gmem<const FitState>(fd.st);
     if (step && st->steps_left <= 0) return;  // uniform: the fit is idle
     const bool cells_only = (mode & kModeCells) != 0;
-    const bool pot_only = (mode & kModePot) != 0;
+    const bool pot_only = (KIN & kKinScf) && (mode & kModePot) != 0;
     // the steps that rebuild the self-consistent potential deposit into its
     // interval sums after the push
     const bool scf_dep = (KIN & kKinScf) &&
