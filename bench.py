@@ -164,9 +164,13 @@ def run_batch(args, Fit, torch, _abi):
                       ntot / (ms_alone * 1e-3), "one_launch_per_fit_ms_per_step": ms_alone}}
 
 
-def run_serve(args, torch):
+SERVE_RATE = 20.0  # requests per second of the serving trace
+
+
+def run_serve(args, torch, rate=SERVE_RATE):
     """Workload 5: a Poisson trace of fit requests through the continuous-
-    batching server; throughput and p50/p99 latency."""
+    batching server; throughput and p50/p99 latency. At another arrival rate
+    the same requests arrive at times scaled by SERVE_RATE / rate."""
     from paper_1202_2355_amd.fit import Fit
     from paper_1202_2355_amd.serve import Request, Server
     from workloads import add_noise, floor_model_noise, workload
@@ -184,6 +188,7 @@ def run_serve(args, torch):
         Y, sig = add_noise(Y_true, base.layout, s, np.random.Generator(np.random.Philox(key=50 + k)))
         datasets.append({"Y": Y, "sigma": floor_model_noise(Y_true, sig, SERVE_N_MIN)})
     arrival, wls = serve_trace(n_requests=args.requests, state=args.state)
+    arrival = np.asarray(arrival) * (SERVE_RATE / rate)
     reqs = [Request(rid=k, arrival=float(arrival[k]), potential=w.potential, params=w.params,
                     layout=w.layout, n=w.N, steps=w.steps, dataset=levels.index(w.noise),
                     seed=w.seed) for k, w in enumerate(wls)]
@@ -210,6 +215,9 @@ def main(argv=None):
     ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
     ap.add_argument("--steps-per-launch", type=int, default=64)
+    ap.add_argument("--sweep", default="", metavar="RATES",
+                    help="workload 5: also serve the same trace at these arrival rates "
+                         "(comma-separated, requests/s): the saturation sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB float32 device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -238,16 +246,25 @@ def main(argv=None):
     _abi.m2m_set_launch(*LAUNCH[args.workload])
     if args.workload == 5:
         m = run_serve(args, torch)
+        sweep = []
+        for rate in [float(x) for x in args.sweep.split(",") if x.strip()]:
+            ms = run_serve(args, torch, rate=rate)
+            sweep.append({"arrival_rate_per_s": rate, "particle_steps_per_s": ms["particle_steps_per_s"],
+                          "p50_s": ms["p50_latency_s"], "p99_s": ms["p99_latency_s"]})
+            print(f"[bench] serve at {rate:g}/s: {ms['particle_steps_per_s']:.3e} particle-steps/s, "
+                  f"p50 {ms['p50_latency_s']:.3f} s, p99 {ms['p99_latency_s']:.3f} s",
+                  file=sys.stderr, flush=True)
         out = {"metric": METRIC,
                "value": m["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
                "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": args.state, "data": "synthetic",
                "config": {"workload": "serve_losvd", "requests": m["requests"],
-                          "arrival_rate_per_s": 20.0, "hbm_budget_gb": args.hbm_gb,
+                          "arrival_rate_per_s": SERVE_RATE, "hbm_budget_gb": args.hbm_gb,
                           "steps_per_launch": args.steps_per_launch,
                           "launch": list(LAUNCH[5])},
                "latency": {"p50_s": m["p50_latency_s"], "p99_s": m["p99_latency_s"],
                            "mean_s": m["mean_latency_s"]},
+               **({"sweep": sweep} if sweep else {}),
                "roofline": None, "cpu_baseline": None}
         print(json.dumps(out), flush=True)
         return 0
