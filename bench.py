@@ -99,9 +99,24 @@ def cpu_baseline(wl, seconds: float):
     t0 = time.perf_counter()
     f.step(k)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over a tenth of the particles for about a
+    # third of the time
+    n1 = max(1, n // 10)
+    f1 = O.OracleFit(wl.potential, wl.layout, wl.params, {key: v[:n1] for key, v in ic.items()},
+                     T["Y"], T["sigma"], T["V_p"], T["sigma_p"], nthreads=1)
+    t0 = time.perf_counter()
+    f1.step(1)
+    t1 = time.perf_counter() - t0
+    k1 = max(1, min(200, int(seconds / 3 / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    f1.step(k1)
+    dt1 = time.perf_counter() - t0
     return {"value": n * k / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} particles of {wl.name}, {k} steps after 1 untimed step "
-                      f"(FP64, OpenMP, targets from a 2^20-particle target realization)"}
+                      f"(FP64, OpenMP, targets from a 2^20-particle target realization)",
+            "value_1_thread": n1 * k1 / dt1,
+            "sample_1_thread": f"the first {n1} of those particles, {k1} steps after 1 untimed step, "
+                               f"one thread"}
 
 
 def run_batch(args, Fit, torch, _abi):
