@@ -41,7 +41,13 @@ struct Mth<float> {
     __device__ static float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
     __device__ static float log2_(float x) { return __builtin_amdgcn_logf(x); }
     __device__ static float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-    __device__ static float log1p_(float x) { return log1pf(x); }
+    // log(1 + x) by Goldberg's method (What every computer scientist should
+    // know about floating-point arithmetic, 1991): with u = 1 + x rounded,
+    // x log(u) / (u - 1), where u - 1 is exact; x itself when u = 1
+    __device__ static float log1p_(float x) {
+        const float u = 1.0f + x;
+        return u == 1.0f ? x : x * (log_(u) * rcp_(u - 1.0f));
+    }
     __device__ static float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static constexpr float nfw_series_max = 0.1f;
     static constexpr float max_ = 3.40282347e38f;  // largest finite value
