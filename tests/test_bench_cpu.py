@@ -1,0 +1,44 @@
+"""Host-side parts of the benchmark (no GPU): the one-GPU rule, the use of the
+committed HBM counters only for the kernel they were taken on, and the shape
+of the CPU baseline."""
+
+import json
+
+import pytest
+
+import bench
+from workloads import workload
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_traffic_is_used_only_for_the_kernel_it_was_measured_on(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"w": {"kernel_hash": bench.kernel_hash(), "bytes_per_launch": 6.1e7,
+                                   "algorithmic_bytes_per_launch": 6.0e7}}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("w", 1_000_000) == pytest.approx(61.0)
+    assert bench.measured_traffic("other", 1_000_000) is None
+    f.write_text(json.dumps({"w": {"kernel_hash": "0" * 16, "bytes_per_launch": 6.1e7}}))
+    assert bench.measured_traffic("w", 1_000_000) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("w", 1_000_000) is None
+
+
+def test_kernel_hash_covers_every_kernel_source():
+    import os
+    srcs = set(bench.KERNEL_SOURCES)
+    csrc = os.path.join(bench.ROOT, "paper_1202_2355_amd", "csrc")
+    for name in os.listdir(csrc):
+        if name.endswith((".hip", ".h")):
+            assert f"paper_1202_2355_amd/csrc/{name}" in srcs, name
+
+
+def test_cpu_baseline_reports_all_cores_and_one_thread():
+    r = bench.cpu_baseline(workload(1), 0.5)
+    assert r["kind"] == "oracle" and r["unit"] == "particle-steps/s"
+    assert r["cores"] >= 1 and r["value"] > 0 and r["value_1_thread"] > 0
+    assert "one thread" in r["sample_1_thread"]
