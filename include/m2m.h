@@ -220,7 +220,13 @@ size_t m2m_workspace_bytes(const m2m_obs_layout* layout, const m2m_params* param
  * (see "Weights"). workspace: NULL to let the library allocate it, else a
  * device buffer of at least m2m_workspace_bytes(...) bytes owned by the
  * caller. hip_stream: the stream all work of this context is ordered on.
- * On success *out receives the context; on failure *out is NULL. */
+ * On success *out receives the context; on failure *out is NULL.
+ * M2M_EUNSUPPORTED if the step kernel's LDS tables do not fit the 160 KiB of
+ * a compute unit: the bins (private copies), the cell sums, the edge tables
+ * and, with the self-consistent potential, its interval table ((scf_nr + 1)
+ * (scf_lmax+1)^2 four-vectors of the state type) and FP64 interval sums
+ * (2 scf_nr (scf_lmax+1)^2); l <= 8 fits up to about 54 nodes with FP32 state
+ * and 35 with FP64 state at a few hundred observables. */
 m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
                       const m2m_params* params, int64_t n, int32_t dtype, void* x, void* y,
                       void* z, void* vx, void* vy, void* vz, void* u, void* u_prior,

@@ -53,11 +53,14 @@ def _oracle_table(oracle, wl, parts, u):
     return oracle.scf_table(pot, parts, u, mass=wl.params["mass"], nthreads=8)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_table_of_one_state_matches_oracle(oracle, Fit, dtype):
-    wl = with_scf(workload(2), l_max=4, n_nodes=24, r_min=0.02, r_max=80.0)
+@pytest.mark.parametrize("dtype,l_max,n_nodes", [("f32", 4, 24), ("f64", 4, 24), ("f64", 0, 2),
+                                                ("f32", 8, 40)])
+def test_table_of_one_state_matches_oracle(oracle, Fit, dtype, l_max, n_nodes):
+    """Also the smallest expansion (the monopole on two nodes: one interval
+    between the core and the outside) and a large one (l <= 8, 40 nodes)."""
+    wl = with_scf(workload(2), l_max=l_max, n_nodes=n_nodes, r_min=0.02, r_max=80.0)
     n = 60_001
-    _say("scf table", dtype, n)
+    _say("scf table", dtype, l_max, n_nodes, n)
     parts = cast(wl.initial_particles(n=n, seed=41), dtype)
     u = cast({"u": random_weights(n, 43, spread=0.5)}, dtype)["u"]
     T = oracle_targets(oracle, wl)
@@ -123,6 +126,33 @@ def test_scf_run_fp32_matches_oracle(oracle, Fit):
     np.testing.assert_allclose(hist_g, hist_o, rtol=1e-4)
     _assert_table(f.potential_table(), o.scf.reshape(f.potential_table().shape), 1e-4,
                   "scf run fp32 table")
+    f.close()
+
+
+def test_expansion_too_large_for_lds_is_refused(oracle, Fit):
+    """l <= 8 on 64 nodes needs more than the 160 KiB of LDS of a CU for its
+    interval table and sums: creation fails cleanly."""
+    from paper_1202_2355_amd._abi import M2M_EUNSUPPORTED, M2MError
+    wl = with_scf(workload(2), l_max=8, n_nodes=64, r_min=0.02, r_max=80.0)
+    parts = cast(wl.initial_particles(n=4_096, seed=57), "f32")
+    with pytest.raises(M2MError) as e:
+        Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    assert e.value.status == M2M_EUNSUPPORTED
+
+
+def test_monopole_on_two_nodes_run_fp64_matches_oracle(oracle, Fit):
+    """The degenerate expansion: l = 0, nodes at r_min and r_max only, so
+    most particles sit in the one interval or beyond the last node."""
+    wl = with_scf(workload(1), l_max=0, n_nodes=2, r_min=0.3, r_max=3.0, every=3)
+    n = 10_007
+    _say("scf monopole two nodes fp64", n)
+    f, o = _scf_pair(oracle, Fit, wl, n, "f64", 1e-12, seed=55)
+    f.step(20)
+    hist_o = o.step(20)
+    st = f.particles()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(st[k], o.arr[k], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(f.chi2_history(20), hist_o, rtol=1e-9)
     f.close()
 
 
