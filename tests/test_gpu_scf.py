@@ -229,3 +229,33 @@ def test_long_fp32_run_with_mass_beyond_the_last_node_stays_finite(oracle, Fit):
         f.close()
     _say("scf long fp32 chi2", chi)
     assert chi["scf"] < 3.0 * chi["analytic"]
+
+
+def test_checkpoint_resume_keeps_the_expansion(oracle, Fit):
+    """The state blob carries the node table: a fit resumed from a state saved
+    between two rebuilds continues exactly like the uninterrupted run."""
+    wl = with_scf(workload(1), l_max=2, n_nodes=16, r_min=0.05, r_max=50.0, every=5)
+    T = oracle_targets(oracle, wl)
+    n = 12_011
+    _say("scf checkpoint", n)
+    parts = cast(wl.initial_particles(n=n, seed=59), "f64")
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f64")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    f.step(7)  # last rebuild after step 5: the table is not that of the current particles
+    blob = f.get_state()
+    mid = f.particles()
+    mid_tab = f.potential_table()
+    f.step(6)
+    end, end_tab = f.particles(), f.potential_table()
+    g = Fit(wl.potential, wl.layout, wl.params,
+            {k: mid[k] for k in ("x", "y", "z", "vx", "vy", "vz")}, dtype="f64", u=mid["u"],
+            u_prior=mid["uh"])
+    g.set_state(blob)
+    assert np.array_equal(g.potential_table(), mid_tab)
+    g.step(6)
+    end2 = g.particles()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "u"):
+        np.testing.assert_allclose(end2[k], end[k], rtol=1e-12, atol=1e-12)
+    _assert_table(g.potential_table(), end_tab, 1e-12, "scf checkpoint table")
+    f.close()
+    g.close()
