@@ -1,0 +1,100 @@
+"""GPU parity at the edges of the particle count (run on an MI355X): fits of
+1, 63, 64 and 65 particles (one tile, shorter than one tile boundary of 64,
+exactly one, one more) and a batch that mixes a one-particle fit with larger
+ones. FP64 state, so the only difference from the oracle is summation
+order: positions within 1e-12, weights within 1e-10, chi^2 within 1e-10.
+Each fit's targets are its own initial observables with 5 % errors (a few
+particles against a full-model target would drive the weights to overflow,
+which the library reports as a non-finite chi^2)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from m2m_testlib import cast
+from workloads import workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def Fit():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_2355_amd import _abi
+    _abi.lib()
+    from paper_1202_2355_amd.fit import Fit
+    return Fit
+
+
+def _wl():
+    wl = workload(1)
+    return wl.with_(params=dict(wl.params, prior_every=4))
+
+
+def _own_targets(oracle, wl, parts):
+    Y = oracle.deposit(parts, np.ones(parts["x"].size), wl.layout, mass=wl.params["mass"])
+    return {"Y": Y, "sigma": 0.05 * np.abs(Y) + 1e-3 * np.abs(Y).max() + 1e-12, "V_p": None,
+            "sigma_p": None}
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65])
+def test_tiny_fits_match_oracle(oracle, Fit, n):
+    wl = _wl()
+    parts = cast(wl.initial_particles(n=n, seed=61 + n), "f64")
+    T = _own_targets(oracle, wl, parts)
+    _say("tiny fit", n)
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f64")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, T["Y"], T["sigma"], T["V_p"],
+                         T["sigma_p"])
+    f.step(10)  # two prior refreshes
+    hist_o = o.step(10)
+    st = f.particles()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(st[k], o.arr[k], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st["u"], o.arr["u"], rtol=1e-10)
+    np.testing.assert_allclose(st["uh"], o.arr["uhat"], rtol=1e-10)
+    np.testing.assert_allclose(f.chi2_history(10), hist_o, rtol=1e-10)
+    f.close()
+
+
+def test_batch_with_a_one_particle_fit_equals_alone(oracle, Fit):
+    from paper_1202_2355_amd.batch import Batch
+    wl = _wl()
+    sizes, steps = [1, 65, 5_003], [9, 12, 7]
+    _say("tiny batch", sizes)
+    parts = [cast(wl.initial_particles(n=n, seed=70 + k), "f64") for k, n in enumerate(sizes)]
+    Ts = [_own_targets(oracle, wl, p) for p in parts]
+    alone = []
+    for k in range(3):
+        f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f64")
+        T = Ts[k]
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        f.step(steps[k])
+        alone.append((f.particles(), f.chi2_history(steps[k])))
+        f.close()
+    b = Batch(max_fits=4)
+    fits = []
+    for k in range(3):
+        f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f64")
+        T = Ts[k]
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        b.admit(f, steps[k])
+        fits.append(f)
+    assert len(b.run_to_completion(steps_per_launch=4)) == 3
+    for k, f in enumerate(fits):
+        st = f.particles()
+        for key in ("x", "y", "z", "vx", "vy", "vz"):
+            np.testing.assert_allclose(st[key], alone[k][0][key], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(st["u"], alone[k][0]["u"], rtol=1e-10)
+        np.testing.assert_allclose(f.chi2_history(steps[k]), alone[k][1], rtol=1e-10)
+        f.close()
+    b.close()
