@@ -98,3 +98,25 @@ def test_batch_with_a_one_particle_fit_equals_alone(oracle, Fit):
         np.testing.assert_allclose(f.chi2_history(steps[k]), alone[k][1], rtol=1e-10)
         f.close()
     b.close()
+
+
+def test_overflowing_weights_are_reported_as_a_non_finite_chi2(oracle, Fit):
+    """One particle against the targets of a whole model: the force of change
+    drives its weight past the largest double within a few steps; the next
+    synchronizing call reports M2M_ENONFINITE (the oracle overflows too)."""
+    from m2m_testlib import oracle_targets
+    from paper_1202_2355_amd._abi import M2M_ENONFINITE, M2MError
+    wl = _wl()
+    T = oracle_targets(oracle, wl)
+    parts = cast(wl.initial_particles(n=1, seed=62), "f64")
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, T["Y"], T["sigma"], T["V_p"],
+                         T["sigma_p"])
+    o.step(10)
+    assert not np.isfinite(o.chi2)
+    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f64")
+    f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+    f.step(10)
+    with pytest.raises(M2MError) as e:
+        f.weights()
+    assert e.value.status == M2M_ENONFINITE
+    f.close()
