@@ -66,3 +66,27 @@ def weight_errors(u_gpu, u_ora, flagged=None):
         return rel2, float(relmax[ok].max()) if ok.any() else 0.0, float(relmax.max()), float(
             (~ok).mean())
     return rel2, float(relmax.max()), float(relmax.max()), 0.0
+
+
+def clean_of_cell_edges(P, cell, E, xc, band_e, band_x):
+    """Particles whose prior cell is certain in a comparison of cell means:
+    not in a cell that holds a particle within the band of a cell edge (in E
+    or in x = L/L_c), nor in the cell across that edge, where such a particle
+    may land when its coordinates are rounded differently. Cells linear in E,
+    without the L_z split."""
+    import numpy as np
+    dE = (P["E_hi"] - P["E_lo"]) / P["n_E"]
+    te = (E - P["E_lo"]) / dE
+    tx = xc * P["n_x"]
+    amb_e = np.abs(te - np.round(te)) * dE <= band_e
+    amb_x = np.abs(tx - np.round(tx)) <= band_x * P["n_x"]
+    k, l = np.divmod(cell, P["n_x"])
+    k_o = np.where(te >= np.round(te), np.round(te) - 1, np.round(te)).astype(int)
+    l_o = np.where(tx >= np.round(tx), np.round(tx) - 1, np.round(tx)).astype(int)
+    k2 = np.where(amb_e, np.clip(k_o, 0, P["n_E"] - 1), k)
+    l2 = np.where(amb_x, np.clip(l_o, 0, P["n_x"] - 1), l)
+    amb = amb_e | amb_x
+    dirty = np.zeros(P["n_E"] * P["n_x"], bool)
+    for kk, ll in ((k, l), (k2, l), (k, l2), (k2, l2)):
+        dirty[(kk * P["n_x"] + ll)[amb]] = True
+    return ~dirty[cell]

@@ -120,3 +120,76 @@ def test_overflowing_weights_are_reported_as_a_non_finite_chi2(oracle, Fit):
         f.weights()
     assert e.value.status == M2M_ENONFINITE
     f.close()
+
+
+# ----------------------------------------------------------- maximum sizes
+def _observe_case(oracle, Fit, wl, lay, dtype, n, seed, gh=False):
+    from m2m_testlib import BAND_F32, BAND_F64, assert_observables, random_weights
+    parts = cast(wl.initial_particles(n=n, seed=seed), dtype)
+    u = cast({"u": random_weights(n, seed + 1)}, dtype)["u"]
+    V = S = None
+    if gh:
+        g = np.random.default_rng(seed)
+        V, S = g.uniform(-0.05, 0.05, lay["n_R"]), g.uniform(0.25, 0.6, lay["n_R"])
+        V, S = cast({"V": V, "S": S}, dtype).values()
+    f = Fit(wl.potential, lay, wl.params, parts, dtype=dtype, u=u)
+    y = f.observe(V, S) if gh else f.observe()
+    band = BAND_F32 if dtype == "f32" else BAND_F64
+    yo, ya, yb = oracle.deposit(parts, u, lay, mass=wl.params["mass"], V_p=V, sigma_p=S,
+                                band=band, nthreads=8, with_abs=True)
+    worst = assert_observables(y, yo, ya, yb, 1e-5 if dtype == "f32" else 1e-12, str(lay["kin"]))
+    _say("observe", lay["kin"], dtype, "J", y.size, "max |dy|/sum|wK| =", worst)
+    f.close()
+
+
+@pytest.mark.parametrize("dtype,n_v", [("f32", 256), ("f64", 128)])
+def test_largest_losvd_layouts_observe_like_the_oracle(oracle, Fit, dtype, n_v):
+    """256 velocity bins in 40 annuli (J = 10290) is the largest LOSVD layout
+    whose in-tile bins and tables fit the LDS of a CU with FP32 state; FP64
+    state takes twice the table space (128 bins, J = 5170)."""
+    wl = workload(3)
+    lay = dict(wl.layout, n_v=n_v)
+    _observe_case(oracle, Fit, wl, lay, dtype, 50_003, 80)
+
+
+def test_gauss_hermite_of_order_eight_observes_like_the_oracle(oracle, Fit):
+    wl = workload(2)
+    lay = dict(wl.layout, gh_nmax=8)
+    _observe_case(oracle, Fit, wl, lay, "f32", 50_003, 82, gh=True)
+
+
+def test_layout_too_large_for_lds_is_refused(Fit):
+    from paper_1202_2355_amd._abi import M2M_EUNSUPPORTED, M2MError
+    wl = workload(3)
+    lay = dict(wl.layout, n_R=62, n_v=256)  # J = 50 + 62 * 256 = 15922 <= 16384
+    parts = cast(wl.initial_particles(n=4_096, seed=84), "f32")
+    with pytest.raises(M2MError) as e:
+        Fit(wl.potential, lay, wl.params, parts, dtype="f32")
+    assert e.value.status == M2M_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_largest_prior_grid_refreshes_like_the_oracle(oracle, Fit, dtype):
+    """64 x 64 = 4096 cells, the largest prior grid."""
+    from m2m_testlib import random_weights
+    wl = workload(3)
+    P = dict(wl.params, n_E=64, n_x=64)
+    n = 50_003
+    _say("largest prior grid", dtype, n)
+    parts = cast(wl.initial_particles(n=n, seed=86), dtype)
+    u = cast({"u": random_weights(n, 87, spread=0.5)}, dtype)["u"]
+    f = Fit(wl.potential, wl.layout, P, parts, dtype=dtype, u=u)
+    f.update_priors()
+    uh = f.particles()["uh"]
+    from m2m_testlib import clean_of_cell_edges
+    cell, E, xc = oracle.cells(wl.potential, P, parts)
+    band = 1e-5 if dtype == "f32" else 1e-12
+    C = P["n_E"] * P["n_x"]
+    sums = np.bincount(cell, weights=u, minlength=C)
+    cnts = np.bincount(cell, minlength=C)
+    uh_o = sums[cell] / cnts[cell]
+    ok = clean_of_cell_edges(P, cell, E, xc, band * abs(P["E_lo"]), band)
+    _say("largest prior grid", dtype, "occupied cells", np.count_nonzero(cnts), "clean", ok.mean())
+    assert np.count_nonzero(cnts) > 1000 and ok.mean() > 0.6
+    np.testing.assert_allclose(uh[ok], uh_o[ok], rtol=1e-6 if dtype == "f32" else 1e-13)
+    f.close()

@@ -159,24 +159,18 @@ def test_prior_refresh_matches_oracle(oracle, Fit, dtype):
     f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype, u=u)
     f.update_priors()
     uh = f.particles()["uh"]
+    from m2m_testlib import clean_of_cell_edges
     cell, E, xc = oracle.cells(wl.potential, wl.params, parts)
     P = wl.params
-    band_e = 1e-5 * abs(P["E_lo"]) if dtype == "f32" else 1e-12
-    band_x = 1e-5 if dtype == "f32" else 1e-12
-    dE = (P["E_hi"] - P["E_lo"]) / P["n_E"]
-    te = (E - P["E_lo"]) / dE
-    tx = xc * P["n_x"]
-    amb = (np.abs(te - np.round(te)) * dE <= band_e) | (np.abs(tx - np.round(tx)) <= band_x * P["n_x"])
+    band = 1e-5 if dtype == "f32" else 1e-12
     C = P["n_E"] * P["n_x"]
     sums = np.bincount(cell, weights=u, minlength=C)
     cnts = np.bincount(cell, minlength=C)
     uh_o = sums[cell] / cnts[cell]
-    dirty = np.zeros(C, bool)
-    dirty[cell[amb]] = True
-    ok = ~dirty[cell]
+    ok = clean_of_cell_edges(P, cell, E, xc, band * abs(P["E_lo"]), band)
     _say("priors", dtype, "clean fraction", ok.mean())
-    # a cell with one member near an edge is excluded whole; most are clean
-    assert ok.mean() > 0.75
+    # cells near an edge crossing are excluded whole; most are clean
+    assert ok.mean() > 0.7
     np.testing.assert_allclose(uh[ok], uh_o[ok], rtol=1e-6 if dtype == "f32" else 1e-13)
     f.close()
 
