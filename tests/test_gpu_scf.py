@@ -259,3 +259,25 @@ def test_checkpoint_resume_keeps_the_expansion(oracle, Fit):
     _assert_table(g.potential_table(), end_tab, 1e-12, "scf checkpoint table")
     f.close()
     g.close()
+
+
+def test_scf_with_alm_observables_run_fp64_matches_oracle(oracle, Fit):
+    """The paper's pairing: spherical-harmonic density observables (l <= 2 on
+    30 mesh radii) in a fit whose stellar potential is its own expansion
+    (l <= 2, 16 nodes, rebuilt every 4 steps)."""
+    from workloads import with_alm
+    wl = with_scf(with_alm(workload(1), n_mesh=30, l_max=2), l_max=2, n_nodes=16, r_min=0.05,
+                  r_max=50.0, every=4)
+    n = 15_013
+    _say("scf + alm run fp64", wl.name, n)
+    f, o = _scf_pair(oracle, Fit, wl, n, "f64", 1e-12, seed=63)
+    f.step(24)
+    hist_o = o.step(24)
+    st = f.particles()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("scf + alm run fp64: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_allclose(st[k], o.arr[k], rtol=0, atol=1e-9)
+    assert r2 <= 1e-10 and rmax <= 1e-10
+    np.testing.assert_allclose(f.chi2_history(24), hist_o, rtol=1e-9)
+    f.close()
