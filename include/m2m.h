@@ -13,7 +13,11 @@
  *   - force of change (eq. modFOC) with the mass-neutral entropy S+ (eq. S+)
  *     or the weight entropy (eq. entropy);
  *   - moving priors (Sec. 2.3.1): mean weight in cells of an (E, x = L/L_c)
- *     grid assigned as the prior of every particle in the cell.
+ *     grid assigned as the prior of every particle in the cell;
+ *   - optionally: thin-plate smoothing of the prior grid (Sec. 2.3.2), the
+ *     spherical-harmonic density observables a_lm (Sec. 3.3), prior cells for
+ *     rotating models and a logarithmic halo (Sec. 5), and the stellar
+ *     potential computed from the particles themselves (Sec. 2.1, Sec. 5).
  *
  * Conventions fixed by this interface
  *   Weights. The library carries u_i = N w_i / M ("u", 1 for equal weights;
