@@ -1263,26 +1263,32 @@ m2m_status rebuild(m2m_batch* b) {
     b->n_jobs = (int)jb.size();
     b->n_fits = (int)fd.size();
     b->lds = lds;
-    // graphs of kBatchGraphSteps steps over this composition, and of the
-    // same steps each followed by a reduction in the measuring mode that
-    // changes no state (m2m_batch_profile)
-    hipError_t e = capture_steps(
+    // the graph of kBatchGraphSteps steps over this composition (the
+    // measuring graph of m2m_batch_profile is captured when first asked for:
+    // serving rebuilds at every change of composition and never measures)
+    const hipError_t e = capture_steps(
         b->cap, kBatchGraphSteps,
         [b, f64](hipStream_t s) { return batch_step(b, f64, s); }, &b->graph);
-    if (e == hipSuccess)
-        e = capture_steps(
-            b->cap, kBatchGraphSteps,
-            [b, f64](hipStream_t s) {
-                hipError_t r = batch_step(b, f64, s);
-                if (r == hipSuccess)
-                    r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
-                                        kModeObserve, s, kin_scf(b->kin));
-                return r;
-            },
-            &b->graph_prof);
     if (e != hipSuccess) return M2M_EDEVICE;
     b->dirty = false;
     return M2M_OK;
+}
+
+// The steps of the step graph, each followed by a reduction in the measuring
+// mode that changes no state, over the current composition.
+hipError_t ensure_batch_prof_graph(m2m_batch* b) {
+    if (b->graph_prof) return hipSuccess;
+    const bool f64 = b->f64 == 1;
+    return capture_steps(
+        b->cap, kBatchGraphSteps,
+        [b, f64](hipStream_t s) {
+            hipError_t r = batch_step(b, f64, s);
+            if (r == hipSuccess)
+                r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
+                                    kModeObserve, s, kin_scf(b->kin));
+            return r;
+        },
+        &b->graph_prof);
 }
 
 }  // namespace
@@ -1404,6 +1410,7 @@ m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, dou
         if (s != M2M_OK) return s;
     }
     if (b->fits.empty()) return M2M_ESTATE;
+    if (ensure_batch_prof_graph(b) != hipSuccess) return M2M_EDEVICE;
     // as m2m_profile_step: r replays of the plain and of the measuring graph
     const int r = (n_steps + kBatchGraphSteps - 1) / kBatchGraphSteps;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
