@@ -315,13 +315,18 @@ constexpr YlmCoef kYlmC = ylm_coef();  // the same, folded where the indices are
 
 // f(l^2 + l + m, Y_lm) for every 0 <= l <= lmax, -l <= m <= l, at the
 // direction (ct, st) = cos, sin of the polar angle and (cp, sp) of the azimuth
-template <typename T, typename F>
-__device__ __forceinline__ void ylm_walk(int lmax, T ct, T st, T cp, T sp, F&& f) {
+// LMAX >= 0: the degree is LMAX, fixed at compile time (loops unrolled,
+// coefficients folded); LMAX < 0: the degree lmax
+template <int LMAX, typename T, typename F>
+__device__ __forceinline__ void ylm_walk_n(int lmax, T ct, T st, T cp, T sp, F&& f) {
+    const int L = LMAX >= 0 ? LMAX : lmax;
     T pmm = T(0.282094791773878143);  // 1/sqrt(4 pi)
     T cm = T(1), sm = T(0);           // cos(m phi), sin(m phi)
-    for (int m = 0; m <= lmax; ++m) {
+#pragma unroll
+    for (int m = 0; m <= (LMAX >= 0 ? LMAX : kMaxLM); ++m) {
+        if (m > L) break;
         if (m > 0) {
-            pmm = -T(kYlm.mm[m]) * st * pmm;
+            pmm = -T(M2M_YC(LMAX, mm[m])) * st * pmm;
             const T c = cm * cp - sm * sp;
             sm = sm * cp + cm * sp;
             cm = c;
@@ -336,17 +341,30 @@ __device__ __forceinline__ void ylm_walk(int lmax, T ct, T st, T cp, T sp, F&& f
             }
         };
         emit(m, pmm);
-        if (m < lmax) {
-            T p2 = pmm, p1 = T(kYlm.m1[m]) * ct * pmm;
+        if (m < L) {
+            T p2 = pmm, p1 = T(M2M_YC(LMAX, m1[m])) * ct * pmm;
             emit(m + 1, p1);
-            for (int l = m + 2; l <= lmax; ++l) {
-                const T p = T(kYlm.a[l][m]) * (ct * p1 - T(kYlm.b[l][m]) * p2);
+#pragma unroll
+            for (int l = m + 2; l <= (LMAX >= 0 ? LMAX : kMaxLM); ++l) {
+                if (l > L) break;
+                const T p = T(M2M_YC(LMAX, a[l][m])) * (ct * p1 - T(M2M_YC(LMAX, b[l][m])) * p2);
                 emit(l, p);
                 p2 = p1;
                 p1 = p;
             }
         }
     }
+}
+
+// the walk with the common degrees 2 and 4 unrolled
+template <typename T, typename F>
+__device__ __forceinline__ void ylm_walk(int lmax, T ct, T st, T cp, T sp, F&& f) {
+    if (lmax == 4)
+        ylm_walk_n<4>(4, ct, st, cp, sp, f);
+    else if (lmax == 2)
+        ylm_walk_n<2>(2, ct, st, cp, sp, f);
+    else
+        ylm_walk_n<-1>(lmax, ct, st, cp, sp, f);
 }
 
 template <typename T, typename A, int KIN>
