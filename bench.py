@@ -306,7 +306,7 @@ def main(argv=None):
         from workloads import with_alm
         wl = with_alm(wl, n_mesh=60, l_max=args.alm)
     if args.smooth:
-        wl.params = dict(wl.params, smooth=1)
+        wl = wl.with_(name=f"{wl.name}_smooth", params=dict(wl.params, smooth=1))
     if args.scf is not None:
         from workloads import with_scf
         wl = with_scf(wl, l_max=args.scf, n_nodes=32, r_min=0.02, r_max=100.0,
