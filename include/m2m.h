@@ -225,6 +225,9 @@ size_t m2m_workspace_bytes(const m2m_obs_layout* layout, const m2m_params* param
  * device buffer of at least m2m_workspace_bytes(...) bytes owned by the
  * caller. hip_stream: the stream all work of this context is ordered on.
  * On success *out receives the context; on failure *out is NULL.
+ * M2M_EINVAL, before any device call, for n < 1 (an empty fit), an unknown
+ * dtype, a NULL array or one that is not 16-byte aligned, and for invalid
+ * potential, layout or parameters.
  * M2M_EUNSUPPORTED if the step kernel's LDS tables do not fit the 160 KiB of
  * a compute unit: the bins (private copies), the cell sums, the edge tables
  * and, with the self-consistent potential, its interval table ((scf_nr + 1)

@@ -90,3 +90,12 @@ def test_create_rejects_bad_arguments_without_touching_memory():
                                C.byref(_abi.obs_layout(wl.layout)), C.byref(_abi.params(bad)),
                                100, 0, *([C.c_void_p(4096)] * 8), None, 0, None, C.byref(ctx))
     assert st == _abi.M2M_EINVAL
+    # an empty fit, an unknown dtype and a misaligned array are refused before
+    # the pointers are used (4096 and 4104 are never dereferenced)
+    for n, dtype, ptrs in ((0, 0, [C.c_void_p(4096)] * 8), (100, 7, [C.c_void_p(4096)] * 8),
+                           (100, 0, [C.c_void_p(4096)] * 7 + [C.c_void_p(4104)])):
+        ctx = C.c_void_p()
+        st = _abi.lib().m2m_create(C.byref(_abi.potential(wl.potential)),
+                                   C.byref(_abi.obs_layout(wl.layout)), C.byref(_abi.params(wl.params)),
+                                   n, dtype, *ptrs, None, 0, None, C.byref(ctx))
+        assert st == _abi.M2M_EINVAL and not ctx.value, (n, dtype)
