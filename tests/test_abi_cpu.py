@@ -99,3 +99,12 @@ def test_create_rejects_bad_arguments_without_touching_memory():
                                    C.byref(_abi.obs_layout(wl.layout)), C.byref(_abi.params(wl.params)),
                                    n, dtype, *ptrs, None, 0, None, C.byref(ctx))
         assert st == _abi.M2M_EINVAL and not ctx.value, (n, dtype)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built HIP library every entry point raises."""
+    from paper_1202_2355_amd import _abi
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB", str(tmp_path / "libm2m.so"))
+    with pytest.raises(ImportError, match="missing"):
+        _abi.lib()
