@@ -795,19 +795,28 @@ static void accel_total(const orc_model *m, double x, double y, double z, double
  * where w^T P w is the sum over the grid of the finite-difference thin-plate
  * terms (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 in the grid's own units
  * (cell widths hE = (E_hi - E_lo)/n_E, or (exp E_hi - exp E_lo)/n_E for
- * energy bins linear in exp(E), and hx = 1/n_x), with reflecting
- * boundaries. With those boundaries the sum equals |Lap w|^2 for the discrete
- * Laplacian Lap = L_E (x) I + I (x) L_x (summation by parts), so P = Lap Lap.
- * Hence w = (I + lambda P)^-1 w0, solved here densely (Cholesky). lambda
- * minimizes the generalized cross validation score
+ * energy bins linear in exp(E), and hx = 1/n_x). Each derivative is a
+ * finite difference taken only where its stencil lies inside the grid, with
+ * no values invented beyond an edge:
+ *   d2w/dE2 at every cell with a neighbour on both sides along E,
+ *     (w[k+1][l] - 2 w[k][l] + w[k-1][l]) / hE^2;
+ *   d2w/dx2 likewise along x;
+ *   d2w/dEdx at every interior corner of four cells,
+ *     (w[k+1][l+1] - w[k+1][l] - w[k][l+1] + w[k][l]) / (hE hx).
+ * Every term vanishes on a plane a + b E + c x, so lambda -> infinity gives
+ * the least-squares plane, and lambda -> 0 the data. P is the sum of d d^T
+ * over those stencils d; w = (I + lambda P)^-1 w0, solved here densely
+ * (Cholesky). lambda minimizes the generalized cross validation score
  *   GCV(lambda) = (|w0 - A w0|^2 / n) / (1 - tr(A)/n)^2,  A = (I + lambda P)^-1,
  * searched over p = log10(lambda) in three stages: steps of 0.25 over
  * [p_lo, p_hi], then 65 points over the two steps around the best point,
  * then 65 points over the two sub-steps around the best one (first minimum
  * on ties). p_lo = -2 log10(G_hi) - 4, p_hi = -2 log10(G_lo) + 4 with G_hi =
  * 4/hE^2 + 4/hx^2 and G_lo the smaller of 4 sin^2(pi/(2n))/h^2 over the axes
- * with more than one cell. The smoothed priors are floored at 1e-3 times the
- * mean of w0 (a prior must stay positive). Dense: meant for small grids. */
+ * with more than one cell (bounds of the spectrum of P from the grid
+ * Laplacian, widened by four decades). The smoothed priors are floored at
+ * 1e-3 times the mean of w0 (a prior must stay positive). Dense: meant for
+ * small grids. */
 static int cholesky(double *A, int n) {  /* in place, lower triangle */
     for (int j = 0; j < n; ++j) {
         double d = A[j * n + j];
@@ -872,28 +881,42 @@ static int smooth_grid(const orc_params *par, double *w, double lambda_in, doubl
     const double hE = (par->cells & 2) ? (exp(par->E_hi) - exp(par->E_lo)) / nE
                                         : (par->E_hi - par->E_lo) / nE;
     const double hx = 1.0 / nx;
-    double *Lap = (double *)calloc((size_t)n * n, sizeof(double));
     double *P = (double *)calloc((size_t)n * n, sizeof(double));
     double *w0 = (double *)malloc(sizeof(double) * n);
     double *scratch = (double *)malloc(sizeof(double) * (2 * (size_t)n * n + n));
-    if (!Lap || !P || !w0 || !scratch) return 1;
+    if (!P || !w0 || !scratch) return 1;
     for (int c = 0; c < n; ++c) w0[c] = w[c];
-    /* discrete Laplacian with reflecting boundaries (the ghost value beyond
-     * an edge equals the edge cell) */
-    for (int k = 0; k < nE; ++k)
+    /* P = sum over the stencils of weight * d d^T; a stencil d is given by
+     * up to four (cell, coefficient) pairs */
+    int sc[4];
+    double sv[4];
+#define ADD_STENCIL(cnt, weight)                                              \
+    for (int a_ = 0; a_ < (cnt); ++a_)                                        \
+        for (int b_ = 0; b_ < (cnt); ++b_)                                    \
+            P[(size_t)sc[a_] * n + sc[b_]] += (weight) * sv[a_] * sv[b_];
+    for (int k = 1; k + 1 < nE; ++k) /* d2w/dE2 */
         for (int l = 0; l < nx; ++l) {
-            const int c = k * nx + l;
-            if (k > 0) { Lap[c * n + c - nx] += 1.0 / (hE * hE); Lap[c * n + c] -= 1.0 / (hE * hE); }
-            if (k < nE - 1) { Lap[c * n + c + nx] += 1.0 / (hE * hE); Lap[c * n + c] -= 1.0 / (hE * hE); }
-            if (l > 0) { Lap[c * n + c - 1] += 1.0 / (hx * hx); Lap[c * n + c] -= 1.0 / (hx * hx); }
-            if (l < nx - 1) { Lap[c * n + c + 1] += 1.0 / (hx * hx); Lap[c * n + c] -= 1.0 / (hx * hx); }
+            sc[0] = (k - 1) * nx + l; sv[0] = 1.0 / (hE * hE);
+            sc[1] = k * nx + l;       sv[1] = -2.0 / (hE * hE);
+            sc[2] = (k + 1) * nx + l; sv[2] = 1.0 / (hE * hE);
+            ADD_STENCIL(3, 1.0)
         }
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k < n; ++k) {
-            const double a = Lap[i * n + k];
-            if (a == 0.0) continue;
-            for (int j = 0; j < n; ++j) P[i * n + j] += a * Lap[k * n + j];
+    for (int k = 0; k < nE; ++k) /* d2w/dx2 */
+        for (int l = 1; l + 1 < nx; ++l) {
+            sc[0] = k * nx + l - 1; sv[0] = 1.0 / (hx * hx);
+            sc[1] = k * nx + l;     sv[1] = -2.0 / (hx * hx);
+            sc[2] = k * nx + l + 1; sv[2] = 1.0 / (hx * hx);
+            ADD_STENCIL(3, 1.0)
         }
+    for (int k = 0; k + 1 < nE; ++k) /* d2w/dEdx, counted twice */
+        for (int l = 0; l + 1 < nx; ++l) {
+            sc[0] = (k + 1) * nx + l + 1; sv[0] = 1.0 / (hE * hx);
+            sc[1] = (k + 1) * nx + l;     sv[1] = -1.0 / (hE * hx);
+            sc[2] = k * nx + l + 1;       sv[2] = -1.0 / (hE * hx);
+            sc[3] = k * nx + l;           sv[3] = 1.0 / (hE * hx);
+            ADD_STENCIL(4, 2.0)
+        }
+#undef ADD_STENCIL
     /* search range */
     double Ghi = 0.0, Glo = INFINITY;
     if (nE > 1) {
@@ -936,7 +959,6 @@ static int smooth_grid(const orc_params *par, double *w, double lambda_in, doubl
     mean /= n;
     for (int c = 0; c < n; ++c) w[c] = fmax(w[c], 1e-3 * mean);
     if (lambda_out) *lambda_out = lam;
-    free(Lap);
     free(P);
     free(w0);
     free(scratch);
@@ -993,6 +1015,37 @@ int orc_refresh_priors(orc_model *m) {
     return rc;
 }
 
+/* One drift-kick-drift leapfrog step (Sec. 4.1) of one particle: drift half
+ * a step, kick a whole step with the acceleration at the midpoint, drift half
+ * a step. The acceleration comes from acc(ctx, x, y, z, g). Both the step loop
+ * of a fit and the bare integrator below use this one function. */
+typedef void (*orc_accel_fn)(const void *ctx, double x, double y, double z, double *g);
+
+static void dkd_step(double dt, double *x, double *y, double *z, double *vx, double *vy,
+                     double *vz, orc_accel_fn acc, const void *ctx) {
+    double g[3];
+    *x += 0.5 * dt * *vx;
+    *y += 0.5 * dt * *vy;
+    *z += 0.5 * dt * *vz;
+    acc(ctx, *x, *y, *z, g);
+    *vx += dt * g[0];
+    *vy += dt * g[1];
+    *vz += dt * g[2];
+    *x += 0.5 * dt * *vx;
+    *y += 0.5 * dt * *vy;
+    *z += 0.5 * dt * *vz;
+}
+
+/* the acceleration of a fit (analytic, or with its self-consistent part) */
+static void accel_of_model(const void *ctx, double x, double y, double z, double *g) {
+    accel_total((const orc_model *)ctx, x, y, z, g);
+}
+
+/* the acceleration of a fixed analytic potential */
+static void accel_of_potential(const void *ctx, double x, double y, double z, double *g) {
+    orc_accel((const orc_potential *)ctx, x, y, z, g);
+}
+
 /* n steps; correct = 0 advances and smooths without weight correction
  * (relaxation). chi2_hist (optional) receives chi^2 after each step. */
 int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) {
@@ -1022,18 +1075,8 @@ int orc_steps(orc_model *m, int32_t nsteps, int32_t correct, double *chi2_hist) 
                 double G = P->mu * (-log(m->u[i] / m->uhat[i]) - cS) - w0 * chi;
                 m->u[i] *= exp(P->eps * dt * G);
             }
-            /* drift - kick - drift */
-            double g[3];
-            m->x[i] += 0.5 * dt * m->vx[i];
-            m->y[i] += 0.5 * dt * m->vy[i];
-            m->z[i] += 0.5 * dt * m->vz[i];
-            accel_total(m, m->x[i], m->y[i], m->z[i], g);
-            m->vx[i] += dt * g[0];
-            m->vy[i] += dt * g[1];
-            m->vz[i] += dt * g[2];
-            m->x[i] += 0.5 * dt * m->vx[i];
-            m->y[i] += 0.5 * dt * m->vy[i];
-            m->z[i] += 0.5 * dt * m->vz[i];
+            dkd_step(dt, &m->x[i], &m->y[i], &m->z[i], &m->vx[i], &m->vy[i], &m->vz[i],
+                     accel_of_model, m);
             if (m->flag &&
                 particle_ambiguous(&m->lay, &E, m->x[i], m->y[i], m->z[i], m->vz[i], m->band))
                 m->flag[i] = 1;
@@ -1069,21 +1112,11 @@ void orc_cell_mass(const orc_potential *p, const orc_params *P, int64_t n, const
     }
 }
 
-/* one DKD step of a single particle (tests of the integrator) */
+/* nsteps DKD steps of n particles in a fixed potential (tests of the
+ * integrator): the same step function as the fit's step loop */
 void orc_push(const orc_potential *p, double dt, int64_t n, double *x, double *y, double *z,
               double *vx, double *vy, double *vz, int32_t nsteps) {
     for (int s = 0; s < nsteps; ++s)
-        for (int64_t i = 0; i < n; ++i) {
-            double g[3];
-            x[i] += 0.5 * dt * vx[i];
-            y[i] += 0.5 * dt * vy[i];
-            z[i] += 0.5 * dt * vz[i];
-            orc_accel(p, x[i], y[i], z[i], g);
-            vx[i] += dt * g[0];
-            vy[i] += dt * g[1];
-            vz[i] += dt * g[2];
-            x[i] += 0.5 * dt * vx[i];
-            y[i] += 0.5 * dt * vy[i];
-            z[i] += 0.5 * dt * vz[i];
-        }
+        for (int64_t i = 0; i < n; ++i)
+            dkd_step(dt, &x[i], &y[i], &z[i], &vx[i], &vy[i], &vz[i], accel_of_potential, p);
 }

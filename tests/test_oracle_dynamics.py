@@ -189,3 +189,77 @@ def test_circular_orbit_radius_and_period(oracle):
     # the phase error is second order in dt
     assert max(dev.values()) < 1e-8
     assert 3.0 < perr[0.02] / perr[0.01] < 5.0
+
+
+# ------------------------------------------- the push inside the fit's step loop
+def _fit_without_correction(oracle, pot, parts):
+    """An oracle fit whose steps only push (correct = 0: relaxation, Sec. 4.1):
+    its step loop is the code whose drift-kick-drift the fit runs."""
+    from workloads import make_layout, make_params, make_potential
+    lay = make_layout(4, 0.05, 20.0)
+    par = make_params(make_potential(), prior_every=0)
+    J = oracle.J_of(lay)
+    return oracle.OracleFit(pot, lay, par, parts, np.ones(J), np.ones(J))
+
+
+@pytest.mark.parametrize("pot", [HERN, NFW])
+def test_step_loop_conserves_angular_momentum(oracle, pot):
+    """10^4 relaxation steps of the fit's own step loop: the kick is radial,
+    so L = r x v is kept to rounding (P1)."""
+    p0 = _orbits()
+    f = _fit_without_correction(oracle, pot, p0)
+    f.step(10000, correct=False)
+    L0, L1 = _L(p0), _L(f.arr)
+    rel = np.linalg.norm(L1 - L0, axis=1) / np.linalg.norm(L0, axis=1)
+    assert rel.max() < 1e-13
+
+
+def test_step_loop_is_time_reversible(oracle):
+    """n relaxation steps of the fit, velocities flipped, n more steps:
+    the start state comes back (P3); a drift and a kick in the wrong order
+    would not."""
+    p0 = _orbits(n=5, seed=11)
+    f = _fit_without_correction(oracle, NFW, p0)
+    f.step(2000, correct=False)
+    back = {k: f.arr[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    for k in ("vx", "vy", "vz"):
+        back[k] = -back[k]
+    g = _fit_without_correction(oracle, NFW, back)
+    g.step(2000, correct=False)
+    for k in ("x", "y", "z"):
+        np.testing.assert_allclose(g.arr[k], p0[k], atol=1e-11)
+    for k in ("vx", "vy", "vz"):
+        np.testing.assert_allclose(-g.arr[k], p0[k], atol=1e-11)
+
+
+def test_step_loop_energy_error_is_second_order(oracle):
+    """The fit's step loop conserves energy to O(dt^2) with no drift (P2):
+    halving dt cuts the largest energy error about four times."""
+    from workloads import make_layout, make_params, make_potential
+    p0 = _orbits(n=4, seed=7)
+    E0 = _E(oracle, HERN, p0)
+    lay = make_layout(4, 0.05, 20.0)
+    J = oracle.J_of(lay)
+    worst = {}
+    for dt in (0.02, 0.01):
+        par = make_params(make_potential(), prior_every=0, dt=dt)
+        f = oracle.OracleFit(HERN, lay, par, p0, np.ones(J), np.ones(J))
+        w = np.zeros(4)
+        n = int(round(20.0 / dt))
+        for _ in range(100):
+            f.step(n // 100, correct=False)
+            w = np.maximum(w, np.abs(_E(oracle, HERN, f.arr) / E0 - 1.0))
+        worst[dt] = w
+    ratio = worst[0.02] / worst[0.01]
+    assert np.all((ratio > 3.0) & (ratio < 5.5)), ratio
+
+
+def test_step_loop_moves_particles_as_the_integrator(oracle):
+    """Without correction the fit's particles follow the bare integrator
+    bit for bit: the step loop adds nothing to the push."""
+    p0 = _orbits(n=7, seed=5)
+    f = _fit_without_correction(oracle, NFW, p0)
+    f.step(300, correct=False)
+    q = oracle.push(NFW, f.m.par.dt, p0, 300)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_array_equal(f.arr[k], q[k])
