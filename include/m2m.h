@@ -79,16 +79,22 @@
  *     (previous priors for empty cells) is replaced by the minimizer of
  *     |w - w0|^2 + lambda w^T P w, P the finite-difference thin-plate
  *     penalty (d2w/dE2)^2 + 2 (d2w/dEdx)^2 + (d2w/dx2)^2 on the grid in its
- *     own units (cell widths (E_hi - E_lo)/n_E and 1/n_x) with reflecting
- *     boundaries, which equals |Lap w|^2 for the grid Laplacian. lambda
+ *     own units (cell widths hE = (E_hi - E_lo)/n_E and hx = 1/n_x), each
+ *     difference taken only where its stencil lies inside the grid:
+ *     w[k+1][l] - 2 w[k][l] + w[k-1][l] over hE^2 at cells with neighbours
+ *     on both sides along E, likewise along x, and w[k+1][l+1] - w[k+1][l] -
+ *     w[k][l+1] + w[k][l] over hE hx at every interior corner. Planes cost
+ *     nothing: lambda -> infinity gives the least-squares plane. lambda
  *     minimizes the generalized cross validation score
  *       GCV = (|w0 - A w0|^2/n) / (1 - tr(A)/n)^2,  A = (I + lambda P)^-1,
  *     over log10 lambda: steps of 0.25 over [-2 log10(G_hi) - 4,
  *     -2 log10(G_lo) + 4] (G_hi = 4/hE^2 + 4/hx^2, G_lo the smaller of
  *     4 sin^2(pi/2n)/h^2 over axes with more than one cell), then 65 points
  *     over the two steps around the best one, then 65 points over the two
- *     sub-steps around the best one. Smoothed priors are floored at 1e-3
- *     times the mean of w0.
+ *     sub-steps around the best one (the first minimum on ties). Smoothed
+ *     priors are floored at 1e-3 times the mean of w0. The library computes
+ *     the eigendecomposition of P once per grid shape on the host (see
+ *     m2m_smoothing_basis) and smooths on the device in that basis.
  *   Self-consistent potential (scf_nr > 0). The stellar potential is the
  *     multipole expansion of the particles, m_i = upsilon u_i M / N:
  *       Phi_*(x) = sum_lm Phi_lm(r) Y_lm(theta, phi)  (l <= scf_lmax, the
@@ -195,7 +201,8 @@ typedef struct {
     int32_t prior_every; /* correction steps between prior refreshes; 0 = never */
     double E_lo, E_hi;   /* energy range of the grid, E_lo < E_hi */
     int32_t smooth;      /* 1: smooth the prior grid at every refresh (Sec. 2.3.2, see
-                            "Prior smoothing"); needs n_E, n_x <= 128; 0: cell means */
+                            "Prior smoothing"); needs n_E, n_x <= 128 and
+                            n_E * n_x <= 2048; 0: cell means */
     int32_t cells;       /* m2m_cells flags of the prior grid (Sec. 5); 0: n_E x n_x
                             cells linear in E */
     /* Self-consistent stellar potential (Sec. 2.1: a potential computed from
@@ -306,6 +313,24 @@ m2m_status m2m_set_state(m2m_ctx* ctx, const void* host_blob, size_t bytes);
  * Synchronizes. Used to report achieved bandwidth against the roofline. */
 m2m_status m2m_profile_step(m2m_ctx* ctx, int32_t n_steps, int32_t correct, double* ms_step,
                             double* ms_finalize);
+
+/* The eigendecomposition P = Q diag(g) Q^T of the prior-smoothing penalty of
+ * an n_E x n_x grid with cell widths hE, hx (Sec. 2.3.2, eq. smooth_grid; see
+ * "Prior smoothing"), as the device smoother uses it; host only, no device
+ * call. Q is the orthonormal parity basis of the two axis reflections times
+ * block eigenvectors. Along an axis of n cells, even vector i < ceil(n/2) is
+ * (e_i + e_{n-1-i})/sqrt(2) (e_i alone for the middle cell of an odd n) and
+ * odd vector i < floor(n/2) is (e_i - e_{n-1-i})/sqrt(2). Block b = 2 pE + pX
+ * (parity 0 even, 1 odd) holds the products of E vector i of parity pE and x
+ * vector j of parity pX at index r = i m_x(pX) + j; its m_b x m_b eigenvector
+ * matrix has entry [r][o] = component r of eigenvector o. out (host,
+ * len doubles) receives the n_E n_x eigenvalues of blocks 0..3, then the
+ * eigenvector matrices of blocks 0..3, row-major. With out = NULL, *len
+ * receives the length. EINVAL for n_E, n_x outside 1..128, n_E n_x > 2048,
+ * hE, hx not > 0 or len too small; EDEVICE if the iteration does not
+ * converge. The result is cached per grid shape for the process. */
+m2m_status m2m_smoothing_basis(int32_t n_E, int32_t n_x, double hE, double hx, double* out,
+                               size_t* len);
 
 /* Release the context and its library-owned workspace (synchronizes). */
 m2m_status m2m_destroy(m2m_ctx* ctx);

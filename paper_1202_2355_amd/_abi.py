@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 from .build import LIB
 
 M2M_OK, M2M_EINVAL, M2M_ENOMEM, M2M_EDEVICE, M2M_ESTATE, M2M_ENONFINITE, M2M_EUNSUPPORTED = range(7)
@@ -80,6 +82,8 @@ SIGNATURES = {
     "m2m_set_state": (_st, [_vp, _vp, C.c_size_t]),
     "m2m_profile_step": (_st, [_vp, _i32, _i32, _dp, _dp]),
     "m2m_destroy": (_st, [_vp]),
+    "m2m_smoothing_basis": (_st, [_i32, _i32, C.c_double, C.c_double, _dp,
+                                  C.POINTER(C.c_size_t)]),
     "m2m_last_error": (C.c_char_p, [_vp]),
     "m2m_set_launch": (_st, [_i32, _i32]),
     "m2m_get_launch": (_st, [C.POINTER(_i32)] * 2),
@@ -186,3 +190,16 @@ def m2m_get_launch():
     b, t = _i32(), _i32()
     lib().m2m_get_launch(C.byref(b), C.byref(t))
     return b.value, t.value
+
+
+def m2m_smoothing_basis(n_E: int, n_x: int, hE: float, hx: float) -> np.ndarray:
+    """The prior-smoothing penalty's eigendecomposition as the library holds
+    it: the n_E n_x eigenvalues of the four parity blocks, then their
+    eigenvector matrices (host only)."""
+    n = C.c_size_t(0)
+    check(lib().m2m_smoothing_basis(int(n_E), int(n_x), float(hE), float(hx), None, C.byref(n)),
+          "m2m_smoothing_basis")
+    out = np.zeros(n.value)
+    check(lib().m2m_smoothing_basis(int(n_E), int(n_x), float(hE), float(hx),
+                                    out.ctypes.data_as(_dp), C.byref(n)), "m2m_smoothing_basis")
+    return out

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libm2m.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("m2m_kernels.hip", "m2m_step_f32d.hip", "m2m_step_f32f.hip",
-                                            "m2m_step_f64.hip", "m2m_api.cpp")]
+                                            "m2m_step_f64.hip", "m2m_api.cpp", "m2m_smooth.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -154,6 +154,8 @@ std::string check_params(const m2m_params* P) {
     if (n_cells(*P) > kMaxCells) return "need n_E*n_x <= 2048 with the L_z split";
     if (P->smooth && (P->n_E > kSmoothMaxSide || P->n_x > kSmoothMaxSide))
         return "prior smoothing needs n_E, n_x <= 128";
+    if (P->smooth && P->n_E * P->n_x > kSmoothMaxCells)
+        return "prior smoothing needs n_E*n_x <= 2048";
     if (P->scf_nr != 0) {
         if (P->scf_nr < 2 || P->scf_nr > kMaxScfNodes) return "scf_nr must be 0 or 2..64";
         if (P->scf_lmax < 0 || P->scf_lmax > kMaxLM) return "scf_lmax must be 0..8";
@@ -283,7 +285,7 @@ constexpr double kLzHalo1 = 3.68887945411394;  // ln 40: with the logarithmic ha
 // ---------------------------------------------------------------- layout ---
 struct WsLayout {
     size_t st, fd, tiles, jobs, redge2, rmesh, Redge2, vedge, Vp, isp, rp, ucell, lctab, cidx;
-    size_t cdata, gprior, scf_rho, scf_sum, scf_tab;
+    size_t cdata, gprior, scf_rho, scf_sum, scf_tab, sm_basis;
     size_t Y, sigma, yv, ytil, delta, obs, hist, chi2p, partials, total;
     int seg_cap, row_len, nbj, ncj, npj, J, C, P;  // P: interval sums of the expansion
 };
@@ -351,6 +353,8 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.scf_rho = take(8 * (size_t)std::max(P.scf_nr, 1));
     w.scf_sum = take(8 * (size_t)std::max(w.P, 1));
     w.scf_tab = take(8 * (size_t)std::max(w.P, 1));
+    // eigendecomposition of the smoothing penalty (both L_z halves share it)
+    w.sm_basis = take(P.smooth ? 8 * smooth_basis_len(P.n_E, P.n_x) : 8);
     w.total = o;
     return w;
 }
@@ -749,6 +753,7 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.cdata = reinterpret_cast<double*>(b + w.cdata);
     f.gprior = reinterpret_cast<double*>(b + w.gprior);
     f.smooth = c->par.smooth;
+    f.sm_basis = reinterpret_cast<double*>(b + w.sm_basis);
     if (c->par.smooth) {
         int k1 = 0;
         smooth_range(c->par, &f.sm_plo, &f.sm_phi, &k1);
@@ -815,6 +820,13 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
         for (int k = 0; k < c->par.scf_nr; ++k)
             rho[k] = log_edge(c->par.scf_rmin, c->par.scf_rmax, c->par.scf_nr - 1, k);
         if ((s = upload64(c, w.scf_rho, rho)) != M2M_OK) return bail(s);
+    }
+    if (c->par.smooth) {
+        // the smoothing penalty's eigendecomposition for this grid shape
+        std::vector<double> basis(smooth_basis_len(c->par.n_E, c->par.n_x));
+        if (!smooth_basis(c->par.n_E, c->par.n_x, f.sm_hE, 1.0 / c->par.n_x, basis.data()))
+            return bail(M2M_EDEVICE);
+        if ((s = upload64(c, w.sm_basis, basis)) != M2M_OK) return bail(s);
     }
     if ((s = upload(c, w.ucell, ones)) != M2M_OK) return bail(s);
     if ((s = upload64(c, w.gprior, ones)) != M2M_OK) return bail(s);
@@ -1145,6 +1157,21 @@ m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double
     return M2M_OK;
 }
 
+m2m_status m2m_smoothing_basis(int32_t n_E, int32_t n_x, double hE, double hx, double* out,
+                               size_t* len) {
+    if (!len || n_E < 1 || n_x < 1 || n_E > kSmoothMaxSide || n_x > kSmoothMaxSide ||
+        n_E * n_x > kSmoothMaxCells || !(is_fin(hE) && hE > 0) || !(is_fin(hx) && hx > 0))
+        return M2M_EINVAL;
+    const size_t need = smooth_basis_len(n_E, n_x);
+    if (!out) {
+        *len = need;
+        return M2M_OK;
+    }
+    if (*len < need) return M2M_EINVAL;
+    *len = need;
+    return smooth_basis(n_E, n_x, hE, hx, out) ? M2M_OK : M2M_EDEVICE;
+}
+
 m2m_status m2m_destroy(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
@@ -1178,6 +1205,7 @@ struct m2m_batch {
     size_t lds = 0;
     int block = 256, kin = -1;
     bool acc64 = true;
+    bool smooth = false;  // some fit smooths its prior grid
     hipGraphExec_t graph = nullptr;
     hipGraphExec_t graph_prof = nullptr;  // steps with an extra measuring reduction
 };
@@ -1205,7 +1233,7 @@ hipError_t batch_step(m2m_batch* b, bool f64, hipStream_t s) {
                                b->lds, kModeStep, s);
     if (e == hipSuccess)
         e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s,
-                            kin_scf(b->kin));
+                            kin_scf(b->kin), b->smooth);
     return e;
 }
 
@@ -1241,8 +1269,10 @@ m2m_status rebuild(m2m_batch* b) {
     int64_t tile = (ntot + room - 1) / room;
     tile = (tile + kSegAlign - 1) / kSegAlign * kSegAlign;
     size_t lds = 0;
+    b->smooth = false;
     for (size_t f = 0; f < b->fits.size(); ++f) {
         m2m_ctx* c = b->fits[f];
+        if (c->par.smooth) b->smooth = true;
         fd.push_back(c->fd);
         int cnt = (int)std::min<int64_t>((c->n + tile - 1) / tile, c->w.seg_cap);
         cnt = std::max(1, cnt);
@@ -1285,7 +1315,7 @@ hipError_t ensure_batch_prof_graph(m2m_batch* b) {
             hipError_t r = batch_step(b, f64, s);
             if (r == hipSuccess)
                 r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
-                                    kModeObserve, s, kin_scf(b->kin));
+                                    kModeObserve, s, kin_scf(b->kin), b->smooth);
             return r;
         },
         &b->graph_prof);

@@ -18,6 +18,7 @@ constexpr int kFinCols = 64;       // columns (bins or cells) per finalize block
 constexpr int kFinThreads = 1024;  // finalize block: 16 waves over the tiles
 constexpr int kFinWaves = kFinThreads / 64;  // row groups of the fixed reduction order
 constexpr int kSmoothMaxSide = 128;   // prior smoothing: at most this many cells per axis
+constexpr int kSmoothMaxCells = 2048; // and per smoothed grid
 constexpr int kSmoothMaxPoints = 256; // and at most this many first-stage search points
 constexpr int kGcvSlots = 5;          // lambda points a wave scores in one pass over the cells
 constexpr int kHistCap = 8192;     // chi^2 history ring per fit
@@ -93,6 +94,9 @@ struct FitDev {
     // smoothing: the log10(lambda) search range, the cell width along energy
     double sm_plo, sm_phi, sm_hE;
     int32_t sm_k1, pad3;         // points of the first search stage
+    // eigenvalues and parity-block eigenvectors of the smoothing penalty
+    // (smooth_basis below), FP64
+    double* sm_basis;
     double lz0, ilz;             // ln zeta of entry 0, 1 / step in ln zeta
     double hv2, hr02, hiq2;      // logarithmic halo: v0^2 (0: none), r0^2, 1/q^2
     // step constants
@@ -149,8 +153,10 @@ hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* f
                        hipStream_t s);
 // the column jobs of the fits of the table (n_fits of them)
 // scf: the fits have the self-consistent potential (kin_scf of their kin class)
+// smooth: some fit of the launch smooths its prior grid (the variant with the
+// smoothing's LDS grids)
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s, bool scf);
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth);
 bool kin_scf(int kin);
 // the step kernel of one particle-state / in-tile-sum type pair (one == nullptr:
 // over the fit and tile tables, else over that one fit); m2m_step_*.hip
@@ -166,6 +172,15 @@ hipError_t launch_step_f32f(int block, int kin, const FitDev* fits, const Tile* 
 hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& fd, int n_tiles,
                         size_t lds, int32_t mode, hipStream_t s);
 hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s);
+
+// ---- prior smoothing basis (m2m_smooth.cpp) -------------------------------
+// Doubles of the eigendecomposition of the thin-plate penalty of an
+// n_E x n_x grid: n_E n_x eigenvalues, then the eigenvectors of its four
+// reflection-parity blocks.
+size_t smooth_basis_len(int nE, int nx);
+// Compute it (or take it from the process-wide cache of grid shapes) into
+// out; false if the eigen-iteration does not converge.
+bool smooth_basis(int nE, int nx, double hE, double hx, double* out);
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
                          hipStream_t s);
 hipError_t launch_weights(bool f64, const void* u, void* w, int64_t n, double scale,

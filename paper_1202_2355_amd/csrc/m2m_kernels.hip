@@ -175,8 +175,8 @@ __device__ __forceinline__ void end_step(const FitDev& fd, G<FitState> gst, cons
 }
 
 // GCV score (RSS/n) / (1 - tr(A)/n)^2 of the spectral smoother at P values
-// of lambda, summed by one wave over the n cells (Gamma^2 in g2, transformed
-// data in wh); 1 / (1 + t) is a hardware reciprocal refined by two Newton
+// of lambda, summed by one wave over the n eigenvalues (in g2) and the
+// transformed data (in wh); 1 / (1 + t) is a hardware reciprocal refined by two Newton
 // steps (within an ulp or two), as the score only ranks the lambdas.
 template <int P>
 __device__ __forceinline__ void gcv_points(const double* g2, const double* wh, int n, int lane,
@@ -210,33 +210,78 @@ __device__ __forceinline__ void gcv_points(const double* g2, const double* wh, i
 }
 
 // Thin-plate smoothing of one n_E x n_x prior grid (the cells from `base`)
-// with the GCV-chosen lambda (Sec. 2.3.2, eq. smooth_grid) by the block
-// that ends a refresh step; the energy cell width is sm_hE. On the grid
-// with reflecting boundaries the penalty is |Lap w|^2 and the orthonormal
-// 2-D DCT-II diagonalizes Lap: its basis along an axis of n cells is
-// s_k cos(pi k (2i+1) / 2n) (s_0 = sqrt(1/n), s_k = sqrt(2/n)) with
-// eigenvalues -(2 - 2 cos(pi k / n)) / h^2. With Gamma the sum of the two
-// axes' eigenvalue magnitudes and the transformed data w^ the smoother is the filter
-// 1/(1 + lambda Gamma^2), and
-//   |w0 - A w0|^2 = sum (t/(1+t))^2 w^^2,  1 - tr(A)/n = sum t/(1+t) / n,
-// t = lambda Gamma^2. The log10(lambda) search: steps of 0.25 from sm_plo
-// (sm_k1 points), then 65 points over the two steps around the best, then
-// 65 points over the two sub-steps around the best (first minimum on
-// ties). Smoothed priors are floored at 1e-3 of the mean of the data.
-// In LDS: the grids sa, sb (kMaxCells doubles each), buf (scores and
-// lambdas of a search stage) and per axis the table
-// cos(pi j / 2n), j < 4n, from which every basis value and eigenvalue is
-// read (the argument k (2i+1) is taken modulo 4n).
+// with the GCV-chosen lambda (Sec. 2.3.2, eq. smooth_grid) by the block that
+// ends a refresh step. The penalty P (finite-difference second derivatives
+// where their stencils fit the grid) has the eigendecomposition
+// P = Q diag(g) Q^T that the host computed per grid shape (fd.sm_basis): Q is
+// the parity basis of the two axis reflections (even/odd pairs of cells)
+// times the eigenvectors of four parity blocks. With w^ = Q^T w0 the
+// smoother is the filter 1/(1 + lambda g), and with t = lambda g
+//   |w0 - A w0|^2 = sum (t/(1+t))^2 w^^2,  1 - tr(A)/n = sum t/(1+t) / n.
+// The log10(lambda) search: steps of 0.25 from sm_plo (sm_k1 points), then
+// 65 points over the two steps around the best, then 65 points over the two
+// sub-steps around the best (first minimum on ties). Smoothed priors are
+// floored at 1e-3 of the mean of the data.
+// LDS: the folded grid / eigenvalues in sa, the transformed data in sb
+// (kSmoothMaxCells doubles each), buf (scores and lambdas of a search stage).
+
+// Parity blocks of an axis of n cells: (n+1)/2 even and n/2 odd vectors.
+// Coefficient of cell k in vector i of parity p (cells i and n-1-i).
+__device__ __forceinline__ double fold_coef(int n, int p, int i, int k) {
+    const int i2 = n - 1 - i;
+    if (i == i2) return (p == 0 && k == i) ? 1.0 : 0.0;
+    const double s = 0.70710678118654752440;
+    if (k == i) return s;
+    if (k == i2) return p == 0 ? s : -s;
+    return 0.0;
+}
+
+// The four parity blocks of an n_E x n_x grid: block b = 2 pE + pX holds
+// mE(pE) mX(pX) folded coefficients from off(b) and its eigenvectors from
+// qoff(b) in the basis (scalars and selects, no indexed arrays, so that
+// nothing goes to scratch memory).
+struct SmBlocks {
+    int mE0, mE1, mX0, mX1;
+    int o1, o2, o3, o4;  // off(1..4); off(0) = 0
+    int q0, q1, q2, q3;  // qoff(0..3)
+    __device__ int mE(int p) const { return p ? mE1 : mE0; }
+    __device__ int mX(int p) const { return p ? mX1 : mX0; }
+    __device__ int off(int b) const {
+        return b == 0 ? 0 : (b == 1 ? o1 : (b == 2 ? o2 : (b == 3 ? o3 : o4)));
+    }
+    __device__ int qoff(int b) const { return b == 0 ? q0 : (b == 1 ? q1 : (b == 2 ? q2 : q3)); }
+    // the block of folded index c (0 <= c < n_E n_x)
+    __device__ int block_of(int c) const { return c < o1 ? 0 : (c < o2 ? 1 : (c < o3 ? 2 : 3)); }
+};
+
+__device__ __forceinline__ SmBlocks sm_blocks(int nE, int nx) {
+    SmBlocks B;
+    B.mE0 = (nE + 1) / 2;
+    B.mE1 = nE / 2;
+    B.mX0 = (nx + 1) / 2;
+    B.mX1 = nx / 2;
+    const int m0 = B.mE0 * B.mX0, m1 = B.mE0 * B.mX1, m2 = B.mE1 * B.mX0, m3 = B.mE1 * B.mX1;
+    B.o1 = m0;
+    B.o2 = m0 + m1;
+    B.o3 = m0 + m1 + m2;
+    B.o4 = m0 + m1 + m2 + m3;
+    B.q0 = nE * nx;
+    B.q1 = B.q0 + m0 * m0;
+    B.q2 = B.q1 + m1 * m1;
+    B.q3 = B.q2 + m2 * m2;
+    return B;
+}
+
 template <typename T>
 __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double* sa, double* sb,
-                                              double* tE,
-                              double* tX, double* buf, int* sidx, double* smean) {
+                                              double* buf, int* sidx, double* smean) {
     static_assert(2 * kSmoothMaxPoints <= kFinWaves * kFinCols, "GCV scores and lambdas in buf");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nE = fd.n_E, nx = fd.n_x, n = nE * nx;
     const G<const double> w0 = gmem<const double>(fd.cdata) + base;
     const G<double> gp = gmem(fd.gprior) + base;
     const G<T> uc = gmem<T>(fd.ucell) + base;
+    const G<const double> basis = gmem<const double>(fd.sm_basis);
     if (n < 2) {
         if (tid == 0) {
             gp[0] = w0[0];
@@ -244,57 +289,43 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
         }
         return;
     }
-    const int pE = 4 * nE, pX = 4 * nx;
-    for (int j = tid; j < pE; j += kFinThreads) tE[j] = cos(M_PI * j / (2.0 * nE));
-    for (int j = tid; j < pX; j += kFinThreads) tX[j] = cos(M_PI * j / (2.0 * nx));
-    for (int c = tid; c < n; c += kFinThreads) sb[c] = w0[c];
-    const double sE0 = sqrt(1.0 / nE), sE = sqrt(2.0 / nE);
-    const double sX0 = sqrt(1.0 / nx), sX = sqrt(2.0 / nx);
-    __syncthreads();
+    const SmBlocks B = sm_blocks(nE, nx);
     if (wave == 0) {
         double sm = 0.0;
-        for (int c = lane; c < n; c += 64) sm += sb[c];
+        for (int c = lane; c < n; c += 64) sm += w0[c];
         for (int off = 32; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 64);
         if (lane == 0) *smean = sm / n;
     }
-    // forward transform along E: sa[k][l] = s_k sum_i cos(pi k (2i+1)/2nE) w0[i][l]
-    for (int o = tid; o < n; o += kFinThreads) {
-        const int k = o / nx, l = o - k * nx;
-        double v = 0.0;
-        int idx = k % pE;  // k (2i + 1) mod 4 nE
-        const int inc = (2 * k) % pE;
-        for (int i = 0; i < nE; ++i) {
-            v += tE[idx] * sb[i * nx + l];
-            idx += inc;
-            if (idx >= pE) idx -= pE;
+    // fold: the coefficient of each parity-basis vector, from its (up to)
+    // four cells (k, l) with k in {i, nE-1-i}, l in {j, nx-1-j}
+    for (int c = tid; c < n; c += kFinThreads) {
+        const int b = B.block_of(c), pE = b >> 1, pX = b & 1;
+        const int r = c - B.off(b), i = r / B.mX(pX), j = r - i * B.mX(pX);
+        const int k1 = nE - 1 - i, l1 = nx - 1 - j;
+        const double ce0 = fold_coef(nE, pE, i, i), ce1 = k1 != i ? fold_coef(nE, pE, i, k1) : 0.0;
+        const double cx0 = fold_coef(nx, pX, j, j), cx1 = l1 != j ? fold_coef(nx, pX, j, l1) : 0.0;
+        double v = ce0 * cx0 * w0[i * nx + j];
+        if (l1 != j) v += ce0 * cx1 * w0[i * nx + l1];
+        if (k1 != i) {
+            v += ce1 * cx0 * w0[k1 * nx + j];
+            if (l1 != j) v += ce1 * cx1 * w0[k1 * nx + l1];
         }
-        sa[o] = (k == 0 ? sE0 : sE) * v;
+        sa[c] = v;
     }
     __syncthreads();
-    // along x: sb[k][m] = s_m sum_j cos(pi m (2j+1)/2nx) sa[k][j]
-    for (int o = tid; o < n; o += kFinThreads) {
-        const int k = o / nx, m = o - k * nx;
+    // w^ = Q_b^T (folded data), one output per thread: Q_b[r][o] over r,
+    // consecutive o in consecutive lanes
+    for (int c = tid; c < n; c += kFinThreads) {
+        const int b = B.block_of(c), m = B.off(b + 1) - B.off(b);
+        const int o = c - B.off(b);
+        const G<const double> Q = basis + B.qoff(b);
+        const double* f = sa + B.off(b);
         double v = 0.0;
-        int idx = m % pX;
-        const int inc = (2 * m) % pX;
-        for (int j = 0; j < nx; ++j) {
-            v += tX[idx] * sa[k * nx + j];
-            idx += inc;
-            if (idx >= pX) idx -= pX;
-        }
-        sb[o] = (m == 0 ? sX0 : sX) * v;
+        for (int r = 0; r < m; ++r) v = fma(Q[(size_t)r * m + o], f[r], v);
+        sb[c] = v;
     }
     __syncthreads();
-    // Gamma^2 of every cell into sa: (2 - 2 cos(pi k/n)) / h^2 per axis
-    {
-        const double hE = fd.sm_hE, hx = 1.0 / nx;
-        for (int c = tid; c < n; c += kFinThreads) {
-            const int k = c / nx, m = c - k * nx;
-            const double g = (2.0 - 2.0 * tE[(2 * k) % pE]) / (hE * hE) +
-                             (2.0 - 2.0 * tX[(2 * m) % pX]) / (hx * hx);
-            sa[c] = g * g;
-        }
-    }
+    for (int c = tid; c < n; c += kFinThreads) sa[c] = basis[c];  // eigenvalues
     __syncthreads();
     // GCV at npts values of log10(lambda) (coarse p = a + 0.25 i, refined
     // p = a + (b - a) i / 64): wave w takes points w, w + 16, ..., up to
@@ -356,32 +387,38 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
     const double nb = a + (b - a) * (i2 < 64 ? i2 + 1 : 64) / 64.0;
     const int i3 = stage(false, na, nb, 65);
     const double lam = pow(10.0, na + (nb - na) * i3 / 64.0);
-    // filter into sa, inverse along E into sb, along x to the output
+    // filter into sa, then back: folded coefficients Q_b (filtered w^), one
+    // row per wave (lanes over its entries), into sb
     for (int c = tid; c < n; c += kFinThreads) sa[c] = sb[c] / (1.0 + lam * sa[c]);
     __syncthreads();
-    for (int o = tid; o < n; o += kFinThreads) {
-        const int i = o / nx, m = o - i * nx;
-        double v = sE0 * sa[m];  // k = 0
-        const int inc = (2 * i + 1) % pE;
-        int idx = inc;            // k (2i + 1) mod 4 nE
-        for (int k = 1; k < nE; ++k) {
-            v += sE * tE[idx] * sa[k * nx + m];
-            idx += inc;
-            if (idx >= pE) idx -= pE;
-        }
-        sb[o] = v;
+    for (int c = wave; c < n; c += kFinWaves) {
+        const int bb = B.block_of(c), m = B.off(bb + 1) - B.off(bb);
+        const int r = c - B.off(bb);
+        const G<const double> Q = basis + B.qoff(bb) + (size_t)r * m;
+        const double* f = sa + B.off(bb);
+        double v = 0.0;
+        for (int o = lane; o < m; o += 64) v = fma(Q[o], f[o], v);
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sb[c] = v;
     }
     __syncthreads();
+    // unfold: cell (k, l) from the vectors of both parities that touch it
     const double floor_v = 1e-3 * (*smean);
     for (int o = tid; o < n; o += kFinThreads) {
-        const int i = o / nx, l = o - i * nx;
-        double v = sX0 * sb[i * nx];  // m = 0
-        const int inc = (2 * l + 1) % pX;
-        int idx = inc;
-        for (int m = 1; m < nx; ++m) {
-            v += sX * tX[idx] * sb[i * nx + m];
-            idx += inc;
-            if (idx >= pX) idx -= pX;
+        const int k = o / nx, l = o - k * nx;
+        const int i = min(k, nE - 1 - k), j = min(l, nx - 1 - l);
+        double v = 0.0;
+        for (int pE = 0; pE < 2; ++pE) {
+            if (i >= B.mE(pE)) continue;
+            const double ce = fold_coef(nE, pE, i, k);
+            if (ce == 0.0) continue;
+            for (int pX = 0; pX < 2; ++pX) {
+                if (j >= B.mX(pX)) continue;
+                const double cx = fold_coef(nx, pX, j, l);
+                if (cx == 0.0) continue;
+                const int bb = 2 * pE + pX;
+                v += ce * cx * sb[B.off(bb) + i * B.mX(pX) + j];
+            }
         }
         v = fmax(v, floor_v);
         gp[o] = v;
@@ -421,16 +458,32 @@ __device__ __forceinline__ void build_scf_table(const FitDev& fd) {
     }
 }
 
+// LDS grids of the prior smoothing, only in the finalize variant that has it
+template <bool SMOOTH>
+struct SmoothLds {
+    double g[2][kSmoothMaxCells];
+};
+template <>
+struct SmoothLds<false> {};
+
 // SCF: the fit has the self-consistent potential (its potential jobs and the
-// node table are compiled in only then)
-template <typename T, bool SCF>
+// node table are compiled in only then); SMOOTH: some fit of the launch
+// smooths its prior grid.
+//
+// Every launched job of a fit takes one ticket, also the jobs with nothing
+// to do in this launch (cell columns on steps without a refresh, potential
+// columns on steps without a rebuild, observable columns in the modes that
+// reduce only cells or the potential). The job that takes the last ticket
+// ends the step and rewrites the fit's counters, so it can only do so once
+// every job has read them: a job that read the counters after the end of
+// the step would see the next step's schedule.
+template <typename T, bool SCF, bool SMOOTH>
 __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb, int32_t mode) {
     __shared__ double part[kFinWaves][kFinCols];
     __shared__ double part2[kFinWaves][kFinCols];
     __shared__ int last, sidx;
     __shared__ double smean;
-    __shared__ double sgrid[2][kMaxCells];  // prior smoothing: grids and cosine tables
-    __shared__ double stab[2][4 * kSmoothMaxSide];
+    __shared__ SmoothLds<SMOOTH> sl;
     FitState* st = fd.st;
     const G<FitState> gst = gmem(fd.st);
     const bool step = (mode & kModeStep) != 0;
@@ -456,36 +509,36 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
         }
     }
     const Snap ss = snap_of(gst);
-    if (step && ss.steps_left <= 0) return;  // uniform: the fit is idle
+    // an idle fit: every job of it reads steps_left <= 0 (no job of this
+    // launch ends its step), and none takes a ticket
+    if (step && ss.steps_left <= 0) return;
     const Flags f = flags_of<SCF>(fd, ss, mode);
-    if (bins && (cells_mode || pot_mode)) return;
-    if (jb.kind == 1 && !f.refresh) return;
-    if (pots && !f.pot) return;
-    // cell columns, read only on refresh steps; potential columns only on
-    // the steps that rebuild it
-    if (jb.kind == 1 && in) group_sum<8>(fd, false, col, jb.n_tiles, wave, acc, acc2);
-    if (pots && in) group_sum<16>(fd, true, fd.scf_col0 + col, jb.n_tiles, wave, acc, acc2);
-    part[wave][lane] = acc;
-    part2[wave][lane] = acc2;
-    __syncthreads();
-    if (wave == 0) {
-        double tot = 0.0, tot2 = 0.0;
-        for (int w = 0; w < kFinWaves; ++w) {
-            tot += part[w][lane];
-            tot2 += part2[w][lane];
-        }
-        if (pots) {
-            if (in) gmem(fd.scf_sum)[col] = tot;
-        } else {
-            (void)column_epilogue<T>(fd, bins, jb.col0, f, tot, tot2, yt0, sg, Yj, lane);
+    // this job's work in this launch
+    const bool work = bins ? !(cells_mode || pot_mode) : (jb.kind == 1 ? f.refresh : (pots && f.pot));
+    if (work) {
+        // cell columns, read only on refresh steps; potential columns only on
+        // the steps that rebuild it
+        if (jb.kind == 1 && in) group_sum<8>(fd, false, col, jb.n_tiles, wave, acc, acc2);
+        if (pots && in) group_sum<16>(fd, true, fd.scf_col0 + col, jb.n_tiles, wave, acc, acc2);
+        part[wave][lane] = acc;
+        part2[wave][lane] = acc2;
+        __syncthreads();
+        if (wave == 0) {
+            double tot = 0.0, tot2 = 0.0;
+            for (int w = 0; w < kFinWaves; ++w) {
+                tot += part[w][lane];
+                tot2 += part2[w][lane];
+            }
+            if (pots) {
+                if (in) gmem(fd.scf_sum)[col] = tot;
+            } else {
+                (void)column_epilogue<T>(fd, bins, jb.col0, f, tot, tot2, yt0, sg, Yj, lane);
+            }
         }
     }
     // the last job of this fit ends the step; in observe mode the same
     // hand-over runs on a separate counter and changes no state
-    const uint32_t n_part = pot_mode ? (uint32_t)fd.n_pot_jobs
-                                     : (cells_mode ? 0u : (uint32_t)fd.n_bin_jobs) +
-                                           (f.refresh ? (uint32_t)fd.n_cell_jobs : 0u) +
-                                           (f.pot ? (uint32_t)fd.n_pot_jobs : 0u);
+    const uint32_t n_part = (uint32_t)(fd.n_bin_jobs + fd.n_cell_jobs + fd.n_pot_jobs);
     uint32_t* ticket = observe ? &st->mticket : &st->ticket;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -498,15 +551,15 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     }
     __syncthreads();
     if (!last) return;
-    // a refresh with smoothing: the whole block smooths the prior grid
-    if (fd.smooth && f.refresh)
-    {
-        // each n_E x n_x grid alone: the first, then the L_z < 0 half if split
-        smooth_priors<T>(fd, 0, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0], &sidx, &smean);
-        if (fd.C > fd.cell_half) {
-            __syncthreads();
-            smooth_priors<T>(fd, fd.cell_half, sgrid[0], sgrid[1], stab[0], stab[1], &part[0][0],
-                             &sidx, &smean);
+    // a refresh with smoothing: the whole block smooths the prior grid, each
+    // n_E x n_x grid alone (the first, then the L_z < 0 half if split)
+    if constexpr (SMOOTH) {
+        if (fd.smooth && f.refresh) {
+            smooth_priors<T>(fd, 0, sl.g[0], sl.g[1], &part[0][0], &sidx, &smean);
+            if (fd.C > fd.cell_half) {
+                __syncthreads();
+                smooth_priors<T>(fd, fd.cell_half, sl.g[0], sl.g[1], &part[0][0], &sidx, &smean);
+            }
         }
     }
     // the node table of the self-consistent potential from the new sums
@@ -522,18 +575,18 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
 }
 
 // the jobs of the fits of a table (batches)
-template <typename T, bool SCF>
+template <typename T, bool SCF, bool SMOOTH>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
                                                          const FinJob* __restrict__ jobs,
                                                          int32_t mode) {
     const FinJob jb = jobs[blockIdx.x];
-    finalize_job<T, SCF>(fits[jb.fit], jb, mode);
+    finalize_job<T, SCF, SMOOTH>(fits[jb.fit], jb, mode);
 }
 
 // one fit, its description passed by value: block b < n_bin_jobs takes bin
 // columns, then n_cell_jobs blocks cell columns, then n_pot_jobs blocks the
 // columns of the self-consistent potential, over n_rows tile rows
-template <typename T, bool SCF>
+template <typename T, bool SCF, bool SMOOTH>
 __global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int32_t n_rows,
                                                           int32_t mode) {
     const int b = blockIdx.x;
@@ -541,7 +594,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize1(const FitDev fd, int3
     const int kind = b < nb ? 0 : (b < nb + nc ? 1 : 2);
     const int base = kind == 0 ? 0 : (kind == 1 ? nb : nb + nc);
     const FinJob jb{0, kind, (b - base) * kFinCols, n_rows};
-    finalize_job<T, SCF>(fd, jb, mode);
+    finalize_job<T, SCF, SMOOTH>(fd, jb, mode);
 }
 
 
@@ -669,44 +722,50 @@ hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& 
     return launch_step_any(f64, acc64, block, kin, nullptr, nullptr, &fd, n_tiles, lds, mode, s);
 }
 
-hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s, bool scf) {
-    if (n_jobs <= 0) return hipSuccess;
-    if (f64 && scf)
-        hipLaunchKernelGGL((k_finalize<double, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fits,
-                           jobs, mode);
-    else if (f64)
-        hipLaunchKernelGGL((k_finalize<double, false>), dim3(n_jobs), dim3(kFinThreads), 0, s,
-                           fits, jobs, mode);
-    else if (scf)
-        hipLaunchKernelGGL((k_finalize<float, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fits,
-                           jobs, mode);
-    else
-        hipLaunchKernelGGL((k_finalize<float, false>), dim3(n_jobs), dim3(kFinThreads), 0, s,
-                           fits, jobs, mode);
-    (void)n_fits;
+namespace {
+template <bool SCF, bool SMOOTH>
+hipError_t launch_fin_t(bool f64, const FitDev* fits, const FinJob* jobs, const FitDev* one,
+                        int n_blocks, int n_rows, int32_t mode, hipStream_t s) {
+    if (one) {
+        if (f64)
+            hipLaunchKernelGGL((k_finalize1<double, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
+                               s, *one, n_rows, mode);
+        else
+            hipLaunchKernelGGL((k_finalize1<float, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
+                               s, *one, n_rows, mode);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL((k_finalize<double, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
+                               s, fits, jobs, mode);
+        else
+            hipLaunchKernelGGL((k_finalize<float, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
+                               s, fits, jobs, mode);
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_fin_any(bool f64, bool scf, bool smooth, const FitDev* fits, const FinJob* jobs,
+                          const FitDev* one, int n_blocks, int n_rows, int32_t mode, hipStream_t s) {
+    if (n_blocks <= 0) return hipSuccess;
+    if (scf && smooth) return launch_fin_t<true, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
+    if (scf) return launch_fin_t<true, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
+    if (smooth) return launch_fin_t<false, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
+    return launch_fin_t<false, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
+}
+}  // namespace
+
+hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth) {
+    (void)n_fits;
+    return launch_fin_any(f64, scf, smooth, fits, jobs, nullptr, n_jobs, 0, mode, s);
 }
 
 bool kin_scf(int kin) { return (kin & kKinScf) != 0; }
 
 hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s) {
     const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs + fd.n_pot_jobs;
-    if (n_jobs <= 0) return hipSuccess;
-    const bool scf = fd.scf_nr > 0;
-    if (f64 && scf)
-        hipLaunchKernelGGL((k_finalize1<double, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
-                           n_rows, mode);
-    else if (f64)
-        hipLaunchKernelGGL((k_finalize1<double, false>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
-                           n_rows, mode);
-    else if (scf)
-        hipLaunchKernelGGL((k_finalize1<float, true>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
-                           n_rows, mode);
-    else
-        hipLaunchKernelGGL((k_finalize1<float, false>), dim3(n_jobs), dim3(kFinThreads), 0, s, fd,
-                           n_rows, mode);
-    return hipGetLastError();
+    return launch_fin_any(f64, fd.scf_nr > 0, fd.smooth != 0, nullptr, nullptr, &fd, n_jobs, n_rows,
+                          mode, s);
 }
 
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,
