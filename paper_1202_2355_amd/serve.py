@@ -41,12 +41,27 @@ class Request:
     t_done: float = float("nan")
     it_admit: int = -1      # server loop iteration of admission / completion
     it_done: int = -1
+    rejected: str = ""      # why the request was refused (empty: served)
     weights: np.ndarray | None = field(default=None, repr=False)
 
 
 def footprint_bytes(req: Request, dtype: str) -> int:
+    """HBM a request holds while it runs: its particle state and the library
+    workspace (0 workspace bytes mark a request the library would refuse)."""
     sz = 8 if dtype == "f64" else 4
     return req.n * 8 * sz + A.m2m_workspace_bytes(req.layout, req.params, req.n, dtype)
+
+
+def refusal(req: Request, dtype: str, budget: int) -> str:
+    """Why a request can never be served under ``budget`` (empty if it can):
+    a layout or parameters the library refuses, or a footprint larger than
+    the whole budget, which no amount of waiting would free."""
+    if A.m2m_workspace_bytes(req.layout, req.params, req.n, dtype) == 0:
+        return "invalid layout, parameters or particle count"
+    need = footprint_bytes(req, dtype)
+    if need > budget:
+        return f"footprint {need} bytes exceeds the HBM budget of {budget} bytes"
+    return ""
 
 
 class Server:
@@ -107,6 +122,7 @@ class Server:
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         waiting = deque()
         done = []
+        rejected = []
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         sim_now = 0.0
@@ -115,7 +131,17 @@ class Server:
             it += 1
             now = clock() if realtime else sim_now
             while pending and pending[0].arrival <= now:
-                waiting.append(pending.popleft())
+                req = pending.popleft()
+                # a request that can never fit is refused at once, so that it
+                # neither blocks the queue behind it nor keeps the loop alive
+                why = refusal(req, self.dtype, self.budget)
+                if why:
+                    req.rejected = why
+                    rejected.append(req)
+                    if log:
+                        print(f"[serve] refused request {req.rid}: {why}", file=log, flush=True)
+                else:
+                    waiting.append(req)
             self._admit(now, it)
             if self.batch.active:
                 self.batch.run(self.spl)
@@ -159,6 +185,7 @@ class Server:
             "particle_steps_per_s": work / max(last - first, 1e-9),
             "makespan_s": makespan,
             "done": done,
+            "rejected": rejected,
         }
 
     def close(self):

@@ -181,15 +181,18 @@ def test_largest_prior_grid_refreshes_like_the_oracle(oracle, Fit, dtype):
     f = Fit(wl.potential, wl.layout, P, parts, dtype=dtype, u=u)
     f.update_priors()
     uh = f.particles()["uh"]
-    from m2m_testlib import clean_of_cell_edges
-    cell, E, xc = oracle.cells(wl.potential, P, parts)
-    band = 1e-5 if dtype == "f32" else 1e-12
-    C = P["n_E"] * P["n_x"]
-    sums = np.bincount(cell, weights=u, minlength=C)
-    cnts = np.bincount(cell, minlength=C)
-    uh_o = sums[cell] / cnts[cell]
-    ok = clean_of_cell_edges(P, cell, E, xc, band * abs(P["E_lo"]), band)
-    _say("largest prior grid", dtype, "occupied cells", np.count_nonzero(cnts), "clean", ok.mean())
-    assert np.count_nonzero(cnts) > 1000 and ok.mean() > 0.6
-    np.testing.assert_allclose(uh[ok], uh_o[ok], rtol=1e-6 if dtype == "f32" else 1e-13)
     f.close()
+    from m2m_testlib import assert_priors_within, prior_bounds
+    band = 1e-5 if dtype == "f32" else 1e-12
+    J = oracle.J_of(wl.layout)
+    o = oracle.OracleFit(wl.potential, wl.layout, P, parts, np.ones(J), np.ones(J), u=u,
+                         track_flags=True, band=band, nthreads=8)
+    o.refresh_priors()
+    lo, hi = prior_bounds(oracle, wl.potential, P, parts, u, o.flag, band)
+    cnts = np.bincount(oracle.cells(wl.potential, P, parts)[0], minlength=P["n_E"] * P["n_x"])
+    _say("largest prior grid", dtype, "occupied cells", np.count_nonzero(cnts), "flagged",
+         float((o.flag != 0).mean()))
+    assert np.count_nonzero(cnts) > 1000
+    unbounded = assert_priors_within(uh, lo, hi, 1e-6 if dtype == "f32" else 1e-13, "64 x 64 grid")
+    _say("largest prior grid", dtype, "unbounded", unbounded)
+    assert unbounded < 1e-3

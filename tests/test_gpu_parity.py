@@ -16,8 +16,8 @@ import sys
 import numpy as np
 import pytest
 
-from m2m_testlib import (BAND_F32, BAND_F64, assert_observables, cast, oracle_targets,
-                         random_weights, weight_errors)
+from m2m_testlib import (BAND_F32, BAND_F64, assert_observables, assert_priors_within, cast,
+                         oracle_targets, prior_bounds, random_weights, weight_errors)
 from workloads import workload
 
 pytestmark = pytest.mark.gpu
@@ -159,20 +159,17 @@ def test_prior_refresh_matches_oracle(oracle, Fit, dtype):
     f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype, u=u)
     f.update_priors()
     uh = f.particles()["uh"]
-    from m2m_testlib import clean_of_cell_edges
-    cell, E, xc = oracle.cells(wl.potential, wl.params, parts)
-    P = wl.params
-    band = 1e-5 if dtype == "f32" else 1e-12
-    C = P["n_E"] * P["n_x"]
-    sums = np.bincount(cell, weights=u, minlength=C)
-    cnts = np.bincount(cell, minlength=C)
-    uh_o = sums[cell] / cnts[cell]
-    ok = clean_of_cell_edges(P, cell, E, xc, band * abs(P["E_lo"]), band)
-    _say("priors", dtype, "clean fraction", ok.mean())
-    # cells near an edge crossing are excluded whole; most are clean
-    assert ok.mean() > 0.7
-    np.testing.assert_allclose(uh[ok], uh_o[ok], rtol=1e-6 if dtype == "f32" else 1e-13)
     f.close()
+    from m2m_testlib import assert_priors_within, prior_bounds
+    band = 1e-5 if dtype == "f32" else 1e-12
+    o = _oracle_priors(oracle, wl, wl.params, parts, u, band)
+    # every particle: its prior within the bounds that the particles near a
+    # cell edge (either side) leave on its cell's mean
+    lo, hi = prior_bounds(oracle, wl.potential, wl.params, parts, u, o.flag, band)
+    np.testing.assert_allclose(o.arr["uhat"], np.clip(o.arr["uhat"], lo, hi), rtol=1e-13)
+    unbounded = assert_priors_within(uh, lo, hi, 1e-6 if dtype == "f32" else 1e-13, "priors")
+    _say("priors", dtype, "flagged", float((o.flag != 0).mean()), "unbounded", unbounded)
+    assert unbounded < 1e-3
 
 
 def test_batch_equals_alone(oracle, Fit):
@@ -490,30 +487,6 @@ def test_alm_run_fp32_matches_oracle(oracle, Fit):
 
 
 # ------------------------------------------------ prior-grid options (Sec. 5)
-def _dirty_cells(oracle, pot, par, parts, cell, flagged, band):
-    """Cells a flagged particle may fall into: the oracle's cells of the
-    particle with its speed, its radius and its azimuthal velocity moved by
-    four bands either way (so across any nearby E, x or L_z = 0 edge)."""
-    C = oracle.n_cells(par)
-    dirty = np.zeros(C, bool)
-    dirty[cell[flagged]] = True
-    q = {k: v[flagged] for k, v in parts.items()}
-    d = 4.0 * band
-    vt = np.sqrt(q["vx"] ** 2 + q["vy"] ** 2 + q["vz"] ** 2)
-    R = np.maximum(np.hypot(q["x"], q["y"]), 1e-300)
-    ex, ey = -q["y"] / R, q["x"] / R   # azimuthal unit vector
-    variants = []
-    for s in (1.0 + d, 1.0 - d):
-        variants.append(dict(q, vx=q["vx"] * s, vy=q["vy"] * s, vz=q["vz"] * s))
-        variants.append(dict(q, x=q["x"] * s, y=q["y"] * s, z=q["z"] * s))
-    for s in (d, -d):
-        variants.append(dict(q, vx=q["vx"] + s * vt * ex, vy=q["vy"] + s * vt * ey))
-    for v in variants:
-        c, _, _ = oracle.cells(pot, par, v)
-        dirty[c] = True
-    return dirty
-
-
 def _oracle_priors(oracle, wl, par, parts, u, band):
     J = oracle.J_of(wl.layout)
     o = oracle.OracleFit(wl.potential, wl.layout, par, parts, np.ones(J), np.ones(J), u=u,
@@ -538,15 +511,15 @@ def test_prior_refresh_with_cell_options_matches_oracle(oracle, Fit, dtype, cell
     f.update_priors()
     uh = f.particles()["uh"]
     f.close()
-    o = _oracle_priors(oracle, wl, par, parts, u, 1e-5 if dtype == "f32" else 1e-12)
-    cell, _, _ = oracle.cells(wl.potential, par, parts)
     band = 1e-5 if dtype == "f32" else 1e-12
-    ok = ~_dirty_cells(oracle, wl.potential, par, parts, cell, o.flag != 0, band)[cell]
-    _say("cell options", cells, dtype, "clean fraction", ok.mean())
-    # exp(E) bins are wide at low E, so their cells are populous and one
-    # flagged member excludes many particles
-    assert ok.mean() > 0.5
-    np.testing.assert_allclose(uh[ok], o.arr["uhat"][ok], rtol=1e-6 if dtype == "f32" else 1e-13)
+    o = _oracle_priors(oracle, wl, par, parts, u, band)
+    cell, _, _ = oracle.cells(wl.potential, par, parts)
+    lo, hi = prior_bounds(oracle, wl.potential, par, parts, u, o.flag, band)
+    unbounded = assert_priors_within(uh, lo, hi, 1e-6 if dtype == "f32" else 1e-13,
+                                     f"cell options {cells}")
+    _say("cell options", cells, dtype, "flagged", float((o.flag != 0).mean()), "unbounded",
+         unbounded)
+    assert unbounded < 1e-3
     if cells & 1:
         half = par["n_E"] * par["n_x"]
         assert (cell >= half).any() and (cell < half).any()
@@ -653,7 +626,7 @@ def test_halo_prior_refresh_matches_oracle(oracle, Fit, dtype):
     o = _oracle_priors(oracle, wl, par, parts, u, band)
     cell, E, xc = oracle.cells(wl.potential, par, parts)
     assert (E > 0).any()   # bound energies above 0 exist in the halo
-    ok = ~_dirty_cells(oracle, wl.potential, par, parts, cell, o.flag != 0, band)[cell]
-    _say("halo priors", dtype, "clean fraction", ok.mean())
-    assert ok.mean() > 0.5
-    np.testing.assert_allclose(uh[ok], o.arr["uhat"][ok], rtol=1e-6 if dtype == "f32" else 1e-13)
+    lo, hi = prior_bounds(oracle, wl.potential, par, parts, u, o.flag, band)
+    unbounded = assert_priors_within(uh, lo, hi, 1e-6 if dtype == "f32" else 1e-13, "halo priors")
+    _say("halo priors", dtype, "flagged", float((o.flag != 0).mean()), "unbounded", unbounded)
+    assert unbounded < 1e-3
