@@ -42,3 +42,16 @@ def test_cpu_baseline_reports_all_cores_and_one_thread():
     assert r["kind"] == "oracle" and r["unit"] == "particle-steps/s"
     assert r["cores"] >= 1 and r["value"] > 0 and r["value_1_thread"] > 0
     assert "one thread" in r["sample_1_thread"]
+
+
+def test_cpu_baseline_of_the_batch_runs_its_own_fits():
+    from workloads.configs import batch_fits
+    r = bench.cpu_baseline_batch(batch_fits(n_fits=3), 0.5, n_cap=4096)
+    assert r["kind"] == "oracle" and r["unit"] == "particle-steps/s"
+    assert r["cores"] >= 1 and r["value"] > 0
+    assert "fits of the batch" in r["sample"]
+
+
+def test_default_workload_is_the_batch():
+    args = bench.parser().parse_args([])
+    assert args.workload == 4 and args.fits == 64 and args.gpus == 1

@@ -1,6 +1,7 @@
-"""The benchmark on an MI355X: a short default run (10^6 particles,
-Gauss-Hermite kinematics, 20 timed steps) in a child process prints one JSON
-line whose fields follow the benchmark's output contract."""
+"""The benchmark on an MI355X: short runs in a child process print one JSON
+line whose fields follow the benchmark's output contract, for the batched
+workload (the default, here with 8 of its 64 fits) and for one fit of the
+Gauss-Hermite workload."""
 
 import json
 import os
@@ -13,33 +14,61 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
+KEYS = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+        "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config", "roofline",
+        "cpu_baseline")
 
-def test_bench_prints_one_json_line_with_roofline():
+
+def _run(args, timeout):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    print("[gpu-test] bench.py --steps 20 --warmup 2", file=sys.stderr, flush=True)
-    r = subprocess.run([sys.executable, "-u", "bench.py", "--steps", "20", "--warmup", "2",
-                        "--no-cpu-baseline"], cwd=ROOT, capture_output=True, text=True, timeout=110)
+    print("[gpu-test] bench.py", *args, file=sys.stderr, flush=True)
+    r = subprocess.run([sys.executable, "-u", "bench.py", *args], cwd=ROOT, capture_output=True,
+                       text=True, timeout=timeout)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
     assert len(lines) == 1, r.stdout[-2000:]
     d = json.loads(lines[0])
-    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
-              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config", "roofline",
-              "cpu_baseline"):
+    for k in KEYS:
         assert k in d, k
-    assert d["n_gpus"] == 1 and d["steps"] == 20 and d["warmup"] == 2
     assert d["unit"] == "particle-steps/s" and d["dtype"] == "f32" and d["data"] == "synthetic"
-    assert d["config"]["workload"] == "hernquist_gh_n1m" and d["config"]["particles"] == 1_000_000
-    # whole-step throughput: N particles per step over the measured time per step
-    assert d["value"] == pytest.approx(1_000_000 / (d["ms_per_step"] * 1e-3), rel=1e-9)
+    assert "latency" not in d   # only the serving workload measures a latency distribution
+    return d
+
+
+def _check_roofline(d, n):
     roof = d["roofline"]
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert 0.0 < roof["frac"] <= 1.0
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-9)
     # achieved: 60 B per particle-step over the step kernel's own duration,
-    # which is shorter than the whole step
-    assert roof["achieved"] == pytest.approx(60 * 1_000_000 / (roof["kernel_ms"] * 1e-3) / 1e9,
-                                             rel=1e-9)
+    # which is shorter than the whole step; the whole step's figure beside it
+    assert roof["achieved"] == pytest.approx(60 * n / (roof["kernel_ms"] * 1e-3) / 1e9, rel=1e-9)
     assert 0.0 < roof["kernel_ms"] < d["ms_per_step"]
+    assert roof["whole_step_achieved"] == pytest.approx(60 * n / (d["ms_per_step"] * 1e-3) / 1e9,
+                                                        rel=1e-9)
+    assert roof["whole_step_frac"] < roof["frac"]
+
+
+def test_bench_batch_line():
+    d = _run(["--workload", "4", "--fits", "8", "--steps", "16", "--warmup", "2",
+              "--no-cpu-baseline"], 170)
+    assert d["n_gpus"] == 1 and d["steps"] == 16 and d["warmup"] == 2
+    c = d["config"]
+    assert c["workload"] == "batch8_gh" and c["fits"] == 8
+    n = c["particles"]
+    # whole-step throughput: all particles of the batch per step over the
+    # measured time per step
+    assert d["value"] == pytest.approx(n / (d["ms_per_step"] * 1e-3), rel=1e-9)
+    _check_roofline(d, n)
+    comp = d["comparator"]
+    assert comp["value"] == pytest.approx(n / (comp["ms_per_step"] * 1e-3), rel=1e-9)
+
+
+def test_bench_single_fit_line():
+    d = _run(["--workload", "2", "--steps", "20", "--warmup", "2", "--no-cpu-baseline"], 110)
+    assert d["n_gpus"] == 1 and d["steps"] == 20 and d["warmup"] == 2
+    assert d["config"]["workload"] == "hernquist_gh_n1m" and d["config"]["particles"] == 1_000_000
+    assert d["value"] == pytest.approx(1_000_000 / (d["ms_per_step"] * 1e-3), rel=1e-9)
+    _check_roofline(d, 1_000_000)
