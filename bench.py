@@ -33,10 +33,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# launch shape (threads per block, tiles per CU) of the fused step kernel per
-# workload, as chosen by paper_1202_2355_amd.autotune
-LAUNCH = {1: (256, 4), 2: (1024, 1), 3: (1024, 1), 4: (512, 12), 5: (512, 6)}
-
 SERVE_N_MIN = 100_000   # smallest fit of the serving trace (errors floored at its noise)
 METRIC = "particle-steps/sec (push+deposit+weight update) at 1 GPU; p50/p99 fit latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
@@ -123,6 +119,29 @@ def cpu_baseline(wl, seconds: float):
                                f"one thread"}
 
 
+PREWARM_MS = 300.0  # device copies before the warm-up steps
+
+
+def prewarm_device(torch, ms: float = PREWARM_MS) -> str:
+    """Keep the GPU streaming memory (256 MiB device copies) for about `ms`
+    milliseconds. Input generation leaves it nearly idle for seconds, and
+    its clocks then take tens of milliseconds of load to come back: the
+    first ~20 steps after an idle second run ~10 % slower than the steps of
+    any fit of hundreds of steps. The copies touch no fit; the W warm-up
+    steps and the K timed steps follow as usual."""
+    src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t0 = time.perf_counter()
+    n = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(20):
+            dst.copy_(src)
+        n += 20
+        torch.cuda.synchronize()
+    del src, dst
+    return f"{n} device copies of 256 MiB ({ms:.0f} ms) before the warm-up steps"
+
+
 def cpu_baseline_batch(fits_wl, seconds: float, n_cap: int = 1 << 18):
     """The FP64 oracle on this host's cores over the first fits of the batch
     (each fit's own potential and targets, at most n_cap of its particles),
@@ -171,12 +190,14 @@ def run_batch(args, Fit, torch, _abi):
     from workloads.configs import batch_fits
     from workloads.device import om_model_device
     fits_wl = batch_fits(args.fits)
+    from paper_1202_2355_amd import tuning
     fits = []
     t0 = time.perf_counter()
-    # contexts take the single-fit launch shape at creation (the comparator
-    # steps them one launch per fit); the batch takes its own at admission
-    _abi.m2m_set_launch(*LAUNCH[2])
+    # each context takes the tuned parameters of a single fit of its size at
+    # creation (the comparator steps them one launch per fit); the batch
+    # takes the batch class's at its rebuild
     for wl in fits_wl:
+        tuning.use("single", "f32", wl.layout, wl.N)
         ic = om_model_device(wl.N, wl.potential, float("inf"), seed=wl.seed * 10 + 1)
         tp = om_model_device(wl.n_target, wl.potential, wl.target_ra, seed=wl.seed * 10 + 2)
         tf = Fit(wl.potential, wl.layout, wl.params, tp, dtype="f32")
@@ -189,10 +210,14 @@ def run_batch(args, Fit, torch, _abi):
     ntot = sum(f.n for f in fits)
     print(f"[bench] batch of {len(fits)} fits, {ntot} particles, inputs in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    _abi.m2m_set_launch(*LAUNCH[4])
+    tuned = tuning.use("batch", "f32", fits_wl[0].layout)
+    if args.groups is not None:
+        _abi.m2m_set_batch_groups(args.groups)
+        tuned["groups"] = args.groups
     b = Batch(max_fits=len(fits))
     for f in fits:
         assert b.admit(f, args.warmup + args.steps + 40)
+    prewarm = prewarm_device(torch)
     b.run(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -202,7 +227,7 @@ def run_batch(args, Fit, torch, _abi):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     assert b.particles() == ntot
-    ms_step, ms_fin = b.profile(16)
+    ms_step, ms_fin = b.profile(32)
     for f in list(fits):
         b.cancel(f)
     # comparator: the same fits, each stepped by its own launches
@@ -220,7 +245,8 @@ def run_batch(args, Fit, torch, _abi):
     cpu = None if args.no_cpu_baseline else cpu_baseline_batch(fits_wl, args.cpu_seconds)
     return {"name": f"batch{len(fits)}_gh", "N": ntot, "J": fits_wl[0].J, "ms": ms,
             "ms_step": ms_step, "ms_fin": ms_fin, "dtype": "f32", "layout": fits_wl[0].layout,
-            "params": fits_wl[0].params, "fits": len(fits), "cpu": cpu,
+            "params": fits_wl[0].params, "fits": len(fits), "cpu": cpu, "tuned": tuned,
+            "prewarm": prewarm,
             "comparator": {"kind": "the same fits, one step kernel and one finalize launch per fit",
                            "value": ntot / (ms_alone * 1e-3), "unit": "particle-steps/s",
                            "ms_per_step": ms_alone, "steps": k_alone}}
@@ -256,6 +282,8 @@ def run_serve(args, torch, rate=SERVE_RATE):
                     seed=w.seed) for k, w in enumerate(wls)]
     tdt = torch.float32 if args.state == "f32" else torch.float64
     model = lambda r: plummer_jeans_device(r.n, r.potential, r.seed, dtype=tdt)
+    from paper_1202_2355_amd import tuning
+    tuning.use("batch", args.state, base.layout)
     srv = Server(datasets, hbm_budget=int(args.hbm_gb * 2 ** 30), max_fits=64,
                  steps_per_launch=args.steps_per_launch, dtype=args.state, initial_model=model)
     # warm-up request (first graph capture, first allocations), not counted
@@ -273,6 +301,9 @@ def parser() -> argparse.ArgumentParser:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", type=int, default=4, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--fits", type=int, default=64, help="workload 4: number of fits")
+    ap.add_argument("--groups", type=int, default=None, choices=[1, 2],
+                    help="workload 4: step the batch as 1 or 2 overlapping groups "
+                         "(default: the library's choice)")
     ap.add_argument("--requests", type=int, default=500, help="workload 5: trace length")
     ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
@@ -305,11 +336,10 @@ def main(argv=None):
         return 2
 
     import torch
-    from paper_1202_2355_amd import _abi
+    from paper_1202_2355_amd import _abi, tuning
     from paper_1202_2355_amd.fit import Fit
     from workloads import workload
 
-    _abi.m2m_set_launch(*LAUNCH[args.workload])
     if args.workload == 5:
         m = run_serve(args, torch)
         sweep = []
@@ -327,7 +357,7 @@ def main(argv=None):
                "config": {"workload": "serve_losvd", "requests": m["requests"],
                           "arrival_rate_per_s": SERVE_RATE, "hbm_budget_gb": args.hbm_gb,
                           "steps_per_launch": args.steps_per_launch,
-                          "launch": list(LAUNCH[5])},
+                          "launch": tuning.current()},
                "latency": {"p50_s": m["p50_latency_s"], "p99_s": m["p99_latency_s"],
                            "mean_s": m["mean_latency_s"]},
                **({"sweep": sweep} if sweep else {}),
@@ -350,7 +380,7 @@ def main(argv=None):
                           "observables": r["J"], "kinematics": r["layout"]["kin"],
                           "prior_grid": [r["params"]["n_E"], r["params"]["n_x"]],
                           "prior_every": r["params"]["prior_every"], "state": "f32",
-                          "launch": list(LAUNCH[4])},
+                          "launch": r["tuned"], "device_warmup": r["prewarm"]},
                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                             "traffic": (tb * r["N"] if tb is not None else None),
@@ -373,9 +403,11 @@ def main(argv=None):
         wl = with_scf(wl, l_max=args.scf, n_nodes=32, r_min=0.02, r_max=100.0,
                       every=args.scf_every)
     dtype = wl.state
-    print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={LAUNCH[args.workload]}",
+    tuned = tuning.use("single", dtype, wl.layout, wl.N)
+    print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={tuned}",
           file=sys.stderr, flush=True)
     fit = make_fit_and_targets(wl, Fit, dtype)
+    prewarm = prewarm_device(torch)
     fit.step(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -426,7 +458,7 @@ def main(argv=None):
                        f"multipole l<={wl.params['scf_lmax']}, {wl.params['scf_nr']} nodes, "
                        f"rebuilt every {wl.params['scf_every']} steps"
                        if wl.params.get("scf_nr", 0) else "analytic"),
-                   "launch": list(LAUNCH[args.workload])},
+                   "launch": tuned, "device_warmup": prewarm},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

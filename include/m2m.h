@@ -345,6 +345,29 @@ const char* m2m_last_error(const m2m_ctx* ctx);
 m2m_status m2m_set_launch(int32_t block, int32_t tiles_per_cu);
 m2m_status m2m_get_launch(int32_t* block, int32_t* tiles_per_cu);
 
+/* Most private copies of the in-tile observable bins per block of the step
+ * kernel, for contexts created afterwards: 1, 2, 4 or 8, or 0 (default) for
+ * as many as fit 48 KiB of LDS, at most 8. Lanes add into copy
+ * (thread index mod copies), which spreads the LDS atomics of a hot bin.
+ * EINVAL otherwise. Chosen by the autotuner. */
+m2m_status m2m_set_private_copies(int32_t copies);
+int32_t m2m_get_private_copies(void);
+
+/* Groups a batch of two or more fits is split into at its next rebuild
+ * (see "batching"): 2 (default, the groups overlap on two streams) or 1 (one
+ * step kernel over all fits). EINVAL otherwise. Chosen by the autotuner. */
+m2m_status m2m_set_batch_groups(int32_t groups);
+int32_t m2m_get_batch_groups(void);
+
+/* How batches rebuilt afterwards enqueue their steps: 1 replays graphs of 8
+ * captured steps (and launches the rest directly), 0 (default) launches
+ * every step's two kernels directly. A newly captured graph is slow on its
+ * first launches, and a batch captures anew at every change of composition;
+ * at the step times of batches, direct launches cost nothing measurable.
+ * EINVAL otherwise. Chosen by the autotuner. */
+m2m_status m2m_set_batch_graphs(int32_t on);
+int32_t m2m_get_batch_graphs(void);
+
 /* In-tile accumulation of the deposits (eq. obs) for FP32 particle state,
  * for contexts and batches created afterwards: M2M_DEPOSIT_F64 (default)
  * adds each w_i K_j(z_i), formed in FP32, into FP64 bins in LDS;
@@ -357,11 +380,16 @@ m2m_status m2m_set_deposit_mode(int32_t mode);
 int32_t m2m_get_deposit_mode(void);
 
 /* ---------------------------------------------------------- batching --
- * Many fits of uneven size stepping together: every step runs one fused
- * kernel over the tiles of all active fits (tiles never straddle fits) and
- * one finalize kernel, replayed from a captured HIP graph. Each fit's
- * result equals the fit run alone up to the rounding of its in-tile sums.
- * Fits keep their own streams for set-up; the batch runs on its own stream. */
+ * Many fits of uneven size stepping together. A batch of two or more fits is
+ * split into two groups of about equal particle count; every step of a group
+ * runs one fused kernel over the tiles of its fits (tiles never straddle
+ * fits) and one finalize kernel, replayed from a captured HIP graph on a
+ * stream of the group's own, so that one group's finalize overlaps the other
+ * group's streaming. The groups start after the work already enqueued on the
+ * batch stream, and the batch stream continues only after both (events), so
+ * to the caller the steps are ordered on the batch stream. Each fit's result
+ * equals the fit run alone up to the rounding of its in-tile sums. Fits keep
+ * their own streams for set-up. */
 
 /* hbm_budget: bytes of particle state plus workspace the batch may hold
  * (0 = no limit). max_fits >= 1. */
@@ -378,9 +406,13 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
  * *n_active (may be NULL) the number still running. */
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
                           int32_t* n_active);
-/* Like m2m_profile_step for the batch, with graphs of 8 batched steps:
- * 16 ceil(n_steps / 8) steps in all, which count against the fits' steps
- * (n_steps 1..4096). Synchronizes. */
+/* Timing of the batch's kernels by HIP events on the batch stream: n_steps
+ * (1..256) batched steps launched one kernel at a time (no graph), each step
+ * kernel between two events. ms_step is the mean time between those two
+ * events (the step kernel, plus the events' own small cost: an upper bound),
+ * ms_finalize the mean rest of a step (the finalize and the gaps around it).
+ * The steps count against the fits' steps. Synchronizes. Used to report the
+ * step kernel's achieved bandwidth against the roofline. */
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize);
 /* Particles of the admitted fits that still have steps left. Synchronizes. */
 int64_t m2m_batch_particles(m2m_batch* b);

@@ -88,6 +88,12 @@ SIGNATURES = {
     "m2m_set_launch": (_st, [_i32, _i32]),
     "m2m_get_launch": (_st, [C.POINTER(_i32)] * 2),
     "m2m_set_deposit_mode": (_st, [_i32]),
+    "m2m_set_batch_groups": (_st, [_i32]),
+    "m2m_set_private_copies": (_st, [_i32]),
+    "m2m_set_batch_graphs": (_st, [_i32]),
+    "m2m_get_batch_graphs": (_i32, []),
+    "m2m_get_private_copies": (_i32, []),
+    "m2m_get_batch_groups": (_i32, []),
     "m2m_get_deposit_mode": (_i32, []),
     "m2m_batch_create": (_st, [_i32, C.c_size_t, _vp, C.POINTER(_vp)]),
     "m2m_batch_admit": (_st, [_vp, _vp, _i32]),
@@ -180,6 +186,36 @@ DEPOSIT = {"f64": M2M_DEPOSIT_F64, "f32c": M2M_DEPOSIT_F32_COMPENSATED}
 def m2m_set_deposit_mode(mode):
     mode = DEPOSIT[mode] if isinstance(mode, str) else int(mode)
     check(lib().m2m_set_deposit_mode(mode), "m2m_set_deposit_mode")
+
+
+def m2m_set_batch_graphs(on: int):
+    """Batches rebuilt from now on replay captured graphs (1) or launch every
+    step directly (0)."""
+    check(lib().m2m_set_batch_graphs(int(on)), "m2m_set_batch_graphs")
+
+
+def m2m_get_batch_graphs() -> int:
+    return int(lib().m2m_get_batch_graphs())
+
+
+def m2m_set_private_copies(copies: int):
+    """Most private copies of the in-tile bins (1, 2, 4, 8; 0: automatic) for
+    contexts created from now on."""
+    check(lib().m2m_set_private_copies(int(copies)), "m2m_set_private_copies")
+
+
+def m2m_get_private_copies() -> int:
+    return int(lib().m2m_get_private_copies())
+
+
+def m2m_set_batch_groups(groups: int):
+    """Groups a batch of two or more fits steps as (1 or 2, overlapping on
+    their own streams) from its next rebuild on."""
+    check(lib().m2m_set_batch_groups(int(groups)), "m2m_set_batch_groups")
+
+
+def m2m_get_batch_groups() -> int:
+    return int(lib().m2m_get_batch_groups())
 
 
 def m2m_get_deposit_mode() -> int:

@@ -1,11 +1,17 @@
-"""Launch-shape search for the fused step kernel.
+"""Search of the step kernel's launch parameters on the GPU, per workload
+class (``tuning.class_key``), and storage of the picks in the package's
+table (``tuning.TUNED_FILE``) that benchmarks, servers and tests apply.
 
-The shape is (threads per block, tiles per compute unit): the tile count
-sets how many blocks stream the particles (and how many partial rows the
-finalize reduces), the block size sets the waves per CU that share one set
-of LDS bins. The
-search times whole M2M steps (step + finalize kernels, graph replays) on
-fresh copies of the same particles and keeps the fastest shape.
+One fit: every launch shape (threads per block, tiles per compute unit),
+then at the best shape every in-tile deposit mode (FP32 state) and bound on
+the private bin copies. A batch: every launch shape with the batch stepped
+as one group and as two overlapping groups, then at the best of them graph
+replays against direct launches and the bound on the private bin copies. Each candidate is timed over
+whole M2M steps (step and finalize kernels, graph replays, HIP events on the
+fit's or batch's stream) on fresh contexts over the same particles.
+
+    python -m paper_1202_2355_amd.autotune --workload 2 [--write]
+    python -m paper_1202_2355_amd.autotune --workload 4 [--write]
 """
 
 from __future__ import annotations
@@ -18,55 +24,83 @@ import time
 import torch
 
 from . import _abi as A
+from . import tuning
 from .fit import Fit
 
 BLOCKS = (256, 512, 1024)
 TILES_PER_CU = (1, 2, 4, 8)
+BATCH_TILES_PER_CU = (4, 6, 8, 12, 16)
+PRIVATE = (0, 1, 2, 4)
+DEPOSITS = ("f64", "f32c")
 
 
-def time_shape(make_fit, shape, steps=40, warmup=16):
-    A.m2m_set_launch(*shape)
-    fit = make_fit()
+def _fmt(p: dict) -> str:
+    return " ".join(f"{k}={v}" for k, v in sorted(p.items()))
+
+
+def time_fit(make_fit, params, steps=64, warmup=32):
+    """ms per whole step of a fresh fit made under ``params``."""
+    before = tuning.current()
+    tuning.apply(params)
+    try:
+        fit = make_fit()
+    finally:
+        tuning.apply(before)
     fit.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(fit.stream)
     fit.step(steps)
-    e1.record()
+    e1.record(fit.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     fit.close()
     return ms
 
 
-def search(make_fit, blocks=BLOCKS, tiles=TILES_PER_CU, steps=40, log=sys.stderr, dtype="f32"):
-    """Time every shape; returns (best shape, {shape: ms per step})."""
-    before = A.m2m_get_launch()
+def search(make_fit, dtype="f32", steps=64, log=sys.stderr, base=None):
+    """The best parameters of one fit; returns (params, {description: ms})."""
+    base = dict(tuning.DEFAULT_F64 if dtype == "f64" else tuning.DEFAULT, **(base or {}))
     res = {}
-    try:
-        for b, t in itertools.product(blocks, tiles):
-            if dtype == "f64" and b != 256:
-                continue
-            ms = time_shape(make_fit, (b, t), steps=steps)
-            res[(b, t)] = ms
-            if log:
-                print(f"[autotune] block={b} tiles/cu={t}: {1e3 * ms:.2f} us/step",
-                      file=log, flush=True)
-    finally:
-        A.m2m_set_launch(*before)
-    best = min(res, key=res.get)
+
+    def trial(p):
+        ms = time_fit(make_fit, p, steps=steps)
+        res[_fmt(p)] = ms
+        if log:
+            print(f"[autotune] {_fmt(p)}: {1e3 * ms:.2f} us/step", file=log, flush=True)
+        return ms
+
+    best, best_ms = None, float("inf")
+    for b, t in itertools.product(BLOCKS, TILES_PER_CU):
+        if dtype == "f64" and b != 256:
+            continue
+        p = dict(base, block=b, tiles_per_cu=t)
+        ms = trial(p)
+        if ms < best_ms:
+            best, best_ms = p, ms
+    for dep, k in itertools.product(DEPOSITS if dtype == "f32" else ("f64",), PRIVATE):
+        p = dict(best, deposit=dep, private_copies=k)
+        if _fmt(p) in res:
+            continue
+        ms = trial(p)
+        if ms < best_ms:
+            best, best_ms = p, ms
     return best, res
 
 
-def time_batch_shape(fits, shape, steps=40, warmup=16):
-    """Mean ms per batched step of ``fits`` with the step kernel in ``shape``."""
+def time_batch(fits, params, steps=40, warmup=16):
+    """ms per batched step of ``fits`` under ``params``."""
     from .batch import Batch
-    A.m2m_set_launch(*shape)
-    b = Batch(max_fits=len(fits))
-    for f in fits:
-        if not b.admit(f, warmup + steps + 8):
-            raise RuntimeError("batch admission failed")
-    b.run(warmup)
+    before = tuning.current()
+    tuning.apply(params)
+    try:
+        b = Batch(max_fits=len(fits))
+        for f in fits:
+            if not b.admit(f, warmup + steps + 8):
+                raise RuntimeError("batch admission failed")
+        b.run(warmup)
+    finally:
+        tuning.apply(before)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(b.stream)
@@ -80,20 +114,30 @@ def time_batch_shape(fits, shape, steps=40, warmup=16):
     return ms
 
 
-def search_batch(fits, blocks=BLOCKS, tiles=TILES_PER_CU + (6, 12), steps=40, log=sys.stderr):
-    """Time every batch shape; returns (best shape, {shape: ms per step})."""
-    before = A.m2m_get_launch()
+def search_batch(fits, steps=40, log=sys.stderr, base=None):
+    """The best batch parameters; returns (params, {description: ms})."""
+    base = dict(tuning.DEFAULT, **(base or {}))
     res = {}
-    try:
-        for b, t in itertools.product(blocks, tiles):
-            ms = time_batch_shape(fits, (b, t), steps=steps)
-            res[(b, t)] = ms
-            if log:
-                print(f"[autotune] batch block={b} tiles/cu={t}: {1e3 * ms:.2f} us/step",
-                      file=log, flush=True)
-    finally:
-        A.m2m_set_launch(*before)
-    best = min(res, key=res.get)
+    best, best_ms = None, float("inf")
+    for b, t, g in itertools.product(BLOCKS, BATCH_TILES_PER_CU, (1, 2)):
+        p = dict(base, block=b, tiles_per_cu=t, groups=g)
+        ms = time_batch(fits, p, steps=steps)
+        res[_fmt(p)] = ms
+        if log:
+            print(f"[autotune] batch {_fmt(p)}: {1e3 * ms:.2f} us/step", file=log, flush=True)
+        if ms < best_ms:
+            best, best_ms = p, ms
+    # at the best shape: graphs, and the private bin copies
+    for gr, k in itertools.product((0, 1), PRIVATE):
+        p = dict(best, graphs=gr, private_copies=k)
+        if _fmt(p) in res:
+            continue
+        ms = time_batch(fits, p, steps=steps)
+        res[_fmt(p)] = ms
+        if log:
+            print(f"[autotune] batch {_fmt(p)}: {1e3 * ms:.2f} us/step", file=log, flush=True)
+        if ms < best_ms:
+            best, best_ms = p, ms
     return best, res
 
 
@@ -107,11 +151,15 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="steps timed per candidate (default: 64 for one fit, two graphs "
+                         "of 32; 40 for a batch, five graphs of 8)")
+    ap.add_argument("--write", action="store_true", help="store the pick in the package's table")
     args = ap.parse_args(argv)
     if args.workload == 4:
+        args.steps = args.steps or 40
         return main_batch(args)
+    args.steps = args.steps or 64
     wl = workload(args.workload)
     t0 = time.time()
     tp = wl.target_particles(n=1 << 20)
@@ -129,13 +177,14 @@ def main(argv=None):
         f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
         return f
 
-    best, res = search(make_fit, steps=args.steps, dtype=wl.state)
-    out = {"workload": wl.name, "best": list(best), "us_per_step": 1e3 * res[best],
-           "all": {f"{b},{t}": 1e3 * ms for (b, t), ms in res.items()}}
+    best, res = search(make_fit, dtype=wl.state, steps=args.steps)
+    key = tuning.class_key("single", wl.state, wl.layout, wl.N)
+    out = {"class": key, "workload": wl.name, "best": best, "us_per_step": 1e3 * res[_fmt(best)],
+           "all": {k: 1e3 * v for k, v in res.items()}}
     print(json.dumps(out))
-    if args.out:
-        with open(args.out, "w") as fh:
-            json.dump(out, fh, indent=1)
+    if args.write:
+        tuning.record(key, best, out["us_per_step"],
+                      f"autotune.py --workload {args.workload} (workload {wl.name}) on an MI355X")
 
 
 def main_batch(args):
@@ -145,7 +194,8 @@ def main_batch(args):
     from workloads.device import om_model_device
     t0 = time.time()
     fits = []
-    for wl in batch_fits(64):
+    wls = batch_fits(64)
+    for wl in wls:
         ic = om_model_device(wl.N, wl.potential, float("inf"), seed=wl.seed * 10 + 1)
         tp = om_model_device(wl.n_target, wl.potential, wl.target_ra, seed=wl.seed * 10 + 2)
         tf = Fit(wl.potential, wl.layout, wl.params, tp, dtype="f32")
@@ -157,12 +207,13 @@ def main_batch(args):
     print(f"[autotune] batch of {len(fits)} fits, {sum(f.n for f in fits)} particles: inputs "
           f"ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     best, res = search_batch(fits, steps=args.steps)
-    out = {"workload": "batch64_gh", "best": list(best), "us_per_step": 1e3 * res[best],
-           "all": {f"{b},{t}": 1e3 * ms for (b, t), ms in res.items()}}
+    key = tuning.class_key("batch", "f32", wls[0].layout)
+    out = {"class": key, "workload": "batch64_gh", "best": best,
+           "us_per_step": 1e3 * res[_fmt(best)], "all": {k: 1e3 * v for k, v in res.items()}}
     print(json.dumps(out))
-    if args.out:
-        with open(args.out, "w") as fh:
-            json.dump(out, fh, indent=1)
+    if args.write:
+        tuning.record(key, best, out["us_per_step"],
+                      "autotune.py --workload 4 (the 64-fit batch) on an MI355X")
     for f in fits:
         f.close()
 

@@ -52,9 +52,9 @@ class Batch:
         self.by_ctx.pop(fit.ctx.value, None)
 
     def profile(self, n_steps: int):
-        """(step kernel, reduction) times in ms per step from HIP events around
-        graph replays with and without one extra measuring reduction per step;
-        runs 2 * 8 * ceil(n / 8) batched steps."""
+        """(step kernel, rest of the step) in ms per step from HIP events
+        around each step kernel of n_steps batched steps launched one kernel
+        at a time."""
         a, b = C.c_double(), C.c_double()
         A.check(A.lib().m2m_batch_profile(self.h, int(n_steps), C.byref(a), C.byref(b)),
                 "m2m_batch_profile")

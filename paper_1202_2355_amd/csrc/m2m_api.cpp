@@ -21,13 +21,22 @@ namespace {
 constexpr int kGraphSteps = 32;     // M2M steps per captured graph of one fit
 constexpr int kBatchGraphSteps = 8; // of a batch (captured again when fits come and go)
 constexpr int kProfileMax = 4096;   // most steps one m2m_profile_step call times
+constexpr int kBatchProfileMax = 256;  // most steps one m2m_batch_profile call times
+// A fit of a batch whose tile rows of observable sums take at most this many
+// bytes is finalized by one block (every column and the end of its step, no
+// hand-over between blocks); larger ones by column jobs.
+constexpr size_t kWholeFitMaxBytes = size_t(1) << 20;
 constexpr uint32_t kStateMagic = 0x4d324d31u;  // "M2M1"
 constexpr uint32_t kStateVersion = 2u;         // 2: with the FP64 prior grid
 constexpr double kPi = 3.14159265358979323846;
 
 // launch shape for contexts and batches created from now on
 int g_block = 1024, g_tiles_per_cu = 1;
+constexpr int kGroups = 2;  // most groups a batch of two or more fits steps as
+int g_groups = 2;           // groups of a batch of two or more fits (1 or 2)
+int g_batch_graphs = 0;     // batches replay captured graphs (1) or launch directly (0)
 int g_deposit = M2M_DEPOSIT_F64;
+int g_kpriv_cap = 0;  // most private bin copies per block (0: as many as fit, at most 8)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -510,15 +519,11 @@ hipError_t launch_one_step(m2m_ctx* c, hipStream_t s) {
     return e;
 }
 
-m2m_status run_direct(m2m_ctx* c, int steps) {
-    for (int k = 0; k < steps; ++k) M2M_HIP(c, launch_one_step(c, c->stream));
-    return M2M_OK;
-}
-
-// Capture n repetitions of body(stream) on the capture stream and
-// instantiate them as one graph.
+// Capture n repetitions of body(stream) on the capture stream, instantiate
+// them as one graph and upload it on stream `up`, so that its first launch
+// costs no more than the later ones.
 template <typename F>
-hipError_t capture_steps(hipStream_t cap, int n, F body, hipGraphExec_t* out) {
+hipError_t capture_steps(hipStream_t cap, int n, F body, hipGraphExec_t* out, hipStream_t up) {
     *out = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -528,7 +533,11 @@ hipError_t capture_steps(hipStream_t cap, int n, F body, hipGraphExec_t* out) {
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess) *out = nullptr;
+    if (e == hipSuccess) e = hipGraphUpload(*out, up);
+    if (e != hipSuccess) {
+        if (*out) (void)hipGraphExecDestroy(*out);
+        *out = nullptr;
+    }
     return e;
 }
 
@@ -537,10 +546,11 @@ m2m_status ensure_graph(m2m_ctx* c) {
     if (!c->cap) M2M_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     const hipError_t e = capture_steps(
         c->cap, kGraphSteps,
-        [c](hipStream_t s) { return launch_one_step(c, s); }, &c->graph);
+        [c](hipStream_t s) { return launch_one_step(c, s); }, &c->graph, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "step graph");
     return M2M_OK;
 }
+
 
 // Steps as in the step graph, each followed by one more reduction in the
 // measuring mode that changes no state (m2m_profile_step).
@@ -555,7 +565,7 @@ m2m_status ensure_prof_graph(m2m_ctx* c) {
                 r = launch_finalize1(c->f64, c->fd, c->n_tiles, kModeObserve, s);
             return r;
         },
-        &c->graph_prof);
+        &c->graph_prof, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "profile graph");
     return M2M_OK;
 }
@@ -583,6 +593,30 @@ m2m_status m2m_set_launch(int32_t block, int32_t tiles_per_cu) {
     g_tiles_per_cu = tiles_per_cu;
     return M2M_OK;
 }
+
+m2m_status m2m_set_batch_graphs(int32_t on) {
+    if (on != 0 && on != 1) return M2M_EINVAL;
+    g_batch_graphs = on;
+    return M2M_OK;
+}
+
+int32_t m2m_get_batch_graphs(void) { return g_batch_graphs; }
+
+m2m_status m2m_set_private_copies(int32_t copies) {
+    if (copies != 0 && copies != 1 && copies != 2 && copies != 4 && copies != 8) return M2M_EINVAL;
+    g_kpriv_cap = copies;
+    return M2M_OK;
+}
+
+int32_t m2m_get_private_copies(void) { return g_kpriv_cap; }
+
+m2m_status m2m_set_batch_groups(int32_t groups) {
+    if (groups < 1 || groups > kGroups) return M2M_EINVAL;
+    g_groups = groups;
+    return M2M_OK;
+}
+
+int32_t m2m_get_batch_groups(void) { return g_groups; }
 
 m2m_status m2m_set_deposit_mode(int32_t mode) {
     if (mode != M2M_DEPOSIT_F64 && mode != M2M_DEPOSIT_F32_COMPENSATED) return M2M_EINVAL;
@@ -630,7 +664,8 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->kin = kin_class(c->lay.kin, c->lay.gh_nmax, c->lay.dens, c->par.scf_nr > 0);
     c->w = plan(c->lay, c->par, n, c->f64);
     const WsLayout& w = c->w;
-    const int kpriv = private_copies(c->f64, w.J);
+    const int kpriv = g_kpriv_cap > 0 ? std::min(private_copies(c->f64, w.J), g_kpriv_cap)
+                                      : private_copies(c->f64, w.J);
     c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
     c->wt = (size_t)n * 8 * (c->f64 ? 8 : 4) <= kWriteThroughMax;
     c->lds = step_lds_bytes(c->f64, c->acc64, w.J, radial_intervals(c->lay),
@@ -901,7 +936,10 @@ m2m_status m2m_step(m2m_ctx* c, int32_t n_steps, int32_t correct) {
         if (s != M2M_OK) return s;
         for (int k = 0; k < full; ++k) M2M_HIP(c, hipGraphLaunch(c->graph, c->stream));
     }
-    return run_direct(c, rem);
+    // the rest as direct launches: a graph launch has a fixed cost of
+    // several kernel launches
+    for (int k = 0; k < rem; ++k) M2M_HIP(c, launch_one_step(c, c->stream));
+    return M2M_OK;
 }
 
 m2m_status m2m_refresh_potential(m2m_ctx* c) {
@@ -1187,6 +1225,22 @@ m2m_status m2m_destroy(m2m_ctx* c) {
 }  // extern "C"
 
 // ================================================================= batch ===
+// The tables of one launch of some fits of a batch: their descriptions, the
+// tiles of the step kernel and the finalize jobs, and the graph of
+// kBatchGraphSteps steps over them. A group also has a stream of its own.
+struct LaunchSet {
+    FitDev* fits_dev = nullptr;
+    Tile* tiles_dev = nullptr;
+    FinJob* jobs_dev = nullptr;
+    size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
+    int n_tiles = 0, n_jobs = 0, n_fits = 0;
+    bool whole = false;  // one whole-fit finalize job per fit (else column jobs)
+    size_t lds = 0;
+    hipGraphExec_t graph = nullptr;   // kBatchGraphSteps steps
+    hipStream_t stream = nullptr;  // groups: the stream the group's steps run on
+    hipEvent_t done = nullptr;     // groups: the group's steps of a run call have ended
+};
+
 struct m2m_batch {
     int max_fits = 0;
     size_t budget = 0;
@@ -1195,19 +1249,21 @@ struct m2m_batch {
     std::vector<m2m_ctx*> fits;
     bool dirty = true;
     int f64 = -1;
-    FitDev* fits_dev = nullptr;
-    Tile* tiles_dev = nullptr;
-    FinJob* jobs_dev = nullptr;
+    // every fit in admission order: completion flags, timing, and the runs
+    // of a batch of one fit
+    LaunchSet all;
+    // two groups of fits of about equal particle count, each stepping on its
+    // own stream, so that one group's finalize and the tail of its step
+    // kernel overlap the other group's streaming
+    LaunchSet grp[kGroups];
+    int n_groups = 1;
+    hipEvent_t start = nullptr;  // work before a run call, which the groups wait for
     int32_t* gather_dev = nullptr;
     int32_t* gather_host = nullptr;
-    size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
-    int n_tiles = 0, n_jobs = 0, n_fits = 0;
-    size_t lds = 0;
     int block = 256, kin = -1;
     bool acc64 = true;
     bool smooth = false;  // some fit smooths its prior grid
-    hipGraphExec_t graph = nullptr;
-    hipGraphExec_t graph_prof = nullptr;  // steps with an extra measuring reduction
+    bool graphs = false;  // steps replayed from captured graphs (else launched directly)
 };
 
 namespace {
@@ -1226,99 +1282,156 @@ hipError_t grow(void** p, size_t* cap, size_t need) {
     return e;
 }
 
-// One batched step: the step kernel over the tiles of all fits, then the
-// finalize jobs of all fits.
-hipError_t batch_step(m2m_batch* b, bool f64, hipStream_t s) {
-    hipError_t e = launch_step(f64, b->acc64, b->block, b->kin, b->fits_dev, b->tiles_dev, b->n_tiles,
-                               b->lds, kModeStep, s);
+// One batched step over a set: the step kernel over the tiles of its fits,
+// then their finalize jobs.
+hipError_t batch_step(const m2m_batch* b, const LaunchSet& L, bool f64, hipStream_t s) {
+    hipError_t e = launch_step(f64, b->acc64, b->block, b->kin, L.fits_dev, L.tiles_dev, L.n_tiles,
+                               L.lds, kModeStep, s);
     if (e == hipSuccess)
-        e = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs, kModeStep, s,
-                            kin_scf(b->kin), b->smooth);
+        e = launch_finalize(f64, L.fits_dev, L.n_fits, L.jobs_dev, L.n_jobs, kModeStep, s,
+                            kin_scf(b->kin), b->smooth, L.whole);
     return e;
 }
 
-m2m_status rebuild(m2m_batch* b) {
-    // launches in flight may still read the old tables and graph
-    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
+void free_set(LaunchSet& L) {
+    if (L.graph) (void)hipGraphExecDestroy(L.graph);
+
+    if (L.fits_dev) (void)hipFree(L.fits_dev);
+    if (L.tiles_dev) (void)hipFree(L.tiles_dev);
+    if (L.jobs_dev) (void)hipFree(L.jobs_dev);
+    L.graph = nullptr;
+    L.fits_dev = nullptr;
+    L.tiles_dev = nullptr;
+    L.jobs_dev = nullptr;
+    L.cap_fits = L.cap_tiles = L.cap_jobs = 0;
+}
+
+// The tables of the fits `members` (indices into b->fits, in that order)
+// into L, and with `capture` the graph of kBatchGraphSteps steps over them.
+// One tile size for all of them, so that every block streams about the
+// same number of particles; each fit's last tile may be short, so the size
+// leaves one spare tile per fit: at most the launch shape's tiles in all.
+m2m_status fill_set(m2m_batch* b, LaunchSet& L, const std::vector<int>& members, bool capture) {
+    if (L.graph) {
+        (void)hipGraphExecDestroy(L.graph);
+        L.graph = nullptr;
     }
-    if (b->graph_prof) {
-        (void)hipGraphExecDestroy(b->graph_prof);
-        b->graph_prof = nullptr;
-    }
-    b->n_tiles = b->n_jobs = b->n_fits = 0;
-    if (b->fits.empty()) {
-        b->dirty = false;
-        return M2M_OK;
-    }
+    L.n_tiles = L.n_jobs = L.n_fits = 0;
+    if (members.empty()) return M2M_OK;
     const bool f64 = b->f64 == 1;
-    b->block = f64 ? 256 : g_block;
-    b->acc64 = f64 || g_deposit == M2M_DEPOSIT_F64;
     std::vector<FitDev> fd;
     std::vector<Tile> tl;
     std::vector<FinJob> jb;
     int64_t ntot = 0;
-    for (m2m_ctx* c : b->fits) ntot += c->n;
-    // one tile size for the whole batch, so that every block streams about
-    // the same number of particles; each fit's last tile may be short, so
-    // the size leaves one spare tile per fit: at most target tiles in all
+    for (int m : members) ntot += b->fits[m]->n;
     const int target = std::max(1, g_tiles_per_cu * n_cus());
-    const int64_t room = std::max<int64_t>(1, target - (int64_t)b->fits.size());
+    const int64_t room = std::max<int64_t>(1, target - (int64_t)members.size());
     int64_t tile = (ntot + room - 1) / room;
     tile = (tile + kSegAlign - 1) / kSegAlign * kSegAlign;
     size_t lds = 0;
-    b->smooth = false;
-    for (size_t f = 0; f < b->fits.size(); ++f) {
-        m2m_ctx* c = b->fits[f];
-        if (c->par.smooth) b->smooth = true;
-        fd.push_back(c->fd);
+    // a launch's finalize is one block per fit when every fit's tile rows of
+    // observable sums are small enough, else column jobs for every fit
+    bool whole = true;
+    std::vector<int> cnts(members.size());
+    for (size_t f = 0; f < members.size(); ++f) {
+        m2m_ctx* c = b->fits[members[f]];
         int cnt = (int)std::min<int64_t>((c->n + tile - 1) / tile, c->w.seg_cap);
-        cnt = std::max(1, cnt);
-        split_tiles(c->n, cnt, (int)f, 0, tl);
-        fin_jobs(c->w, (int)f, cnt, jb);
+        cnts[f] = std::max(1, cnt);
+        if ((size_t)cnts[f] * (size_t)c->w.J * 8 > kWholeFitMaxBytes) whole = false;
+    }
+    for (size_t f = 0; f < members.size(); ++f) {
+        m2m_ctx* c = b->fits[members[f]];
+        fd.push_back(c->fd);
+        split_tiles(c->n, cnts[f], (int)f, 0, tl);
+        if (whole)
+            jb.push_back(FinJob{(int)f, kFinWholeFit, 0, cnts[f]});
+        else
+            fin_jobs(c->w, (int)f, cnts[f], jb);
         lds = std::max(lds, c->lds);
     }
-    if (grow(reinterpret_cast<void**>(&b->fits_dev), &b->cap_fits, sizeof(FitDev) * fd.size()) != hipSuccess ||
-        grow(reinterpret_cast<void**>(&b->tiles_dev), &b->cap_tiles, sizeof(Tile) * tl.size()) != hipSuccess ||
-        grow(reinterpret_cast<void**>(&b->jobs_dev), &b->cap_jobs, sizeof(FinJob) * jb.size()) != hipSuccess)
+    if (grow(reinterpret_cast<void**>(&L.fits_dev), &L.cap_fits, sizeof(FitDev) * fd.size()) != hipSuccess ||
+        grow(reinterpret_cast<void**>(&L.tiles_dev), &L.cap_tiles, sizeof(Tile) * tl.size()) != hipSuccess ||
+        grow(reinterpret_cast<void**>(&L.jobs_dev), &L.cap_jobs, sizeof(FinJob) * jb.size()) != hipSuccess)
         return M2M_ENOMEM;
-    if (hipMemcpyAsync(b->fits_dev, fd.data(), sizeof(FitDev) * fd.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(b->tiles_dev, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(b->jobs_dev, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+    if (hipMemcpyAsync(L.fits_dev, fd.data(), sizeof(FitDev) * fd.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(L.tiles_dev, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(L.jobs_dev, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return M2M_EDEVICE;
-    b->n_tiles = (int)tl.size();
-    b->n_jobs = (int)jb.size();
-    b->n_fits = (int)fd.size();
-    b->lds = lds;
-    // the graph of kBatchGraphSteps steps over this composition (the
-    // measuring graph of m2m_batch_profile is captured when first asked for:
-    // serving rebuilds at every change of composition and never measures)
-    const hipError_t e = capture_steps(
-        b->cap, kBatchGraphSteps,
-        [b, f64](hipStream_t s) { return batch_step(b, f64, s); }, &b->graph);
-    if (e != hipSuccess) return M2M_EDEVICE;
+    L.n_tiles = (int)tl.size();
+    L.n_jobs = (int)jb.size();
+    L.n_fits = (int)fd.size();
+    L.whole = whole;
+    L.lds = lds;
+    if (capture) {
+        // the graph of kBatchGraphSteps steps, uploaded on the stream it
+        // will run on
+        const LaunchSet* Lp = &L;
+        auto body = [b, Lp, f64](hipStream_t s) { return batch_step(b, *Lp, f64, s); };
+        hipStream_t up = L.stream ? L.stream : b->stream;
+        if (capture_steps(b->cap, kBatchGraphSteps, body, &L.graph, up) != hipSuccess)
+            return M2M_EDEVICE;
+    }
+    return M2M_OK;
+}
+
+m2m_status rebuild(m2m_batch* b) {
+    // launches in flight may still read the old tables and graphs (the
+    // groups' work is joined to the batch stream at the end of every run)
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+    const int nf = (int)b->fits.size();
+    b->n_groups = nf >= 2 ? g_groups : 1;
+    if (nf == 0) {
+        for (LaunchSet* L : {&b->all, &b->grp[0], &b->grp[1]}) {
+            if (L->graph) (void)hipGraphExecDestroy(L->graph);
+            L->graph = nullptr;
+            L->n_tiles = L->n_jobs = L->n_fits = 0;
+        }
+        b->dirty = false;
+        return M2M_OK;
+    }
+    b->block = b->f64 == 1 ? 256 : g_block;
+    b->acc64 = b->f64 == 1 || g_deposit == M2M_DEPOSIT_F64;
+    b->smooth = false;
+    for (m2m_ctx* c : b->fits)
+        if (c->par.smooth) b->smooth = true;
+    std::vector<int> every(nf);
+    for (int f = 0; f < nf; ++f) every[f] = f;
+    b->graphs = g_batch_graphs != 0;
+    m2m_status s = fill_set(b, b->all, every, b->graphs && b->n_groups == 1);
+    if (s != M2M_OK) return s;
+    if (b->n_groups > 1) {
+        // the largest fits first, each to the group with fewer particles
+        std::vector<int> order = every;
+        std::stable_sort(order.begin(), order.end(),
+                         [b](int x, int y) { return b->fits[x]->n > b->fits[y]->n; });
+        std::vector<int> mem[kGroups];
+        int64_t load[kGroups] = {0, 0};
+        for (int f : order) {
+            const int g = load[1] < load[0] ? 1 : 0;
+            mem[g].push_back(f);
+            load[g] += b->fits[f]->n;
+        }
+        for (int g = 0; g < kGroups; ++g) {
+            std::sort(mem[g].begin(), mem[g].end());
+            if ((s = fill_set(b, b->grp[g], mem[g], b->graphs)) != M2M_OK) return s;
+        }
+    }
     b->dirty = false;
     return M2M_OK;
 }
 
-// The steps of the step graph, each followed by a reduction in the measuring
-// mode that changes no state, over the current composition.
-hipError_t ensure_batch_prof_graph(m2m_batch* b) {
-    if (b->graph_prof) return hipSuccess;
+// steps of the set L on stream st: with graphs, graphs of kBatchGraphSteps
+// steps and then direct launches (a graph launch has a fixed cost of several
+// kernel launches); without, direct launches only
+hipError_t run_set(const m2m_batch* b, const LaunchSet& L, int steps, hipStream_t st) {
     const bool f64 = b->f64 == 1;
-    return capture_steps(
-        b->cap, kBatchGraphSteps,
-        [b, f64](hipStream_t s) {
-            hipError_t r = batch_step(b, f64, s);
-            if (r == hipSuccess)
-                r = launch_finalize(f64, b->fits_dev, b->n_fits, b->jobs_dev, b->n_jobs,
-                                    kModeObserve, s, kin_scf(b->kin), b->smooth);
-            return r;
-        },
-        &b->graph_prof);
+    const int full = L.graph ? steps / kBatchGraphSteps : 0;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(L.graph, st);
+    for (int k = full * kBatchGraphSteps; k < steps && e == hipSuccess; ++k)
+        e = batch_step(b, L, f64, st);
+    return e;
 }
 
 }  // namespace
@@ -1335,12 +1448,15 @@ m2m_status m2m_batch_create(int32_t max_fits, size_t hbm_budget, void* hip_strea
     b->max_fits = max_fits;
     b->budget = hbm_budget;
     b->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&b->gather_dev), sizeof(int32_t) * 2 * (size_t)max_fits) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->gather_host), sizeof(int32_t) * 2 * (size_t)max_fits, 0) != hipSuccess) {
-        if (b->cap) (void)hipStreamDestroy(b->cap);
-        if (b->gather_dev) (void)hipFree(b->gather_dev);
-        delete b;
+    bool ok = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b->start, hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; g < kGroups && ok; ++g)
+        ok = hipStreamCreateWithFlags(&b->grp[g].stream, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->grp[g].done, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b->gather_dev), sizeof(int32_t) * 2 * (size_t)max_fits) == hipSuccess &&
+         hipHostMalloc(reinterpret_cast<void**>(&b->gather_host), sizeof(int32_t) * 2 * (size_t)max_fits, 0) == hipSuccess;
+    if (!ok) {
+        (void)m2m_batch_destroy(b);
         return M2M_EDEVICE;
     }
     *out = b;
@@ -1383,13 +1499,29 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
         if (s != M2M_OK) return s;
     }
     if (b->fits.empty() || steps_per_launch == 0) return M2M_OK;
+    if (b->n_groups == 1)
+        return run_set(b, b->all, steps_per_launch, b->stream) == hipSuccess ? M2M_OK : M2M_EDEVICE;
+    // the groups start after the work already on the batch stream, and the
+    // batch stream continues after both; their steps are enqueued in turn
+    // (step k of every group, then step k + 1), as the runtime blocks the
+    // host once a stream has many launches outstanding, and a group enqueued
+    // whole before the other would run alone meanwhile
+    hipError_t e = hipEventRecord(b->start, b->stream);
+    for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
+        e = hipStreamWaitEvent(b->grp[g].stream, b->start, 0);
     const bool f64 = b->f64 == 1;
-    const int full = steps_per_launch / kBatchGraphSteps, rem = steps_per_launch % kBatchGraphSteps;
-    for (int k = 0; k < full; ++k)
-        if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return M2M_EDEVICE;
-    for (int k = 0; k < rem; ++k)
-        if (batch_step(b, f64, b->stream) != hipSuccess) return M2M_EDEVICE;
-    return M2M_OK;
+    const int full = b->graphs ? steps_per_launch / kBatchGraphSteps : 0;
+    for (int k = 0; k < full && e == hipSuccess; ++k)
+        for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
+            e = hipGraphLaunch(b->grp[g].graph, b->grp[g].stream);
+    for (int k = full * kBatchGraphSteps; k < steps_per_launch && e == hipSuccess; ++k)
+        for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
+            e = batch_step(b, b->grp[g], f64, b->grp[g].stream);
+    for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
+        e = hipEventRecord(b->grp[g].done, b->grp[g].stream);
+    for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
+        e = hipStreamWaitEvent(b->stream, b->grp[g].done, 0);
+    return e == hipSuccess ? M2M_OK : M2M_EDEVICE;
 }
 
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
@@ -1402,7 +1534,7 @@ m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_
     }
     const int nf = (int)b->fits.size();
     if (nf > 0) {
-        if (launch_gather(b->fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
+        if (launch_gather(b->all.fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
             hipMemcpyAsync(b->gather_host, b->gather_dev, sizeof(int32_t) * 2 * nf,
                            hipMemcpyDeviceToHost, b->stream) != hipSuccess)
             return M2M_EDEVICE;
@@ -1434,34 +1566,48 @@ m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_
 }
 
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize) {
-    if (!b || n_steps < 1 || n_steps > kProfileMax) return M2M_EINVAL;
+    if (!b || n_steps < 1 || n_steps > kBatchProfileMax) return M2M_EINVAL;
     if (b->dirty) {
         m2m_status s = rebuild(b);
         if (s != M2M_OK) return s;
     }
     if (b->fits.empty()) return M2M_ESTATE;
-    if (ensure_batch_prof_graph(b) != hipSuccess) return M2M_EDEVICE;
-    // as m2m_profile_step: r replays of the plain and of the measuring graph
-    const int r = (n_steps + kBatchGraphSteps - 1) / kBatchGraphSteps;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // n_steps steps of all fits launched one kernel at a time (one step
+    // kernel over the tiles of every fit, not the overlapping groups), each
+    // step kernel between two events on the batch stream: its duration (with
+    // the events' own small cost, so an upper bound), and the rest of the
+    // step (the finalize and the gaps) from its second event to the next
+    // step's first
+    const bool f64 = b->f64 == 1;
+    std::vector<hipEvent_t> ev(2 * (size_t)n_steps + 1, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
-    if (e == hipSuccess) e = hipEventRecord(ev[0], b->stream);
-    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(b->graph, b->stream);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
-    for (int k = 0; k < r && e == hipSuccess; ++k) e = hipGraphLaunch(b->graph_prof, b->stream);
-    if (e == hipSuccess) e = hipEventRecord(ev[2], b->stream);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        e = hipEventRecord(ev[2 * k], b->stream);
+        if (e == hipSuccess)
+            e = launch_step(f64, b->acc64, b->block, b->kin, b->all.fits_dev, b->all.tiles_dev,
+                            b->all.n_tiles, b->all.lds, kModeStep, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], b->stream);
+        if (e == hipSuccess)
+            e = launch_finalize(f64, b->all.fits_dev, b->all.n_fits, b->all.jobs_dev, b->all.n_jobs,
+                                kModeStep, b->stream, kin_scf(b->kin), b->smooth, b->all.whole);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * (size_t)n_steps], b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    float t1 = 0.f, t2 = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[0], ev[1]);
-    if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[1], ev[2]);
+    double ts = 0.0, tf = 0.0;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        float a = 0.f, c = 0.f;
+        e = hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[2 * k + 1], ev[2 * k + 2]);
+        ts += a;
+        tf += c;
+    }
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return M2M_EDEVICE;
-    const double S = (double)t1 / (r * kBatchGraphSteps), S2 = (double)t2 / (r * kBatchGraphSteps);
-    if (ms_step) *ms_step = S - (S2 - S);
-    if (ms_finalize) *ms_finalize = S2 - S;
+    if (ms_step) *ms_step = ts / n_steps;
+    if (ms_finalize) *ms_finalize = tf / n_steps;
     return M2M_OK;
 }
 
@@ -1470,7 +1616,7 @@ int64_t m2m_batch_particles(m2m_batch* b) {
     const int nf = (int)b->fits.size();
     if (nf == 0) return 0;
     if (b->dirty && rebuild(b) != M2M_OK) return -1;
-    if (launch_gather(b->fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
+    if (launch_gather(b->all.fits_dev, nf, b->gather_dev, b->stream) != hipSuccess ||
         hipMemcpyAsync(b->gather_host, b->gather_dev, sizeof(int32_t) * 2 * nf,
                        hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
@@ -1498,12 +1644,14 @@ m2m_status m2m_batch_destroy(m2m_batch* b) {
     if (!b) return M2M_EINVAL;
     (void)hipStreamSynchronize(b->stream);
     for (m2m_ctx* c : b->fits) c->batch = nullptr;
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    if (b->graph_prof) (void)hipGraphExecDestroy(b->graph_prof);
+    free_set(b->all);
+    for (int g = 0; g < kGroups; ++g) {
+        free_set(b->grp[g]);
+        if (b->grp[g].stream) (void)hipStreamDestroy(b->grp[g].stream);
+        if (b->grp[g].done) (void)hipEventDestroy(b->grp[g].done);
+    }
+    if (b->start) (void)hipEventDestroy(b->start);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->fits_dev) (void)hipFree(b->fits_dev);
-    if (b->tiles_dev) (void)hipFree(b->tiles_dev);
-    if (b->jobs_dev) (void)hipFree(b->jobs_dev);
     if (b->gather_dev) (void)hipFree(b->gather_dev);
     if (b->gather_host) (void)hipHostFree(b->gather_host);
     delete b;

@@ -138,10 +138,12 @@ __host__ __device__ inline Tile tile_of(int64_t n, int t, int count, int fit, in
     return Tile{fit, row0 + t, b, e, count, 0};
 }
 
-// One finalize block: kFinCols columns of one fit.
+// One finalize block: kFinCols columns of one fit, or (kind kFinWholeFit)
+// every column of one fit and the end of its step.
+constexpr int32_t kFinWholeFit = 3;
 struct FinJob {
     int32_t fit;
-    int32_t kind;  // 0: observable columns, 1: cell columns, 2: potential columns
+    int32_t kind;  // 0: observable columns, 1: cell columns, 2: potential columns, 3: all
     int32_t col0;
     int32_t n_tiles;  // rows of the fit to reduce
 };
@@ -154,9 +156,11 @@ hipError_t launch_step(bool f64, bool acc64, int block, int kin, const FitDev* f
 // the column jobs of the fits of the table (n_fits of them)
 // scf: the fits have the self-consistent potential (kin_scf of their kin class)
 // smooth: some fit of the launch smooths its prior grid (the variant with the
-// smoothing's LDS grids)
+// smoothing's LDS grids); whole: every job is a whole-fit job (one block per
+// fit, the kernel with small blocks), else every job is a column job
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth);
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth,
+                           bool whole);
 bool kin_scf(int kin);
 // the step kernel of one particle-state / in-tile-sum type pair (one == nullptr:
 // over the fit and tile tables, else over that one fit); m2m_step_*.hip

@@ -542,11 +542,20 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     uint32_t* ticket = observe ? &st->mticket : &st->ticket;
     __syncthreads();
     if (threadIdx.x == 0) {
-        // release of this job's results (wave 0 wrote them) with the count;
-        // acquire of the others' for the last job, passed on to its block by
-        // the barrier below
-        const uint32_t prev =
-            __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // a job with results: release of them (wave 0 wrote them) with the
+        // count; acquire of the others' for the last job, passed on to its
+        // block by the barrier below. A job without results only counts
+        // itself: its reads of the counters have completed, as their values
+        // decided the branch that led here, so a relaxed add suffices (an
+        // agent-scope release would write back the whole L2 of its XCD); if
+        // it is the last, it acquires the others' results by a fence.
+        uint32_t prev;
+        if (work) {
+            prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == n_part - 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
         last = (prev == n_part - 1) ? 1 : 0;
     }
     __syncthreads();
@@ -574,13 +583,184 @@ __device__ __forceinline__ void finalize_job(const FitDev& fd, const FinJob& jb,
     end_step(fd, gst, f, ss, chi2);
 }
 
-// the jobs of the fits of a table (batches)
+// One block reduces every column of one fit and ends its step (batches of
+// fits with few tile rows): the observable columns in chunks of kFinCols
+// (each chunk summed over the rows exactly as one column job sums them,
+// then its epilogue and its chi^2 part), on refresh steps the cell columns,
+// on rebuild steps the potential columns, then the smoothing, the node table,
+// chi^2 from the parts in chunk order and the step counters. Nothing else
+// reads or writes the fit's counters during the launch, so no ticket is
+// taken. The results equal those of the column jobs bit for bit.
+constexpr int kMaxChunks = 16384 / kFinCols;
+constexpr int kFitChunks = 4;  // column chunks summed together by the whole-fit finalize
+
+// Row group `wave` (of NW) of nb <= kFitChunks chunks of kFinCols columns
+// from column base + c0 (columns c < ncols of the section): for each column
+// the sum of rows wave, wave + NW, ... in row order (with counts from column
+// + C for cells); four rows of every chunk in flight.
+template <int NW>
+__device__ __forceinline__ void chunk_sums(const FitDev& fd, int base, int c0, int ncols, int nb,
+                                           bool counts, int n_rows, int wave, int lane,
+                                           double* acc, double* acc2) {
+    const size_t stride = (size_t)fd.row_len;
+    const G<const double> P = gmem<const double>(fd.partials) + base;
+    bool ok[kFitChunks];
+#pragma unroll
+    for (int k = 0; k < kFitChunks; ++k) {
+        acc[k] = acc2[k] = 0.0;
+        ok[k] = k < nb && c0 + k * kFinCols + lane < ncols;
+    }
+    for (int t0 = wave; t0 < n_rows; t0 += 4 * NW) {
+        double v[4][kFitChunks], w[4][kFitChunks];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NW;
+#pragma unroll
+            for (int k = 0; k < kFitChunks; ++k) {
+                const size_t at = (size_t)t * stride + c0 + k * kFinCols + lane;
+                v[u][k] = (t < n_rows && ok[k]) ? P[at] : 0.0;
+                w[u][k] = (counts && t < n_rows && ok[k]) ? P[at + fd.C] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < kFitChunks; ++k) {
+                acc[k] += v[u][k];
+                acc2[k] += w[u][k];
+            }
+    }
+}
+
+// NW waves (row groups); the smoothing needs a block of kFinWaves waves.
+template <typename T, bool SCF, bool SMOOTH, int NW>
+__device__ __forceinline__ void finalize_fit(const FitDev& fd, int n_rows, int32_t mode) {
+    static_assert(!SMOOTH || NW == kFinWaves, "prior smoothing needs kFinWaves waves");
+    __shared__ double part[NW][kFinCols];
+    __shared__ double part2[NW][kFinCols];
+    __shared__ double chi2p[kMaxChunks];
+    __shared__ int sidx;
+    __shared__ double smean;
+    __shared__ SmoothLds<SMOOTH> sl;
+    const G<FitState> gst = gmem(fd.st);
+    const bool cells_mode = (mode & kModeCells) != 0;
+    const bool observe = (mode & kModeObserve) != 0;
+    const bool pot_mode = SCF && (mode & kModePot) != 0;
+    const bool step = (mode & kModeStep) != 0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const Snap ss = snap_of(gst);
+    if (step && ss.steps_left <= 0) return;  // uniform: the fit is idle
+    const Flags f = flags_of<SCF>(fd, ss, mode);
+    const int nbj = fd.n_bin_jobs;
+    // observable columns, up to kFitChunks chunks of kFinCols at a time: their
+    // row loads (and wave 0's epilogue inputs) are all issued before any sum
+    if (!cells_mode && !pot_mode)
+        for (int b0 = 0; b0 < nbj; b0 += kFitChunks) {
+            const int nb = min(kFitChunks, nbj - b0);
+            double acc[kFitChunks], acc2[kFitChunks], yt0[kFitChunks], sg[kFitChunks], Yj[kFitChunks];
+#pragma unroll
+            for (int k = 0; k < kFitChunks; ++k) {
+                acc[k] = acc2[k] = yt0[k] = Yj[k] = 0.0;
+                sg[k] = 1.0;
+                const int col = (b0 + k) * kFinCols + lane;
+                if (k < nb && col < fd.J && wave == 0 && !observe) {
+                    yt0[k] = gmem(fd.ytil)[col];
+                    sg[k] = gmem(fd.sigma)[col];
+                    Yj[k] = gmem(fd.Y)[col];
+                }
+            }
+            chunk_sums<NW>(fd, 0, b0 * kFinCols, fd.J, nb, false, n_rows, wave, lane, acc, acc2);
+            for (int k = 0; k < nb; ++k) {
+                part[wave][lane] = acc[k];
+                __syncthreads();
+                if (wave == 0) {
+                    double tot = 0.0;
+                    for (int w = 0; w < NW; ++w) tot += part[w][lane];
+                    const double d2 = column_epilogue<T>(fd, true, (b0 + k) * kFinCols, f, tot, 0.0,
+                                                         yt0[k], sg[k], Yj[k], lane);
+                    if (lane == 0) chi2p[b0 + k] = d2;
+                }
+                __syncthreads();
+            }
+        }
+    // cell columns on refresh steps (sums and counts)
+    if (f.refresh)
+        for (int b0 = 0; b0 < fd.n_cell_jobs; b0 += kFitChunks) {
+            const int nb = min(kFitChunks, fd.n_cell_jobs - b0);
+            double acc[kFitChunks], acc2[kFitChunks];
+            chunk_sums<NW>(fd, fd.J, b0 * kFinCols, fd.C, nb, true, n_rows, wave, lane, acc, acc2);
+            for (int k = 0; k < nb; ++k) {
+                part[wave][lane] = acc[k];
+                part2[wave][lane] = acc2[k];
+                __syncthreads();
+                if (wave == 0) {
+                    double tot = 0.0, tot2 = 0.0;
+                    for (int w = 0; w < NW; ++w) {
+                        tot += part[w][lane];
+                        tot2 += part2[w][lane];
+                    }
+                    (void)column_epilogue<T>(fd, false, (b0 + k) * kFinCols, f, tot, tot2, 0.0, 1.0,
+                                             0.0, lane);
+                }
+                __syncthreads();
+            }
+        }
+    // potential columns on rebuild steps
+    if (SCF && f.pot)
+        for (int b0 = 0; b0 < fd.n_pot_jobs; b0 += kFitChunks) {
+            const int nb = min(kFitChunks, fd.n_pot_jobs - b0);
+            double acc[kFitChunks], acc2[kFitChunks];
+            chunk_sums<NW>(fd, fd.scf_col0, b0 * kFinCols, fd.scf_P, nb, false, n_rows, wave, lane, acc,
+                       acc2);
+            for (int k = 0; k < nb; ++k) {
+                const int col = (b0 + k) * kFinCols + lane;
+                part[wave][lane] = acc[k];
+                __syncthreads();
+                if (wave == 0 && col < fd.scf_P) {
+                    double tot = 0.0;
+                    for (int w = 0; w < NW; ++w) tot += part[w][lane];
+                    gmem(fd.scf_sum)[col] = tot;
+                }
+                __syncthreads();
+            }
+        }
+    // the prior smoothing, then the node table (the block's own writes above
+    // are ordered before them by the barriers)
+    if constexpr (SMOOTH) {
+        if (fd.smooth && f.refresh) {
+            smooth_priors<T>(fd, 0, sl.g[0], sl.g[1], &part[0][0], &sidx, &smean);
+            if (fd.C > fd.cell_half) {
+                __syncthreads();
+                smooth_priors<T>(fd, fd.cell_half, sl.g[0], sl.g[1], &part[0][0], &sidx, &smean);
+            }
+        }
+    }
+    if (SCF && f.pot) build_scf_table(fd);
+    if (wave != 0) return;
+    const double chi2 = (cells_mode || pot_mode) ? 0.0 : chi2_of_parts(chi2p, nbj, lane);
+    if (lane != 0 || observe || pot_mode) return;
+    end_step(fd, gst, f, ss, chi2);
+}
+
+// the column jobs of the fits of a table (batches of fits with many rows)
 template <typename T, bool SCF, bool SMOOTH>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const FitDev* __restrict__ fits,
                                                          const FinJob* __restrict__ jobs,
                                                          int32_t mode) {
     const FinJob jb = jobs[blockIdx.x];
     finalize_job<T, SCF, SMOOTH>(fits[jb.fit], jb, mode);
+}
+
+// one block of NW waves per fit of a table, each reducing every column of
+// its fit (batches of fits with few rows); blocks of one wave per SIMD, so
+// that they find room beside the step kernel of another group of the batch
+template <typename T, bool SCF, bool SMOOTH, int NW>
+__global__ __launch_bounds__(NW * 64) void k_finalize_fits(const FitDev* __restrict__ fits,
+                                                          const FinJob* __restrict__ jobs,
+                                                          int32_t mode) {
+    const FinJob jb = jobs[blockIdx.x];
+    finalize_fit<T, SCF, SMOOTH, NW>(fits[jb.fit], jb.n_tiles, mode);
 }
 
 // one fit, its description passed by value: block b < n_bin_jobs takes bin
@@ -723,9 +903,11 @@ hipError_t launch_step1(bool f64, bool acc64, int block, int kin, const FitDev& 
 }
 
 namespace {
+constexpr int kFitWaves = 4;  // waves of a whole-fit finalize block without smoothing
+
 template <bool SCF, bool SMOOTH>
 hipError_t launch_fin_t(bool f64, const FitDev* fits, const FinJob* jobs, const FitDev* one,
-                        int n_blocks, int n_rows, int32_t mode, hipStream_t s) {
+                        int n_blocks, int n_rows, int32_t mode, hipStream_t s, bool whole) {
     if (one) {
         if (f64)
             hipLaunchKernelGGL((k_finalize1<double, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
@@ -733,6 +915,14 @@ hipError_t launch_fin_t(bool f64, const FitDev* fits, const FinJob* jobs, const 
         else
             hipLaunchKernelGGL((k_finalize1<float, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
                                s, *one, n_rows, mode);
+    } else if (whole) {
+        constexpr int NW = SMOOTH ? kFinWaves : kFitWaves;
+        if (f64)
+            hipLaunchKernelGGL((k_finalize_fits<double, SCF, SMOOTH, NW>), dim3(n_blocks),
+                               dim3(NW * 64), 0, s, fits, jobs, mode);
+        else
+            hipLaunchKernelGGL((k_finalize_fits<float, SCF, SMOOTH, NW>), dim3(n_blocks),
+                               dim3(NW * 64), 0, s, fits, jobs, mode);
     } else {
         if (f64)
             hipLaunchKernelGGL((k_finalize<double, SCF, SMOOTH>), dim3(n_blocks), dim3(kFinThreads), 0,
@@ -745,19 +935,22 @@ hipError_t launch_fin_t(bool f64, const FitDev* fits, const FinJob* jobs, const 
 }
 
 hipError_t launch_fin_any(bool f64, bool scf, bool smooth, const FitDev* fits, const FinJob* jobs,
-                          const FitDev* one, int n_blocks, int n_rows, int32_t mode, hipStream_t s) {
+                          const FitDev* one, int n_blocks, int n_rows, int32_t mode, hipStream_t s,
+                          bool whole) {
     if (n_blocks <= 0) return hipSuccess;
-    if (scf && smooth) return launch_fin_t<true, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
-    if (scf) return launch_fin_t<true, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
-    if (smooth) return launch_fin_t<false, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
-    return launch_fin_t<false, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s);
+    if (scf && smooth)
+        return launch_fin_t<true, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s, whole);
+    if (scf) return launch_fin_t<true, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s, whole);
+    if (smooth) return launch_fin_t<false, true>(f64, fits, jobs, one, n_blocks, n_rows, mode, s, whole);
+    return launch_fin_t<false, false>(f64, fits, jobs, one, n_blocks, n_rows, mode, s, whole);
 }
 }  // namespace
 
 hipError_t launch_finalize(bool f64, const FitDev* fits, int n_fits, const FinJob* jobs,
-                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth) {
+                           int n_jobs, int32_t mode, hipStream_t s, bool scf, bool smooth,
+                           bool whole) {
     (void)n_fits;
-    return launch_fin_any(f64, scf, smooth, fits, jobs, nullptr, n_jobs, 0, mode, s);
+    return launch_fin_any(f64, scf, smooth, fits, jobs, nullptr, n_jobs, 0, mode, s, whole);
 }
 
 bool kin_scf(int kin) { return (kin & kKinScf) != 0; }
@@ -765,7 +958,7 @@ bool kin_scf(int kin) { return (kin & kKinScf) != 0; }
 hipError_t launch_finalize1(bool f64, const FitDev& fd, int n_rows, int32_t mode, hipStream_t s) {
     const int n_jobs = fd.n_bin_jobs + fd.n_cell_jobs + fd.n_pot_jobs;
     return launch_fin_any(f64, fd.scf_nr > 0, fd.smooth != 0, nullptr, nullptr, &fd, n_jobs, n_rows,
-                          mode, s);
+                          mode, s, false);
 }
 
 hipError_t launch_assign(bool f64, const FitDev* fits, const Tile* tiles, int n_tiles,

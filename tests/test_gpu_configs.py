@@ -46,20 +46,11 @@ def Fit():
     return Fit
 
 
-class _launch:
-    """Run the enclosed code in a given launch shape of the step kernel."""
-
-    def __init__(self, shape):
-        self.shape = shape
-
-    def __enter__(self):
-        from paper_1202_2355_amd import _abi
-        self.before = _abi.m2m_get_launch()
-        _abi.m2m_set_launch(*self.shape)
-
-    def __exit__(self, *exc):
-        from paper_1202_2355_amd import _abi
-        _abi.m2m_set_launch(*self.before)
+def _tuned(mode, wl):
+    """The package's tuned launch parameters of the workload's class (as the
+    benchmark runs it), restored on exit."""
+    from paper_1202_2355_amd import tuning
+    return tuning.tuned(mode, wl.state, wl.layout, wl.N)
 
 
 def _counters(fit):
@@ -84,13 +75,12 @@ def test_losvd_nfw_configuration_over_two_refreshes(oracle, Fit):
     40 annuli x 64 velocity bins, 64 x 32 prior grid refreshed every 25
     steps) with 200 003 particles in its benchmark launch shape, 60 FP32
     steps: two in-step refreshes and their assignments."""
-    from bench import LAUNCH
     wl = workload(3)
     n, steps = 200_003, 60
-    _say("losvd/nfw", n, steps, "launch", LAUNCH[3])
     T = oracle_targets(oracle, wl)
     parts = cast(wl.initial_particles(n=n, seed=301), "f32")
-    with _launch(LAUNCH[3]):
+    with _tuned("single", wl) as shape:
+        _say("losvd/nfw", n, steps, "launch", shape)
         f, o = _run_pair(oracle, Fit, wl, parts, T, "f32", 1e-5)
         f.step(steps)
         hist_g = f.chi2_history(steps)
@@ -119,13 +109,12 @@ def test_gauss_hermite_configuration_200_steps(oracle, Fit):
     binned on the other side of an edge moves the residual of a faint annulus
     enough to shift every particle of it by about 1e-4 over the run; the
     shift falls as 1/sqrt(N).)"""
-    from bench import LAUNCH
     wl = workload(2)
     n, steps = wl.N, 200
-    _say("gh", n, steps, "launch", LAUNCH[2])
     T = oracle_targets(oracle, wl)
     parts = cast(wl.initial_particles(n=n, seed=302), "f32")
-    with _launch(LAUNCH[2]):
+    with _tuned("single", wl) as shape:
+        _say("gh", n, steps, "launch", shape)
         f, o = _run_pair(oracle, Fit, wl, parts, T, "f32", 1e-5)
         f.step(steps)
         hist_g = f.chi2_history(steps)
@@ -151,24 +140,26 @@ def test_batched_configuration_in_its_launch_shape(oracle, Fit):
     concentration, N from 4 100 to 130 000 after dividing by 16) in the
     batch's benchmark launch shape: each fit against the oracle and against
     the same fit run alone, 50 steps (two refreshes)."""
-    from bench import LAUNCH
     from paper_1202_2355_amd.batch import Batch
     members = _batch_members(10, 16)
+    full = _batch_members(10, 1)
     steps = 50
-    _say("batch", [wl.N for wl in members], "launch", LAUNCH[4])
     data = []
     for wl in members:
         T = oracle_targets(oracle, wl, n_target=1 << 16)
         parts = cast(wl.initial_particles(), "f32")
         data.append((T, parts))
-    with _launch(LAUNCH[4]):
-        alone = []
-        for wl, (T, parts) in zip(members, data):
+    alone = []
+    for wl, wf, (T, parts) in zip(members, full, data):
+        # alone: in the tuned shape of a single fit of the batch member's size
+        with _tuned("single", wf):
             f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
-            f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
-            f.step(steps)
-            alone.append((f.particles()["u"], f.chi2_history(steps)))
-            f.close()
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        f.step(steps)
+        alone.append((f.particles()["u"], f.chi2_history(steps)))
+        f.close()
+    with _tuned("batch", members[0]) as shape:
+        _say("batch", [wl.N for wl in members], "launch", shape)
         b = Batch(max_fits=len(members))
         fits = []
         for wl, (T, parts) in zip(members, data):

@@ -294,15 +294,14 @@ def test_full_size_workloads(oracle, Fit, wlid, steps):
     """Workloads 2 and 3 at their full particle counts, in the launch shape
     the benchmark uses: observables of the initial state and weights after a
     few steps against the oracle."""
-    from bench import LAUNCH
-    from paper_1202_2355_amd import _abi
+    from paper_1202_2355_amd import tuning
     wl = workload(wlid)
-    before = _abi.m2m_get_launch()
-    _abi.m2m_set_launch(*LAUNCH[wlid])
-    _say("full size", wl.name, wl.N, "launch", LAUNCH[wlid])
     T = oracle_targets(oracle, wl)
     parts = cast(wl.initial_particles(), "f32")
-    f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    # the library reads its launch settings when a context is made
+    with tuning.tuned("single", wl.state, wl.layout, wl.N) as shape:
+        _say("full size", wl.name, wl.N, "launch", shape)
+        f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
     y0 = f.observe(T["V_p"], T["sigma_p"])
     yo, ya, yb = oracle.deposit(parts, np.ones(wl.N), wl.layout, V_p=T["V_p"], sigma_p=T["sigma_p"],
                                 band=BAND_F32, nthreads=16, with_abs=True)
@@ -315,9 +314,8 @@ def test_full_size_workloads(oracle, Fit, wlid, steps):
     st = f.particles()
     r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
     _say("full size", wl.name, "rel2", r2, "max(unflagged)", rmax, "flagged", frac)
-    assert r2 <= 1e-4 and rmax <= 1e-4
     f.close()
-    _abi.m2m_set_launch(*before)
+    assert r2 <= 1e-4 and rmax <= 1e-4
 
 
 def test_fp32_vs_fp64_state_per_observable(oracle, Fit):
