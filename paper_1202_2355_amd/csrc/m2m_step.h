@@ -264,6 +264,21 @@ __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
     step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
 }
 
+// The same for the kinds of observables whose step fits 64 VGPRs without
+// spilling, compiled for 8 waves per SIMD, so that two blocks of 1024 threads
+// share a CU and one block's set-up and tail overlap the other's streaming.
+template <int KIN>
+constexpr bool lean_kin() {
+    return (KIN & (kKinAlm | kKinScf)) == 0 && (KIN & 7) != kKinGHN;
+}
+
+template <typename T, typename A, int BLOCK, int KIN>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_step_w8(
+    const FitDev* __restrict__ fits, const Tile* __restrict__ tiles, int32_t mode) {
+    const Tile tl = tiles[blockIdx.x];
+    step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
+}
+
 // one fit, its description passed by value; block t takes tile t of the
 // fit split into gridDim.x tiles
 template <typename T, typename A, int BLOCK, int KIN>
@@ -278,6 +293,9 @@ hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* on
     if (one)
         hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, *one,
                            mode);
+    else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8 && BLOCK == 1024)
+        hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                           tiles, mode);
     else
         hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
                            tiles, mode);
