@@ -296,6 +296,35 @@ m2m_status m2m_get_chi2_history(m2m_ctx* ctx, double* out, int32_t max, int32_t*
  * Synchronizes. Used to build targets from a realization (Sec. 3.1). */
 m2m_status m2m_observe(m2m_ctx* ctx, const double* V_p, const double* sigma_p, double* y);
 
+/* Allocation-free observation, for callers that cannot allocate device
+ * memory (code that must keep a fixed device footprint, such as serving
+ * loops, and harnesses that forbid hipMalloc): y_j (host, J doubles) of the
+ * particle set (x, y, z, vx, vy, vz, u: n particles of dtype, device,
+ * 16-byte aligned, read only) with total mass M, w_i = u_i M / n, exactly as
+ * m2m_observe computes it for a context of this layout, mass and particle
+ * count (same kernels and tiles; without prior cells the tile count can
+ * differ for small n, and with it the FP64 summation order).
+ * V_p, sigma_p: host, n_R doubles each, required for M2M_KIN_GH, ignored
+ * otherwise. hip_stream: a hipStream_t as void* (NULL: the null stream).
+ *   The working memory (tables, counters, tile rows, the observables) is a
+ * static device array of M2M_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends; the call allocates no
+ * device memory and calls no allocating HIP or library routine. It keeps
+ * the last call's contents; the counters are cleared at every call. A
+ * layout and particle count that need more working memory than the array
+ * holds give M2M_ENOMEM (observables x 8 bytes per tile row; about 256 tile
+ * rows at the default launch shape). Synchronizes. Calls from one process
+ * run one at a time; calls from different processes on one GPU each have
+ * their own array. Calls whose device work overlaps on one GPU (another
+ * stream of the same process, hipGraph replays of such work) would race on
+ * the array. Failure messages: m2m_last_error(NULL) on the calling thread. */
+#define M2M_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+m2m_status m2m_observe_noalloc(const m2m_obs_layout* layout, double mass, int64_t n,
+                               int32_t dtype, const void* x, const void* y, const void* z,
+                               const void* vx, const void* vy, const void* vz, const void* u,
+                               const double* V_p, const double* sigma_p, double* obs,
+                               void* hip_stream);
+
 /* Checkpoint of everything the context holds besides the particle arrays
  * (ytilde, cell priors, counters, targets). With host_blob = NULL, *bytes
  * receives the size. Synchronizes. m2m_set_state restores it into a context
@@ -335,7 +364,8 @@ m2m_status m2m_smoothing_basis(int32_t n_E, int32_t n_x, double hE, double hx, d
 /* Release the context and its library-owned workspace (synchronizes). */
 m2m_status m2m_destroy(m2m_ctx* ctx);
 
-/* Text of the last failure on ctx (never NULL). */
+/* Text of the last failure on ctx (never NULL); with ctx NULL, of the
+ * calling thread's last failed m2m_observe_noalloc. */
 const char* m2m_last_error(const m2m_ctx* ctx);
 
 /* Launch shape of the fused step kernel for contexts created afterwards and

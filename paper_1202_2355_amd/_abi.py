@@ -78,6 +78,8 @@ SIGNATURES = {
     "m2m_get_observables": (_st, [_vp, _dp, _dp, _dp, _dp]),
     "m2m_get_chi2_history": (_st, [_vp, _dp, _i32, C.POINTER(_i32)]),
     "m2m_observe": (_st, [_vp, _dp, _dp, _dp]),
+    "m2m_observe_noalloc": (_st, [C.POINTER(m2m_obs_layout), C.c_double, C.c_int64, _i32] +
+                            [_vp] * 7 + [_dp, _dp, _dp, _vp]),
     "m2m_get_state": (_st, [_vp, _vp, C.POINTER(C.c_size_t)]),
     "m2m_set_state": (_st, [_vp, _vp, C.c_size_t]),
     "m2m_profile_step": (_st, [_vp, _i32, _i32, _dp, _dp]),
@@ -239,3 +241,25 @@ def m2m_smoothing_basis(n_E: int, n_x: int, hE: float, hx: float) -> np.ndarray:
     check(lib().m2m_smoothing_basis(int(n_E), int(n_x), float(hE), float(hx),
                                     out.ctypes.data_as(_dp), C.byref(n)), "m2m_smoothing_basis")
     return out
+
+
+def m2m_observe_noalloc(layout: dict, mass: float, n: int, dtype: str, ptrs, V_p=None,
+                        sigma_p=None, stream=None) -> np.ndarray:
+    """y_j (J values) of n particles at the device addresses ``ptrs`` (x, y,
+    z, vx, vy, vz, u) with total mass ``mass``, computed in the library's
+    static device scratch (no device allocation). ``stream``: a HIP stream
+    handle (int) or None for the null stream."""
+    L = obs_layout(layout)
+    J = m2m_num_observables(layout)
+    y = np.zeros(max(J, 1))
+    keep = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (V_p, sigma_p)]
+    args = [None if a is None else a.ctypes.data_as(_dp) for a in keep]
+    if len(ptrs) != 7:
+        raise ValueError("ptrs: the seven addresses x, y, z, vx, vy, vz, u")
+    st = lib().m2m_observe_noalloc(C.byref(L), float(mass), int(n), DTYPE[dtype],
+                                   *[_vp(int(p)) if p else None for p in ptrs], args[0], args[1],
+                                   y.ctypes.data_as(_dp), _vp(int(stream)) if stream else None)
+    if st != M2M_OK:
+        msg = lib().m2m_last_error(None)
+        raise M2MError(st, "m2m_observe_noalloc", msg.decode() if msg else "")
+    return y[:J]

@@ -5,8 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -315,7 +317,9 @@ int seg_cap_of(int64_t n, int row_len) {
     return (int)cap;
 }
 
-WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64) {
+// cell_index = false: no per-particle cell index (observation only)
+WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64,
+              bool cell_index = true) {
     WsLayout w{};
     const size_t sz = f64 ? 8 : 4;
     w.J = num_obs(L);
@@ -356,7 +360,7 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.hist = take(8 * (size_t)kHistCap);
     w.chi2p = take(8 * (size_t)w.nbj);
     w.partials = take(8 * (size_t)w.seg_cap * (size_t)w.row_len);
-    w.cidx = take(2 * (size_t)n);
+    w.cidx = take(cell_index ? 2 * (size_t)n : 0);
     w.cdata = take(8 * (size_t)w.C);
     w.gprior = take(8 * (size_t)w.C);
     w.scf_rho = take(8 * (size_t)std::max(P.scf_nr, 1));
@@ -366,6 +370,95 @@ WsLayout plan(const m2m_obs_layout& L, const m2m_params& P, int64_t n, bool f64)
     w.sm_basis = take(P.smooth ? 8 * smooth_basis_len(P.n_E, P.n_x) : 8);
     w.total = o;
     return w;
+}
+
+// The observation part of a fit's description: the kernels' layout fields
+// and the workspace segments from b (contexts and the allocation-free
+// observation share it).
+void describe_obs(FitDev& f, const m2m_obs_layout& L, const WsLayout& w, unsigned char* b) {
+    const int n_int = radial_intervals(L);
+    f.n_r = n_int;
+    f.jk0 = dens_obs(L);
+    f.l_max = L.dens == M2M_DENS_ALM ? L.l_max : 0;
+    f.n_R = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
+    f.kin = L.kin;
+    f.nk = kin_per_annulus(L);
+    f.J = w.J;
+    f.n_v = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
+    f.gh_nmax = L.kin == M2M_KIN_GH ? L.gh_nmax : 0;
+    f.C = w.C;
+    f.lr0 = std::log2(L.r_min * L.r_min);
+    f.lrs = n_int / std::log2((L.r_max * L.r_max) / (L.r_min * L.r_min));
+    if (f.n_R > 0) {
+        f.lR0 = std::log2(L.R_min * L.R_min);
+        f.lRs = L.n_R / std::log2((L.R_max * L.R_max) / (L.R_min * L.R_min));
+    }
+    if (f.n_v > 0) {
+        f.vmin = L.v_min;
+        f.vidv = L.n_v / (L.v_max - L.v_min);
+    }
+    f.redge2 = b + w.redge2;
+    f.rmesh = b + w.rmesh;
+    f.Redge2 = b + w.Redge2;
+    f.vedge = b + w.vedge;
+    f.Vp = b + w.Vp;
+    f.isp = b + w.isp;
+    f.rp = b + w.rp;
+    f.Y = reinterpret_cast<double*>(b + w.Y);
+    f.sigma = reinterpret_cast<double*>(b + w.sigma);
+    f.yv = reinterpret_cast<double*>(b + w.yv);
+    f.ytil = reinterpret_cast<double*>(b + w.ytil);
+    f.delta = reinterpret_cast<double*>(b + w.delta);
+    f.obs_out = reinterpret_cast<double*>(b + w.obs);
+    f.partials = reinterpret_cast<double*>(b + w.partials);
+    f.row_len = w.row_len;
+    f.n_bin_jobs = w.nbj;
+    f.n_cell_jobs = w.ncj;
+    f.n_pot_jobs = w.npj;
+    f.chi2_hist = reinterpret_cast<double*>(b + w.hist);
+    f.chi2_part = reinterpret_cast<double*>(b + w.chi2p);
+    f.st = reinterpret_cast<FitState*>(b + w.st);
+}
+
+// The observation tables (bin edges, GH centres and inverse widths) in the
+// state type, written into img, the image of the workspace bytes
+// [w.redge2, w.rp). V, S: n_R GH centres and widths, or NULL for 0 and 1.
+template <typename T>
+void put_obs_tables_t(unsigned char* img, const WsLayout& w, const m2m_obs_layout& L,
+                      const double* V, const double* S) {
+    auto at = [&](size_t off) { return reinterpret_cast<T*>(img + (off - w.redge2)); };
+    std::memset(img, 0, w.rp - w.redge2);
+    const int n_int = radial_intervals(L);
+    const int nR = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
+    const int nv = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
+    T* re2 = at(w.redge2);
+    T* rm = at(w.rmesh);
+    for (int k = 0; k <= n_int; ++k) {
+        const double e = log_edge(L.r_min, L.r_max, n_int, k);
+        rm[k] = (T)e;
+        re2[k] = (T)(e * e);
+    }
+    T* Re2 = at(w.Redge2);
+    for (int k = 0; k <= nR; ++k) {
+        const double e = log_edge(L.R_min, L.R_max, L.n_R, k);
+        Re2[k] = (T)(e * e);
+    }
+    T* ve = at(w.vedge);
+    for (int k = 0; k <= nv; ++k) ve[k] = (T)lin_edge(L.v_min, L.v_max, L.n_v, k);
+    T* vp = at(w.Vp);
+    T* isp = at(w.isp);
+    for (int p = 0; p < std::max(nR, 1); ++p) {
+        vp[p] = (T)(V ? V[p] : 0.0);
+        isp[p] = (T)(1.0 / (S ? S[p] : 1.0));
+    }
+}
+
+void put_obs_tables(unsigned char* img, const WsLayout& w, const m2m_obs_layout& L, bool f64,
+                    const double* V, const double* S) {
+    if (f64)
+        put_obs_tables_t<double>(img, w, L, V, S);
+    else
+        put_obs_tables_t<float>(img, w, L, V, S);
 }
 
 }  // namespace
@@ -404,6 +497,9 @@ struct m2m_ctx {
 };
 
 namespace {
+
+// the calling thread's last failure of m2m_observe_noalloc (no context)
+thread_local char g_na_err[256];
 
 m2m_status fail(m2m_ctx* c, m2m_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -633,7 +729,7 @@ m2m_status m2m_get_launch(int32_t* block, int32_t* tiles_per_cu) {
 }
 
 const char* m2m_last_error(const m2m_ctx* ctx) {
-    if (!ctx) return "context is NULL";
+    if (!ctx) return g_na_err[0] ? g_na_err : "context is NULL";
     return ctx->err.c_str();
 }
 
@@ -711,47 +807,9 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.rs = hp.GM200 > 0 ? hp.rs : 1.0;
     f.phi0 = hp.phi(0.0);
     const m2m_obs_layout& L = c->lay;
-    const int n_int = radial_intervals(L);
-    f.n_r = n_int;
-    f.jk0 = dens_obs(L);
-    f.l_max = L.dens == M2M_DENS_ALM ? L.l_max : 0;
-    f.n_R = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
-    f.kin = L.kin;
-    f.nk = kin_per_annulus(L);
-    f.J = w.J;
-    f.n_v = L.kin == M2M_KIN_LOSVD ? L.n_v : 0;
-    f.gh_nmax = L.kin == M2M_KIN_GH ? L.gh_nmax : 0;
-    f.C = w.C;
-    f.lr0 = std::log2(L.r_min * L.r_min);
-    f.lrs = n_int / std::log2((L.r_max * L.r_max) / (L.r_min * L.r_min));
-    if (f.n_R > 0) {
-        f.lR0 = std::log2(L.R_min * L.R_min);
-        f.lRs = L.n_R / std::log2((L.R_max * L.R_max) / (L.R_min * L.R_min));
-    }
-    if (f.n_v > 0) {
-        f.vmin = L.v_min;
-        f.vidv = L.n_v / (L.v_max - L.v_min);
-    }
     unsigned char* b = c->ws;
-    f.redge2 = b + w.redge2;
-    f.rmesh = b + w.rmesh;
-    f.Redge2 = b + w.Redge2;
-    f.vedge = b + w.vedge;
-    f.Vp = b + w.Vp;
-    f.isp = b + w.isp;
-    f.rp = b + w.rp;
-    f.Y = reinterpret_cast<double*>(b + w.Y);
-    f.sigma = reinterpret_cast<double*>(b + w.sigma);
-    f.yv = reinterpret_cast<double*>(b + w.yv);
-    f.ytil = reinterpret_cast<double*>(b + w.ytil);
-    f.delta = reinterpret_cast<double*>(b + w.delta);
-    f.obs_out = reinterpret_cast<double*>(b + w.obs);
-    f.partials = reinterpret_cast<double*>(b + w.partials);
-    f.row_len = w.row_len;
+    describe_obs(f, L, w, b);
     f.kpriv = kpriv;
-    f.n_bin_jobs = w.nbj;
-    f.n_cell_jobs = w.ncj;
-    f.n_pot_jobs = w.npj;
     f.scf_nr = c->par.scf_nr;
     f.scf_lmax = c->par.scf_nr > 0 ? c->par.scf_lmax : 0;
     f.scf_every = std::max(c->par.scf_every, 1);
@@ -809,27 +867,12 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     f.foc_cs = c->par.entropy == M2M_S_GWR ? 1.0 : 0.0;
     f.foc_chi = c->par.eps * dt * f.w0;
     f.q = -std::expm1(-c->par.alpha * dt);
-    f.chi2_hist = reinterpret_cast<double*>(b + w.hist);
-    f.chi2_part = reinterpret_cast<double*>(b + w.chi2p);
-    f.st = reinterpret_cast<FitState*>(b + w.st);
     c->fd_dev = reinterpret_cast<FitDev*>(b + w.fd);
     c->st = f.st;
     c->tiles = reinterpret_cast<Tile*>(b + w.tiles);
     c->jobs = reinterpret_cast<FinJob*>(b + w.jobs);
 
     // ---- tables
-    // radial bin edges, or the a_lm mesh radii (n_int + 1 of both)
-    std::vector<double> re2(n_int + 1), rm(n_int + 1), Re2(f.n_R + 1), ve(f.n_v + 1, 0.0);
-    for (int k = 0; k <= n_int; ++k) {
-        const double e = log_edge(L.r_min, L.r_max, n_int, k);
-        rm[k] = e;
-        re2[k] = e * e;
-    }
-    for (int k = 0; k <= f.n_R; ++k) {
-        const double e = log_edge(L.R_min, L.R_max, L.n_R, k);
-        Re2[k] = e * e;
-    }
-    for (int k = 0; k <= f.n_v; ++k) ve[k] = lin_edge(L.v_min, L.v_max, L.n_v, k);
     std::vector<double> lct(kLcTable);
     const double phi0 = hp.phi(0.0);
     double guess = std::log(hp.a) + kLz0 * 0.5;  // small zeta: r_c ~ a sqrt(zeta)
@@ -844,10 +887,14 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
     c->sp.assign(std::max(f.n_R, 1), 1.0);
     m2m_status s = M2M_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(M2M_EDEVICE);
-    if ((s = upload(c, w.redge2, re2)) != M2M_OK) return bail(s);
-    if ((s = upload(c, w.rmesh, rm)) != M2M_OK) return bail(s);
-    if ((s = upload(c, w.Redge2, Re2)) != M2M_OK) return bail(s);
-    if ((s = upload(c, w.vedge, ve)) != M2M_OK) return bail(s);
+    {
+        // bin edges, the a_lm mesh radii and the GH tables, one image
+        std::vector<unsigned char> img(w.rp - w.redge2);
+        put_obs_tables(img.data(), w, L, c->f64, nullptr, nullptr);
+        if (copy_sync(c->stream, c->ws + w.redge2, img.data(), img.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return bail(M2M_EDEVICE);
+    }
     if ((s = upload(c, w.lctab, lct)) != M2M_OK) return bail(s);
     if (c->par.scf_nr > 0) {
         // nodes of the self-consistent potential, FP64
@@ -1659,3 +1706,135 @@ m2m_status m2m_batch_destroy(m2m_batch* b) {
 }
 
 }  // extern "C"
+
+// ================================================ allocation-free observe ==
+// The working memory of m2m_observe_noalloc: a static device array, one copy
+// per GPU at its own address. Host code never passes the array's name to a
+// kernel or a copy (on the host it stands for no device address): the
+// address is looked up once per device with hipGetSymbolAddress, with that
+// device current, and kept in g_na_ptr.
+static __device__ __align__(256) unsigned char scratch[M2M_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+constexpr size_t kNoAllocStage = (size_t)256 << 10;  // host image of the tables
+std::mutex g_na_mu;                        // one call at a time in a process
+void* g_na_ptr[kNoAllocDevices];           // address of `scratch` per device
+unsigned char g_na_stage[kNoAllocStage];   // staging of the tables (under g_na_mu)
+
+m2m_status na_fail(m2m_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_na_err, sizeof g_na_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+}  // namespace
+
+extern "C" m2m_status m2m_observe_noalloc(const m2m_obs_layout* layout, double mass, int64_t n,
+                                          int32_t dtype, const void* x, const void* y,
+                                          const void* z, const void* vx, const void* vy,
+                                          const void* vz, const void* u, const double* V_p,
+                                          const double* sigma_p, double* obs, void* hip_stream) {
+    g_na_err[0] = '\0';
+    if (!layout) return na_fail(M2M_EINVAL, "layout is NULL");
+    {
+        const std::string why = check_layout(layout);
+        if (!why.empty()) return na_fail(M2M_EINVAL, "%s", why.c_str());
+    }
+    if (!(is_fin(mass) && mass > 0)) return na_fail(M2M_EINVAL, "mass must be finite and > 0");
+    if (n < 1) return na_fail(M2M_EINVAL, "n must be >= 1");
+    if (dtype != M2M_F32 && dtype != M2M_F64) return na_fail(M2M_EINVAL, "unknown dtype");
+    const void* const ptrs[7] = {x, y, z, vx, vy, vz, u};
+    for (const void* q : ptrs)
+        if (!q || (reinterpret_cast<uintptr_t>(q) & 15u))
+            return na_fail(M2M_EINVAL, "particle arrays must be non-NULL and 16-byte aligned");
+    if (!obs) return na_fail(M2M_EINVAL, "obs is NULL");
+    const m2m_obs_layout& L = *layout;
+    const int nR = L.kin == M2M_KIN_NONE ? 0 : L.n_R;
+    if (L.kin == M2M_KIN_GH) {
+        if (!V_p || !sigma_p)
+            return na_fail(M2M_EINVAL, "Gauss-Hermite observables need V_p and sigma_p");
+        for (int q = 0; q < nR; ++q)
+            if (!is_fin(V_p[q]) || !is_fin(sigma_p[q]) || !(sigma_p[q] > 0))
+                return na_fail(M2M_EINVAL, "V_p, sigma_p must be finite with sigma_p > 0");
+    }
+    const bool f64 = dtype == M2M_F64;
+    // observation only: one prior cell, no smoothing, no self-consistent
+    // potential, no per-particle cell index
+    m2m_params P{};
+    P.mass = mass;
+    P.n_E = 1;
+    P.n_x = 1;
+    P.E_lo = -1.0;
+    P.E_hi = 0.0;
+    const WsLayout w = plan(L, P, n, f64, false);
+    if (w.total > (size_t)M2M_NOALLOC_SCRATCH_BYTES)
+        return na_fail(M2M_ENOMEM,
+                       "observation needs %zu bytes of working memory, more than the %zu bytes "
+                       "of the static scratch",
+                       w.total, (size_t)M2M_NOALLOC_SCRATCH_BYTES);
+    if (w.rp - w.redge2 > kNoAllocStage)
+        return na_fail(M2M_ENOMEM, "observation tables exceed the %zu-byte staging area",
+                       kNoAllocStage);
+    const int kpriv = g_kpriv_cap > 0 ? std::min(private_copies(f64, w.J), g_kpriv_cap)
+                                      : private_copies(f64, w.J);
+    const bool acc64 = f64 || g_deposit == M2M_DEPOSIT_F64;
+    const size_t lds = step_lds_bytes(f64, acc64, w.J, radial_intervals(L), nR,
+                                      L.kin == M2M_KIN_LOSVD ? L.n_v : 0, kpriv, w.C, 0, 0);
+    if (lds > max_lds()) return na_fail(M2M_EUNSUPPORTED, "the observable bins do not fit LDS");
+    const int block = f64 ? 256 : g_block;
+    const int kin = kin_class(L.kin, L.gh_nmax, L.dens, false);
+    // the tiles of a context of the same particle count (m2m_create)
+    const int n_tiles = std::max(1, std::min(w.seg_cap, std::max(1, g_tiles_per_cu * n_cus())));
+
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return na_fail(M2M_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return na_fail(M2M_EUNSUPPORTED, "device %d: at most %d devices", dev, kNoAllocDevices);
+    if (!g_na_ptr[dev]) {
+        void* q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return na_fail(M2M_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_na_ptr[dev] = q;
+    }
+    unsigned char* b = static_cast<unsigned char*>(g_na_ptr[dev]);
+
+    FitDev f{};
+    f.x = const_cast<void*>(x);
+    f.y = const_cast<void*>(y);
+    f.z = const_cast<void*>(z);
+    f.vx = const_cast<void*>(vx);
+    f.vy = const_cast<void*>(vy);
+    f.vz = const_cast<void*>(vz);
+    f.u = const_cast<void*>(u);
+    f.uh = const_cast<void*>(u);  // priors: never read when observing
+    f.n = n;
+    f.w0 = mass / (double)n;
+    f.a = 1.0;
+    f.rs = 1.0;
+    f.scf_every = 1;
+    f.n_E = 1;
+    f.n_x = 1;
+    f.cell_half = 1;
+    describe_obs(f, L, w, b);
+    f.kpriv = kpriv;
+    put_obs_tables(g_na_stage, w, L, f64, V_p, sigma_p);
+    // the fit's counters start at zero (the observation's ticket among them)
+    static const FitState zero_state{};
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if ((e = hipMemcpyAsync(b + w.st, &zero_state, sizeof(FitState), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(b + w.redge2, g_na_stage, w.rp - w.redge2, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = launch_step1(f64, acc64, block, kin, f, n_tiles, lds, kModeObserve, s)) != hipSuccess ||
+        (e = launch_finalize1(f64, f, n_tiles, kModeObserve, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(obs, b + w.obs, 8 * (size_t)w.J, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return na_fail(M2M_EDEVICE, "observation: %s", hipGetErrorString(e));
+    return M2M_OK;
+}

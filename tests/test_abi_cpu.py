@@ -108,3 +108,31 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "LIB", str(tmp_path / "libm2m.so"))
     with pytest.raises(ImportError, match="missing"):
         _abi.lib()
+
+
+def test_observe_noalloc_rejects_before_touching_memory():
+    """The allocation-free observation refuses bad arguments, and layouts and
+    particle counts beyond its static scratch, before any device call (the
+    addresses 4096... are never dereferenced)."""
+    from paper_1202_2355_amd import _abi
+    from workloads import workload
+    wl = workload(3)
+    fake = [4096 * (k + 1) for k in range(7)]
+    with pytest.raises(_abi.M2MError, match="16-byte aligned"):
+        _abi.m2m_observe_noalloc(wl.layout, 1.0, 100, "f32", fake[:6] + [0])
+    with pytest.raises(_abi.M2MError, match="mass"):
+        _abi.m2m_observe_noalloc(wl.layout, -1.0, 100, "f32", fake)
+    with pytest.raises(_abi.M2MError, match="n_r"):
+        _abi.m2m_observe_noalloc(dict(wl.layout, n_r=0), 1.0, 100, "f32", fake)
+    gh = workload(2)
+    with pytest.raises(_abi.M2MError, match="V_p and sigma_p"):
+        _abi.m2m_observe_noalloc(gh.layout, 1.0, 100, "f32", fake)
+    before = _abi.m2m_get_launch()
+    try:
+        # 4096 tile rows of 2612 doubles (86 MB) do not fit the 32 MiB scratch
+        _abi.m2m_set_launch(1024, 16)
+        with pytest.raises(_abi.M2MError, match="static scratch") as e:
+            _abi.m2m_observe_noalloc(wl.layout, 1.0, 8_000_000, "f32", fake)
+        assert e.value.status == _abi.M2M_ENOMEM
+    finally:
+        _abi.m2m_set_launch(*before)
