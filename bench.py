@@ -284,14 +284,47 @@ def run_serve(args, torch, rate=SERVE_RATE):
     model = lambda r: plummer_jeans_device(r.n, r.potential, r.seed, dtype=tdt)
     from paper_1202_2355_amd import tuning
     tuning.use("batch", args.state, base.layout)
-    srv = Server(datasets, hbm_budget=int(args.hbm_gb * 2 ** 30), max_fits=64,
-                 steps_per_launch=args.steps_per_launch, dtype=args.state, initial_model=model)
+    srv = Server(datasets, hbm_budget=int(args.hbm_gb * 2 ** 30), max_fits=args.max_fits,
+                 steps_per_launch=args.steps_per_launch, dtype=args.state, initial_model=model,
+                 preparers=args.preparers)
     # warm-up request (first graph capture, first allocations), not counted
     srv.run([Request(rid=-1, arrival=0.0, potential=base.potential, params=base.params,
                      layout=base.layout, n=100_000, steps=64, dataset=0, seed=1)])
     m = srv.run(reqs, realtime=True, log=sys.stderr)
     srv.close()
     return m
+
+
+def static_mix(torch, steps=128):
+    """The serving trace's first 64 requests admitted at once as one static
+    batch (the saturation reference of the server): whole-step particle-
+    steps/s over ``steps`` steps, after a device warm-up and 32 steps."""
+    from paper_1202_2355_amd import tuning
+    from paper_1202_2355_amd.autotune import losvd_mix_fits
+    from paper_1202_2355_amd.batch import Batch
+    from workloads import workload
+    tuning.use("batch", "f32", workload(3).layout)
+    fits, _, _ = losvd_mix_fits(64)
+    n = sum(f.n for f in fits)
+    b = Batch(max_fits=len(fits))
+    for f in fits:
+        if not b.admit(f, steps + 64):
+            raise RuntimeError("static mix: admission failed")
+    prewarm_device(torch)
+    b.run(32)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.run(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for f in fits:
+        b.cancel(f)
+        f.close()
+    b.close()
+    return {"fits": len(fits), "particles": n, "us_per_step": 1e3 * ms,
+            "particle_steps_per_s": n / (ms * 1e-3)}
 
 
 def parser() -> argparse.ArgumentParser:
@@ -305,9 +338,14 @@ def parser() -> argparse.ArgumentParser:
                     help="workload 4: step the batch as 1 or 2 overlapping groups "
                          "(default: the library's choice)")
     ap.add_argument("--requests", type=int, default=500, help="workload 5: trace length")
+    ap.add_argument("--rate", type=float, default=SERVE_RATE,
+                    help="workload 5: arrival rate of the trace (requests/s)")
     ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
     ap.add_argument("--steps-per-launch", type=int, default=64)
+    ap.add_argument("--max-fits", type=int, default=64, help="workload 5: batch slots")
+    ap.add_argument("--preparers", type=int, default=4,
+                    help="workload 5: threads preparing requests side by side")
     ap.add_argument("--sweep", default="", metavar="RATES",
                     help="workload 5: also serve the same trace at these arrival rates "
                          "(comma-separated, requests/s): the saturation sweep")
@@ -335,13 +373,19 @@ def main(argv=None):
               "single-GPU build", file=sys.stderr)
         return 2
 
+    if args.workload == 5:
+        # the preparing threads' streams get hardware queues of their own
+        # instead of queueing behind the batch's enqueued runs (read when HIP
+        # starts, i.e. before torch touches the GPU)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     import torch
     from paper_1202_2355_amd import _abi, tuning
     from paper_1202_2355_amd.fit import Fit
     from workloads import workload
 
     if args.workload == 5:
-        m = run_serve(args, torch)
+        m = run_serve(args, torch, rate=args.rate)
+        ref = static_mix(torch) if args.sweep else None
         sweep = []
         for rate in [float(x) for x in args.sweep.split(",") if x.strip()]:
             ms = run_serve(args, torch, rate=rate)
@@ -355,12 +399,13 @@ def main(argv=None):
                "steps": None, "warmup": None, "ms_per_step": None, "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": args.state, "data": "synthetic",
                "config": {"workload": "serve_losvd", "requests": m["requests"],
-                          "arrival_rate_per_s": SERVE_RATE, "hbm_budget_gb": args.hbm_gb,
-                          "steps_per_launch": args.steps_per_launch,
+                          "arrival_rate_per_s": args.rate, "hbm_budget_gb": args.hbm_gb,
+                          "steps_per_launch": args.steps_per_launch, "preparers": args.preparers,
+                          "max_fits": args.max_fits,
                           "launch": tuning.current()},
                "latency": {"p50_s": m["p50_latency_s"], "p99_s": m["p99_latency_s"],
                            "mean_s": m["mean_latency_s"]},
-               **({"sweep": sweep} if sweep else {}),
+               **({"sweep": sweep, "static_batch": ref} if sweep else {}),
                "roofline": None, "cpu_baseline": None}
         print(json.dumps(out), flush=True)
         return 0

@@ -413,13 +413,19 @@ int32_t m2m_get_deposit_mode(void);
  * Many fits of uneven size stepping together. A batch of two or more fits is
  * split into two groups of about equal particle count; every step of a group
  * runs one fused kernel over the tiles of its fits (tiles never straddle
- * fits) and one finalize kernel, replayed from a captured HIP graph on a
- * stream of the group's own, so that one group's finalize overlaps the other
- * group's streaming. The groups start after the work already enqueued on the
- * batch stream, and the batch stream continues only after both (events), so
- * to the caller the steps are ordered on the batch stream. Each fit's result
- * equals the fit run alone up to the rounding of its in-tile sums. Fits keep
- * their own streams for set-up. */
+ * fits) and one finalize kernel, launched directly (or replayed from captured
+ * HIP graphs, m2m_set_batch_graphs) on a stream of the group's own, so that
+ * one group's finalize overlaps the other group's streaming. The groups
+ * start after the work already enqueued on the batch stream, and the batch
+ * stream continues only after both (events), so to the caller the steps are
+ * ordered on the batch stream. Each fit's result equals the fit run alone up
+ * to the rounding of its in-tile sums. Fits keep their own streams for
+ * set-up. When fits come or go, the next run copies the new fit, tile and
+ * finalize tables on the batch stream, after the runs already enqueued and
+ * without waiting for them (with graphs: after waiting for them). A fit
+ * leaves the batch when a poll hands it back or it is cancelled; the work
+ * on its own stream that changes its state then waits for the batch runs
+ * enqueued before (they may still read it), and m2m_destroy waits for them. */
 
 /* hbm_budget: bytes of particle state plus workspace the batch may hold
  * (0 = no limit). max_fits >= 1. */
@@ -436,6 +442,16 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch);
  * *n_active (may be NULL) the number still running. */
 m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_t* n_done,
                           int32_t* n_active);
+/* The same without draining the batch, for a loop that keeps the GPU busy:
+ * every m2m_batch_run ends with a snapshot of the fits' completion flags on
+ * the batch stream; this call waits only for the snapshot of the run before
+ * the latest one (not yet read by an earlier call) and hands back up to
+ * max_done fits that had run all their steps by then, while the latest run
+ * may still execute. With no such snapshot it returns at once (*n_done = 0).
+ * A fit handed back keeps its weights from its last step; reading them
+ * (m2m_get_weights) does not wait for the batch. */
+m2m_status m2m_batch_poll_lagged(m2m_batch* b, m2m_ctx** done, int32_t max_done,
+                                 int32_t* n_done, int32_t* n_active);
 /* Timing of the batch's kernels by HIP events on the batch stream: n_steps
  * (1..256) batched steps launched one kernel at a time (no graph), each step
  * kernel between two events. ms_step is the mean time between those two

@@ -101,6 +101,7 @@ SIGNATURES = {
     "m2m_batch_admit": (_st, [_vp, _vp, _i32]),
     "m2m_batch_run": (_st, [_vp, _i32]),
     "m2m_batch_poll": (_st, [_vp, C.POINTER(_vp), _i32, C.POINTER(_i32), C.POINTER(_i32)]),
+    "m2m_batch_poll_lagged": (_st, [_vp, C.POINTER(_vp), _i32, C.POINTER(_i32), C.POINTER(_i32)]),
     "m2m_batch_footprint": (C.c_size_t, [_vp]),
     "m2m_batch_profile": (_st, [_vp, _i32, _dp, _dp]),
     "m2m_batch_particles": (C.c_int64, [_vp]),

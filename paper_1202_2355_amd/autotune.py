@@ -11,7 +11,8 @@ whole M2M steps (step and finalize kernels, graph replays, HIP events on the
 fit's or batch's stream) on fresh contexts over the same particles.
 
     python -m paper_1202_2355_amd.autotune --workload 2 [--write]
-    python -m paper_1202_2355_amd.autotune --workload 4 [--write]
+    python -m paper_1202_2355_amd.autotune --workload 4 [--write]   (the Gauss-Hermite batch)
+    python -m paper_1202_2355_amd.autotune --workload 5 [--write]   (the serving mix, LOSVD)
 """
 
 from __future__ import annotations
@@ -28,6 +29,10 @@ from . import tuning
 from .fit import Fit
 
 BLOCKS = (256, 512, 1024)
+# in the second stage of a search, an option (graphs, private copies, deposit
+# mode) replaces the best only if it is faster by more than this fraction:
+# smaller differences are timing noise, and the defaults are the simpler path
+MARGIN = 0.005
 TILES_PER_CU = (1, 2, 4, 8)
 BATCH_TILES_PER_CU = (4, 6, 8, 12, 16)
 PRIVATE = (0, 1, 2, 4)
@@ -83,7 +88,7 @@ def search(make_fit, dtype="f32", steps=64, log=sys.stderr, base=None):
         if _fmt(p) in res:
             continue
         ms = trial(p)
-        if ms < best_ms:
+        if ms < best_ms * (1.0 - MARGIN):
             best, best_ms = p, ms
     return best, res
 
@@ -114,9 +119,22 @@ def time_batch(fits, params, steps=40, warmup=16):
     return ms
 
 
+def _warm_device(ms=300.0):
+    """Device copies for ``ms`` milliseconds, so that the first candidates
+    are not timed while the GPU's clocks still ramp up after host idle."""
+    a = torch.empty(1 << 26, device="cuda")
+    b = torch.empty_like(a)
+    t = time.time()
+    while (time.time() - t) * 1e3 < ms:
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+
 def search_batch(fits, steps=40, log=sys.stderr, base=None):
     """The best batch parameters; returns (params, {description: ms})."""
     base = dict(tuning.DEFAULT, **(base or {}))
+    _warm_device()
     res = {}
     best, best_ms = None, float("inf")
     for b, t, g in itertools.product(BLOCKS, BATCH_TILES_PER_CU, (1, 2)):
@@ -136,7 +154,7 @@ def search_batch(fits, steps=40, log=sys.stderr, base=None):
         res[_fmt(p)] = ms
         if log:
             print(f"[autotune] batch {_fmt(p)}: {1e3 * ms:.2f} us/step", file=log, flush=True)
-        if ms < best_ms:
+        if ms < best_ms * (1.0 - MARGIN):
             best, best_ms = p, ms
     return best, res
 
@@ -156,7 +174,7 @@ def main(argv=None):
                          "of 32; 40 for a batch, five graphs of 8)")
     ap.add_argument("--write", action="store_true", help="store the pick in the package's table")
     args = ap.parse_args(argv)
-    if args.workload == 4:
+    if args.workload in (4, 5):
         args.steps = args.steps or 40
         return main_batch(args)
     args.steps = args.steps or 64
@@ -187,12 +205,11 @@ def main(argv=None):
                       f"autotune.py --workload {args.workload} (workload {wl.name}) on an MI355X")
 
 
-def main_batch(args):
+def _gh_batch_fits():
     """The 64-fit batch of uneven sizes (device-drawn models and targets)."""
     from workloads import make_targets
     from workloads.configs import batch_fits
     from workloads.device import om_model_device
-    t0 = time.time()
     fits = []
     wls = batch_fits(64)
     for wl in wls:
@@ -204,16 +221,50 @@ def main_batch(args):
         f = Fit(wl.potential, wl.layout, wl.params, ic, dtype="f32")
         f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
         fits.append(f)
-    print(f"[autotune] batch of {len(fits)} fits, {sum(f.n for f in fits)} particles: inputs "
+    return fits, wls[0].layout, "batch64_gh"
+
+
+def losvd_mix_fits(n_fits=64):
+    """The first requests of the serving trace admitted at once: LOSVD
+    layout, per-request potentials, Plummer initial models, one data set."""
+    import numpy as np
+    from workloads import add_noise, floor_model_noise, workload
+    from workloads.configs import serve_trace
+    from workloads.device import om_model_device, plummer_jeans_device
+    base = workload(3)
+    tp = om_model_device(1 << 22, base.potential, base.target_ra, seed=base.seed * 10 + 2)
+    tf = Fit(base.potential, base.layout, base.params, tp, dtype="f32")
+    Y_true = tf.observe()
+    tf.close()
+    del tp
+    Y, sig = add_noise(Y_true, base.layout, 0.02, np.random.Generator(np.random.Philox(key=51)))
+    sig = floor_model_noise(Y_true, sig, 100_000)
+    _, wls = serve_trace(n_requests=n_fits, state="f32")
+    fits = []
+    for w in wls:
+        parts = plummer_jeans_device(w.N, w.potential, w.seed, dtype=torch.float32)
+        f = Fit(w.potential, w.layout, w.params, parts, dtype="f32")
+        f.set_targets(Y, sig)
+        fits.append(f)
+    return fits, base.layout, "serve_losvd_mix64"
+
+
+def main_batch(args):
+    """Workload 4: the 64-fit Gauss-Hermite batch; workload 5: the first 64
+    requests of the serving trace (LOSVD) as one static batch."""
+    t0 = time.time()
+    fits, layout, name = _gh_batch_fits() if args.workload == 4 else losvd_mix_fits()
+    print(f"[autotune] {name}: {len(fits)} fits, {sum(f.n for f in fits)} particles: inputs "
           f"ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     best, res = search_batch(fits, steps=args.steps)
-    key = tuning.class_key("batch", "f32", wls[0].layout)
-    out = {"class": key, "workload": "batch64_gh", "best": best,
+    key = tuning.class_key("batch", "f32", layout)
+    out = {"class": key, "workload": name, "best": best,
            "us_per_step": 1e3 * res[_fmt(best)], "all": {k: 1e3 * v for k, v in res.items()}}
     print(json.dumps(out))
     if args.write:
         tuning.record(key, best, out["us_per_step"],
-                      "autotune.py --workload 4 (the 64-fit batch) on an MI355X")
+                      f"autotune.py --workload {args.workload} ({name}, {args.steps} steps per "
+                      "candidate) on an MI355X")
     for f in fits:
         f.close()
 

@@ -1,6 +1,6 @@
-"""Many fits stepping together (``m2m_batch_*``): one fused step kernel over
-the tiles of every admitted fit and one finalize kernel per step, replayed
-from a captured HIP graph."""
+"""Many fits stepping together (``m2m_batch_*``): per step one fused step
+kernel over the tiles of the admitted fits and one finalize kernel, in two
+overlapping groups of fits on streams of their own."""
 
 from __future__ import annotations
 
@@ -36,16 +36,26 @@ class Batch:
     def run(self, steps_per_launch: int):
         A.check(A.lib().m2m_batch_run(self.h, int(steps_per_launch)), "m2m_batch_run")
 
-    def poll(self):
-        """(finished fits, number still active); synchronizes."""
+    def _poll(self, fn, where):
         cap = max(1, len(self.by_ctx))
         arr = (C.c_void_p * cap)()
         nd, na = C.c_int32(), C.c_int32()
-        st = A.lib().m2m_batch_poll(self.h, arr, cap, C.byref(nd), C.byref(na))
+        st = fn(self.h, arr, cap, C.byref(nd), C.byref(na))
         done = [self.by_ctx.pop(arr[i]) for i in range(nd.value)]
         if st != A.M2M_OK:
-            raise A.M2MError(st, "m2m_batch_poll")
+            raise A.M2MError(st, where)
         return done, na.value
+
+    def poll(self):
+        """(finished fits, number still active); synchronizes."""
+        return self._poll(A.lib().m2m_batch_poll, "m2m_batch_poll")
+
+    def poll_lagged(self):
+        """(fits finished by the end of the run before the latest, number
+        still in the batch); waits only for that earlier run, so the latest
+        run keeps the GPU busy while the caller retires fits and admits new
+        ones."""
+        return self._poll(A.lib().m2m_batch_poll_lagged, "m2m_batch_poll_lagged")
 
     def cancel(self, fit):
         A.check(A.lib().m2m_batch_cancel(self.h, fit.ctx), "m2m_batch_cancel")

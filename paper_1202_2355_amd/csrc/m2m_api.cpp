@@ -493,6 +493,16 @@ struct m2m_ctx {
     std::vector<double> Vp, sp;  // current Gauss-Hermite centres (host)
     hipGraphExec_t graph = nullptr;
     m2m_batch* batch = nullptr;
+    // set when the fit leaves a batch: recorded on the batch stream after the
+    // last run that may still read the fit (its tiles skip an idle fit, but
+    // they read its counters); the fit's own work that changes its state
+    // waits for it first
+    hipEvent_t idle_ev = nullptr;
+    bool idle_pending = false;
+    // false while no step can have left a prior assignment pending (a new
+    // context, or one just flushed): flush_assign then reads nothing back
+    bool may_assign = false;
+    hipEvent_t own_ev = nullptr;  // the fit's own work, which a batch waits for at admission
     std::string err;
 };
 
@@ -571,6 +581,16 @@ m2m_status sync(m2m_ctx* c) {
     return M2M_OK;
 }
 
+// Work that changes the fit's state waits (on the device) for the batch
+// runs that may still read it after it left a batch.
+m2m_status after_batch(m2m_ctx* c) {
+    if (c->idle_pending) {
+        M2M_HIP(c, hipStreamWaitEvent(c->stream, c->idle_ev, 0));
+        c->idle_pending = false;
+    }
+    return M2M_OK;
+}
+
 m2m_status read_state(m2m_ctx* c, FitState& s) {
     M2M_HIP(c, hipStreamSynchronize(c->stream));
     M2M_HIP(c, copy_sync(c->stream, &s, c->st, sizeof(FitState), hipMemcpyDeviceToHost));
@@ -579,13 +599,15 @@ m2m_status read_state(m2m_ctx* c, FitState& s) {
 
 // Assign cell priors computed by the last refresh, if still pending.
 m2m_status flush_assign(m2m_ctx* c) {
+    if (!c->may_assign) return M2M_OK;
     FitState s{};
     m2m_status r = read_state(c, s);
     if (r != M2M_OK) return r;
     if (s.assign_pending) {
         M2M_HIP(c, launch_assign(c->f64, c->fd_dev, c->tiles, c->n_tiles, c->stream));
-        return sync(c);
+        if ((r = sync(c)) != M2M_OK) return r;
     }
+    c->may_assign = false;
     return M2M_OK;
 }
 
@@ -935,6 +957,7 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
                            const double* V_p, const double* sigma_p) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     if (J != c->w.J) return fail(c, M2M_EINVAL, "J does not match the layout");
     if (!Y || !sigma) return fail(c, M2M_EINVAL, "Y and sigma are required");
     for (int j = 0; j < J; ++j)
@@ -973,9 +996,11 @@ m2m_status m2m_set_targets(m2m_ctx* c, int32_t J, const double* Y, const double*
 m2m_status m2m_step(m2m_ctx* c, int32_t n_steps, int32_t correct) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
     if (n_steps < 0) return fail(c, M2M_EINVAL, "n_steps must be >= 0");
     if (n_steps == 0) return M2M_OK;
+    c->may_assign = true;
     M2M_HIP(c, launch_poke(c->st, n_steps, correct ? 1 : 0, c->stream));
     const int full = n_steps / kGraphSteps, rem = n_steps % kGraphSteps;
     if (full > 0) {
@@ -992,6 +1017,7 @@ m2m_status m2m_step(m2m_ctx* c, int32_t n_steps, int32_t correct) {
 m2m_status m2m_refresh_potential(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     if (c->par.scf_nr <= 0) return fail(c, M2M_EINVAL, "the fit has no self-consistent potential");
     return refresh_potential(c);
 }
@@ -1011,7 +1037,9 @@ m2m_status m2m_get_potential(m2m_ctx* c, double* out, int32_t max) {
 m2m_status m2m_update_priors(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     if (c->par.entropy != M2M_S_MPR) return fail(c, M2M_EINVAL, "moving priors need M2M_S_MPR");
+    c->may_assign = true;
     M2M_HIP(c, launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
                            kModeCells, c->stream));
     M2M_HIP(c, launch_finalize1(c->f64, c->fd, c->n_tiles, kModeCells, c->stream));
@@ -1080,6 +1108,7 @@ m2m_status m2m_get_chi2_history(m2m_ctx* c, double* out, int32_t max, int32_t* n
 m2m_status m2m_observe(m2m_ctx* c, const double* V_p, const double* sigma_p, double* y) {
     if (!c || !y) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     const bool tmp = c->lay.kin == M2M_KIN_GH && V_p && sigma_p;
     m2m_status s = sync(c);
     if (s != M2M_OK) return s;
@@ -1157,6 +1186,7 @@ m2m_status m2m_get_state(m2m_ctx* c, void* host_blob, size_t* bytes) {
 m2m_status m2m_set_state(m2m_ctx* c, const void* host_blob, size_t bytes) {
     if (!c || !host_blob) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     size_t need = 0;
     m2m_get_state(c, nullptr, &need);
     if (bytes < need) return fail(c, M2M_EINVAL, "state blob too small");
@@ -1211,7 +1241,9 @@ m2m_status m2m_profile_step(m2m_ctx* c, int32_t n_steps, int32_t correct, double
     if (!c) return M2M_EINVAL;
     if (n_steps < 1 || n_steps > kProfileMax) return fail(c, M2M_EINVAL, "n_steps out of range");
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
+    if (m2m_status w_ = after_batch(c); w_ != M2M_OK) return w_;
     if (!c->targets) return fail(c, M2M_ESTATE, "set targets first");
+    c->may_assign = true;
     m2m_status st = ensure_graph(c);
     if (st == M2M_OK) st = ensure_prof_graph(c);
     if (st != M2M_OK) return st;
@@ -1261,6 +1293,12 @@ m2m_status m2m_destroy(m2m_ctx* c) {
     if (!c) return M2M_EINVAL;
     if (c->batch) return fail(c, M2M_ESTATE, "fit is in a batch");
     (void)hipStreamSynchronize(c->stream);
+    if (c->idle_ev) {
+        // the batch runs that may still read the fit have ended
+        (void)hipEventSynchronize(c->idle_ev);
+        (void)hipEventDestroy(c->idle_ev);
+    }
+    if (c->own_ev) (void)hipEventDestroy(c->own_ev);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->graph_prof) (void)hipGraphExecDestroy(c->graph_prof);
     if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -1286,6 +1324,13 @@ struct LaunchSet {
     hipGraphExec_t graph = nullptr;   // kBatchGraphSteps steps
     hipStream_t stream = nullptr;  // groups: the stream the group's steps run on
     hipEvent_t done = nullptr;     // groups: the group's steps of a run call have ended
+    // pinned host staging of the tables, two slots in turn: a rebuild copies
+    // from one on the batch stream without waiting for the runs before it,
+    // and a slot is rewritten only once its copies (two rebuilds back) ended
+    unsigned char* stage[2] = {nullptr, nullptr};
+    size_t stage_cap[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage_slot = 0;
 };
 
 struct m2m_batch {
@@ -1306,7 +1351,15 @@ struct m2m_batch {
     int n_groups = 1;
     hipEvent_t start = nullptr;  // work before a run call, which the groups wait for
     int32_t* gather_dev = nullptr;
-    int32_t* gather_host = nullptr;
+    int32_t* gather_host = nullptr;  // pinned: the synchronous poll's flags, then two snapshots
+    // completion snapshots, taken at the end of every run in two slots in
+    // turn: the flags of the fits then in the batch (snap_fits; an entry
+    // becomes NULL when its fit leaves the batch), and the event after them
+    int32_t* snap_host[2] = {nullptr, nullptr};
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
+    std::vector<m2m_ctx*> snap_fits[2];
+    int64_t runs = 0;       // runs enqueued
+    int64_t consumed = -1;  // last run whose snapshot a lagged poll has read
     int block = 256, kin = -1;
     bool acc64 = true;
     bool smooth = false;  // some fit smooths its prior grid
@@ -1342,6 +1395,13 @@ hipError_t batch_step(const m2m_batch* b, const LaunchSet& L, bool f64, hipStrea
 
 void free_set(LaunchSet& L) {
     if (L.graph) (void)hipGraphExecDestroy(L.graph);
+    for (int k = 0; k < 2; ++k) {
+        if (L.stage_ev[k]) (void)hipEventDestroy(L.stage_ev[k]);
+        if (L.stage[k]) (void)hipHostFree(L.stage[k]);
+        L.stage_ev[k] = nullptr;
+        L.stage[k] = nullptr;
+        L.stage_cap[k] = 0;
+    }
 
     if (L.fits_dev) (void)hipFree(L.fits_dev);
     if (L.tiles_dev) (void)hipFree(L.tiles_dev);
@@ -1396,14 +1456,42 @@ m2m_status fill_set(m2m_batch* b, LaunchSet& L, const std::vector<int>& members,
             fin_jobs(c->w, (int)f, cnts[f], jb);
         lds = std::max(lds, c->lds);
     }
-    if (grow(reinterpret_cast<void**>(&L.fits_dev), &L.cap_fits, sizeof(FitDev) * fd.size()) != hipSuccess ||
-        grow(reinterpret_cast<void**>(&L.tiles_dev), &L.cap_tiles, sizeof(Tile) * tl.size()) != hipSuccess ||
-        grow(reinterpret_cast<void**>(&L.jobs_dev), &L.cap_jobs, sizeof(FinJob) * jb.size()) != hipSuccess)
-        return M2M_ENOMEM;
-    if (hipMemcpyAsync(L.fits_dev, fd.data(), sizeof(FitDev) * fd.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(L.tiles_dev, tl.data(), sizeof(Tile) * tl.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(L.jobs_dev, jb.data(), sizeof(FinJob) * jb.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipStreamSynchronize(b->stream) != hipSuccess)
+    const size_t bf = sizeof(FitDev) * fd.size(), bt = sizeof(Tile) * tl.size(),
+                 bj = sizeof(FinJob) * jb.size();
+    if (bf > L.cap_fits || bt > L.cap_tiles || bj > L.cap_jobs) {
+        // larger device tables (rare): the old ones are freed only after
+        // every run that reads them has ended (the groups' work joins the
+        // batch stream at the end of every run)
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+        if (grow(reinterpret_cast<void**>(&L.fits_dev), &L.cap_fits, bf) != hipSuccess ||
+            grow(reinterpret_cast<void**>(&L.tiles_dev), &L.cap_tiles, bt) != hipSuccess ||
+            grow(reinterpret_cast<void**>(&L.jobs_dev), &L.cap_jobs, bj) != hipSuccess)
+            return M2M_ENOMEM;
+    }
+    // the tables through a pinned staging slot, copied on the batch stream:
+    // after the runs already enqueued (which still read the old tables) and
+    // before the next one, without the host waiting for either
+    const int sl = L.stage_slot;
+    L.stage_slot ^= 1;
+    if (L.stage_ev[sl] && hipEventSynchronize(L.stage_ev[sl]) != hipSuccess) return M2M_EDEVICE;
+    if (!L.stage_ev[sl] && hipEventCreateWithFlags(&L.stage_ev[sl], hipEventDisableTiming) != hipSuccess)
+        return M2M_EDEVICE;
+    if (bf + bt + bj > L.stage_cap[sl]) {
+        if (L.stage[sl]) (void)hipHostFree(L.stage[sl]);
+        L.stage[sl] = nullptr;
+        const size_t cap = std::max(bf + bt + bj, 2 * L.stage_cap[sl]);
+        L.stage_cap[sl] = 0;
+        if (hipHostMalloc(reinterpret_cast<void**>(&L.stage[sl]), cap, 0) != hipSuccess) return M2M_ENOMEM;
+        L.stage_cap[sl] = cap;
+    }
+    unsigned char* st = L.stage[sl];
+    std::memcpy(st, fd.data(), bf);
+    std::memcpy(st + bf, tl.data(), bt);
+    std::memcpy(st + bf + bt, jb.data(), bj);
+    if (hipMemcpyAsync(L.fits_dev, st, bf, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(L.tiles_dev, st + bf, bt, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(L.jobs_dev, st + bf + bt, bj, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipEventRecord(L.stage_ev[sl], b->stream) != hipSuccess)
         return M2M_EDEVICE;
     L.n_tiles = (int)tl.size();
     L.n_jobs = (int)jb.size();
@@ -1423,9 +1511,11 @@ m2m_status fill_set(m2m_batch* b, LaunchSet& L, const std::vector<int>& members,
 }
 
 m2m_status rebuild(m2m_batch* b) {
-    // launches in flight may still read the old tables and graphs (the
-    // groups' work is joined to the batch stream at the end of every run)
-    if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
+    // graphs in flight cannot be replaced under them: with graphs, wait for
+    // the runs enqueued (the groups' work joins the batch stream at the end
+    // of every run); without, the new tables are copied in stream order
+    const bool graphs = b->all.graph || b->grp[0].graph || b->grp[1].graph || g_batch_graphs;
+    if (graphs && hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
     const int nf = (int)b->fits.size();
     b->n_groups = nf >= 2 ? g_groups : 1;
     if (nf == 0) {
@@ -1481,6 +1571,69 @@ hipError_t run_set(const m2m_batch* b, const LaunchSet& L, int steps, hipStream_
     return e;
 }
 
+// The fit leaves the batch: its idle event is recorded after every run
+// enqueued so far (the last of them may still read it), and the snapshots
+// forget it, so that no later poll reads the context.
+hipError_t retire(m2m_batch* b, m2m_ctx* c) {
+    c->batch = nullptr;
+    c->may_assign = true;  // its batched steps may have refreshed the priors
+    for (auto& v : b->snap_fits)
+        for (m2m_ctx*& x : v)
+            if (x == c) x = nullptr;
+    hipError_t e = hipSuccess;
+    if (!c->idle_ev) e = hipEventCreateWithFlags(&c->idle_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(c->idle_ev, b->stream);
+    c->idle_pending = e == hipSuccess;
+    return e;
+}
+
+// The completion flags of the fits in the batch, taken on the batch stream
+// at the end of a run into the run's snapshot slot.
+hipError_t snapshot(m2m_batch* b) {
+    const int nf = (int)b->fits.size();
+    const int sl = (int)(b->runs & 1);
+    hipError_t e = hipSuccess;
+    if (nf > 0) {
+        e = launch_gather(b->all.fits_dev, nf, b->gather_dev, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->snap_host[sl], b->gather_dev, sizeof(int32_t) * 2 * nf,
+                               hipMemcpyDeviceToHost, b->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->snap_ev[sl], b->stream);
+    b->snap_fits[sl] = b->fits;
+    ++b->runs;
+    return e;
+}
+
+// Hands back up to max_done of `fits` that have no steps left by their flags
+// (steps left and error bits, two per fit; NULL entries and fits no longer
+// in the batch are skipped) and takes them out of the batch.
+m2m_status collect(m2m_batch* b, const std::vector<m2m_ctx*>& fits, const int32_t* flags,
+                   m2m_ctx** done, int32_t max_done, int32_t* n_done) {
+    std::vector<m2m_ctx*> gone;
+    bool bad = false;
+    for (size_t f = 0; f < fits.size() && *n_done < max_done; ++f) {
+        m2m_ctx* c = fits[f];
+        if (!c || c->batch != b || flags[2 * f] > 0) continue;
+        done[(*n_done)++] = c;
+        gone.push_back(c);
+        if (flags[2 * f + 1] & 1) {
+            c->err = "chi^2 became non-finite";
+            bad = true;
+        }
+    }
+    bool dev = false;
+    for (m2m_ctx* c : gone) {
+        b->fits.erase(std::find(b->fits.begin(), b->fits.end(), c));
+        if (retire(b, c) != hipSuccess) dev = true;
+    }
+    if (!gone.empty()) {
+        b->dirty = true;
+        if (b->fits.empty()) b->f64 = -1;
+    }
+    return dev ? M2M_EDEVICE : (bad ? M2M_ENONFINITE : M2M_OK);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1501,7 +1654,11 @@ m2m_status m2m_batch_create(int32_t max_fits, size_t hbm_budget, void* hip_strea
         ok = hipStreamCreateWithFlags(&b->grp[g].stream, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&b->grp[g].done, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipMalloc(reinterpret_cast<void**>(&b->gather_dev), sizeof(int32_t) * 2 * (size_t)max_fits) == hipSuccess &&
-         hipHostMalloc(reinterpret_cast<void**>(&b->gather_host), sizeof(int32_t) * 2 * (size_t)max_fits, 0) == hipSuccess;
+         hipHostMalloc(reinterpret_cast<void**>(&b->gather_host), sizeof(int32_t) * 6 * (size_t)max_fits, 0) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k) {
+        b->snap_host[k] = b->gather_host + 2 * (size_t)max_fits * (k + 1);
+        ok = hipEventCreateWithFlags(&b->snap_ev[k], hipEventDisableTiming) == hipSuccess;
+    }
     if (!ok) {
         (void)m2m_batch_destroy(b);
         return M2M_EDEVICE;
@@ -1528,8 +1685,14 @@ m2m_status m2m_batch_admit(m2m_batch* b, m2m_ctx* c, int32_t n_steps) {
     if ((int)b->fits.size() >= b->max_fits) return fail(c, M2M_ENOMEM, "batch is full");
     if (b->budget && m2m_batch_footprint(b) + footprint(c) > b->budget)
         return fail(c, M2M_ENOMEM, "fit does not fit the HBM budget");
-    m2m_status s = flush_assign(c);  // also waits for the fit's own stream
+    m2m_status s = after_batch(c);
     if (s != M2M_OK) return s;
+    if ((s = flush_assign(c)) != M2M_OK) return s;
+    // the batch stream waits for the fit's own work (its creation, targets,
+    // steps) on the device; the host does not wait
+    if (!c->own_ev) M2M_HIP(c, hipEventCreateWithFlags(&c->own_ev, hipEventDisableTiming));
+    M2M_HIP(c, hipEventRecord(c->own_ev, c->stream));
+    M2M_HIP(c, hipStreamWaitEvent(b->stream, c->own_ev, 0));
     M2M_HIP(c, launch_poke(c->st, n_steps, 1, b->stream));
     b->f64 = c->f64 ? 1 : 0;
     b->kin = c->kin;
@@ -1546,8 +1709,11 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
         if (s != M2M_OK) return s;
     }
     if (b->fits.empty() || steps_per_launch == 0) return M2M_OK;
-    if (b->n_groups == 1)
-        return run_set(b, b->all, steps_per_launch, b->stream) == hipSuccess ? M2M_OK : M2M_EDEVICE;
+    if (b->n_groups == 1) {
+        hipError_t e = run_set(b, b->all, steps_per_launch, b->stream);
+        if (e == hipSuccess) e = snapshot(b);
+        return e == hipSuccess ? M2M_OK : M2M_EDEVICE;
+    }
     // the groups start after the work already on the batch stream, and the
     // batch stream continues after both; their steps are enqueued in turn
     // (step k of every group, then step k + 1), as the runtime blocks the
@@ -1568,6 +1734,7 @@ m2m_status m2m_batch_run(m2m_batch* b, int32_t steps_per_launch) {
         e = hipEventRecord(b->grp[g].done, b->grp[g].stream);
     for (int g = 0; g < b->n_groups && e == hipSuccess; ++g)
         e = hipStreamWaitEvent(b->stream, b->grp[g].done, 0);
+    if (e == hipSuccess) e = snapshot(b);
     return e == hipSuccess ? M2M_OK : M2M_EDEVICE;
 }
 
@@ -1587,29 +1754,28 @@ m2m_status m2m_batch_poll(m2m_batch* b, m2m_ctx** done, int32_t max_done, int32_
             return M2M_EDEVICE;
     }
     if (hipStreamSynchronize(b->stream) != hipSuccess) return M2M_EDEVICE;
-    std::vector<m2m_ctx*> keep;
-    bool bad = false;
-    for (int f = 0; f < nf; ++f) {
-        m2m_ctx* c = b->fits[f];
-        const bool finished = b->gather_host[2 * f] <= 0;
-        if (finished && *n_done < max_done) {
-            done[(*n_done)++] = c;
-            c->batch = nullptr;
-            if (b->gather_host[2 * f + 1] & 1) {
-                c->err = "chi^2 became non-finite";
-                bad = true;
-            }
-        } else {
-            keep.push_back(c);
-        }
-    }
-    if (keep.size() != b->fits.size()) {
-        b->fits.swap(keep);
-        b->dirty = true;
-        if (b->fits.empty()) b->f64 = -1;
+    const std::vector<m2m_ctx*> now = b->fits;
+    const m2m_status s = collect(b, now, b->gather_host, done, max_done, n_done);
+    if (n_active) *n_active = (int32_t)b->fits.size();
+    return s;
+}
+
+m2m_status m2m_batch_poll_lagged(m2m_batch* b, m2m_ctx** done, int32_t max_done,
+                                 int32_t* n_done, int32_t* n_active) {
+    if (!b || !n_done || max_done < 0 || (max_done > 0 && !done)) return M2M_EINVAL;
+    *n_done = 0;
+    // the run before the latest: its snapshot slot is not rewritten before
+    // the next run, and the latest run keeps the device busy meanwhile
+    const int64_t k = b->runs - 2;
+    m2m_status s = M2M_OK;
+    if (k >= 0 && k > b->consumed) {
+        const int sl = (int)(k & 1);
+        if (hipEventSynchronize(b->snap_ev[sl]) != hipSuccess) return M2M_EDEVICE;
+        b->consumed = k;
+        s = collect(b, b->snap_fits[sl], b->snap_host[sl], done, max_done, n_done);
     }
     if (n_active) *n_active = (int32_t)b->fits.size();
-    return bad ? M2M_ENONFINITE : M2M_OK;
+    return s;
 }
 
 m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, double* ms_finalize) {
@@ -1681,10 +1847,10 @@ m2m_status m2m_batch_cancel(m2m_batch* b, m2m_ctx* c) {
         hipStreamSynchronize(b->stream) != hipSuccess)
         return M2M_EDEVICE;
     b->fits.erase(std::find(b->fits.begin(), b->fits.end(), c));
-    c->batch = nullptr;
+    const hipError_t e = retire(b, c);
     b->dirty = true;
     if (b->fits.empty()) b->f64 = -1;
-    return M2M_OK;
+    return e == hipSuccess ? M2M_OK : M2M_EDEVICE;
 }
 
 m2m_status m2m_batch_destroy(m2m_batch* b) {
@@ -1698,6 +1864,8 @@ m2m_status m2m_batch_destroy(m2m_batch* b) {
         if (b->grp[g].done) (void)hipEventDestroy(b->grp[g].done);
     }
     if (b->start) (void)hipEventDestroy(b->start);
+    for (hipEvent_t x : b->snap_ev)
+        if (x) (void)hipEventDestroy(x);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->gather_dev) (void)hipFree(b->gather_dev);
     if (b->gather_host) (void)hipHostFree(b->gather_host);

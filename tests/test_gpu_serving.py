@@ -1,7 +1,8 @@
 """Continuous-batching server on the GPU: requests that arrive while others
-run are admitted as slots free up, their steps share the batched launches, and
-every result equals the same fit run alone (same library, one context) and
-the FP64 oracle within the weight tolerance of the FP32 path."""
+run are admitted as slots free up (prepared ahead on a thread of their own),
+their steps share the batched launches, and every result equals the same fit
+run alone (same library, one context) and the FP64 oracle within the weight
+tolerance of the FP32 path."""
 
 import sys
 
@@ -53,14 +54,17 @@ def test_served_fits_equal_alone_and_oracle(oracle, gpu):
                 for key, v in parts[req.rid].items()}
 
     srv = Server(data, hbm_budget=1 << 30, max_fits=2, steps_per_launch=8, dtype="f32",
-                 keep_weights=True, initial_model=model)
+                 keep_weights=True, initial_model=model, preparers=1)
     m = srv.run(reqs, realtime=False)
     srv.close()
     assert m["requests"] == 4
     done = {r.rid: r for r in m["done"]}
-    # requests 2 and 3 could only start after a slot was freed
-    assert done[0].it_admit == done[1].it_admit
-    assert done[2].it_admit >= min(done[0].it_done, done[1].it_done) > done[0].it_admit
+    # never more than the two slots in use (a fit holds its slot from the
+    # turn it is admitted to the turn it is handed back), so requests 2 and 3
+    # could only start after a slot was freed
+    for t in range(1, max(r.it_done for r in done.values()) + 1):
+        assert sum(r.it_admit <= t <= r.it_done for r in done.values()) <= 2, t
+    assert done[2].it_admit > min(done[0].it_done, done[1].it_done)
     for k, r in done.items():
         f = Fit(r.potential, r.layout, r.params, parts[k], dtype="f32")
         f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
