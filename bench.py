@@ -361,6 +361,8 @@ def parser() -> argparse.ArgumentParser:
     ap.add_argument("--scf", type=int, default=None, metavar="L",
                     help="workloads 1-3: the stellar potential from the particles, a multipole "
                          "expansion (l <= L, 32 nodes on [0.02, 100]) instead of the Hernquist part")
+    ap.add_argument("--deposit", default=None, choices=["f64", "f32c"],
+                    help="workloads 1-3: the in-tile deposit mode instead of the tuned one")
     ap.add_argument("--scf-every", type=int, default=10,
                     help="with --scf: steps between rebuilds of the expansion")
     return ap
@@ -449,6 +451,9 @@ def main(argv=None):
                       every=args.scf_every)
     dtype = wl.state
     tuned = tuning.use("single", dtype, wl.layout, wl.N)
+    if args.deposit:
+        tuned = dict(tuned, deposit=args.deposit)
+        tuning.apply(tuned)
     print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={tuned}",
           file=sys.stderr, flush=True)
     fit = make_fit_and_targets(wl, Fit, dtype)

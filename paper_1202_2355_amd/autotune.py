@@ -10,7 +10,7 @@ replays against direct launches and the bound on the private bin copies. Each ca
 whole M2M steps (step and finalize kernels, graph replays, HIP events on the
 fit's or batch's stream) on fresh contexts over the same particles.
 
-    python -m paper_1202_2355_amd.autotune --workload 2 [--write]
+    python -m paper_1202_2355_amd.autotune --workload 2 [--alm 4] [--write]
     python -m paper_1202_2355_amd.autotune --workload 4 [--write]   (the Gauss-Hermite batch)
     python -m paper_1202_2355_amd.autotune --workload 5 [--write]   (the serving mix, LOSVD)
 """
@@ -172,6 +172,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None,
                     help="steps timed per candidate (default: 64 for one fit, two graphs "
                          "of 32; 40 for a batch, five graphs of 8)")
+    ap.add_argument("--alm", type=int, default=None, metavar="L",
+                    help="one fit with a_lm density observables (l <= L, 60 mesh radii)")
     ap.add_argument("--write", action="store_true", help="store the pick in the package's table")
     args = ap.parse_args(argv)
     if args.workload in (4, 5):
@@ -179,6 +181,9 @@ def main(argv=None):
         return main_batch(args)
     args.steps = args.steps or 64
     wl = workload(args.workload)
+    if args.alm is not None:
+        from workloads import with_alm
+        wl = with_alm(wl, n_mesh=60, l_max=args.alm)
     t0 = time.time()
     tp = wl.target_particles(n=1 << 20)
     tf = Fit(wl.potential, wl.layout, wl.params, tp, dtype=wl.state)

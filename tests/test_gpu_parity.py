@@ -484,6 +484,54 @@ def test_alm_run_fp32_matches_oracle(oracle, Fit):
     f.close()
 
 
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_alm_at_every_block_size_and_batched(oracle, Fit, block):
+    """a_lm density observables (l <= 4, 60 mesh radii) with Gauss-Hermite
+    annuli at every block size of the step kernel: two states against the
+    oracle (the per-observable bar of the FP32 path), then the two fits run
+    30 steps with refreshes as a batch against each fit alone."""
+    from paper_1202_2355_amd import tuning
+    from paper_1202_2355_amd.batch import Batch
+    from workloads import with_alm
+    wl = with_alm(workload(2), n_mesh=60, l_max=4)
+    wl = wl.with_(params=dict(wl.params, prior_every=10))
+    T = {"Y": np.ones(wl.J), "sigma": np.full(wl.J, 0.05)}
+    V, S = _gh_centres(wl.layout["n_R"])
+    V, S = cast({"V": V, "S": S}, "f32").values()
+    sizes = (40_009, 9_001)
+    parts = [cast(wl.initial_particles(n=n, seed=230 + k), "f32") for k, n in enumerate(sizes)]
+    _say("alm block", block, sizes)
+    before = tuning.current()
+    try:
+        tuning.apply(dict(before, block=block, tiles_per_cu=2))
+        alone = []
+        for k in range(2):
+            f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f32")
+            y = f.observe(V, S)
+            yo, yab, yamb = oracle.deposit(parts[k], np.ones(sizes[k]), wl.layout,
+                                           mass=wl.params["mass"], V_p=V, sigma_p=S,
+                                           band=BAND_F32, nthreads=8, with_abs=True)
+            assert_observables(y, yo, yab, yamb, 1e-5, f"alm block {block} fit {k}")
+            f.set_targets(T["Y"], T["sigma"], V, S)
+            f.step(30)
+            alone.append(f.particles()["u"])
+            f.close()
+        b = Batch(max_fits=2)
+        fits = []
+        for k in range(2):
+            f = Fit(wl.potential, wl.layout, wl.params, parts[k], dtype="f32")
+            f.set_targets(T["Y"], T["sigma"], V, S)
+            assert b.admit(f, 30)
+            fits.append(f)
+        b.run_to_completion(steps_per_launch=10)
+        for k, f in enumerate(fits):
+            np.testing.assert_allclose(f.particles()["u"], alone[k], rtol=1e-5)
+            f.close()
+        b.close()
+    finally:
+        tuning.apply(before)
+
+
 # ------------------------------------------------ prior-grid options (Sec. 5)
 def _oracle_priors(oracle, wl, par, parts, u, band):
     J = oracle.J_of(wl.layout)
