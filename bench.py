@@ -37,9 +37,11 @@ SERVE_N_MIN = 100_000   # smallest fit of the serving trace (errors floored at i
 METRIC = "particle-steps/sec (push+deposit+weight update) at 1 GPU; p50/p99 fit latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BYTES_PER_PSTEP = {"f32": 60, "f64": 120}   # read x, v, u, uhat; write x, v, u
+# the sources of the step kernel (the kernel the counters are taken on): its
+# code, its launchers, the device helpers and structures it uses
 KERNEL_SOURCES = tuple(f"paper_1202_2355_amd/csrc/{f}" for f in (
-    "m2m_kernels.hip", "m2m_device.h", "m2m_step.h", "m2m_step_f32d.hip", "m2m_step_f32f.hip",
-    "m2m_step_f64.hip", "m2m_internal.h"))
+    "m2m_device.h", "m2m_step.h", "m2m_step_f32d.hip", "m2m_step_f32f.hip", "m2m_step_f64.hip",
+    "m2m_internal.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 

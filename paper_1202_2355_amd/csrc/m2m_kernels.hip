@@ -236,6 +236,31 @@ __device__ __forceinline__ double fold_coef(int n, int p, int i, int k) {
     return 0.0;
 }
 
+// sum_k A[k stride] x[k] over k < m (A in global memory, x in LDS) with
+// kDotDepth loads in flight per thread: one block reads the smoothing basis
+// alone, so it is bound by how many of its loads are outstanding, not by
+// bandwidth; four partial sums, combined at the end.
+constexpr int kDotDepth = 16;
+__device__ __forceinline__ double dot_global(G<const double> A, size_t stride, const double* x,
+                                             int m) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int k = 0;
+    for (; k + kDotDepth <= m; k += kDotDepth) {
+        double q[kDotDepth];
+#pragma unroll
+        for (int u = 0; u < kDotDepth; ++u) q[u] = A[(size_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kDotDepth; u += 4) {
+            acc0 = fma(q[u], x[k + u], acc0);
+            acc1 = fma(q[u + 1], x[k + u + 1], acc1);
+            acc2 = fma(q[u + 2], x[k + u + 2], acc2);
+            acc3 = fma(q[u + 3], x[k + u + 3], acc3);
+        }
+    }
+    for (; k < m; ++k) acc0 = fma(A[(size_t)k * stride], x[k], acc0);
+    return (acc0 + acc1) + (acc2 + acc3);
+}
+
 // The four parity blocks of an n_E x n_x grid: block b = 2 pE + pX holds
 // mE(pE) mX(pX) folded coefficients from off(b) and its eigenvectors from
 // qoff(b) in the basis (scalars and selects, no indexed arrays, so that
@@ -318,11 +343,7 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
     for (int c = tid; c < n; c += kFinThreads) {
         const int b = B.block_of(c), m = B.off(b + 1) - B.off(b);
         const int o = c - B.off(b);
-        const G<const double> Q = basis + B.qoff(b);
-        const double* f = sa + B.off(b);
-        double v = 0.0;
-        for (int r = 0; r < m; ++r) v = fma(Q[(size_t)r * m + o], f[r], v);
-        sb[c] = v;
+        sb[c] = dot_global(basis + B.qoff(b) + o, (size_t)m, sa + B.off(b), m);
     }
     __syncthreads();
     for (int c = tid; c < n; c += kFinThreads) sa[c] = basis[c];  // eigenvalues
@@ -388,18 +409,13 @@ __device__ __forceinline__ void smooth_priors(const FitDev& fd, int base, double
     const int i3 = stage(false, na, nb, 65);
     const double lam = pow(10.0, na + (nb - na) * i3 / 64.0);
     // filter into sa, then back: folded coefficients Q_b (filtered w^), one
-    // row per wave (lanes over its entries), into sb
+    // row per thread, into sb
     for (int c = tid; c < n; c += kFinThreads) sa[c] = sb[c] / (1.0 + lam * sa[c]);
     __syncthreads();
-    for (int c = wave; c < n; c += kFinWaves) {
+    for (int c = tid; c < n; c += kFinThreads) {
         const int bb = B.block_of(c), m = B.off(bb + 1) - B.off(bb);
         const int r = c - B.off(bb);
-        const G<const double> Q = basis + B.qoff(bb) + (size_t)r * m;
-        const double* f = sa + B.off(bb);
-        double v = 0.0;
-        for (int o = lane; o < m; o += 64) v = fma(Q[o], f[o], v);
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) sb[c] = v;
+        sb[c] = dot_global(basis + B.qoff(bb) + (size_t)r * m, 1, sa + B.off(bb), m);
     }
     __syncthreads();
     // unfold: cell (k, l) from the vectors of both parities that touch it
