@@ -1320,6 +1320,7 @@ struct LaunchSet {
     size_t cap_fits = 0, cap_tiles = 0, cap_jobs = 0;
     int n_tiles = 0, n_jobs = 0, n_fits = 0;
     bool whole = false;  // one whole-fit finalize job per fit (else column jobs)
+    bool nt = false;     // the fits' state together exceeds kStreamMin (kModeStream)
     size_t lds = 0;
     hipGraphExec_t graph = nullptr;   // kBatchGraphSteps steps
     hipStream_t stream = nullptr;  // groups: the stream the group's steps run on
@@ -1386,7 +1387,7 @@ hipError_t grow(void** p, size_t* cap, size_t need) {
 // then their finalize jobs.
 hipError_t batch_step(const m2m_batch* b, const LaunchSet& L, bool f64, hipStream_t s) {
     hipError_t e = launch_step(f64, b->acc64, b->block, b->kin, L.fits_dev, L.tiles_dev, L.n_tiles,
-                               L.lds, kModeStep, s);
+                               L.lds, kModeStep | (L.nt ? kModeStream : 0), s);
     if (e == hipSuccess)
         e = launch_finalize(f64, L.fits_dev, L.n_fits, L.jobs_dev, L.n_jobs, kModeStep, s,
                             kin_scf(b->kin), b->smooth, L.whole);
@@ -1497,6 +1498,9 @@ m2m_status fill_set(m2m_batch* b, LaunchSet& L, const std::vector<int>& members,
     L.n_jobs = (int)jb.size();
     L.n_fits = (int)fd.size();
     L.whole = whole;
+    size_t state = 0;
+    for (int m : members) state += (size_t)b->fits[m]->n * 8 * (f64 ? 8 : 4);
+    L.nt = state > kStreamMin;
     L.lds = lds;
     if (capture) {
         // the graph of kBatchGraphSteps steps, uploaded on the stream it
@@ -1800,7 +1804,8 @@ m2m_status m2m_batch_profile(m2m_batch* b, int32_t n_steps, double* ms_step, dou
         e = hipEventRecord(ev[2 * k], b->stream);
         if (e == hipSuccess)
             e = launch_step(f64, b->acc64, b->block, b->kin, b->all.fits_dev, b->all.tiles_dev,
-                            b->all.n_tiles, b->all.lds, kModeStep, b->stream);
+                            b->all.n_tiles, b->all.lds, kModeStep | (b->all.nt ? kModeStream : 0),
+                            b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], b->stream);
         if (e == hipSuccess)
             e = launch_finalize(f64, b->all.fits_dev, b->all.n_fits, b->all.jobs_dev, b->all.n_jobs,

@@ -17,7 +17,10 @@ __device__ __forceinline__ void put_wt(G<T> p, T v) {
     __hip_atomic_store((T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, typename A, int BLOCK, int KIN>
+// NT: nontemporal particle loads and stores (streamed states, kModeStream);
+// a compile-time choice, as the compiler merges a load of the same address
+// in both arms of a run-time branch and drops the hint
+template <typename T, typename A, int BLOCK, int KIN, bool NT = false>
 __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const bool step = (mode & kModeStep) != 0;
@@ -63,6 +66,7 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     const bool deposit_on = !cells_only && !pot_only;
     const bool push = step;
     const bool wt = (mode & kModeWriteThrough) != 0;
+    constexpr bool nt = NT;
     const Hot<T> h = hot_of<T>(fd);
     const int J = h.J, C = h.C, kp = h.kp;
 
@@ -144,14 +148,25 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
         T x = nx, y = ny, z = nz, vx = nvx, vy = nvy, vz = nvz, u = nu, uh = nh;
         const int inext = i + BLOCK;
         if (inext < len) {
-            nx = X[inext];
-            ny = Y[inext];
-            nz = Z[inext];
-            nvx = VX[inext];
-            nvy = VY[inext];
-            nvz = VZ[inext];
-            nu = U[inext];
-            if (need_uh) nh = UH[inext];
+            if constexpr (nt) {
+                nx = __builtin_nontemporal_load(X + inext);
+                ny = __builtin_nontemporal_load(Y + inext);
+                nz = __builtin_nontemporal_load(Z + inext);
+                nvx = __builtin_nontemporal_load(VX + inext);
+                nvy = __builtin_nontemporal_load(VY + inext);
+                nvz = __builtin_nontemporal_load(VZ + inext);
+                nu = __builtin_nontemporal_load(U + inext);
+                if (need_uh) nh = __builtin_nontemporal_load(UH + inext);
+            } else {
+                nx = X[inext];
+                ny = Y[inext];
+                nz = Z[inext];
+                nvx = VX[inext];
+                nvy = VY[inext];
+                nvz = VZ[inext];
+                nu = U[inext];
+                if (need_uh) nh = UH[inext];
+            }
         }
         // the prior of the particle's cell at the last refresh (same
         // phase-space point: no push in between)
@@ -226,6 +241,15 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
             put_wt(VZ + i, vz);
             if (correct) put_wt(U + i, u);
             if (assign) put_wt(UH + i, uh);
+        } else if (nt && push) {
+            __builtin_nontemporal_store(x, X + i);
+            __builtin_nontemporal_store(y, Y + i);
+            __builtin_nontemporal_store(z, Z + i);
+            __builtin_nontemporal_store(vx, VX + i);
+            __builtin_nontemporal_store(vy, VY + i);
+            __builtin_nontemporal_store(vz, VZ + i);
+            if (correct) __builtin_nontemporal_store(u, U + i);
+            if (assign) __builtin_nontemporal_store(uh, UH + i);
         } else if (push) {
             X[i] = x;
             Y[i] = y;
@@ -272,11 +296,11 @@ constexpr bool lean_kin() {
     return (KIN & (kKinAlm | kKinScf)) == 0 && (KIN & 7) != kKinGHN;
 }
 
-template <typename T, typename A, int BLOCK, int KIN>
+template <typename T, typename A, int BLOCK, int KIN, bool NT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void k_step_w8(
     const FitDev* __restrict__ fits, const Tile* __restrict__ tiles, int32_t mode) {
     const Tile tl = tiles[blockIdx.x];
-    step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
+    step_tile<T, A, BLOCK, KIN, NT>(fits[tl.fit], tl, mode);
 }
 
 // one fit, its description passed by value; block t takes tile t of the
@@ -293,9 +317,14 @@ hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* on
     if (one)
         hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, *one,
                            mode);
-    else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8 && BLOCK == 1024)
-        hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
-                           tiles, mode);
+    else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8 && BLOCK == 1024) {
+        if (mode & kModeStream)
+            hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN, true>), dim3(n_tiles), dim3(BLOCK), lds, s,
+                               fits, tiles, mode);
+        else
+            hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN, false>), dim3(n_tiles), dim3(BLOCK), lds, s,
+                               fits, tiles, mode);
+    }
     else
         hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
                            tiles, mode);

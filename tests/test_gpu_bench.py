@@ -48,10 +48,12 @@ def _check_roofline(d, n):
     # graph replays without them, so with a cheap finalize the two can be
     # within a few per cent either way.
     assert roof["achieved"] == pytest.approx(60 * n / (roof["kernel_ms"] * 1e-3) / 1e9, rel=1e-9)
-    assert 0.0 < roof["kernel_ms"] < 1.05 * d["ms_per_step"]
+    # the step kernel alone (one launch over every fit) and the whole step
+    # (for a batch, two groups whose kernels overlap) stay within a factor of
+    # each other
+    assert 0.5 * d["ms_per_step"] < roof["kernel_ms"] < 1.5 * d["ms_per_step"]
     assert roof["whole_step_achieved"] == pytest.approx(60 * n / (d["ms_per_step"] * 1e-3) / 1e9,
                                                         rel=1e-9)
-    assert roof["whole_step_frac"] < 1.05 * roof["frac"]
 
 
 def test_bench_batch_line():
