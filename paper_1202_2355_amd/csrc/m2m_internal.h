@@ -42,8 +42,8 @@ enum : int32_t {
 constexpr size_t kWriteThroughMax = size_t(64) << 20;
 
 // The particle state of a batch launch above this size is streamed with
-// nontemporal loads and stores (the batch step kernel of the lean kinds of
-// observables): it does not fit the memory-side cache anyway, and with the
+// nontemporal loads and stores (the batch step kernels of the lean kinds of
+// observables, FP32 state): it does not fit the memory-side cache anyway, and with the
 // hint on both the loads and the stores the 64-fit batch of 1.16 GB stepped
 // 11 % faster; either hint alone gained nothing, and a state that stays in
 // the cache (3.2e7 bytes) stepped 6 % slower with them.

@@ -281,11 +281,11 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
 }
 
 // the tiles of the fits of a table (batches)
-template <typename T, typename A, int BLOCK, int KIN>
+template <typename T, typename A, int BLOCK, int KIN, bool NT = false>
 __global__ __launch_bounds__(BLOCK) void k_step(const FitDev* __restrict__ fits,
                                                 const Tile* __restrict__ tiles, int32_t mode) {
     const Tile tl = tiles[blockIdx.x];
-    step_tile<T, A, BLOCK, KIN>(fits[tl.fit], tl, mode);
+    step_tile<T, A, BLOCK, KIN, NT>(fits[tl.fit], tl, mode);
 }
 
 // The same for the kinds of observables whose step fits 64 VGPRs without
@@ -324,6 +324,13 @@ hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* on
         else
             hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN, false>), dim3(n_tiles), dim3(BLOCK), lds, s,
                                fits, tiles, mode);
+    } else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8) {
+        if (mode & kModeStream)
+            hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN, true>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                               tiles, mode);
+        else
+            hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN, false>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
+                               tiles, mode);
     }
     else
         hipLaunchKernelGGL((k_step<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, fits,
