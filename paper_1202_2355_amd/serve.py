@@ -101,6 +101,10 @@ class Server:
         self.batch = Batch(max_fits=max_fits, hbm_budget=self.budget, stream=self.stream)
         self.live = {}
 
+    def _new_stream(self):
+        """A stream for one preparing thread."""
+        return torch.cuda.Stream()
+
     def _make(self, req: Request, st):
         """The request's fit, prepared on the preparing thread's stream ``st``
         (admission orders the batch after it on the device, without waiting
@@ -133,7 +137,7 @@ class Server:
                 # one stream per preparing thread, made once: with the
                 # hardware queues HIP gives a process, the few streams of the
                 # server each get a queue of their own
-                st = torch.cuda.Stream()
+                st = self._new_stream()
                 while True:
                     req = todo.get()
                     if req is None:
