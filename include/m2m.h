@@ -409,6 +409,16 @@ typedef enum { M2M_DEPOSIT_F64 = 0, M2M_DEPOSIT_F32_COMPENSATED = 1 } m2m_deposi
 m2m_status m2m_set_deposit_mode(int32_t mode);
 int32_t m2m_get_deposit_mode(void);
 
+/* Which particles a tile of the step kernel of one fit takes, for contexts
+ * created afterwards: 0 its contiguous range, 1 interleaved chunks of one
+ * block's width (tile t of T takes chunks t, t + T, t + 2T, ...), or -1
+ * (default) interleaved for particle states above 128 MiB (8 arrays of n
+ * values) and contiguous below. Interleaving only applies below 2^30
+ * particles. Batches always take contiguous ranges. The sums are the same up
+ * to rounding order. EINVAL otherwise. */
+m2m_status m2m_set_interleave(int32_t mode);
+int32_t m2m_get_interleave(void);
+
 /* ---------------------------------------------------------- batching --
  * Many fits of uneven size stepping together. A batch of two or more fits is
  * split into two groups of about equal particle count; every step of a group

@@ -97,6 +97,8 @@ SIGNATURES = {
     "m2m_get_private_copies": (_i32, []),
     "m2m_get_batch_groups": (_i32, []),
     "m2m_get_deposit_mode": (_i32, []),
+    "m2m_set_interleave": (_st, [_i32]),
+    "m2m_get_interleave": (_i32, []),
     "m2m_batch_create": (_st, [_i32, C.c_size_t, _vp, C.POINTER(_vp)]),
     "m2m_batch_admit": (_st, [_vp, _vp, _i32]),
     "m2m_batch_run": (_st, [_vp, _i32]),
@@ -223,6 +225,16 @@ def m2m_get_batch_groups() -> int:
 
 def m2m_get_deposit_mode() -> int:
     return int(lib().m2m_get_deposit_mode())
+
+
+def m2m_set_interleave(mode: int):
+    """Particles of a tile for single fits created from now on: contiguous
+    (0), interleaved chunks (1), or by state size (-1, the default)."""
+    check(lib().m2m_set_interleave(int(mode)), "m2m_set_interleave")
+
+
+def m2m_get_interleave() -> int:
+    return int(lib().m2m_get_interleave())
 
 
 def m2m_get_launch():

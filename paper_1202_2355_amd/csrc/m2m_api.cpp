@@ -39,6 +39,7 @@ int g_groups = 2;           // groups of a batch of two or more fits (1 or 2)
 int g_batch_graphs = 0;     // batches replay captured graphs (1) or launch directly (0)
 int g_deposit = M2M_DEPOSIT_F64;
 int g_kpriv_cap = 0;  // most private bin copies per block (0: as many as fit, at most 8)
+int g_interleave = -1;  // tiles of one fit: contiguous (0), interleaved (1), by state size (-1)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -487,6 +488,7 @@ struct m2m_ctx {
     int block = 256, kin = 0;
     bool acc64 = true;
     bool wt = false;  // write-through particle stores (kModeWriteThrough)
+    bool il = false;  // interleaved tiles in the step kernel (kModeInterleave)
     hipGraphExec_t graph_prof = nullptr;  // steps with an extra measuring reduction
     bool targets = false;
     bool ytil_init = false;
@@ -631,8 +633,10 @@ m2m_status refresh_potential(m2m_ctx* c) {
 
 // One M2M step: the step kernel over all tiles, then the finalize.
 hipError_t launch_one_step(m2m_ctx* c, hipStream_t s) {
-    hipError_t e = launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles,
-                               c->lds, kModeStep | (c->wt ? kModeWriteThrough : 0), s);
+    hipError_t e = launch_step1(c->f64, c->acc64, c->block, c->kin, c->fd, c->n_tiles, c->lds,
+                               kModeStep | (c->wt ? kModeWriteThrough : 0) |
+                                   (c->il ? kModeInterleave : 0),
+                               s);
     if (e == hipSuccess) e = launch_finalize1(c->f64, c->fd, c->n_tiles, kModeStep, s);
     return e;
 }
@@ -744,6 +748,14 @@ m2m_status m2m_set_deposit_mode(int32_t mode) {
 
 int32_t m2m_get_deposit_mode(void) { return g_deposit; }
 
+m2m_status m2m_set_interleave(int32_t mode) {
+    if (mode < -1 || mode > 1) return M2M_EINVAL;
+    g_interleave = mode;
+    return M2M_OK;
+}
+
+int32_t m2m_get_interleave(void) { return g_interleave; }
+
 m2m_status m2m_get_launch(int32_t* block, int32_t* tiles_per_cu) {
     if (block) *block = g_block;
     if (tiles_per_cu) *tiles_per_cu = g_tiles_per_cu;
@@ -786,6 +798,9 @@ m2m_status m2m_create(const m2m_potential* pot, const m2m_obs_layout* layout,
                                       : private_copies(c->f64, w.J);
     c->acc64 = c->f64 || g_deposit == M2M_DEPOSIT_F64;
     c->wt = (size_t)n * 8 * (c->f64 ? 8 : 4) <= kWriteThroughMax;
+    // interleaved particle indices are 32-bit: n + n_tiles * block stays below 2^31
+    c->il = (g_interleave < 0 ? (size_t)n * 8 * (c->f64 ? 8 : 4) > kStreamMin : g_interleave == 1) &&
+            n < (int64_t(1) << 30);
     c->lds = step_lds_bytes(c->f64, c->acc64, w.J, radial_intervals(c->lay),
                             c->lay.kin == M2M_KIN_NONE ? 0 : c->lay.n_R,
                             c->lay.kin == M2M_KIN_LOSVD ? c->lay.n_v : 0, kpriv, w.C,

@@ -34,6 +34,7 @@ enum : int32_t {
     kModeWriteThrough = 16,  // step: particle stores write through L2 (small fits)
     kModePot = 32,       // rebuild the self-consistent potential from the current state only
     kModeStream = 64,    // batch step: nontemporal particle loads and stores (large states)
+    kModeInterleave = 128,  // one fit: tiles take interleaved chunks of particles (large states)
 };
 
 // Particle state up to this size is stepped with write-through stores: it
@@ -48,6 +49,13 @@ constexpr size_t kWriteThroughMax = size_t(64) << 20;
 // 11 % faster; either hint alone gained nothing, and a state that stays in
 // the cache (3.2e7 bytes) stepped 6 % slower with them.
 constexpr size_t kStreamMin = size_t(128) << 20;
+
+// The step kernel of one fit whose particle state exceeds kStreamMin takes
+// its particles interleaved (kModeInterleave): chunks of one block's width,
+// dealt to the tiles in turn, so that the blocks in flight read and write a
+// narrow window of each array. At 8e6 particles (480 MB) the step kernel ran
+// 10 % faster so; at 1e6 (in the memory-side cache) 2-4 % slower, and the
+// 64-fit batch (many fits of about 24 tiles each) gained nothing.
 
 // Dynamic per-fit state, device resident, written only by the kernels (and by
 // the host between launches, on the fit's stream).

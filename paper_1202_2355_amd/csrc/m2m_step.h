@@ -19,8 +19,10 @@ __device__ __forceinline__ void put_wt(G<T> p, T v) {
 
 // NT: nontemporal particle loads and stores (streamed states, kModeStream);
 // a compile-time choice, as the compiler merges a load of the same address
-// in both arms of a run-time branch and drops the hint
-template <typename T, typename A, int BLOCK, int KIN, bool NT = false>
+// in both arms of a run-time branch and drops the hint. ONE: the launch of
+// one fit, whose tiles may take interleaved chunks (kModeInterleave); the
+// batch kernels keep contiguous ranges with a compile-time stride.
+template <typename T, typename A, int BLOCK, int KIN, bool NT = false, bool ONE = false>
 __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const bool step = (mode & kModeStep) != 0;
@@ -28,17 +30,24 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     // particle arrays from the tile start (32-bit offsets within the tile);
     // the first particle of every lane is requested before anything else so
     // that its latency overlaps the set-up below
-    const G<T> __restrict__ X = gmem<T>(fd.x) + tl.begin;
-    const G<T> __restrict__ Y = gmem<T>(fd.y) + tl.begin;
-    const G<T> __restrict__ Z = gmem<T>(fd.z) + tl.begin;
-    const G<T> __restrict__ VX = gmem<T>(fd.vx) + tl.begin;
-    const G<T> __restrict__ VY = gmem<T>(fd.vy) + tl.begin;
-    const G<T> __restrict__ VZ = gmem<T>(fd.vz) + tl.begin;
-    const G<T> __restrict__ U = gmem<T>(fd.u) + tl.begin;
-    const G<T> __restrict__ UH = gmem<T>(fd.uh) + tl.begin;
-    const G<uint16_t> __restrict__ CI = gmem(fd.cidx) + tl.begin;
-    const int len = (int)(tl.end - tl.begin);
-    int i = threadIdx.x;
+    // The tile's particles: its contiguous range, or (kModeInterleave) the
+    // chunks of BLOCK consecutive particles t, t + n_rows, t + 2 n_rows, ...
+    // of the fit for tile t of n_rows. Interleaved, the blocks in flight
+    // stream one narrow window of each array instead of a range each.
+    const bool il = ONE && (mode & kModeInterleave) != 0;  // one fit's launch only
+    const int64_t off = il ? 0 : tl.begin;
+    const int len = (int)(il ? fd.n : tl.end - tl.begin);
+    const int istep = il ? tl.n_rows * BLOCK : BLOCK;
+    int i = (il ? tl.row * BLOCK : 0) + (int)threadIdx.x;
+    const G<T> __restrict__ X = gmem<T>(fd.x) + off;
+    const G<T> __restrict__ Y = gmem<T>(fd.y) + off;
+    const G<T> __restrict__ Z = gmem<T>(fd.z) + off;
+    const G<T> __restrict__ VX = gmem<T>(fd.vx) + off;
+    const G<T> __restrict__ VY = gmem<T>(fd.vy) + off;
+    const G<T> __restrict__ VZ = gmem<T>(fd.vz) + off;
+    const G<T> __restrict__ U = gmem<T>(fd.u) + off;
+    const G<T> __restrict__ UH = gmem<T>(fd.uh) + off;
+    const G<uint16_t> __restrict__ CI = gmem(fd.cidx) + off;
     T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
     if (i < len) {
         nx = X[i];
@@ -144,9 +153,9 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
 
     // software pipeline: the loads of the next particle are in flight while
     // the current one is computed
-    for (; i < len; i += BLOCK) {
+    for (; i < len; i += istep) {
         T x = nx, y = ny, z = nz, vx = nvx, vy = nvy, vz = nvz, u = nu, uh = nh;
-        const int inext = i + BLOCK;
+        const int inext = i + istep;
         if (inext < len) {
             if constexpr (nt) {
                 nx = __builtin_nontemporal_load(X + inext);
@@ -307,7 +316,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
 // fit split into gridDim.x tiles
 template <typename T, typename A, int BLOCK, int KIN>
 __global__ __launch_bounds__(BLOCK) void k_step1(const FitDev fd, int32_t mode) {
-    step_tile<T, A, BLOCK, KIN>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0), mode);
+    step_tile<T, A, BLOCK, KIN, false, true>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0),
+                                             mode);
 }
 
 

@@ -128,6 +128,44 @@ def test_run_fp32_matches_oracle_200_steps(oracle, Fit, mode):
     f.close()
 
 
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_interleaved_tiles_match_oracle_and_contiguous_tiles(oracle, Fit, block):
+    """Tiles of interleaved chunks (the mapping the library picks for single
+    fits whose state exceeds the memory-side cache), forced on a fit of
+    workload 2's layout at every block size, one tile per compute unit, so
+    that every tile takes several chunks and the last chunk is ragged:
+    weights and the chi^2 history after 60 FP32 steps (two prior refreshes)
+    against the oracle, and the weights against the same fit with
+    contiguous tiles (rounding order only)."""
+    from paper_1202_2355_amd import _abi, tuning
+    wl = workload(2)
+    n = 600_011
+    steps = 60
+    _say("interleaved tiles, block", block, "n", n)
+    before = tuning.current()
+    u = {}
+    try:
+        tuning.apply(dict(before, block=block, tiles_per_cu=1))
+        for il in (1, 0):
+            _abi.m2m_set_interleave(il)
+            T, parts, f, o = _run_pair(oracle, Fit, wl, n, steps, "f32", 1e-5)
+            f.step(steps)
+            hist_g = f.chi2_history(steps)
+            u[il] = f.particles()["u"]
+            f.close()
+            if il == 1:
+                hist_o = o.step(steps)
+                r2, rmax, rall, frac = weight_errors(u[1], o.arr["u"], o.flag)
+                _say("interleaved: rel2", r2, "max(unflagged)", rmax, "max(all)", rall,
+                     "flagged", frac)
+                assert r2 <= 1e-4 and rmax <= 1e-4
+                np.testing.assert_allclose(hist_g, hist_o, rtol=1e-4)
+    finally:
+        _abi.m2m_set_interleave(-1)
+        tuning.apply(before)
+    np.testing.assert_allclose(u[1], u[0], rtol=1e-5)
+
+
 def test_run_fp64_matches_oracle_200_steps(oracle, Fit):
     """Workload 1 as specified (FP64 particle state): weights after 200 steps."""
     wl = workload(1)

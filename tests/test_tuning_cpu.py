@@ -59,3 +59,10 @@ def test_library_refuses_bad_settings():
     for bad in (0, 3):
         with pytest.raises(_abi.M2MError):
             _abi.m2m_set_batch_groups(bad)
+    for bad in (-2, 2):
+        with pytest.raises(_abi.M2MError):
+            _abi.m2m_set_interleave(bad)
+    assert _abi.m2m_get_interleave() == -1   # the default: by state size
+    for mode in (0, 1, -1):
+        _abi.m2m_set_interleave(mode)
+        assert _abi.m2m_get_interleave() == mode
