@@ -413,9 +413,11 @@ int32_t m2m_get_deposit_mode(void);
  * created afterwards: 0 its contiguous range, 1 interleaved chunks of one
  * block's width (tile t of T takes chunks t, t + T, t + 2T, ...), or -1
  * (default) interleaved for particle states above 128 MiB (8 arrays of n
- * values) and contiguous below. Interleaving only applies below 2^30
- * particles. Batches always take contiguous ranges. The sums are the same up
- * to rounding order. EINVAL otherwise. */
+ * values) and contiguous below. Interleaving applies to fits of FP32 state
+ * with FP64 bins (M2M_DEPOSIT_F64) and observables without a_lm
+ * coefficients, Gauss-Hermite moments beyond h_4 or the self-consistent
+ * potential, below 2^30 particles; other fits and batches take contiguous
+ * ranges. The sums are the same up to rounding order. EINVAL otherwise. */
 m2m_status m2m_set_interleave(int32_t mode);
 int32_t m2m_get_interleave(void);
 

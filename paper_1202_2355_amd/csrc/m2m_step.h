@@ -19,10 +19,11 @@ __device__ __forceinline__ void put_wt(G<T> p, T v) {
 
 // NT: nontemporal particle loads and stores (streamed states, kModeStream);
 // a compile-time choice, as the compiler merges a load of the same address
-// in both arms of a run-time branch and drops the hint. ONE: the launch of
-// one fit, whose tiles may take interleaved chunks (kModeInterleave); the
-// batch kernels keep contiguous ranges with a compile-time stride.
-template <typename T, typename A, int BLOCK, int KIN, bool NT = false, bool ONE = false>
+// in both arms of a run-time branch and drops the hint. IL: the tiles take
+// interleaved chunks (one fit, kModeInterleave), also a compile-time
+// choice: as a run-time branch it slowed the contiguous loop of a
+// cache-resident fit by 2-3 %.
+template <typename T, typename A, int BLOCK, int KIN, bool NT = false, bool IL = false>
 __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int32_t mode) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const bool step = (mode & kModeStep) != 0;
@@ -34,11 +35,8 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     // chunks of BLOCK consecutive particles t, t + n_rows, t + 2 n_rows, ...
     // of the fit for tile t of n_rows. Interleaved, the blocks in flight
     // stream one narrow window of each array instead of a range each.
-    const bool il = ONE && (mode & kModeInterleave) != 0;  // one fit's launch only
+    constexpr bool il = IL;
     const int64_t off = il ? 0 : tl.begin;
-    const int len = (int)(il ? fd.n : tl.end - tl.begin);
-    const int istep = il ? tl.n_rows * BLOCK : BLOCK;
-    int i = (il ? tl.row * BLOCK : 0) + (int)threadIdx.x;
     const G<T> __restrict__ X = gmem<T>(fd.x) + off;
     const G<T> __restrict__ Y = gmem<T>(fd.y) + off;
     const G<T> __restrict__ Z = gmem<T>(fd.z) + off;
@@ -48,6 +46,9 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     const G<T> __restrict__ U = gmem<T>(fd.u) + off;
     const G<T> __restrict__ UH = gmem<T>(fd.uh) + off;
     const G<uint16_t> __restrict__ CI = gmem(fd.cidx) + off;
+    const int len = (int)(il ? fd.n : tl.end - tl.begin);
+    const int istep = il ? tl.n_rows * BLOCK : BLOCK;
+    int i = il ? tl.row * BLOCK + (int)threadIdx.x : (int)threadIdx.x;
     T nx = T(0), ny = T(0), nz = T(0), nvx = T(0), nvy = T(0), nvz = T(0), nu = T(0), nh = T(1);
     if (i < len) {
         nx = X[i];
@@ -314,20 +315,28 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
 
 // one fit, its description passed by value; block t takes tile t of the
 // fit split into gridDim.x tiles
-template <typename T, typename A, int BLOCK, int KIN>
+template <typename T, typename A, int BLOCK, int KIN, bool IL = false>
 __global__ __launch_bounds__(BLOCK) void k_step1(const FitDev fd, int32_t mode) {
-    step_tile<T, A, BLOCK, KIN, false, true>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0),
-                                             mode);
+    step_tile<T, A, BLOCK, KIN, false, IL>(fd, tile_of(fd.n, (int)blockIdx.x, (int)gridDim.x, 0, 0),
+                                           mode);
 }
 
 
 template <typename T, typename A, int BLOCK, int KIN>
 hipError_t launch_step_t(const FitDev* fits, const Tile* tiles, const FitDev* one, int n_tiles,
                          size_t lds, int32_t mode, hipStream_t s) {
-    if (one)
+    if (one) {
+        // interleaved tiles are built for the lean kinds with FP32 state and
+        // FP64 bins; other fits keep contiguous ranges
+        if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8)
+            if (mode & kModeInterleave) {
+                hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN, true>), dim3(n_tiles), dim3(BLOCK), lds, s,
+                                   *one, mode);
+                return hipGetLastError();
+            }
         hipLaunchKernelGGL((k_step1<T, A, BLOCK, KIN>), dim3(n_tiles), dim3(BLOCK), lds, s, *one,
                            mode);
-    else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8 && BLOCK == 1024) {
+    } else if constexpr (lean_kin<KIN>() && sizeof(T) == 4 && sizeof(A) == 8 && BLOCK == 1024) {
         if (mode & kModeStream)
             hipLaunchKernelGGL((k_step_w8<T, A, BLOCK, KIN, true>), dim3(n_tiles), dim3(BLOCK), lds, s,
                                fits, tiles, mode);
