@@ -343,7 +343,12 @@ def parser() -> argparse.ArgumentParser:
     ap.add_argument("--requests", type=int, default=500, help="workload 5: trace length")
     ap.add_argument("--rate", type=float, default=SERVE_RATE,
                     help="workload 5: arrival rate of the trace (requests/s)")
-    ap.add_argument("--state", default="f32", choices=["f32", "f64"], help="workload 5 state")
+    ap.add_argument("--interleave", type=int, default=None, choices=[-1, 0, 1],
+                    help="workloads 1-3: tiles of the step kernel take contiguous ranges (0) or "
+                         "interleaved chunks (1); default: the library's choice by state size")
+    ap.add_argument("--state", default=None, choices=["f32", "f64"],
+                    help="particle state of workloads 2, 3 and 5 (default: the workload's own, "
+                         "FP32 for the serving trace)")
     ap.add_argument("--hbm-gb", type=float, default=96.0, help="workload 5: HBM budget")
     ap.add_argument("--steps-per-launch", type=int, default=64)
     ap.add_argument("--max-fits", type=int, default=64, help="workload 5: batch slots")
@@ -378,6 +383,8 @@ def main(argv=None):
               "single-GPU build", file=sys.stderr)
         return 2
 
+    if args.workload == 5 and args.state is None:
+        args.state = "f32"
     if args.workload == 5:
         # the preparing threads' streams get hardware queues of their own
         # instead of queueing behind the batch's enqueued runs (read when HIP
@@ -452,11 +459,17 @@ def main(argv=None):
         from workloads import with_scf
         wl = with_scf(wl, l_max=args.scf, n_nodes=32, r_min=0.02, r_max=100.0,
                       every=args.scf_every)
+    if args.state:
+        wl = wl.with_(name=f"{wl.name}_{args.state}" if args.state != wl.state else wl.name,
+                      state=args.state)
     dtype = wl.state
     tuned = tuning.use("single", dtype, wl.layout, wl.N)
     if args.deposit:
         tuned = dict(tuned, deposit=args.deposit)
         tuning.apply(tuned)
+    if args.interleave is not None:
+        _abi.m2m_set_interleave(args.interleave)
+        tuned = dict(tuned, interleave=args.interleave)
     print(f"[bench] {wl.name}: N={wl.N} J={wl.J} dtype={dtype} launch={tuned}",
           file=sys.stderr, flush=True)
     fit = make_fit_and_targets(wl, Fit, dtype)

@@ -132,11 +132,11 @@ def test_run_fp32_matches_oracle_200_steps(oracle, Fit, mode):
 def test_interleaved_tiles_match_oracle_and_contiguous_tiles(oracle, Fit, block):
     """Tiles of interleaved chunks (the mapping the library picks for single
     fits whose state exceeds the memory-side cache), forced on a fit of
-    workload 2's layout at every block size, one tile per compute unit, so
-    that every tile takes several chunks and the last chunk is ragged:
-    weights and the chi^2 history after 60 FP32 steps (two prior refreshes)
-    against the oracle, and the weights against the same fit with
-    contiguous tiles (rounding order only)."""
+    workload 2's layout at every block size (FP32 state, the one it is built
+    for), one tile per compute unit, so that every tile takes several chunks
+    and the last chunk is ragged: weights and the chi^2 history after 60
+    steps (two prior refreshes) against the oracle, and the weights against
+    the same fit with contiguous tiles (rounding order only)."""
     from paper_1202_2355_amd import _abi, tuning
     wl = workload(2)
     n = 600_011
