@@ -166,6 +166,42 @@ def test_interleaved_tiles_match_oracle_and_contiguous_tiles(oracle, Fit, block)
     np.testing.assert_allclose(u[1], u[0], rtol=1e-5)
 
 
+@pytest.mark.parametrize("n", [1, 1_023, 70_001])
+def test_interleaved_tiles_with_empty_tiles(oracle, Fit, n):
+    """Interleaved tiles when the fit has fewer chunks than tiles (up to 256
+    tiles of 1024 threads): most tiles take no particle and deposit nothing.
+    One particle, one short chunk, and 69 chunks with a ragged last one, FP32
+    state, workload 1's layout with a prior refresh every 4 steps and the
+    fit's own initial observables as targets (5 % errors; a few particles
+    against a full model's targets would overflow the weights): weights
+    after 12 steps against the oracle."""
+    from paper_1202_2355_amd import _abi, tuning
+    wl = workload(1)
+    wl = wl.with_(params=dict(wl.params, prior_every=4))
+    parts = cast(wl.initial_particles(n=n, seed=12 + n), "f32")
+    Y = oracle.deposit(parts, np.ones(n), wl.layout, mass=wl.params["mass"])
+    sig = 0.05 * np.abs(Y) + 1e-3 * np.abs(Y).max() + 1e-12
+    _say("interleaved tiles, empty tiles, n", n)
+    before = tuning.current()
+    try:
+        tuning.apply(dict(before, block=1024, tiles_per_cu=1))
+        _abi.m2m_set_interleave(1)
+        f = Fit(wl.potential, wl.layout, wl.params, parts, dtype="f32")
+    finally:
+        _abi.m2m_set_interleave(-1)
+        tuning.apply(before)
+    f.set_targets(Y, sig)
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, Y, sig, None, None,
+                         track_flags=True, band=1e-5, nthreads=8)
+    f.step(12)
+    o.step(12)
+    st = f.particles()
+    f.close()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say("empty tiles: rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    assert r2 <= 1e-4 and rmax <= 1e-4
+
+
 def test_run_fp64_matches_oracle_200_steps(oracle, Fit):
     """Workload 1 as specified (FP64 particle state): weights after 200 steps."""
     wl = workload(1)
