@@ -202,6 +202,43 @@ def test_interleaved_tiles_with_empty_tiles(oracle, Fit, n):
     assert r2 <= 1e-4 and rmax <= 1e-4
 
 
+@pytest.mark.parametrize("case", ["alm_f32", "v2_f64"])
+def test_interleave_request_on_fits_built_without_it(oracle, Fit, case):
+    """Interleaving forced on fits whose step kernel is built with contiguous
+    tiles only (a_lm density observables; FP64 state): the request is
+    ignored and the fit matches the oracle as always (weights after 12 steps
+    with three prior refreshes)."""
+    from paper_1202_2355_amd import _abi, tuning
+    from workloads import with_alm
+    if case == "alm_f32":
+        wl, dtype, n, band, tol = with_alm(workload(1), n_mesh=20, l_max=2), "f32", 30_011, 1e-5, 1e-4
+    else:
+        wl, dtype, n, band, tol = workload(1), "f64", 30_011, 1e-12, 1e-10
+    wl = wl.with_(params=dict(wl.params, prior_every=4))
+    parts = cast(wl.initial_particles(n=n, seed=14), dtype)
+    Y = oracle.deposit(parts, np.ones(n), wl.layout, mass=wl.params["mass"])
+    sig = 0.05 * np.abs(Y) + 1e-3 * np.abs(Y).max() + 1e-12
+    _say("interleave requested on", case, n)
+    before = tuning.current()
+    try:
+        tuning.apply(dict(before, block=1024, tiles_per_cu=1))
+        _abi.m2m_set_interleave(1)
+        f = Fit(wl.potential, wl.layout, wl.params, parts, dtype=dtype)
+    finally:
+        _abi.m2m_set_interleave(-1)
+        tuning.apply(before)
+    f.set_targets(Y, sig)
+    o = oracle.OracleFit(wl.potential, wl.layout, wl.params, parts, Y, sig, None, None,
+                         track_flags=True, band=band, nthreads=8)
+    f.step(12)
+    o.step(12)
+    st = f.particles()
+    f.close()
+    r2, rmax, rall, frac = weight_errors(st["u"], o.arr["u"], o.flag)
+    _say(case, "rel2", r2, "max(unflagged)", rmax, "flagged", frac)
+    assert r2 <= tol and rmax <= tol
+
+
 def test_run_fp64_matches_oracle_200_steps(oracle, Fit):
     """Workload 1 as specified (FP64 particle state): weights after 200 steps."""
     wl = workload(1)
