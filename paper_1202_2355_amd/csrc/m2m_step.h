@@ -28,13 +28,13 @@ __device__ __forceinline__ void step_tile(const FitDev& fd, const Tile& tl, int3
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const bool step = (mode & kModeStep) != 0;
 
-    // particle arrays from the tile start (32-bit offsets within the tile);
-    // the first particle of every lane is requested before anything else so
-    // that its latency overlaps the set-up below
-    // The tile's particles: its contiguous range, or (kModeInterleave) the
-    // chunks of BLOCK consecutive particles t, t + n_rows, t + 2 n_rows, ...
-    // of the fit for tile t of n_rows. Interleaved, the blocks in flight
-    // stream one narrow window of each array instead of a range each.
+    // The tile's particles: its contiguous range (arrays from the tile start),
+    // or (IL) the chunks of BLOCK consecutive particles t, t + n_rows,
+    // t + 2 n_rows, ... of the fit for tile t of n_rows (arrays from the fit
+    // start); 32-bit offsets either way. Interleaved, the blocks in flight
+    // stream one narrow window of each array instead of a range each. The
+    // first particle of every lane is requested before anything else so that
+    // its latency overlaps the set-up below.
     constexpr bool il = IL;
     const int64_t off = il ? 0 : tl.begin;
     const G<T> __restrict__ X = gmem<T>(fd.x) + off;
