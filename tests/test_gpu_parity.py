@@ -400,11 +400,12 @@ def test_invalid_arguments(Fit):
     f.close()
 
 
-@pytest.mark.parametrize("wlid,steps", [(2, 10), (3, 3)])
+@pytest.mark.parametrize("wlid,steps", [(2, 10), (3, 3), (3, 26)])
 def test_full_size_workloads(oracle, Fit, wlid, steps):
     """Workloads 2 and 3 at their full particle counts, in the launch shape
-    the benchmark uses: observables of the initial state and weights after a
-    few steps against the oracle."""
+    the benchmark uses (workload 3: interleaved tiles): observables of the
+    initial state and weights after a few steps against the oracle; for
+    workload 3 also across its first in-step prior refresh (26 steps)."""
     from paper_1202_2355_amd import tuning
     wl = workload(wlid)
     T = oracle_targets(oracle, wl)
