@@ -188,6 +188,61 @@ def test_batched_configuration_in_its_launch_shape(oracle, Fit):
         np.testing.assert_allclose(hist, hist_o, rtol=1e-4)
 
 
+def test_full_size_batch_across_a_refresh(oracle, Fit):
+    """The benchmarked batch itself: all 64 fits at their full particle
+    counts (3.6e7 in all, drawn on the device as the benchmark draws them),
+    oracle targets, the batch's tuned launch, 26 steps (the first in-step
+    prior refresh). Every fit ends with 26 steps taken and a finite chi^2;
+    the smallest, the median and the largest fit match the oracle run alone
+    from the same initial state (weights within 1e-4)."""
+    from paper_1202_2355_amd.batch import Batch
+    from workloads.configs import batch_fits
+    from workloads.device import om_model_device
+    steps = 26
+    fits_wl = batch_fits(64)
+    sizes = [wl.N for wl in fits_wl]
+    order = sorted(range(len(fits_wl)), key=lambda k: sizes[k])
+    sample = sorted({order[0], order[len(order) // 2], order[-1]})
+    _say("full-size batch", sum(sizes), "particles; oracle on fits", [sizes[k] for k in sample])
+    fits, Ts, ics = [], [], {}
+    for k, wl in enumerate(fits_wl):
+        T = oracle_targets(oracle, wl, n_target=1 << 15, nthreads=16)
+        ic = om_model_device(wl.N, wl.potential, float("inf"), seed=wl.seed * 10 + 1)
+        f = Fit(wl.potential, wl.layout, wl.params, ic, dtype="f32")
+        f.set_targets(T["Y"], T["sigma"], T["V_p"], T["sigma_p"])
+        if k in sample:
+            st = f.particles()
+            ics[k] = {q: st[q] for q in ("x", "y", "z", "vx", "vy", "vz")}
+        del ic
+        fits.append(f)
+        Ts.append(T)
+    with _tuned("batch", fits_wl[0]) as shape:
+        _say("batch launch", shape)
+        b = Batch(max_fits=len(fits))
+        for f in fits:
+            assert b.admit(f, steps)
+        done = b.run_to_completion(steps_per_launch=16, max_steps=10 * steps)
+        assert len(done) == len(fits)
+        got = {}
+        for k, f in enumerate(fits):
+            assert _counters(f) == (steps, steps), k
+            assert np.isfinite(f.observables()["chi2"]), k
+            if k in sample:
+                got[k] = f.particles()["u"]
+        for f in fits:
+            f.close()
+        b.close()
+    for k in sample:
+        wl, T = fits_wl[k], Ts[k]
+        o = oracle.OracleFit(wl.potential, wl.layout, wl.params, ics[k], T["Y"], T["sigma"],
+                             T["V_p"], T["sigma_p"], track_flags=True, band=1e-5, nthreads=16)
+        o.step(steps)
+        r2, rmax, rall, frac = weight_errors(got[k], o.arr["u"], o.flag)
+        _say("full-size batch fit", k, "N", wl.N, "rel2", r2, "max(unflagged)", rmax,
+             "flagged", frac)
+        assert r2 <= 1e-4 and rmax <= 1e-4
+
+
 @pytest.mark.parametrize("scf", [False, True])
 def test_batch_finalize_hand_over_with_frequent_refreshes(oracle, Fit, scf):
     """Sixteen LOSVD fits (41 observable and 32 cell finalize jobs each), the
